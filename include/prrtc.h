@@ -1,0 +1,190 @@
+/*
+ * prrtc.h -- C ABI of the MI355X (gfx950) pRRTC hot-path library, libprrtc.so.
+ *
+ * pRRTC (Huang, Jadhav, Plancher, Kingston; arXiv 2503.06757) is RRT-Connect
+ * with many sample-extend-connect iterations running at once on two shared
+ * trees (Alg. 1), every candidate edge validated by checking all of its
+ * discretised configurations at once (Alg. 2, Sec. III-A): forward kinematics
+ * of the robot's collision spheres, then sphere tests against primitive
+ * obstacles and between the robot's own spheres.
+ *
+ * Conventions shared by every call
+ *   - Every call returns a prrtc_status; no C++ exception crosses the ABI.
+ *     Argument errors are detected on the host before any GPU work; the
+ *     reason is readable through prrtc_last_error() until the next call on
+ *     the same context.
+ *   - A context owns every device table it creates.  One context per host
+ *     thread; calls on one context are not thread-safe.
+ *   - Descriptor memory passed in is copied; the caller may free it when the
+ *     call returns.
+ *   - Pointers documented as "device" are HIP device pointers on the
+ *     context's device; "host" pointers are ordinary host memory.
+ *   - Angles in radians, lengths in metres, all floating point is IEEE FP32.
+ */
+#ifndef PRRTC_H
+#define PRRTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PRRTC_OK = 0,
+    PRRTC_E_ARG = -1,              /* invalid argument (detail in prrtc_last_error) */
+    PRRTC_E_STATE = -2,            /* unknown robot/scene id, or context unusable */
+    PRRTC_E_CAPACITY = -3,         /* output buffer too small; required size reported */
+    PRRTC_E_INVALID_ENDPOINT = -4, /* start/goal outside the limits or in collision */
+    PRRTC_E_NO_SOLUTION = -5,      /* round or time budget exhausted: a result, not a fault */
+    PRRTC_E_BUSY = -6,             /* admission refused (resource budget full) */
+    PRRTC_E_HIP = -7               /* a HIP runtime call failed */
+} prrtc_status;
+
+typedef struct prrtc_ctx prrtc_ctx;
+
+#define PRRTC_MAX_DOF 16
+#define PRRTC_MAX_CHAINS 2
+#define PRRTC_MAX_SPHERES 256
+#define PRRTC_MAX_PRIMS 1024
+#define PRRTC_MAX_SELF_PAIRS 16384
+
+/* Create a context on HIP device `device` (its own non-blocking stream). */
+prrtc_status prrtc_create(prrtc_ctx **out, int device);
+/* Free every table and buffer of the context.  destroy(NULL) is a no-op. */
+void prrtc_destroy(prrtc_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *prrtc_last_error(const prrtc_ctx *ctx);
+
+/*
+ * Robot: one or two serial chains of revolute joints with collision spheres
+ * (Sec. III-A represents the robot by bounding spheres attached to its links).
+ *
+ * Joint j of a chain applies, in modified DH form,
+ *     frame_{j+1} = frame_j * Rx(alpha_j) * Tx(a_j) * Rz(q_j) * Tz(d_j),
+ * with frame_0 = the chain's base pose.  Global frame ids number chain 0's
+ * frames 0..dof_0, then chain 1's dof_0+1 .. dof_0+1+dof_1.  The
+ * configuration vector is chain 0's joints followed by chain 1's.
+ */
+typedef struct {
+    int32_t n_chains;                          /* 1 or 2 */
+    int32_t chain_dof[PRRTC_MAX_CHAINS];       /* joints per chain; total <= 16 */
+    float base_pose[PRRTC_MAX_CHAINS][12];     /* row-major 3x4 [R | t], R orthonormal */
+    const float *dh;                           /* host [dof][3] = (alpha, a, d) */
+    const float *q_lo;                         /* host [dof] lower joint limit */
+    const float *q_hi;                         /* host [dof] upper joint limit (> q_lo) */
+    int32_t n_spheres;                         /* 1..256 */
+    const int32_t *sphere_frame;               /* host [n_spheres] global frame id */
+    const float *sphere_xyzr;                  /* host [n_spheres][4] centre in frame, radius > 0 */
+    int32_t n_self_pairs;                      /* 0..16384 */
+    const int32_t *self_pairs;                 /* host [n_self_pairs][2] sphere indices, i != j */
+} prrtc_robot_desc;
+
+/* Validate and copy a robot to the device.  E_ARG on non-finite values,
+ * lo >= hi, frame ids or pair indices out of range, non-positive radii. */
+prrtc_status prrtc_load_robot(prrtc_ctx *ctx, const prrtc_robot_desc *desc, int32_t *robot_id);
+
+/*
+ * Scene primitive, 64 bytes (Sec. III-A: environments as primitive shapes).
+ *   type 0 sphere:   c = centre, dims[0] = radius
+ *   type 1 cuboid:   c = centre, columns of rot = box axes, dims = half-extents
+ *   type 2 cylinder: c = centre, column 2 of rot = axis, dims[0] = radius,
+ *                    dims[1] = half-height (solid, flat caps)
+ * rot is row-major and must be orthonormal to 1e-5 (not re-orthonormalised).
+ */
+typedef struct {
+    int32_t type;
+    float c[3];
+    float rot[9];
+    float dims[3];
+} prrtc_prim;
+
+/* Validate and copy n primitives (0 allowed: empty scene). */
+prrtc_status prrtc_load_scene(prrtc_ctx *ctx, const prrtc_prim *prims, int32_t n,
+                              int32_t *scene_id);
+
+/*
+ * check_edges (Alg. 2 / Sec. III-A).  For edge e with endpoints a_e, b_e:
+ *     L = |b_e - a_e| (FP32, squares summed in joint order, no fused
+ *         multiply-add, correctly rounded sqrt),
+ *     n = max(1, ceil(res * L)) (capped at 2^24),
+ *     q_i = a_e + (i/n)(b_e - a_e), i = 0..n,
+ * and valid[e] = 1 iff no q_i puts a robot sphere strictly inside an
+ * obstacle or another robot sphere of a self-collision pair; else 0.
+ *
+ * a, b:   device float32 [n_edges][dof], row-major, finite.
+ * valid:  device uint8 [n_edges], written.
+ * res:    points per radian (> 0).
+ * stream: hipStream_t to enqueue on (NULL = the context's stream).  The call
+ *         is asynchronous; buffers must stay alive until the stream is
+ *         synchronised.  n_edges = 0 is a no-op.
+ */
+prrtc_status prrtc_check_edges(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id,
+                               const float *a, const float *b, int64_t n_edges, float res,
+                               uint8_t *valid, void *stream);
+
+/*
+ * Test hook: world-frame sphere centres of every configuration (FK only).
+ * q: device float32 [n][dof]; xyz: device float32 [n][n_spheres][3], in the
+ * robot descriptor's sphere order.  Asynchronous on `stream`.
+ */
+prrtc_status prrtc_fk_spheres(prrtc_ctx *ctx, int32_t robot_id, const float *q, int64_t n,
+                              float *xyz, void *stream);
+
+/*
+ * plan (Alg. 1): parallel RRT-Connect from start to goal.
+ *
+ * Rounds r = 0..max_rounds-1 run on the GPU inside one persistent launch.
+ * In each round every worker w sees the same snapshot of both trees, grows
+ * the smaller one (tie: start tree): RANDOM_CONFIG from Philox4x32-10
+ * (key = seed, counter = (draw, w, r, query)), nearest neighbour (exact
+ * argmin, ties to the lowest node index), steer by at most delta, edge check
+ * at points i = 1..n, then greedy connect toward the nearest node of the
+ * other tree in ceil(L/delta) equal steps.  Staged nodes are appended in
+ * worker order, so a given seed gives the same trees and path on every run.
+ * The lowest-numbered connected worker yields the path, which is re-checked
+ * at validate_factor * res (i = 0..n); on failure its offending node is
+ * excluded and rounds continue.
+ */
+typedef struct {
+    uint64_t seed;
+    uint32_t query;          /* counter word; 0 for a single query */
+    int32_t workers;         /* parallel workers W (default 256) */
+    float delta;             /* extension range (default 0.5 rad) */
+    float res;               /* edge resolution, points per radian (default 32) */
+    int32_t max_rounds;      /* >= 0 */
+    int32_t tree_capacity;   /* nodes per tree, >= 2 */
+    float time_budget_ms;    /* <= 0: none.  Checked between rounds on the GPU clock */
+    int32_t validate_factor; /* 0 disables the final re-check (default 4) */
+} prrtc_plan_params;
+
+typedef struct {
+    int32_t rounds;
+    int32_t nodes_a, nodes_b;
+    int64_t edges_checked;
+    int32_t validation_failures;
+    int32_t connect_worker;
+    float gpu_ms;            /* device time of the planner launch */
+} prrtc_plan_stats;
+
+/* Fill *p with the defaults above (seed 1, 256 workers, 0.5 rad, 32/rad,
+ * 1000 rounds, 65536 nodes, no time budget, factor 4). */
+void prrtc_plan_params_default(prrtc_plan_params *p);
+
+/*
+ * start, goal: host float32 [dof].  path: host float32 [path_cap][dof].
+ * Synchronous.  Returns OK with *path_len nodes written (path[0] == start,
+ * path[len-1] == goal bit for bit; every segment no longer than delta);
+ * E_CAPACITY if path_cap is too small (then *path_len = nodes needed and
+ * nothing is written: call again with a larger buffer);
+ * E_INVALID_ENDPOINT, E_NO_SOLUTION as documented above.  stats may be NULL.
+ */
+prrtc_status prrtc_plan(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, const float *start,
+                        const float *goal, const prrtc_plan_params *params, float *path,
+                        int32_t path_cap, int32_t *path_len, prrtc_plan_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRRTC_H */

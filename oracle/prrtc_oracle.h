@@ -1,0 +1,130 @@
+/*
+ * prrtc_oracle.h -- serial reference ("oracle") for the pRRTC hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes,
+ * links or calls this code; only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load it.  It shares no code, header, table or
+ * constant generator with the HIP implementation.
+ *
+ * What it follows (pRRTC, Huang et al., arXiv 2503.06757):
+ *   - Alg. 1 (pRRTC main loop: balanced tree choice, sample, nearest
+ *     neighbour, extend, add, greedy connect, path),
+ *   - Alg. 2 (pEXTEND: steer by at most delta, check the discretised edge),
+ *   - Sec. III-A (forward kinematics of collision spheres, sphere tests
+ *     against primitive obstacles, discretised edge checking),
+ *   - Sec. III-B (nearest neighbour = exact argmin over the tree).
+ * Geometry (FK, clearances, interpolated points) is in FP64.  The steps
+ * whose floating point decides an integer or a tree node (edge point count,
+ * steer, nearest-neighbour argmin, connect targets, random configurations)
+ * follow a fixed FP32 contract that the GPU side implements identically:
+ * sequential sums with no fused multiply-add, correctly rounded sqrtf and
+ * division, explicit fmaf where stated.
+ *
+ * Status codes match the product library's (0 ok, negative errors).
+ */
+#ifndef PRRTC_ORACLE_H
+#define PRRTC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_DOF 16
+#define ORC_MAX_CHAINS 2
+#define ORC_FLAG_BAND 1e-5 /* metres: |clearance| within this is "near contact" */
+
+typedef struct {
+    int32_t n_chains;
+    int32_t chain_dof[ORC_MAX_CHAINS];
+    float base_pose[ORC_MAX_CHAINS][12]; /* row-major 3x4 */
+    const float *dh;                     /* [dof][3] = (alpha, a, d), modified DH */
+    const float *q_lo, *q_hi;            /* [dof] */
+    int32_t n_spheres;
+    const int32_t *sphere_frame; /* global frame id: chain c's frames follow chain c-1's */
+    const float *sphere_xyzr;    /* [n][4], centre in its frame + radius */
+    int32_t n_self_pairs;
+    const int32_t *self_pairs; /* [m][2] sphere indices */
+} orc_robot;
+
+typedef struct {
+    int32_t type; /* 0 sphere, 1 cuboid, 2 cylinder */
+    float c[3];
+    float rot[9]; /* row-major; columns are the primitive's axes */
+    float dims[3];
+} orc_prim;
+
+typedef struct {
+    uint64_t seed;
+    uint32_t query;
+    int32_t workers;
+    float delta;
+    float res;
+    int32_t max_rounds;
+    int32_t tree_capacity;
+    int32_t validate_factor;
+} orc_plan_params;
+
+typedef struct {
+    int32_t rounds;
+    int32_t nodes_a, nodes_b;
+    int64_t edges_checked;
+    int32_t flagged_edges;      /* edges whose verdict lay within the flag band */
+    int32_t validation_failures;
+    int32_t connect_worker;
+} orc_plan_stats;
+
+int orc_dof(const orc_robot *R);
+int orc_n_frames(const orc_robot *R);
+
+/* FK: frames[f] as row-major 3x4 (FP64) for every global frame. */
+void orc_fk_frames(const orc_robot *R, const double *q, double *frames);
+/* Sphere centres in world coordinates for configuration q (float32 input). */
+void orc_fk_spheres(const orc_robot *R, const float *q, double *xyz);
+
+/* Signed clearance of a sphere (centre c, radius r) to one primitive. */
+double orc_clearance(const double c[3], double r, const orc_prim *p);
+/* min over environment and self pairs at configuration q (FP64). */
+double orc_config_clearance(const orc_robot *R, const orc_prim *prims, int32_t n_prims,
+                            const double *q);
+
+/* FP32-contract point count of an edge. */
+int32_t orc_edge_count(const float *a, const float *b, int32_t dof, float res);
+
+/* min clearance over points i = i_first..n of edge (a, b).  With early_exit
+ * the scan stops once a clearance below -flag band is seen. */
+double orc_edge_clearance(const orc_robot *R, const orc_prim *prims, int32_t n_prims,
+                          const float *a, const float *b, float res, int32_t i_first,
+                          int32_t early_exit);
+
+/* Batch edge verdicts: valid = (m >= 0), flagged = (|m| <= flag band). */
+void orc_check_edges(const orc_robot *R, const orc_prim *prims, int32_t n_prims,
+                     const float *a, const float *b, int64_t n_edges, float res,
+                     uint8_t *valid, uint8_t *flagged, double *m_out, int32_t early_exit,
+                     int32_t n_threads);
+
+/* Nearest neighbour over tree[dof][cap] (nodes 0..size-1), FP32 contract. */
+int32_t orc_nearest(const float *tree, int32_t cap, int32_t size, const uint8_t *blocked,
+                    const float *x, int32_t dof);
+/* Steer: at most delta from `from` toward `to` (FP32 contract). */
+void orc_steer(const float *from, const float *to, int32_t dof, float delta, float *out);
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
+                       const float *lo, const float *hi, int32_t dof, float *out);
+
+int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, const float *start,
+                 const float *goal, const orc_plan_params *p, float *path, int32_t path_cap,
+                 int32_t *path_len, orc_plan_stats *st, int32_t n_threads);
+
+/* Re-check a path's segments (points i = 0..n at resolution res).  Returns
+ * the minimum clearance over all segments; *n_flag counts segments within
+ * the flag band. */
+double orc_path_clearance(const orc_robot *R, const orc_prim *prims, int32_t n_prims,
+                          const float *path, int32_t len, float res, int32_t *n_flag);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

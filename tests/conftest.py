@@ -1,0 +1,36 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    import oracle
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+        oracle.build()
+    return oracle
+
+
+@pytest.fixture(scope="session")
+def wl():
+    from paper_2503_06757_amd import workloads
+    return workloads
+
+
+@pytest.fixture(scope="session")
+def r7(wl):
+    return wl.robot_r7()
+
+
+@pytest.fixture(scope="session")
+def r14(wl):
+    return wl.robot_r14()

@@ -1,0 +1,232 @@
+"""Pins of the oracle's geometry (Sec. III-A: sphere FK and sphere-vs-primitive
+tests) against closed forms, brute force and invariants -- never against a
+re-typed copy of the oracle's own formulas."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2503_06757_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def prim(t, c=(0, 0, 0), rot=None, dims=(0, 0, 0)):
+    return W.make_prims([(t, c, np.eye(3) if rot is None else rot, dims)])[0]
+
+
+def rand_rot(rng):
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+# ---- closed forms ---------------------------------------------------------------
+def test_sphere_sphere_closed_form(orc):
+    p = prim(W.PRIM_SPHERE, (0, 0, 0), dims=(0.1, 0, 0))
+    assert orc.clearance([0.25, 0, 0], 0.1, p) == pytest.approx(0.05, abs=1e-7)
+    assert orc.clearance([0.0, 0.19, 0], 0.1, p) == pytest.approx(-0.01, abs=1e-7)
+
+
+def test_cuboid_closed_form(orc):
+    # half-extents (0.1, 0.2, 0.3), sphere radius 0.05
+    p = prim(W.PRIM_CUBOID, (0, 0, 0), dims=(0.1, 0.2, 0.3))
+    # face region: 0.2 - 0.1 = 0.1 from the face, minus r
+    assert orc.clearance([0.2, 0, 0], 0.05, p) == pytest.approx(0.05, abs=1e-7)
+    # corner region: offset (0.1, 0.1, 0.1) from the corner (0.1, 0.2, 0.3)
+    assert orc.clearance([0.2, 0.3, 0.4], 0.05, p) == pytest.approx(math.sqrt(0.03) - 0.05, abs=1e-7)
+    # centre: nearest face 0.1 away -> -(0.1) - r
+    assert orc.clearance([0, 0, 0], 0.05, p) == pytest.approx(-0.15, abs=1e-7)
+    # edge region: beyond x and y faces, within z
+    assert orc.clearance([0.13, 0.24, 0.0], 0.0, p) == pytest.approx(0.05, abs=1e-7)
+
+
+def test_cylinder_closed_form(orc):
+    p = prim(W.PRIM_CYLINDER, (0, 0, 0), dims=(0.1, 0.2, 0))  # axis z, R=0.1, H=0.2
+    assert orc.clearance([0.3, 0, 0], 0.0, p) == pytest.approx(0.2, abs=1e-7)   # radial
+    assert orc.clearance([0, 0, 0.5], 0.0, p) == pytest.approx(0.3, abs=1e-7)   # axial
+    assert orc.clearance([0.2, 0, 0.3], 0.0, p) == pytest.approx(math.sqrt(0.02), abs=1e-7)  # rim
+    assert orc.clearance([0, 0, 0], 0.0, p) == pytest.approx(-0.1, abs=1e-7)     # inside: radial wall
+    assert orc.clearance([0, 0, 0.15], 0.01, p) == pytest.approx(-0.06, abs=1e-7)  # inside: cap nearer
+
+
+def test_clearance_rotation_translation_invariance(orc):
+    """Moving obstacle and sphere by the same rigid motion keeps the clearance."""
+    rng = np.random.default_rng(7)
+    for t in (W.PRIM_SPHERE, W.PRIM_CUBOID, W.PRIM_CYLINDER):
+        dims = (0.12, 0.2, 0.07) if t != W.PRIM_SPHERE else (0.15, 0, 0)
+        base = prim(t, (0, 0, 0), dims=dims)
+        for _ in range(50):
+            c = rng.uniform(-0.5, 0.5, 3)
+            r = rng.uniform(0.0, 0.1)
+            s0 = orc.clearance(c, r, base)
+            Rm = rand_rot(rng)
+            tr = rng.uniform(-1, 1, 3)
+            moved = prim(t, tr, rot=Rm, dims=dims)
+            s1 = orc.clearance(Rm @ c + tr, r, moved)
+            assert s1 == pytest.approx(s0, abs=2e-6)
+
+
+def _solid_points(t, dims, n=41):
+    """Dense grid of points filling a primitive at the origin (local frame)."""
+    if t == W.PRIM_CUBOID:
+        axes = [np.linspace(-h, h, n) for h in dims]
+        g = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+        return g
+    if t == W.PRIM_CYLINDER:
+        R, H = dims[0], dims[1]
+        g = np.stack(np.meshgrid(np.linspace(-R, R, n), np.linspace(-R, R, n),
+                                 np.linspace(-H, H, n), indexing="ij"), -1).reshape(-1, 3)
+        return g[g[:, 0] ** 2 + g[:, 1] ** 2 <= R * R + 1e-15]
+    R = dims[0]
+    g = np.stack(np.meshgrid(*[np.linspace(-R, R, n)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    return g[np.sum(g * g, 1) <= R * R + 1e-15]
+
+
+@pytest.mark.parametrize("t,dims", [(W.PRIM_CUBOID, (0.1, 0.2, 0.15)),
+                                    (W.PRIM_CYLINDER, (0.1, 0.15, 0.0)),
+                                    (W.PRIM_SPHERE, (0.12, 0.0, 0.0))])
+def test_clearance_vs_brute_force_outside(orc, t, dims):
+    """Outside the solid, clearance + r = distance to the nearest solid point
+    (brute-force minimum over a dense grid of the solid; grid spacing bounds the error)."""
+    rng = np.random.default_rng(11)
+    pts = _solid_points(t, dims)
+    spacing = 2 * max(dims) / 40
+    p = prim(t, dims=dims)
+    for _ in range(40):
+        c = rng.uniform(-0.45, 0.45, 3)
+        d_brute = np.min(np.linalg.norm(pts - c, axis=1))
+        if d_brute < 2 * spacing:
+            continue
+        s = orc.clearance(c, 0.0, p)
+        assert d_brute - spacing * math.sqrt(3) <= s <= d_brute + 1e-12
+
+
+@pytest.mark.parametrize("t,dims", [(W.PRIM_CUBOID, (0.1, 0.2, 0.15)),
+                                    (W.PRIM_CYLINDER, (0.1, 0.15, 0.0))])
+def test_clearance_sign_vs_point_membership(orc, t, dims):
+    """With r = 0, clearance < 0 exactly for points strictly inside the solid."""
+    rng = np.random.default_rng(12)
+    p = prim(t, dims=dims)
+    for c in rng.uniform(-0.25, 0.25, (400, 3)):
+        if t == W.PRIM_CUBOID:
+            inside = np.all(np.abs(c) < np.array(dims))
+        else:
+            inside = (c[0] ** 2 + c[1] ** 2 < dims[0] ** 2) and abs(c[2]) < dims[1]
+        assert (orc.clearance(c, 0.0, p) < 0) == inside
+
+
+# ---- forward kinematics -----------------------------------------------------------
+def planar_robot(l1, l2):
+    """2-link planar arm: joint axes along z, link 1 of length l1 (a_1 = l1),
+    tool sphere at (l2, 0, 0) in the last frame."""
+    pose = np.zeros(12, np.float32)
+    pose[0] = pose[5] = pose[10] = 1
+    return dict(n_chains=1, chain_dof=[2], base_pose=pose[None, :],
+                dh=np.array([[0, 0, 0], [0, l1, 0]], np.float32),
+                q_lo=np.full(2, -3.1, np.float32), q_hi=np.full(2, 3.1, np.float32),
+                sphere_frame=np.array([2], np.int32),
+                sphere_xyzr=np.array([[l2, 0, 0, 0.01]], np.float32),
+                self_pairs=np.zeros((0, 2), np.int32))
+
+
+def test_fk_planar_two_link_closed_form(orc):
+    l1, l2 = 0.5, 0.25
+    rob = orc.OracleRobot(planar_robot(l1, l2))
+    rng = np.random.default_rng(3)
+    for q in rng.uniform(-3, 3, (100, 2)).astype(np.float32):
+        q1, q2 = float(q[0]), float(q[1])
+        exp = [l1 * math.cos(q1) + l2 * math.cos(q1 + q2), l1 * math.sin(q1) + l2 * math.sin(q1 + q2), 0]
+        np.testing.assert_allclose(orc.fk_spheres(rob, q)[0], exp, atol=1e-7)
+
+
+def test_fk_r7_origins_at_zero(orc, r7):
+    rob = orc.OracleRobot(r7)
+    F = orc.fk_frames(rob, np.zeros(7))
+    rows = np.loadtxt(os.path.join(GOLDEN, "r7_frame_origins_q0.txt"))
+    for f, x, y, z in rows:
+        np.testing.assert_allclose(F[int(f)][[3, 7, 11]], [x, y, z], atol=1e-6)
+
+
+def test_fk_rotations_orthonormal(orc, r14):
+    rob = orc.OracleRobot(r14)
+    rng = np.random.default_rng(5)
+    for q in rng.uniform(-2.8, 2.8, (20, 14)):
+        for Fm in orc.fk_frames(rob, q):
+            Rm = Fm.reshape(3, 4)[:, :3]
+            np.testing.assert_allclose(Rm.T @ Rm, np.eye(3), atol=1e-12)
+            assert np.linalg.det(Rm) == pytest.approx(1.0, abs=1e-12)
+
+
+def _rodrigues(axis, angle):
+    k = axis / np.linalg.norm(axis)
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(angle) * K + (1 - math.cos(angle)) * K @ K
+
+
+def test_fk_joint_rotation_moves_distal_spheres_rigidly(orc, r7):
+    """Changing q_j by theta rotates every sphere attached to frames > j about
+    the joint axis (z of frame j+1, through its origin) by theta, and leaves
+    the spheres on frames <= j where they were.  Checked with an independent
+    Rodrigues rotation, for every joint."""
+    rob = orc.OracleRobot(r7)
+    rng = np.random.default_rng(9)
+    frames = r7["sphere_frame"]
+    for _ in range(10):
+        q = rng.uniform(-2.5, 2.5, 7)
+        for j in range(7):
+            theta = float(rng.uniform(-0.3, 0.3))
+            q2 = q.copy()
+            q2[j] += theta
+            F = orc.fk_frames(rob, q.astype(np.float32).astype(np.float64)).reshape(-1, 3, 4)
+            # The joint axis is frame j+1's z axis; frame j+1 includes Rz(q_j),
+            # which leaves its z axis and origin unchanged.
+            axis = F[j + 1][:, 2]
+            origin = F[j + 1][:, 3]
+            before = orc.fk_spheres(rob, q.astype(np.float32))
+            after = orc.fk_spheres(rob, q2.astype(np.float32))
+            # the float32 cast of q2 perturbs theta slightly; use the cast values
+            th = float(np.float32(q2[j])) - float(np.float32(q[j]))
+            Rm = _rodrigues(axis, th)
+            for k in range(len(frames)):
+                if frames[k] > j:
+                    exp = Rm @ (before[k] - origin) + origin
+                else:
+                    exp = before[k]
+                np.testing.assert_allclose(after[k], exp, atol=1e-9)
+
+
+def test_fk_dual_arm_base_offsets(orc, r7, r14):
+    """Chain B of the dual arm is chain A shifted by the base offset (0.6 m in y)."""
+    ra, rb = orc.OracleRobot(r7), orc.OracleRobot(r14)
+    rng = np.random.default_rng(2)
+    for _ in range(10):
+        qa = rng.uniform(-2.8, 2.8, 7).astype(np.float32)
+        qb = rng.uniform(-2.8, 2.8, 7).astype(np.float32)
+        xyz = orc.fk_spheres(rb, np.concatenate([qa, qb]))
+        np.testing.assert_allclose(xyz[:60], orc.fk_spheres(ra, qa) + [0, float(np.float32(-0.3)), 0], atol=1e-12)
+        np.testing.assert_allclose(xyz[60:], orc.fk_spheres(ra, qb) + [0, float(np.float32(0.3)), 0], atol=1e-12)
+
+
+def test_config_clearance_is_min_over_tests(orc, r14):
+    """The configuration clearance is the minimum over every sphere/obstacle
+    test and every self pair (brute force through the single-test routine)."""
+    rob = orc.OracleRobot(r14)
+    prims = W.scene_mixed(123, r14, 10)
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        q = rng.uniform(-2.8, 2.8, 14).astype(np.float32)
+        xyz = orc.fk_spheres(rob, q)
+        rad = r14["sphere_xyzr"][:, 3].astype(np.float64)
+        m = min(orc.clearance(xyz[k], rad[k], pr) for k in range(len(rad)) for pr in prims)
+        for i, j in r14["self_pairs"][::7]:
+            m = min(m, orc.clearance(xyz[i], rad[i], prim(W.PRIM_SPHERE, xyz[j], dims=(rad[j], 0, 0))))
+        # the remaining pairs through the same pinned single test, vectorised by brute force
+        pairs = r14["self_pairs"]
+        d = np.linalg.norm(xyz[pairs[:, 0]] - xyz[pairs[:, 1]], axis=1) - rad[pairs[:, 0]] - rad[pairs[:, 1]]
+        m = min(m, d.min())
+        assert orc.config_clearance(rob, prims, q.astype(np.float64)) == pytest.approx(m, abs=1e-15)
