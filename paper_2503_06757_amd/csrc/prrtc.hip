@@ -1,0 +1,447 @@
+// prrtc.hip -- libprrtc.so: C ABI, resident robot/scene tables and kernel launches.
+//
+// The entry points are declared (with their contracts) in include/prrtc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "prrtc.h"
+#include "prrtc_device.h"
+#include "prrtc_planner.h"
+
+using namespace prrtc;
+
+// ----------------------------------------------------------------------------
+// Kernels
+// ----------------------------------------------------------------------------
+
+// check_edges: one wavefront per workgroup, edges strided over the grid.
+template <int TP, int B>
+__global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
+                                                       const float* __restrict__ A,
+                                                       const float* __restrict__ Bv,
+                                                       long long n_edges, float res,
+                                                       uint8_t* __restrict__ valid) {
+    extern __shared__ float4 lds4[];
+    const int lane = threadIdx.x;
+    const int dof = R.dof;
+    WaveWs ws;
+    ws.frames = lds4;
+    float* wp = reinterpret_cast<float*>(lds4 + TP * 3 * R.n_frames);
+    ws.pk = reinterpret_cast<int*>(wp + 2 * kMaxDof);
+    ws.sub_n = ws.pk + TP;
+    ws.sub_off = ws.sub_n + 2;
+    const bool fixed_hit = static_collision(R, S, nullptr);
+    for (long long e = blockIdx.x; e < n_edges; e += gridDim.x) {
+        int ok = 0;
+        if (!fixed_hit) {
+            if (lane < dof) {
+                wp[lane] = A[e * dof + lane];
+                wp[dof + lane] = Bv[e * dof + lane];
+            }
+            __syncthreads();
+            ok = wave_check<TP, B, false>(R, S, wp, 1, 0, res, ws) == 1;
+        }
+        if (lane == 0) valid[e] = (uint8_t)ok;
+        __syncthreads();
+    }
+}
+
+// FK test hook: one lane per configuration, frames staged in LDS.
+__global__ __launch_bounds__(kWave) void k_fk_spheres(RobotArgs R, const float* __restrict__ q,
+                                                      long long n, float* __restrict__ xyz) {
+    extern __shared__ float4 lds4[];
+    const long long cfg = (long long)blockIdx.x * kWave + threadIdx.x;
+    if (cfg >= n) return;
+    float4* fr = lds4 + threadIdx.x * 3 * R.n_frames;
+    const float* qc = q + cfg * R.dof;
+    fk_frames(R, [&](int j) { return qc[j]; }, fr);
+    const int ns = R.n_move + R.n_static;
+    for (int s = 0; s < ns; ++s) {
+        const float4 loc = R.sph[s];
+        const float3 c = frame_apply(fr + 3 * R.sph_frame[s], loc.x, loc.y, loc.z);
+        float* o = xyz + (cfg * ns + R.desc_index[s]) * 3;
+        o[0] = c.x;
+        o[1] = c.y;
+        o[2] = c.z;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Host side
+// ----------------------------------------------------------------------------
+namespace {
+
+struct RobotRec {
+    RobotArgs args{};
+    void* mem = nullptr;
+    int dof = 0, n_spheres = 0;
+};
+
+struct SceneRec {
+    SceneArgs args{};
+    void* mem = nullptr;
+    int n = 0;
+};
+
+}  // namespace
+
+struct prrtc_ctx {
+    int device = 0;
+    int n_cu = 256;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<RobotRec> robots;
+    std::vector<SceneRec> scenes;
+    PlannerBuffers plan;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+prrtc_status fail(prrtc_ctx* ctx, prrtc_status st, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+#define PRRTC_HIP(ctx, call)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), PRRTC_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_all(const float* p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool orthonormal(const float* m, int stride) {  // rows of a 3x3 with the given row stride
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += (double)m[k * stride + i] * (double)m[k * stride + j];
+            if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-5) return false;
+        }
+    return true;
+}
+
+template <class T>
+size_t align_up(size_t x) {
+    return (x + 255) & ~size_t(255);
+}
+
+}  // namespace
+
+extern "C" {
+
+prrtc_status prrtc_create(prrtc_ctx** out, int device) {
+    if (!out) return PRRTC_E_ARG;
+    *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return PRRTC_E_ARG;
+    std::unique_ptr<prrtc_ctx> ctx(new prrtc_ctx());
+    ctx->device = device;
+    PRRTC_HIP(ctx.get(), hipSetDevice(device));
+    hipDeviceProp_t prop;
+    PRRTC_HIP(ctx.get(), hipGetDeviceProperties(&prop, device));
+    ctx->n_cu = prop.multiProcessorCount;
+    PRRTC_HIP(ctx.get(), hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev0));
+    PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev1));
+    *out = ctx.release();
+    return PRRTC_OK;
+}
+
+void prrtc_destroy(prrtc_ctx* ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    for (auto& r : ctx->robots) hipFree(r.mem);
+    for (auto& s : ctx->scenes) hipFree(s.mem);
+    planner_free(ctx->plan);
+    if (ctx->ev0) hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) hipEventDestroy(ctx->ev1);
+    if (ctx->stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* prrtc_last_error(const prrtc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t* robot_id) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (!d || !robot_id) return fail(ctx, PRRTC_E_ARG, "null descriptor or id");
+    if (d->n_chains < 1 || d->n_chains > PRRTC_MAX_CHAINS)
+        return fail(ctx, PRRTC_E_ARG, "n_chains must be 1 or 2");
+    int dof = 0, n_frames = 0;
+    int chain_f0[2] = {0, 0}, chain_q0[2] = {0, 0};
+    for (int c = 0; c < d->n_chains; ++c) {
+        if (d->chain_dof[c] < 1) return fail(ctx, PRRTC_E_ARG, "chain %d has no joints", c);
+        chain_q0[c] = dof;
+        chain_f0[c] = n_frames;
+        dof += d->chain_dof[c];
+        n_frames += d->chain_dof[c] + 1;
+        if (!finite_all(d->base_pose[c], 12) || !orthonormal(d->base_pose[c], 4))
+            return fail(ctx, PRRTC_E_ARG, "base pose of chain %d not finite/orthonormal", c);
+    }
+    if (dof > PRRTC_MAX_DOF) return fail(ctx, PRRTC_E_ARG, "dof %d exceeds %d", dof, PRRTC_MAX_DOF);
+    if (!d->dh || !d->q_lo || !d->q_hi || !finite_all(d->dh, 3 * dof) || !finite_all(d->q_lo, dof) ||
+        !finite_all(d->q_hi, dof))
+        return fail(ctx, PRRTC_E_ARG, "DH table or limits missing or not finite");
+    for (int j = 0; j < dof; ++j)
+        if (!(d->q_lo[j] < d->q_hi[j])) return fail(ctx, PRRTC_E_ARG, "joint %d: lo >= hi", j);
+    const int ns = d->n_spheres;
+    if (ns < 1 || ns > PRRTC_MAX_SPHERES || !d->sphere_frame || !d->sphere_xyzr)
+        return fail(ctx, PRRTC_E_ARG, "n_spheres must be in 1..%d", PRRTC_MAX_SPHERES);
+    for (int k = 0; k < ns; ++k) {
+        if (d->sphere_frame[k] < 0 || d->sphere_frame[k] >= n_frames)
+            return fail(ctx, PRRTC_E_ARG, "sphere %d: frame id out of range", k);
+        if (!finite_all(d->sphere_xyzr + 4 * k, 4) || !(d->sphere_xyzr[4 * k + 3] > 0.0f))
+            return fail(ctx, PRRTC_E_ARG, "sphere %d: not finite or radius <= 0", k);
+    }
+    const int np = d->n_self_pairs;
+    if (np < 0 || np > PRRTC_MAX_SELF_PAIRS || (np > 0 && !d->self_pairs))
+        return fail(ctx, PRRTC_E_ARG, "n_self_pairs must be in 0..%d", PRRTC_MAX_SELF_PAIRS);
+    for (int p = 0; p < np; ++p) {
+        const int i = d->self_pairs[2 * p], j = d->self_pairs[2 * p + 1];
+        if (i < 0 || j < 0 || i >= ns || j >= ns || i == j)
+            return fail(ctx, PRRTC_E_ARG, "self pair %d invalid", p);
+    }
+    // re-order: moving spheres (frame > chain base) sorted by frame, most distal first
+    auto is_fixed = [&](int k) {
+        for (int c = 0; c < d->n_chains; ++c)
+            if (d->sphere_frame[k] == chain_f0[c]) return true;
+        return false;
+    };
+    std::vector<int> order;
+    for (int k = 0; k < ns; ++k)
+        if (!is_fixed(k)) order.push_back(k);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return d->sphere_frame[x] > d->sphere_frame[y]; });
+    const int n_move = (int)order.size();
+    for (int k = 0; k < ns; ++k)
+        if (is_fixed(k)) order.push_back(k);
+    std::vector<int> new_of(ns);
+    for (int k = 0; k < ns; ++k) new_of[order[k]] = k;
+    std::vector<float4> sph(ns);
+    std::vector<int> frame(ns), desc(ns);
+    for (int k = 0; k < ns; ++k) {
+        const float* p = d->sphere_xyzr + 4 * order[k];
+        sph[k] = make_float4(p[0], p[1], p[2], p[3]);
+        frame[k] = d->sphere_frame[order[k]];
+        desc[k] = order[k];
+    }
+    std::vector<int2> pairs, spairs;
+    for (int p = 0; p < np; ++p) {
+        const int i = new_of[d->self_pairs[2 * p]], j = new_of[d->self_pairs[2 * p + 1]];
+        if (i >= n_move && j >= n_move) spairs.push_back(make_int2(i, j));
+        else pairs.push_back(make_int2(i, j));
+    }
+    const size_t o_sph = 0;
+    const size_t o_frame = align_up<int>(o_sph + sizeof(float4) * ns);
+    const size_t o_desc = align_up<int>(o_frame + sizeof(int) * ns);
+    const size_t o_pairs = align_up<int>(o_desc + sizeof(int) * ns);
+    const size_t o_spairs = align_up<int>(o_pairs + sizeof(int2) * pairs.size());
+    const size_t bytes = align_up<int>(o_spairs + sizeof(int2) * spairs.size());
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    RobotRec rec;
+    PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
+    char* base = static_cast<char*>(rec.mem);
+    std::vector<char> host(bytes, 0);
+    memcpy(host.data() + o_sph, sph.data(), sizeof(float4) * ns);
+    memcpy(host.data() + o_frame, frame.data(), sizeof(int) * ns);
+    memcpy(host.data() + o_desc, desc.data(), sizeof(int) * ns);
+    if (!pairs.empty()) memcpy(host.data() + o_pairs, pairs.data(), sizeof(int2) * pairs.size());
+    if (!spairs.empty()) memcpy(host.data() + o_spairs, spairs.data(), sizeof(int2) * spairs.size());
+    hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(rec.mem);
+        return fail(ctx, PRRTC_E_HIP, "hipMemcpy robot: %s", hipGetErrorString(e));
+    }
+    RobotArgs& A = rec.args;
+    A.n_chains = d->n_chains;
+    A.dof = dof;
+    A.n_frames = n_frames;
+    A.n_move = n_move;
+    A.n_static = ns - n_move;
+    A.n_pairs = (int)pairs.size();
+    A.n_static_pairs = (int)spairs.size();
+    for (int c = 0; c < kMaxChains; ++c) {
+        A.chain_dof[c] = c < d->n_chains ? d->chain_dof[c] : 0;
+        A.chain_q0[c] = chain_q0[c];
+        A.chain_f0[c] = chain_f0[c];
+        for (int i = 0; i < 12; ++i) A.base[c][i] = c < d->n_chains ? d->base_pose[c][i] : 0.0f;
+    }
+    for (int j = 0; j < kMaxDof; ++j) {
+        const bool in = j < dof;
+        const double alpha = in ? (double)d->dh[3 * j + 0] : 0.0;
+        A.ca[j] = (float)std::cos(alpha);
+        A.sa[j] = (float)std::sin(alpha);
+        A.a[j] = in ? d->dh[3 * j + 1] : 0.0f;
+        A.d[j] = in ? d->dh[3 * j + 2] : 0.0f;
+        A.lo[j] = in ? d->q_lo[j] : 0.0f;
+        A.hi[j] = in ? d->q_hi[j] : 0.0f;
+    }
+    A.sph = reinterpret_cast<const float4*>(base + o_sph);
+    A.sph_frame = reinterpret_cast<const int*>(base + o_frame);
+    A.desc_index = reinterpret_cast<const int*>(base + o_desc);
+    A.pairs = reinterpret_cast<const int2*>(base + o_pairs);
+    A.static_pairs = reinterpret_cast<const int2*>(base + o_spairs);
+    rec.dof = dof;
+    rec.n_spheres = ns;
+    ctx->robots.push_back(rec);
+    *robot_id = (int32_t)ctx->robots.size() - 1;
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, int32_t* scene_id) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (!scene_id || n < 0 || n > PRRTC_MAX_PRIMS || (n > 0 && !p))
+        return fail(ctx, PRRTC_E_ARG, "bad scene arguments (n must be in 0..%d)", PRRTC_MAX_PRIMS);
+    std::vector<float4> sph;
+    std::vector<float> box, cyl;
+    for (int i = 0; i < n; ++i) {
+        const prrtc_prim& q = p[i];
+        if (!finite_all(q.c, 3) || !finite_all(q.rot, 9) || !finite_all(q.dims, 3))
+            return fail(ctx, PRRTC_E_ARG, "primitive %d not finite", i);
+        if (q.type == 0) {
+            if (!(q.dims[0] > 0.0f)) return fail(ctx, PRRTC_E_ARG, "primitive %d: radius <= 0", i);
+            sph.push_back(make_float4(q.c[0], q.c[1], q.c[2], q.dims[0]));
+        } else if (q.type == 1 || q.type == 2) {
+            if (!orthonormal(q.rot, 3)) return fail(ctx, PRRTC_E_ARG, "primitive %d: rotation not orthonormal", i);
+            if (q.type == 1) {
+                if (!(q.dims[0] > 0.0f && q.dims[1] > 0.0f && q.dims[2] > 0.0f))
+                    return fail(ctx, PRRTC_E_ARG, "primitive %d: half-extent <= 0", i);
+                const float rec[16] = {q.c[0], q.c[1], q.c[2], 0.0f,
+                                       q.rot[0], q.rot[3], q.rot[6],
+                                       q.rot[1], q.rot[4], q.rot[7],
+                                       q.rot[2], q.rot[5], q.rot[8],
+                                       q.dims[0], q.dims[1], q.dims[2]};
+                box.insert(box.end(), rec, rec + 16);
+            } else {
+                if (!(q.dims[0] > 0.0f && q.dims[1] > 0.0f))
+                    return fail(ctx, PRRTC_E_ARG, "primitive %d: cylinder radius/half-height <= 0", i);
+                const float rec[8] = {q.c[0], q.c[1], q.c[2], q.rot[2], q.rot[5], q.rot[8], q.dims[0], q.dims[1]};
+                cyl.insert(cyl.end(), rec, rec + 8);
+            }
+        } else {
+            return fail(ctx, PRRTC_E_ARG, "primitive %d: unknown type %d", i, q.type);
+        }
+    }
+    const size_t o_sph = 0;
+    const size_t o_box = align_up<int>(sizeof(float4) * sph.size());
+    const size_t o_cyl = align_up<int>(o_box + sizeof(float) * box.size());
+    const size_t bytes = std::max<size_t>(256, align_up<int>(o_cyl + sizeof(float) * cyl.size()));
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    SceneRec rec;
+    PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
+    std::vector<char> host(bytes, 0);
+    if (!sph.empty()) memcpy(host.data() + o_sph, sph.data(), sizeof(float4) * sph.size());
+    if (!box.empty()) memcpy(host.data() + o_box, box.data(), sizeof(float) * box.size());
+    if (!cyl.empty()) memcpy(host.data() + o_cyl, cyl.data(), sizeof(float) * cyl.size());
+    hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(rec.mem);
+        return fail(ctx, PRRTC_E_HIP, "hipMemcpy scene: %s", hipGetErrorString(e));
+    }
+    char* base = static_cast<char*>(rec.mem);
+    rec.args.n_sph = (int)sph.size();
+    rec.args.n_box = (int)(box.size() / 16);
+    rec.args.n_cyl = (int)(cyl.size() / 8);
+    rec.args.sph = reinterpret_cast<const float4*>(base + o_sph);
+    rec.args.box = reinterpret_cast<const float*>(base + o_box);
+    rec.args.cyl = reinterpret_cast<const float*>(base + o_cyl);
+    rec.n = n;
+    ctx->scenes.push_back(rec);
+    *scene_id = (int32_t)ctx->scenes.size() - 1;
+    return PRRTC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kEdgeTile = 32;
+constexpr int kEdgeItems = 4;
+
+size_t check_lds_bytes(const RobotArgs& R, int tp) {
+    return sizeof(float4) * tp * 3 * R.n_frames + sizeof(float) * 2 * kMaxDof + sizeof(int) * (tp + 4);
+}
+
+prrtc_status lookup(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const RobotRec** r,
+                    const SceneRec** s) {
+    if (robot_id < 0 || robot_id >= (int32_t)ctx->robots.size())
+        return fail(ctx, PRRTC_E_STATE, "unknown robot id %d", robot_id);
+    *r = &ctx->robots[robot_id];
+    if (s) {
+        if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size())
+            return fail(ctx, PRRTC_E_STATE, "unknown scene id %d", scene_id);
+        *s = &ctx->scenes[scene_id];
+    }
+    return PRRTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const float* a,
+                               const float* b, int64_t n_edges, float res, uint8_t* valid,
+                               void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    const RobotRec* r = nullptr;
+    const SceneRec* s = nullptr;
+    prrtc_status st = lookup(ctx, robot_id, scene_id, &r, &s);
+    if (st != PRRTC_OK) return st;
+    if (n_edges < 0) return fail(ctx, PRRTC_E_ARG, "n_edges < 0");
+    if (!(res > 0.0f) || !std::isfinite(res)) return fail(ctx, PRRTC_E_ARG, "res must be finite and > 0");
+    if (n_edges == 0) return PRRTC_OK;
+    if (!a || !b || !valid) return fail(ctx, PRRTC_E_ARG, "null buffer");
+    hipStream_t sm = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    const long long grid = std::min<long long>(n_edges, (long long)ctx->n_cu * 16);
+    const size_t lds = check_lds_bytes(r->args, kEdgeTile);
+    hipLaunchKernelGGL((k_check_edges<kEdgeTile, kEdgeItems>), dim3((unsigned)grid), dim3(kWave), lds, sm,
+                       r->args, s->args, a, b, (long long)n_edges, res, valid);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, int64_t n, float* xyz,
+                              void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    const RobotRec* r = nullptr;
+    prrtc_status st = lookup(ctx, robot_id, 0, &r, nullptr);
+    if (st != PRRTC_OK) return st;
+    if (n < 0) return fail(ctx, PRRTC_E_ARG, "n < 0");
+    if (n == 0) return PRRTC_OK;
+    if (!q || !xyz) return fail(ctx, PRRTC_E_ARG, "null buffer");
+    hipStream_t sm = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    const long long blocks = (n + kWave - 1) / kWave;
+    const size_t lds = sizeof(float4) * kWave * 3 * r->args.n_frames;
+    hipLaunchKernelGGL(k_fk_spheres, dim3((unsigned)blocks), dim3(kWave), lds, sm, r->args, q, (long long)n, xyz);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+}  // extern "C"

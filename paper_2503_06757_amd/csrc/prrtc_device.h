@@ -1,0 +1,398 @@
+// prrtc_device.h -- device-side tables and routines of the pRRTC hot path on gfx950.
+//
+// One wavefront (64 lanes) is the unit of work: it validates a list of
+// consecutive sub-edges (a single edge for check_edges and pEXTEND, the equal
+// steps of a greedy CONNECT, or the segments of a path), Alg. 2 / Sec. III-A.
+// Its lanes first run forward kinematics for a tile of interpolated
+// configurations (one configuration per lane, chain transforms in registers,
+// frames written to LDS), then sweep (configuration, sphere) items against
+// the obstacles.  Obstacle records are indexed only by loop counters, so the
+// compiler keeps them in scalar registers (wave-uniform operands of the
+// vector ALU); a ballot after every obstacle ends the sweep at the first hit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace prrtc {
+
+constexpr int kMaxDof = 16;
+constexpr int kMaxChains = 2;
+constexpr int kMaxFrames = kMaxDof + kMaxChains;
+constexpr int kWave = 64;
+
+// Robot tables.  Spheres are re-ordered on load: spheres that move come
+// first (their frame depends on some joint), spheres on a chain's base frame
+// (which never move) after them.
+struct RobotArgs {
+    int n_chains, dof, n_frames;
+    int n_move, n_static;          // spheres [0, n_move) move; [n_move, n_move + n_static) fixed
+    int n_pairs, n_static_pairs;   // self pairs with a moving sphere / with two fixed spheres
+    int chain_dof[kMaxChains], chain_q0[kMaxChains], chain_f0[kMaxChains];
+    float base[kMaxChains][12];
+    float ca[kMaxDof], sa[kMaxDof], a[kMaxDof], d[kMaxDof];  // cos/sin(alpha), a, d per joint
+    float lo[kMaxDof], hi[kMaxDof];
+    const float4* sph;        // local centre + radius, re-ordered
+    const int* sph_frame;     // global frame id, re-ordered
+    const int2* pairs;        // re-ordered indices
+    const int2* static_pairs;
+    const int* desc_index;    // re-ordered sphere -> descriptor order
+};
+
+// Scene tables, one array per primitive type.
+//   sph: (cx, cy, cz, R)
+//   box: 16 floats: c(3), pad, axis0(3), axis1(3), axis2(3), half-extents(3)
+//   cyl: 8 floats: c(3), unit axis(3), R, half-height
+struct SceneArgs {
+    int n_sph, n_box, n_cyl;
+    const float4* sph;
+    const float* box;
+    const float* cyl;
+};
+
+// ----------------------------------------------------------------------------
+// FP32 contract helpers: sums in index order, no contraction, correctly
+// rounded sqrt/division (the compiler default for HIP device code).
+// ----------------------------------------------------------------------------
+__device__ inline float norm_diff_f32(const float* a, const float* b, int dof) {
+#pragma clang fp contract(off)
+    float s = 0.0f;
+    for (int j = 0; j < dof; ++j) {
+        const float d = b[j] - a[j];
+        const float sq = d * d;
+        s = s + sq;
+    }
+    return sqrtf(s);
+}
+
+// n = max(1, ceil(res * L)), capped at 2^24.
+__device__ inline int edge_count_f32(const float* a, const float* b, int dof, float res) {
+#pragma clang fp contract(off)
+    const float L = norm_diff_f32(a, b, dof);
+    const float prod = res * L;
+    const float x = ceilf(prod);
+    if (!(x >= 1.0f)) return 1;
+    if (x > 16777216.0f) return 16777216;
+    return (int)x;
+}
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).
+// ----------------------------------------------------------------------------
+__device__ inline uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+// RANDOM_CONFIG joint j: counter (draw = j / 4, worker, round, query), word j % 4,
+// u = (word >> 8) * 2^-24, q_j = fmaf(u, hi_j - lo_j, lo_j).
+__device__ inline float sample_joint(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
+                                     int j, float lo, float hi) {
+#pragma clang fp contract(off)
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)(j >> 2), worker, round, query),
+                                  make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+    const int m = j & 3;
+    const uint32_t word = m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));
+    const float u = (float)(word >> 8) * 0x1p-24f;
+    const float span = hi - lo;
+    return fmaf(u, span, lo);
+}
+
+// ----------------------------------------------------------------------------
+// Forward kinematics of one configuration (one lane).  Frame j+1 = frame j *
+// Rx(alpha_j) Tx(a_j) Rz(q_j) Tz(d_j); every frame is written as three float4
+// rows [R | t].  With M = R Rx(alpha):  M0 = R0, M1 = ca R1 + sa R2,
+// M2 = ca R2 - sa R1; new R = (cq M0 + sq M1, cq M1 - sq M0, M2) and
+// new t = t + a R0 + d M2.
+// ----------------------------------------------------------------------------
+template <class QF>
+__device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
+    for (int c = 0; c < R.n_chains; ++c) {
+        const float* B = R.base[c];
+        float r00 = B[0], r01 = B[1], r02 = B[2], t0 = B[3];
+        float r10 = B[4], r11 = B[5], r12 = B[6], t1 = B[7];
+        float r20 = B[8], r21 = B[9], r22 = B[10], t2 = B[11];
+        int f = R.chain_f0[c];
+        out[3 * f + 0] = make_float4(r00, r01, r02, t0);
+        out[3 * f + 1] = make_float4(r10, r11, r12, t1);
+        out[3 * f + 2] = make_float4(r20, r21, r22, t2);
+        const int q0 = R.chain_q0[c];
+        for (int jj = 0; jj < R.chain_dof[c]; ++jj) {
+            const int j = q0 + jj;
+            float sq, cq;
+            sincosf(qf(j), &sq, &cq);
+            const float ca = R.ca[j], sa = R.sa[j], a = R.a[j], d = R.d[j];
+            const float u0 = ca * r01 + sa * r02, u1 = ca * r11 + sa * r12, u2 = ca * r21 + sa * r22;
+            const float m0 = ca * r02 - sa * r01, m1 = ca * r12 - sa * r11, m2 = ca * r22 - sa * r21;
+            t0 += a * r00 + d * m0;
+            t1 += a * r10 + d * m1;
+            t2 += a * r20 + d * m2;
+            const float n00 = cq * r00 + sq * u0, n10 = cq * r10 + sq * u1, n20 = cq * r20 + sq * u2;
+            const float n01 = cq * u0 - sq * r00, n11 = cq * u1 - sq * r10, n21 = cq * u2 - sq * r20;
+            r00 = n00; r10 = n10; r20 = n20;
+            r01 = n01; r11 = n11; r21 = n21;
+            r02 = m0; r12 = m1; r22 = m2;
+            ++f;
+            out[3 * f + 0] = make_float4(r00, r01, r02, t0);
+            out[3 * f + 1] = make_float4(r10, r11, r12, t1);
+            out[3 * f + 2] = make_float4(r20, r21, r22, t2);
+        }
+    }
+}
+
+__device__ inline float3 frame_apply(const float4* fr, float x, float y, float z) {
+    const float4 a = fr[0], b = fr[1], c = fr[2];
+    return make_float3(a.x * x + a.y * y + a.z * z + a.w, b.x * x + b.y * y + b.z * z + b.w,
+                       c.x * x + c.y * y + c.z * z + c.w);
+}
+
+// ----------------------------------------------------------------------------
+// Penetration predicates in FP32: a sphere (centre c, radius r) collides with
+// a primitive iff its centre lies strictly closer than r to the solid.
+// ----------------------------------------------------------------------------
+__device__ inline bool hit_sphere(float cx, float cy, float cz, float r, float4 o) {
+    const float dx = cx - o.x, dy = cy - o.y, dz = cz - o.z;
+    const float rr = r + o.w;
+    return dx * dx + dy * dy + dz * dz < rr * rr;
+}
+
+__device__ inline bool hit_box(float cx, float cy, float cz, float r, const float* o) {
+    const float vx = cx - o[0], vy = cy - o[1], vz = cz - o[2];
+    const float l0 = o[4] * vx + o[5] * vy + o[6] * vz;
+    const float l1 = o[7] * vx + o[8] * vy + o[9] * vz;
+    const float l2 = o[10] * vx + o[11] * vy + o[12] * vz;
+    const float e0 = fmaxf(fabsf(l0) - o[13], 0.0f);
+    const float e1 = fmaxf(fabsf(l1) - o[14], 0.0f);
+    const float e2 = fmaxf(fabsf(l2) - o[15], 0.0f);
+    return e0 * e0 + e1 * e1 + e2 * e2 < r * r;
+}
+
+__device__ inline bool hit_cyl(float cx, float cy, float cz, float r, const float* o) {
+    const float vx = cx - o[0], vy = cy - o[1], vz = cz - o[2];
+    const float z = o[3] * vx + o[4] * vy + o[5] * vz;
+    const float wx = vx - z * o[3], wy = vy - z * o[4], wz = vz - z * o[5];
+    const float rho = __builtin_amdgcn_sqrtf(wx * wx + wy * wy + wz * wz);
+    const float dr = fmaxf(rho - o[6], 0.0f);
+    const float dz = fmaxf(fabsf(z) - o[7], 0.0f);
+    return dr * dr + dz * dz < r * r;
+}
+
+__device__ inline bool hit_pair(float4 a, float4 b) {
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const float rr = a.w + b.w;
+    return dx * dx + dy * dy + dz * dz < rr * rr;
+}
+
+// Wave-wide minimum of a uniform-result integer.
+__device__ inline int wave_min_int(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Does any fixed sphere (or fixed-fixed self pair) collide?  Evaluated once
+// per wave: those spheres are at the same place in every configuration.
+__device__ inline bool static_collision(const RobotArgs& R, const SceneArgs& S, float4* fr_ws) {
+    const int lane = threadIdx.x & (kWave - 1);
+    // fixed spheres use their chain's base pose
+    bool hit = false;
+    for (int k = lane; k < R.n_static; k += kWave) {
+        const int s = R.n_move + k;
+        const int f = R.sph_frame[s];
+        const int c = (R.n_chains > 1 && f >= R.chain_f0[1]) ? 1 : 0;
+        const float* B = R.base[c];
+        const float4 p = R.sph[s];
+        const float cx = B[0] * p.x + B[1] * p.y + B[2] * p.z + B[3];
+        const float cy = B[4] * p.x + B[5] * p.y + B[6] * p.z + B[7];
+        const float cz = B[8] * p.x + B[9] * p.y + B[10] * p.z + B[11];
+        for (int o = 0; o < S.n_sph; ++o) hit |= hit_sphere(cx, cy, cz, p.w, S.sph[o]);
+        for (int o = 0; o < S.n_box; ++o) hit |= hit_box(cx, cy, cz, p.w, S.box + 16 * o);
+        for (int o = 0; o < S.n_cyl; ++o) hit |= hit_cyl(cx, cy, cz, p.w, S.cyl + 8 * o);
+    }
+    for (int k = lane; k < R.n_static_pairs; k += kWave) {
+        const int2 pr = R.static_pairs[k];
+        float4 cen[2];
+        const int idx[2] = {pr.x, pr.y};
+        for (int m = 0; m < 2; ++m) {
+            const int f = R.sph_frame[idx[m]];
+            const int c = (R.n_chains > 1 && f >= R.chain_f0[1]) ? 1 : 0;
+            const float* B = R.base[c];
+            const float4 p = R.sph[idx[m]];
+            cen[m] = make_float4(B[0] * p.x + B[1] * p.y + B[2] * p.z + B[3],
+                                 B[4] * p.x + B[5] * p.y + B[6] * p.z + B[7],
+                                 B[8] * p.x + B[9] * p.y + B[10] * p.z + B[11], p.w);
+        }
+        hit |= hit_pair(cen[0], cen[1]);
+    }
+    (void)fr_ws;
+    return __any(hit);
+}
+
+// ----------------------------------------------------------------------------
+// Wave-level check of a waypoint list.
+//
+// Sub-edge k joins waypoint k to k+1 (wp is LDS, row-major [n_sub + 1][dof]).
+// Its points are i = i_first..n_k with n_k from edge_count_f32 and
+// q = fmaf((float)i / (float)n_k, w_{k+1} - w_k, w_k).  Returns the index of
+// the first sub-edge with a colliding point, or n_sub when none collides.
+// MULTI = false specialises the single-sub-edge case (any hit ends the call).
+//
+// Workspace (LDS, per wave): frames [TP][n_frames][3] float4, pk [TP] int,
+// sub_n / sub_off [n_sub + 1] int.
+// ----------------------------------------------------------------------------
+struct WaveWs {
+    float4* frames;
+    int* pk;
+    int* sub_n;
+    int* sub_off;
+};
+
+template <int TP, int B, bool MULTI>
+__device__ int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
+                          int i_first, float res, const WaveWs& ws) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int dof = R.dof;
+    const int fstride = 3 * R.n_frames;
+    // point counts and prefix offsets, in chunks of 64 sub-edges
+    int total = 0;
+    for (int k0 = 0; k0 < n_sub; k0 += kWave) {
+        const int k = k0 + lane;
+        int cnt = 0;
+        if (k < n_sub) {
+            const int n = edge_count_f32(wp + k * dof, wp + (k + 1) * dof, dof, res);
+            ws.sub_n[k] = n;
+            cnt = n - i_first + 1;
+        }
+        // inclusive scan across the wave
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        if (k < n_sub) ws.sub_off[k] = total + incl - cnt;
+        total += __shfl(incl, kWave - 1, kWave);
+    }
+    __syncthreads();
+    int kmin = n_sub;
+    const int S_move = R.n_move;
+    for (int g0 = 0; g0 < total; g0 += TP) {
+        const int np = min(TP, total - g0);
+        // ---- FK of the tile's configurations: lane l takes point g0 + l
+        if (lane < np) {
+            const int g = g0 + lane;
+            int k = 0;
+            while (k + 1 < n_sub && ws.sub_off[k + 1] <= g) ++k;
+            const int i = i_first + (g - ws.sub_off[k]);
+            const float t = (float)i / (float)ws.sub_n[k];
+            const float* w0 = wp + k * dof;
+            const float* w1 = w0 + dof;
+            ws.pk[lane] = k;
+            fk_frames(R, [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); },
+                      ws.frames + lane * fstride);
+        }
+        __syncthreads();
+        // ---- (point, sphere) items against the obstacles
+        const int nitems = np * S_move;
+        for (int base = 0; base < nitems; base += kWave * B) {
+            float cx[B], cy[B], cz[B], cr[B];
+            int ck[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int it = min(base + lane + kWave * b, nitems - 1);
+                const int s = it / np;
+                const int p = it - s * np;
+                const float4 loc = R.sph[s];
+                const float3 c = frame_apply(ws.frames + p * fstride + 3 * R.sph_frame[s], loc.x, loc.y, loc.z);
+                cx[b] = c.x; cy[b] = c.y; cz[b] = c.z; cr[b] = loc.w;
+                ck[b] = MULTI ? ws.pk[p] : 0;
+            }
+            if (MULTI) {
+                bool alive = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) alive |= ck[b] < kmin;
+                if (!__any(alive)) continue;
+            }
+            bool done = false;
+            auto on_hit = [&](const bool* h) {
+                // returns true when nothing alive remains in this block
+                if (!MULTI) { kmin = 0; return true; }
+                int mk = 0x7fffffff;
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    if (h[b] && ck[b] < kmin) mk = min(mk, ck[b]);
+                kmin = min(kmin, wave_min_int(mk));
+                bool alive = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) alive |= ck[b] < kmin;
+                return !__any(alive);
+            };
+            for (int o = 0; o < S.n_sph && !done; ++o) {
+                const float4 ob = S.sph[o];
+                bool h[B], any = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    h[b] = hit_sphere(cx[b], cy[b], cz[b], cr[b], ob);
+                    any |= MULTI ? (h[b] && ck[b] < kmin) : h[b];
+                }
+                if (__any(any)) done = on_hit(h);
+            }
+            for (int o = 0; o < S.n_box && !done; ++o) {
+                const float* ob = S.box + 16 * o;
+                bool h[B], any = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    h[b] = hit_box(cx[b], cy[b], cz[b], cr[b], ob);
+                    any |= MULTI ? (h[b] && ck[b] < kmin) : h[b];
+                }
+                if (__any(any)) done = on_hit(h);
+            }
+            for (int o = 0; o < S.n_cyl && !done; ++o) {
+                const float* ob = S.cyl + 8 * o;
+                bool h[B], any = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    h[b] = hit_cyl(cx[b], cy[b], cz[b], cr[b], ob);
+                    any |= MULTI ? (h[b] && ck[b] < kmin) : h[b];
+                }
+                if (__any(any)) done = on_hit(h);
+            }
+            if (!MULTI && done) break;
+        }
+        // ---- self-collision pairs: (point, pair) items
+        if (R.n_pairs > 0 && (MULTI || kmin == n_sub)) {
+            const int npi = np * R.n_pairs;
+            for (int base = 0; base < npi; base += kWave) {
+                const int it = min(base + lane, npi - 1);
+                const int pr_i = it / np;
+                const int p = it - pr_i * np;
+                const int k = MULTI ? ws.pk[p] : 0;
+                const int2 pr = R.pairs[pr_i];
+                const float4 la = R.sph[pr.x], lb = R.sph[pr.y];
+                const float4* fp = ws.frames + p * fstride;
+                const float3 ca = frame_apply(fp + 3 * R.sph_frame[pr.x], la.x, la.y, la.z);
+                const float3 cb = frame_apply(fp + 3 * R.sph_frame[pr.y], lb.x, lb.y, lb.z);
+                const bool h = hit_pair(make_float4(ca.x, ca.y, ca.z, la.w), make_float4(cb.x, cb.y, cb.z, lb.w)) &&
+                               k < kmin;
+                if (__any(h)) {
+                    kmin = min(kmin, wave_min_int(h ? k : 0x7fffffff));
+                    if (!MULTI) break;
+                }
+            }
+        }
+        __syncthreads();
+        if (kmin < n_sub) return kmin;
+    }
+    return kmin;
+}
+
+}  // namespace prrtc

@@ -1,0 +1,431 @@
+// prrtc_planner.h -- persistent round-synchronous RRT-Connect (Alg. 1) on gfx950.
+//
+// One workgroup of one wavefront per parallel worker (the paper's "block");
+// all workers stay resident for the whole query and meet at grid barriers.
+// A round is:
+//   A. every worker, against the same snapshot of both trees: RANDOM_CONFIG
+//      (Philox), NEAREST_NEIGHBOR in the smaller tree (wave argmin), steer
+//      by at most delta, check the edge (points i = 1..n), then greedy
+//      CONNECT toward the nearest node of the other tree (all equal steps
+//      checked together, the longest valid prefix kept).  New nodes are
+//      staged per worker.
+//   -- barrier --
+//   B. every worker scans the staged counts, appends its own nodes at its
+//      prefix offset (deterministic node ids), and all agree on the lowest
+//      connected worker.
+//   -- barrier --
+//   C. (only when a connection exists) the path is extracted and each
+//      segment re-checked at validate_factor x res by the workers in
+//      parallel; an offending node is blocked and the rounds go on.
+// The paper's blocks insert asynchronously with atomics; rounds trade that
+// for reproducibility: a seed fixes the trees and the path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "prrtc_device.h"
+
+namespace prrtc {
+
+// Control words (int32) in device memory; zeroed before each launch.
+enum Ctl {
+    kBarCount = 0,
+    kBarGen = 32,      // separate cache line from the arrival counter
+    kAbort = 64,
+    kSizeA,
+    kSizeB,
+    kStatus,
+    kPathLen,
+    kRounds,
+    kConnWorker,
+    kValFails,
+    kStop,
+    kEndpointBad,
+    kValBad,
+    kNa,
+    kEdgesLo,          // 64-bit edge counter (two words)
+    kEdgesHi,
+    kCtlWords = 96
+};
+
+// Status codes written by the kernel (mirror prrtc_status).
+constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInternal = -7;
+
+struct PlanArgs {
+    RobotArgs R;
+    SceneArgs S;
+    float start[kMaxDof], goal[kMaxDof];
+    unsigned long long seed;
+    unsigned int query;
+    int W;
+    float delta, res, res_v;
+    int max_rounds, cap, stage_cap, validate;
+    long long budget_ticks;   // <= 0: none
+    float* qa; int* pa; unsigned char* ba;
+    float* qb; int* pb; unsigned char* bb;
+    int* ctl;
+    float* stage;             // [W][stage_cap][dof]
+    int* st_count; int* st_nn; int* st_other; int* st_conn;
+    float* path;              // [path_cap][dof]
+    int* path_idx;            // [path_cap] tree node index; tree = (k < na ? A : B)
+    int path_cap;
+};
+
+// Device memory owned by a context for planner launches (grown on demand).
+struct PlannerBuffers {
+    void* mem = nullptr;
+    size_t bytes = 0;
+};
+
+inline void planner_free(PlannerBuffers& b) {
+    if (b.mem) (void)hipFree(b.mem);
+    b.mem = nullptr;
+    b.bytes = 0;
+}
+
+// ----------------------------------------------------------------------------
+// Grid barrier with a bounded wait.  Arrival counter + generation word; the
+// generation is read before arriving, so a late reader cannot miss a release.
+// A wait longer than ~2 s (the GPU wall clock) raises the abort word, and
+// every workgroup leaves its round loop on abort, so the grid always drains.
+// ----------------------------------------------------------------------------
+__device__ inline bool grid_barrier(int* ctl, int nblocks) {
+    __shared__ int ok_s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned* cnt = reinterpret_cast<unsigned*>(ctl + kBarCount);
+        unsigned* gen = reinterpret_cast<unsigned*>(ctl + kBarGen);
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == (unsigned)nblocks - 1u) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (__hip_atomic_load(ctl + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > 200000000ull) {  // 2 s at the 100 MHz wall clock
+                    __hip_atomic_store(ctl + kAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        if (__hip_atomic_load(ctl + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+// Wave argmin of the FP32 squared distance (in joint order, no FMA) over
+// the non-blocked nodes 0..size-1 of a [dof][cap] tree; ties -> lowest index.
+__device__ inline int wave_nearest(const float* tq, const unsigned char* blocked, int cap, int size,
+                                   const float* x, int dof) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & (kWave - 1);
+    float bd = __builtin_inff();
+    int bi = 0x7fffffff;
+    for (int i = lane; i < size; i += kWave) {
+        if (blocked[i]) continue;
+        float s = 0.0f;
+        for (int j = 0; j < dof; ++j) {
+            const float d = x[j] - tq[(size_t)j * cap + i];
+            const float sq = d * d;
+            s = s + sq;
+        }
+        if (s < bd) {
+            bd = s;
+            bi = i;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ob = __shfl_xor(bd, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        if (ob < bd || (ob == bd && oi < bi)) {
+            bd = ob;
+            bi = oi;
+        }
+    }
+    return bi == 0x7fffffff ? -1 : bi;
+}
+
+template <int TP, int B>
+__global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
+    extern __shared__ float4 lds4[];
+    const int lane = threadIdx.x;
+    const int w = blockIdx.x;
+    const RobotArgs& R = P.R;
+    const int dof = R.dof;
+    const int cap = P.cap;
+    // ---- LDS carve-up
+    WaveWs ws;
+    ws.frames = lds4;
+    float* vec = reinterpret_cast<float*>(lds4 + TP * 3 * R.n_frames);
+    float* c_rand = vec;
+    float* c_nn = vec + kMaxDof;
+    float* c_new = vec + 2 * kMaxDof;
+    float* c_nno = vec + 3 * kMaxDof;
+    float* wp = vec + 4 * kMaxDof;                      // [(stage_cap + 1)][dof]
+    ws.pk = reinterpret_cast<int*>(wp + (P.stage_cap + 1) * dof);
+    ws.sub_n = ws.pk + TP;
+    ws.sub_off = ws.sub_n + P.stage_cap + 2;
+    __shared__ int sh_i[8];
+    int* ctl = P.ctl;
+    long long my_edges = 0;
+
+    // ---- prologue: roots, endpoint checks
+    if (w == 0 && lane < dof) {
+        P.qa[(size_t)lane * cap] = P.start[lane];
+        P.qb[(size_t)lane * cap] = P.goal[lane];
+    }
+    if (w == 0 && lane == 0) {
+        P.pa[0] = -1;
+        P.pb[0] = -1;
+        P.ba[0] = 0;
+        P.bb[0] = 0;
+        ctl[kSizeA] = 1;
+        ctl[kSizeB] = 1;
+    }
+    const bool fixed_hit = static_collision(R, P.S, nullptr);
+    const int n_end_workers = P.W > 1 ? 2 : 1;
+    for (int e = w; e < 2; e += n_end_workers) {
+        const float* q = e == 0 ? P.start : P.goal;
+        if (lane < dof) {
+            wp[lane] = q[lane];
+            wp[dof + lane] = q[lane];
+        }
+        __syncthreads();
+        const bool ok = !fixed_hit && wave_check<TP, B, false>(R, P.S, wp, 1, 0, P.res, ws) == 1;
+        if (!ok && lane == 0) atomicOr(ctl + kEndpointBad, 1);
+        __syncthreads();
+    }
+    if (!grid_barrier(ctl, P.W)) return;
+    if (ctl[kEndpointBad]) {
+        if (w == 0 && lane == 0) ctl[kStatus] = kStInvalidEndpoint;
+        return;
+    }
+    const unsigned long long t_start = wall_clock64();
+    int status = kStNoSolution;
+    int round = 0;
+    for (; round < P.max_rounds; ++round) {
+        const int na = __hip_atomic_load(ctl + kSizeA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int nb = __hip_atomic_load(ctl + kSizeB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool s_is_a = na <= nb;
+        float* qs = s_is_a ? P.qa : P.qb;
+        int* ps = s_is_a ? P.pa : P.pb;
+        unsigned char* bs = s_is_a ? P.ba : P.bb;
+        const float* qo = s_is_a ? P.qb : P.qa;
+        const unsigned char* bo = s_is_a ? P.bb : P.ba;
+        const int ns = s_is_a ? na : nb, no = s_is_a ? nb : na;
+        // ===== phase A: sample, nearest, extend, connect
+        int count = 0, nn = -1, other = -1, conn = 0;
+        if (lane < dof) c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, lane, R.lo[lane], R.hi[lane]);
+        __syncthreads();
+        nn = wave_nearest(qs, bs, cap, ns, c_rand, dof);
+        if (nn >= 0) {
+            if (lane < dof) c_nn[lane] = qs[(size_t)lane * cap + nn];
+            __syncthreads();
+            {
+#pragma clang fp contract(off)
+                const float L = norm_diff_f32(c_nn, c_rand, dof);
+                if (lane < dof) {
+                    if (L <= P.delta) {
+                        c_new[lane] = c_rand[lane];
+                    } else {
+                        const float k = P.delta / L;
+                        c_new[lane] = fmaf(k, c_rand[lane] - c_nn[lane], c_nn[lane]);
+                    }
+                    wp[lane] = c_nn[lane];
+                    wp[dof + lane] = c_new[lane];
+                }
+            }
+            __syncthreads();
+            const bool ext_ok = wave_check<TP, B, false>(R, P.S, wp, 1, 1, P.res, ws) == 1;
+            my_edges += 1;
+            if (ext_ok) {
+                count = 1;
+                other = wave_nearest(qo, bo, cap, no, c_new, dof);
+                if (other >= 0) {
+                    if (lane < dof) c_nno[lane] = qo[(size_t)lane * cap + other];
+                    __syncthreads();
+                    int n_ext;
+                    {
+#pragma clang fp contract(off)
+                        const float L = norm_diff_f32(c_new, c_nno, dof);
+                        const float ratio = L / P.delta;
+                        const float xf = ceilf(ratio);
+                        n_ext = xf >= 1.0f ? (int)fminf(xf, 1.0e9f) : 1;
+                    }
+                    if (n_ext > P.stage_cap) {
+                        // cannot happen for nodes inside the joint limits
+                        if (lane == 0) atomicExch(ctl + kAbort, 2);
+                        n_ext = P.stage_cap;
+                    }
+                    // waypoints t_0 = c_new, t_k = fmaf(k / n_ext, c_nno - c_new, c_new), t_n = c_nno
+                    for (int e = lane; e < (n_ext + 1) * dof; e += kWave) {
+                        const int k = e / dof, j = e - k * dof;
+                        float v;
+                        if (k == 0) v = c_new[j];
+                        else if (k == n_ext) v = c_nno[j];
+                        else {
+#pragma clang fp contract(off)
+                            const float t = (float)k / (float)n_ext;
+                            v = fmaf(t, c_nno[j] - c_new[j], c_new[j]);
+                        }
+                        wp[e] = v;
+                    }
+                    __syncthreads();
+                    const int K = wave_check<TP, B, true>(R, P.S, wp, n_ext, 1, P.res, ws);
+                    my_edges += min(K + 1, n_ext);
+                    count = 1 + min(K, n_ext - 1);
+                    conn = K == n_ext;
+                }
+                // stage c_new and the valid intermediate targets
+                float* st = P.stage + (size_t)w * P.stage_cap * dof;
+                for (int e = lane; e < count * dof; e += kWave) st[e] = (e < dof) ? c_new[e] : wp[e];
+            }
+        }
+        if (lane == 0) {
+            P.st_count[w] = count;
+            P.st_nn[w] = nn;
+            P.st_other[w] = other;
+            P.st_conn[w] = conn;
+        }
+        if (!grid_barrier(ctl, P.W)) break;
+        // ===== phase B: ordered commit
+        int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1;
+        for (int c0 = 0; c0 < P.W; c0 += kWave) {
+            const int wi = c0 + lane;
+            const int cnt = wi < P.W ? P.st_count[wi] : 0;
+            const int cn = wi < P.W ? P.st_conn[wi] : 0;
+            int incl = cnt;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int v = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += v;
+            }
+            const int base_i = ns + running + incl - cnt;
+            const bool fits = base_i + cnt <= cap;
+            if (wi == w) sh_i[0] = base_i;
+            const int cand = wave_min_int((cn && fits) ? wi : 0x7fffffff);
+            if (first == 0x7fffffff && cand != 0x7fffffff) {
+                first = cand;
+                const int src = cand - c0;
+                const int fb = __shfl(base_i, src, kWave);
+                const int fc = __shfl(cnt, src, kWave);
+                first_last = fb + fc - 1;
+                first_other = P.st_other[cand];
+            }
+            running += __shfl(incl, kWave - 1, kWave);
+        }
+        __syncthreads();
+        my_base = sh_i[0];
+        {
+            const int c = max(0, min(count, cap - my_base));
+            const float* st = P.stage + (size_t)w * P.stage_cap * dof;
+            for (int e = lane; e < c * dof; e += kWave) {
+                const int k = e / dof, j = e - k * dof;
+                qs[(size_t)j * cap + my_base + k] = st[e];
+            }
+            for (int k = lane; k < c; k += kWave) {
+                ps[my_base + k] = k == 0 ? nn : my_base + k - 1;
+                bs[my_base + k] = 0;
+            }
+        }
+        if (w == 0 && lane == 0) {
+            const int new_size = min(cap, ns + running);
+            ctl[s_is_a ? kSizeA : kSizeB] = new_size;
+            if (P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks) ctl[kStop] = 1;
+        }
+        if (!grid_barrier(ctl, P.W)) break;
+        // ===== phase C: path and re-check
+        if (first != 0x7fffffff) {
+            const int xa = s_is_a ? first_last : first_other;
+            const int xb = s_is_a ? first_other : first_last;
+            if (w == 0) {
+                if (lane == 0) {
+                    int bad = 0, la = 0, lb = 0;
+                    for (int x = xa; x >= 0; x = P.pa[x]) { ++la; bad |= P.ba[x]; }
+                    for (int x = xb; x >= 0; x = P.pb[x]) { ++lb; bad |= P.bb[x]; }
+                    const int len = la + lb;
+                    if (len <= P.path_cap) {
+                        int m = la - 1;
+                        for (int x = xa; x >= 0; x = P.pa[x]) P.path_idx[m--] = x;
+                        m = la;
+                        for (int x = xb; x >= 0; x = P.pb[x]) P.path_idx[m++] = x;
+                    } else {
+                        bad = 1;
+                        atomicExch(ctl + kAbort, 3);
+                    }
+                    ctl[kNa] = la;
+                    ctl[kPathLen] = len;
+                    ctl[kValBad] = bad;
+                    if (bad) {
+                        if (xa != 0) P.ba[xa] = 1;
+                        if (xb != 0) P.bb[xb] = 1;
+                    }
+                    __threadfence_block();
+                    sh_i[1] = la;
+                    sh_i[2] = len;
+                }
+                __syncthreads();
+                __threadfence_block();
+                const int la = sh_i[1], len = sh_i[2];
+                if (len <= P.path_cap) {
+                    for (int e = lane; e < len * dof; e += kWave) {
+                        const int m = e / dof, j = e - m * dof;
+                        const bool in_a = m < la;
+                        const float* q = in_a ? P.qa : P.qb;
+                        P.path[e] = q[(size_t)j * cap + P.path_idx[m]];
+                    }
+                }
+            }
+            if (!grid_barrier(ctl, P.W)) break;
+            const int la = ctl[kNa], len = ctl[kPathLen];
+            if (P.validate > 0) {
+                for (int k = w; k + 1 < len; k += P.W) {
+                    if (lane < 2 * dof) wp[lane] = P.path[(size_t)k * dof + lane];
+                    __syncthreads();
+                    const bool ok = wave_check<TP, B, false>(R, P.S, wp, 1, 0, P.res_v, ws) == 1;
+                    my_edges += 1;
+                    if (!ok && lane == 0) {
+                        ctl[kValBad] = 1;
+                        if (k + 1 < la) P.ba[P.path_idx[k + 1]] = 1;
+                        else if (k + 1 == la) { if (s_is_a) P.ba[xa] = 1; else P.bb[xb] = 1; }
+                        else P.bb[P.path_idx[k]] = 1;
+                    }
+                    __syncthreads();
+                }
+            }
+            if (!grid_barrier(ctl, P.W)) break;
+            if (!ctl[kValBad]) {
+                status = kStOk;
+                if (w == 0 && lane == 0) ctl[kConnWorker] = first;
+                ++round;
+                break;
+            }
+            if (w == 0 && lane == 0) ctl[kValFails] += 1;
+        }
+        if (ctl[kStop]) {
+            ++round;
+            break;
+        }
+    }
+    if (lane == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
+    if (w == 0 && lane == 0) {
+        ctl[kRounds] = round;
+        if (ctl[kAbort]) ctl[kStatus] = kStInternal;
+        else ctl[kStatus] = status;
+    }
+}
+
+}  // namespace prrtc

@@ -1,0 +1,217 @@
+"""Thin ctypes binding of libprrtc.so (argument marshalling only).
+
+Every function keeps the C name and argument order of include/prrtc.h.
+Device buffers are passed as integer device addresses (e.g. a torch tensor's
+``data_ptr()``); torch is used by callers only to own device memory and
+streams.  There is no fallback: if the HIP library is missing, importing this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprrtc.so")
+
+PRRTC_OK = 0
+PRRTC_E_ARG = -1
+PRRTC_E_STATE = -2
+PRRTC_E_CAPACITY = -3
+PRRTC_E_INVALID_ENDPOINT = -4
+PRRTC_E_NO_SOLUTION = -5
+PRRTC_E_BUSY = -6
+PRRTC_E_HIP = -7
+
+MAX_DOF = 16
+
+
+class prrtc_robot_desc(C.Structure):
+    _fields_ = [
+        ("n_chains", C.c_int32),
+        ("chain_dof", C.c_int32 * 2),
+        ("base_pose", (C.c_float * 12) * 2),
+        ("dh", C.POINTER(C.c_float)),
+        ("q_lo", C.POINTER(C.c_float)),
+        ("q_hi", C.POINTER(C.c_float)),
+        ("n_spheres", C.c_int32),
+        ("sphere_frame", C.POINTER(C.c_int32)),
+        ("sphere_xyzr", C.POINTER(C.c_float)),
+        ("n_self_pairs", C.c_int32),
+        ("self_pairs", C.POINTER(C.c_int32)),
+    ]
+
+
+class prrtc_plan_params(C.Structure):
+    _fields_ = [
+        ("seed", C.c_uint64),
+        ("query", C.c_uint32),
+        ("workers", C.c_int32),
+        ("delta", C.c_float),
+        ("res", C.c_float),
+        ("max_rounds", C.c_int32),
+        ("tree_capacity", C.c_int32),
+        ("time_budget_ms", C.c_float),
+        ("validate_factor", C.c_int32),
+    ]
+
+
+class prrtc_plan_stats(C.Structure):
+    _fields_ = [
+        ("rounds", C.c_int32),
+        ("nodes_a", C.c_int32),
+        ("nodes_b", C.c_int32),
+        ("edges_checked", C.c_int64),
+        ("validation_failures", C.c_int32),
+        ("connect_worker", C.c_int32),
+        ("gpu_ms", C.c_float),
+    ]
+
+
+class PrrtcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"prrtc status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2503_06757_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, F, VP = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_void_p
+    L.prrtc_create.argtypes = [C.POINTER(P), C.c_int]
+    L.prrtc_create.restype = I32
+    L.prrtc_destroy.argtypes = [P]
+    L.prrtc_destroy.restype = None
+    L.prrtc_last_error.argtypes = [P]
+    L.prrtc_last_error.restype = C.c_char_p
+    L.prrtc_load_robot.argtypes = [P, C.POINTER(prrtc_robot_desc), C.POINTER(I32)]
+    L.prrtc_load_robot.restype = I32
+    L.prrtc_load_scene.argtypes = [P, VP, I32, C.POINTER(I32)]
+    L.prrtc_load_scene.restype = I32
+    L.prrtc_check_edges.argtypes = [P, I32, I32, VP, VP, I64, F, VP, VP]
+    L.prrtc_check_edges.restype = I32
+    L.prrtc_fk_spheres.argtypes = [P, I32, VP, I64, VP, VP]
+    L.prrtc_fk_spheres.restype = I32
+    if hasattr(L, "prrtc_plan"):
+        L.prrtc_plan_params_default.argtypes = [C.POINTER(prrtc_plan_params)]
+        L.prrtc_plan_params_default.restype = None
+        L.prrtc_plan.argtypes = [P, I32, I32, VP, VP, C.POINTER(prrtc_plan_params), VP, I32,
+                                 C.POINTER(I32), C.POINTER(prrtc_plan_stats)]
+        L.prrtc_plan.restype = I32
+    return L
+
+
+lib = _load()
+
+# the symbols include/prrtc.h declares (checked by the CPU test-suite)
+EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
+            "prrtc_load_scene", "prrtc_check_edges", "prrtc_fk_spheres",
+            "prrtc_plan_params_default", "prrtc_plan")
+
+
+# ---- C-named wrappers ------------------------------------------------------------
+def prrtc_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    st = lib.prrtc_create(C.byref(h), int(device))
+    if st != PRRTC_OK:
+        raise PrrtcError(st, "prrtc_create failed")
+    return h.value
+
+
+def prrtc_destroy(ctx: int) -> None:
+    lib.prrtc_destroy(ctx)
+
+
+def prrtc_last_error(ctx: int) -> str:
+    return lib.prrtc_last_error(ctx).decode()
+
+
+def _check(ctx, st):
+    if st != PRRTC_OK:
+        raise PrrtcError(st, prrtc_last_error(ctx))
+    return st
+
+
+def robot_desc(robot: dict):
+    """Build a prrtc_robot_desc from a workload dict; returns (desc, keepalive)."""
+    keep = dict(
+        dh=np.ascontiguousarray(robot["dh"], np.float32),
+        lo=np.ascontiguousarray(robot["q_lo"], np.float32),
+        hi=np.ascontiguousarray(robot["q_hi"], np.float32),
+        frame=np.ascontiguousarray(robot["sphere_frame"], np.int32),
+        xyzr=np.ascontiguousarray(robot["sphere_xyzr"], np.float32),
+        pairs=np.ascontiguousarray(robot["self_pairs"], np.int32).reshape(-1, 2),
+    )
+    d = prrtc_robot_desc()
+    d.n_chains = int(robot["n_chains"])
+    for c in range(d.n_chains):
+        d.chain_dof[c] = int(robot["chain_dof"][c])
+        for i in range(12):
+            d.base_pose[c][i] = float(robot["base_pose"][c][i])
+    fp = C.POINTER(C.c_float)
+    ip = C.POINTER(C.c_int32)
+    d.dh = keep["dh"].ctypes.data_as(fp)
+    d.q_lo = keep["lo"].ctypes.data_as(fp)
+    d.q_hi = keep["hi"].ctypes.data_as(fp)
+    d.n_spheres = keep["xyzr"].shape[0]
+    d.sphere_frame = keep["frame"].ctypes.data_as(ip)
+    d.sphere_xyzr = keep["xyzr"].ctypes.data_as(fp)
+    d.n_self_pairs = keep["pairs"].shape[0]
+    d.self_pairs = keep["pairs"].ctypes.data_as(ip)
+    return d, keep
+
+
+def prrtc_load_robot(ctx: int, robot: dict) -> int:
+    d, keep = robot_desc(robot)
+    rid = C.c_int32(-1)
+    _check(ctx, lib.prrtc_load_robot(ctx, C.byref(d), C.byref(rid)))
+    del keep
+    return rid.value
+
+
+def prrtc_load_scene(ctx: int, prims: np.ndarray) -> int:
+    prims = np.ascontiguousarray(prims)
+    assert prims.dtype.itemsize == 64
+    sid = C.c_int32(-1)
+    _check(ctx, lib.prrtc_load_scene(ctx, prims.ctypes.data if prims.size else None,
+                                     int(prims.shape[0]), C.byref(sid)))
+    return sid.value
+
+
+def prrtc_check_edges(ctx: int, robot_id: int, scene_id: int, a_dev: int, b_dev: int, n_edges: int,
+                      res: float, valid_dev: int, stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_check_edges(ctx, robot_id, scene_id, a_dev, b_dev, int(n_edges),
+                                             float(res), valid_dev, stream))
+
+
+def prrtc_fk_spheres(ctx: int, robot_id: int, q_dev: int, n: int, xyz_dev: int,
+                     stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_fk_spheres(ctx, robot_id, q_dev, int(n), xyz_dev, stream))
+
+
+def prrtc_plan_params_default() -> prrtc_plan_params:
+    p = prrtc_plan_params()
+    lib.prrtc_plan_params_default(C.byref(p))
+    return p
+
+
+def prrtc_plan(ctx: int, robot_id: int, scene_id: int, start: np.ndarray, goal: np.ndarray,
+               params: prrtc_plan_params, path_cap: int = 4096):
+    """Returns (status, path ndarray (len, dof) or None, stats).  Status codes
+    E_NO_SOLUTION / E_INVALID_ENDPOINT are returned, not raised."""
+    s = np.ascontiguousarray(start, np.float32)
+    g = np.ascontiguousarray(goal, np.float32)
+    path = np.zeros((path_cap, s.shape[0]), np.float32)
+    ln = C.c_int32(0)
+    st = prrtc_plan_stats()
+    status = lib.prrtc_plan(ctx, robot_id, scene_id, s.ctypes.data, g.ctypes.data, C.byref(params),
+                            path.ctypes.data, int(path_cap), C.byref(ln), C.byref(st))
+    if status in (PRRTC_E_ARG, PRRTC_E_STATE, PRRTC_E_HIP):
+        raise PrrtcError(status, prrtc_last_error(ctx))
+    stats = {f: getattr(st, f) for f, _ in prrtc_plan_stats._fields_}
+    stats["path_len"] = ln.value
+    return status, (path[: ln.value].copy() if status == PRRTC_OK else None), stats

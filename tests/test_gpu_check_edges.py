@@ -1,0 +1,165 @@
+"""GPU parity of prrtc_fk_spheres and prrtc_check_edges against the oracle,
+through the C ABI (Alg. 2 / Sec. III-A)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_06757_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FK_TOL = 1e-5      # metres: FP32 sphere centres vs the FP64 oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_check(gpu, rid, sid, a, b, res=32.0):
+    P, ctx, torch = gpu
+    n = a.shape[0]
+    ta = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tb = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    tv = torch.full((max(n, 1),), 7, dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), n, res, tv.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return tv[:n].cpu().numpy()
+
+
+def assert_parity(orc, robot, prims, a, b, got, res=32.0, threads=0):
+    rob = orc.OracleRobot(robot)
+    v, f, _ = orc.check_edges(rob, prims, a, b, res, early_exit=True, n_threads=threads)
+    assert set(np.unique(got)) <= {0, 1}
+    mism = (got != v) & (f == 0)
+    assert not mism.any(), f"{mism.sum()} unflagged mismatches, first at {np.nonzero(mism)[0][:10]}"
+    return v, f
+
+
+@pytest.mark.parametrize("robot_name", ["r7", "r14"])
+def test_fk_spheres_parity(gpu, orc, robot_name, request):
+    P, ctx, torch = gpu
+    robot = request.getfixturevalue(robot_name)
+    say("fk parity", robot_name)
+    rid = P.prrtc_load_robot(ctx, robot)
+    rng = np.random.default_rng(1)
+    dof = W.robot_dof(robot)
+    q = rng.uniform(-3.2, 3.2, (3000, dof)).astype(np.float32)   # also a little outside limits
+    tq = torch.from_numpy(q).cuda()
+    ns = robot["sphere_xyzr"].shape[0]
+    out = torch.zeros((3000, ns, 3), dtype=torch.float32, device="cuda")
+    P.prrtc_fk_spheres(ctx, rid, tq.data_ptr(), 3000, out.data_ptr(),
+                       torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    rob = orc.OracleRobot(robot)
+    err = max(np.max(np.abs(got[i] - orc.fk_spheres(rob, q[i]))) for i in range(0, 3000, 7))
+    say("  max |fk err| =", err)
+    assert err <= FK_TOL
+
+
+def test_check_edges_parity_s12_s64(gpu, orc, r7):
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    for name, prims in (("S12", W.scene_s12(r7, 0)), ("S64", W.scene_s64(r7))):
+        sid = P.prrtc_load_scene(ctx, prims)
+        a, b = W.random_edges(r7, 20011, seed=1234)     # ragged count
+        say("check_edges parity", name, a.shape)
+        got = gpu_check(gpu, rid, sid, a, b)
+        v, f = assert_parity(orc, r7, prims, a, b, got)
+        say("  valid frac %.4f flagged %d" % (v.mean(), f.sum()))
+
+
+def test_check_edges_parity_r14_shelf(gpu, orc, r14):
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r14)
+    prims = W.scene_shelf(r14)
+    sid = P.prrtc_load_scene(ctx, prims)
+    a, b = W.random_edges(r14, 3001, seed=77)
+    say("check_edges parity R14 shelf", a.shape)
+    got = gpu_check(gpu, rid, sid, a, b)
+    v, f = assert_parity(orc, r14, prims, a, b, got)
+    say("  valid frac %.4f flagged %d" % (v.mean(), f.sum()))
+    # an empty scene leaves only the self pairs between the arms
+    sid0 = P.prrtc_load_scene(ctx, np.zeros(0, W.PRIM_DTYPE))
+    got0 = gpu_check(gpu, rid, sid0, a, b)
+    v0, f0 = assert_parity(orc, r14, np.zeros(0, W.PRIM_DTYPE), a, b, got0)
+    say("  self-only valid frac %.4f" % v0.mean())
+    assert 0.0 < v0.mean() < 1.0
+
+
+def test_check_edges_edge_cases(gpu, orc, r7):
+    P, ctx, torch = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    prims = W.scene_s12(r7, 2)
+    sid = P.prrtc_load_scene(ctx, prims)
+    rng = np.random.default_rng(5)
+    say("edge cases")
+    # n = 0 is a no-op
+    P.prrtc_check_edges(ctx, rid, sid, 0, 0, 0, 32.0, 0, None)
+    # zero-length edges, one edge, and long edges spanning many FK tiles
+    a = rng.uniform(-2.8, 2.8, (300, 7)).astype(np.float32)
+    b = a.copy()
+    b[100:] = rng.uniform(-2.8, 2.8, (200, 7)).astype(np.float32)  # long: up to ~14 rad -> ~450 points
+    got = gpu_check(gpu, rid, sid, a, b)
+    assert_parity(orc, r7, prims, a, b, got)
+    got1 = gpu_check(gpu, rid, sid, a[150:151], b[150:151])
+    assert got1[0] == got[150]
+    # coarse and fine resolutions
+    for res in (0.5, 3.0, 200.0):
+        got = gpu_check(gpu, rid, sid, a[100:160], b[100:160], res)
+        assert_parity(orc, r7, prims, a[100:160], b[100:160], got, res)
+    # empty scene: everything valid; enclosing sphere: nothing valid
+    sid_e = P.prrtc_load_scene(ctx, np.zeros(0, W.PRIM_DTYPE))
+    assert gpu_check(gpu, rid, sid_e, a, b).all()
+    big = W.make_prims([(W.PRIM_SPHERE, (0, 0, 0.5), np.eye(3), (5.0, 0, 0))])
+    assert not gpu_check(gpu, rid, P.prrtc_load_scene(ctx, big), a, b).any()
+    # an obstacle touching only the fixed base spheres invalidates every edge
+    base_hit = W.make_prims([(W.PRIM_CUBOID, (0.0, 0.0, 0.1), np.eye(3), (0.02, 0.02, 0.02))])
+    got = gpu_check(gpu, rid, P.prrtc_load_scene(ctx, base_hit), a, b)
+    assert_parity(orc, r7, base_hit, a, b, got)
+    assert not got.any()
+
+
+def test_check_edges_deterministic_and_stream_order(gpu, r7):
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    sid = P.prrtc_load_scene(ctx, W.scene_s64(r7))
+    a, b = W.random_edges(r7, 50000, seed=99)
+    say("determinism")
+    g1 = gpu_check(gpu, rid, sid, a, b)
+    g2 = gpu_check(gpu, rid, sid, a, b)
+    assert np.array_equal(g1, g2)
+
+
+def test_check_edges_argument_errors(gpu, r7):
+    P, ctx, torch = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    sid = P.prrtc_load_scene(ctx, W.scene_s12(r7, 0))
+    t = torch.zeros((4, 7), device="cuda")
+    v = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    for args, code in (((rid + 100, sid, 32.0, 4), P.PRRTC_E_STATE),
+                       ((rid, sid + 100, 32.0, 4), P.PRRTC_E_STATE),
+                       ((rid, sid, 0.0, 4), P.PRRTC_E_ARG),
+                       ((rid, sid, float("nan"), 4), P.PRRTC_E_ARG),
+                       ((rid, sid, 32.0, -1), P.PRRTC_E_ARG)):
+        r_, s_, res, n = args
+        st = P.lib.prrtc_check_edges(ctx, r_, s_, t.data_ptr(), t.data_ptr(), n, res, v.data_ptr(), None)
+        assert st == code
+        assert P.prrtc_last_error(ctx)
+
+
+def test_check_edges_full_size_configuration(gpu, orc, r7):
+    """The benchmarked configuration: 64 obstacles, 2^20 edges, the same
+    launch as the benchmark.  Every edge is compared with the oracle (OpenMP)."""
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    prims = W.scene_s64(r7)
+    sid = P.prrtc_load_scene(ctx, prims)
+    a, b = W.random_edges(r7, 1 << 20)
+    say("full-size parity 2^20 edges")
+    got = gpu_check(gpu, rid, sid, a, b)
+    v, f = assert_parity(orc, r7, prims, a, b, got, threads=16)
+    say("  valid frac %.4f flagged %d" % (v.mean(), f.sum()))
