@@ -96,6 +96,7 @@ struct SceneRec {
 struct prrtc_ctx {
     int device = 0;
     int n_cu = 256;
+    double wall_khz = 100000.0;  // GPU wall-clock ticks per millisecond
     hipStream_t stream = nullptr;
     std::string err;
     std::vector<RobotRec> robots;
@@ -161,6 +162,9 @@ prrtc_status prrtc_create(prrtc_ctx** out, int device) {
     hipDeviceProp_t prop;
     PRRTC_HIP(ctx.get(), hipGetDeviceProperties(&prop, device));
     ctx->n_cu = prop.multiProcessorCount;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && wall_khz > 0)
+        ctx->wall_khz = (double)wall_khz;
     PRRTC_HIP(ctx.get(), hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev0));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev1));
@@ -441,6 +445,172 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
     const size_t lds = sizeof(float4) * kWave * 3 * r->args.n_frames;
     hipLaunchKernelGGL(k_fk_spheres, dim3((unsigned)blocks), dim3(kWave), lds, sm, r->args, q, (long long)n, xyz);
     PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// plan
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr int kPlanTile = 32;
+constexpr int kPlanItems = 4;
+
+struct PlanLayout {
+    size_t qa, pa, ba, qb, pb, bb, ctl, stage, st, path, path_idx, bytes;
+};
+
+PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
+    PlanLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t n) { const size_t at = o; o = align_up<int>(o + n); return at; };
+    L.qa = take(sizeof(float) * (size_t)dof * cap);
+    L.pa = take(sizeof(int) * (size_t)cap);
+    L.ba = take((size_t)cap);
+    L.qb = take(sizeof(float) * (size_t)dof * cap);
+    L.pb = take(sizeof(int) * (size_t)cap);
+    L.bb = take((size_t)cap);
+    L.ctl = take(sizeof(int) * kCtlWords);
+    L.stage = take(sizeof(float) * (size_t)W * stage_cap * dof);
+    L.st = take(sizeof(int) * 4 * (size_t)W);
+    L.path = take(sizeof(float) * (size_t)path_cap * dof);
+    L.path_idx = take(sizeof(int) * (size_t)path_cap);
+    L.bytes = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+void prrtc_plan_params_default(prrtc_plan_params* p) {
+    if (!p) return;
+    p->seed = 1;
+    p->query = 0;
+    p->workers = 256;
+    p->delta = 0.5f;
+    p->res = 32.0f;
+    p->max_rounds = 1000;
+    p->tree_capacity = 65536;
+    p->time_budget_ms = 0.0f;
+    p->validate_factor = 4;
+}
+
+prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const float* start,
+                        const float* goal, const prrtc_plan_params* prm, float* path, int32_t path_cap,
+                        int32_t* path_len, prrtc_plan_stats* stats) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (path_len) *path_len = 0;
+    if (stats) memset(stats, 0, sizeof *stats);
+    const RobotRec* r = nullptr;
+    const SceneRec* s = nullptr;
+    prrtc_status st = lookup(ctx, robot_id, scene_id, &r, &s);
+    if (st != PRRTC_OK) return st;
+    if (!start || !goal || !prm || !path_len) return fail(ctx, PRRTC_E_ARG, "null argument");
+    if (path_cap < 0 || (path_cap > 0 && !path)) return fail(ctx, PRRTC_E_ARG, "bad path buffer");
+    const int dof = r->dof;
+    const prrtc_plan_params& p = *prm;
+    if (p.workers < 1 || p.workers > 4096) return fail(ctx, PRRTC_E_ARG, "workers must be in 1..4096");
+    if (!(p.delta > 0.0f) || !std::isfinite(p.delta)) return fail(ctx, PRRTC_E_ARG, "delta must be > 0");
+    if (!(p.res > 0.0f) || !std::isfinite(p.res)) return fail(ctx, PRRTC_E_ARG, "res must be > 0");
+    if (p.max_rounds < 0) return fail(ctx, PRRTC_E_ARG, "max_rounds < 0");
+    if (p.tree_capacity < 2 || p.tree_capacity > (1 << 24))
+        return fail(ctx, PRRTC_E_ARG, "tree_capacity must be in 2..2^24");
+    if (p.validate_factor < 0 || p.validate_factor > 1024)
+        return fail(ctx, PRRTC_E_ARG, "validate_factor must be in 0..1024");
+    if (!finite_all(start, dof) || !finite_all(goal, dof))
+        return fail(ctx, PRRTC_E_ARG, "start/goal not finite");
+    const RobotArgs& RA = r->args;
+    for (int j = 0; j < dof; ++j)
+        if (!(start[j] >= RA.lo[j] && start[j] <= RA.hi[j] && goal[j] >= RA.lo[j] && goal[j] <= RA.hi[j]))
+            return fail(ctx, PRRTC_E_INVALID_ENDPOINT, "start/goal joint %d outside the limits", j);
+    // longest greedy connect: ceil(|hi - lo| / delta) steps (+ margin for rounding)
+    double diag = 0.0;
+    for (int j = 0; j < dof; ++j) diag += (double)(RA.hi[j] - RA.lo[j]) * (double)(RA.hi[j] - RA.lo[j]);
+    const int stage_cap = (int)std::ceil(std::sqrt(diag) / (double)p.delta * (1.0 + 1e-6)) + 2;
+    if (stage_cap > 4096) return fail(ctx, PRRTC_E_ARG, "delta too small for the joint range");
+    const int W = p.workers, cap = p.tree_capacity;
+    const int path_cap_dev = 2 * cap;
+    const PlanLayout L = plan_layout(dof, cap, W, stage_cap, path_cap_dev);
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->plan.bytes < L.bytes) {
+        planner_free(ctx->plan);
+        PRRTC_HIP(ctx, hipMalloc(&ctx->plan.mem, L.bytes));
+        ctx->plan.bytes = L.bytes;
+    }
+    char* m = static_cast<char*>(ctx->plan.mem);
+    PlanArgs A;
+    A.R = RA;
+    A.S = s->args;
+    for (int j = 0; j < kMaxDof; ++j) {
+        A.start[j] = j < dof ? start[j] : 0.0f;
+        A.goal[j] = j < dof ? goal[j] : 0.0f;
+    }
+    A.seed = p.seed;
+    A.query = p.query;
+    A.W = W;
+    A.delta = p.delta;
+    A.res = p.res;
+    A.res_v = p.res * (float)p.validate_factor;
+    A.max_rounds = p.max_rounds;
+    A.cap = cap;
+    A.stage_cap = stage_cap;
+    A.validate = p.validate_factor;
+    A.budget_ticks = p.time_budget_ms > 0.0f ? (long long)((double)p.time_budget_ms * ctx->wall_khz) : 0;
+    A.qa = reinterpret_cast<float*>(m + L.qa);
+    A.pa = reinterpret_cast<int*>(m + L.pa);
+    A.ba = reinterpret_cast<unsigned char*>(m + L.ba);
+    A.qb = reinterpret_cast<float*>(m + L.qb);
+    A.pb = reinterpret_cast<int*>(m + L.pb);
+    A.bb = reinterpret_cast<unsigned char*>(m + L.bb);
+    A.ctl = reinterpret_cast<int*>(m + L.ctl);
+    A.stage = reinterpret_cast<float*>(m + L.stage);
+    int* sti = reinterpret_cast<int*>(m + L.st);
+    A.st_count = sti;
+    A.st_nn = sti + W;
+    A.st_other = sti + 2 * W;
+    A.st_conn = sti + 3 * W;
+    A.path = reinterpret_cast<float*>(m + L.path);
+    A.path_idx = reinterpret_cast<int*>(m + L.path_idx);
+    A.path_cap = path_cap_dev;
+    const size_t lds = sizeof(float4) * kPlanTile * 3 * RA.n_frames +
+                       sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) +
+                       sizeof(int) * (kPlanTile + 2 * (stage_cap + 2));
+    hipStream_t sm = ctx->stream;
+    PRRTC_HIP(ctx, hipMemsetAsync(A.ctl, 0, sizeof(int) * kCtlWords, sm));
+    void* kargs[] = {&A};
+    PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
+                                              dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
+    PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
+    int ctl[kCtlWords];
+    PRRTC_HIP(ctx, hipMemcpyAsync(ctl, A.ctl, sizeof ctl, hipMemcpyDeviceToHost, sm));
+    PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (stats) {
+        stats->rounds = ctl[kRounds];
+        stats->nodes_a = ctl[kSizeA];
+        stats->nodes_b = ctl[kSizeB];
+        stats->edges_checked = (int64_t)((unsigned long long)(unsigned)ctl[kEdgesLo] |
+                                         ((unsigned long long)(unsigned)ctl[kEdgesHi] << 32));
+        stats->validation_failures = ctl[kValFails];
+        stats->connect_worker = ctl[kStatus] == kStOk ? ctl[kConnWorker] : -1;
+        stats->gpu_ms = ms;
+    }
+    const int status = ctl[kStatus];
+    if (status == kStInternal)
+        return fail(ctx, PRRTC_E_HIP, "planner aborted on the device (code %d)", ctl[kAbort]);
+    if (status == kStInvalidEndpoint) return fail(ctx, PRRTC_E_INVALID_ENDPOINT, "start or goal in collision");
+    if (status == kStNoSolution) return fail(ctx, PRRTC_E_NO_SOLUTION, "no connection within the round/time budget");
+    const int len = ctl[kPathLen];
+    *path_len = len;
+    if (len > path_cap) return fail(ctx, PRRTC_E_CAPACITY, "path needs %d nodes, buffer holds %d", len, path_cap);
+    PRRTC_HIP(ctx, hipMemcpyAsync(path, A.path, sizeof(float) * (size_t)len * dof, hipMemcpyDeviceToHost, sm));
+    PRRTC_HIP(ctx, hipStreamSynchronize(sm));
     return PRRTC_OK;
 }
 

@@ -366,10 +366,11 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
                         bad = 1;
                         atomicExch(ctl + kAbort, 3);
                     }
+                    if (P.validate <= 0) bad = len > P.path_cap;  // no re-check: blocked nodes cannot exist
                     ctl[kNa] = la;
                     ctl[kPathLen] = len;
                     ctl[kValBad] = bad;
-                    if (bad) {
+                    if (bad && len <= P.path_cap) {
                         if (xa != 0) P.ba[xa] = 1;
                         if (xb != 0) P.bb[xb] = 1;
                     }
