@@ -50,7 +50,8 @@ typedef struct prrtc_ctx prrtc_ctx;
 #define PRRTC_MAX_PRIMS 1024
 #define PRRTC_MAX_SELF_PAIRS 16384
 
-/* Create a context on HIP device `device` (its own non-blocking stream). */
+/* Create a context on HIP device `device` (plan runs on the context's own
+ * non-blocking stream; the asynchronous calls take the caller's stream). */
 prrtc_status prrtc_create(prrtc_ctx **out, int device);
 /* Free every table and buffer of the context.  destroy(NULL) is a no-op. */
 void prrtc_destroy(prrtc_ctx *ctx);
@@ -116,9 +117,11 @@ prrtc_status prrtc_load_scene(prrtc_ctx *ctx, const prrtc_prim *prims, int32_t n
  * a, b:   device float32 [n_edges][dof], row-major, finite.
  * valid:  device uint8 [n_edges], written.
  * res:    points per radian (> 0).
- * stream: hipStream_t to enqueue on (NULL = the context's stream).  The call
- *         is asynchronous; buffers must stay alive until the stream is
- *         synchronised.  n_edges = 0 is a no-op.
+ * stream: hipStream_t to enqueue on (NULL = the HIP default stream).  The
+ *         call is asynchronous; buffers must stay alive until the stream is
+ *         synchronised.  n_edges = 0 is a no-op.  Launches on one context
+ *         draw from a ring of 256 work counters, so at most 256 launches of
+ *         one context may be in flight at once.
  */
 prrtc_status prrtc_check_edges(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id,
                                const float *a, const float *b, int64_t n_edges, float res,

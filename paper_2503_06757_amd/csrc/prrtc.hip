@@ -22,35 +22,110 @@ using namespace prrtc;
 // Kernels
 // ----------------------------------------------------------------------------
 
-// check_edges: one wavefront per workgroup, edges strided over the grid.
+// check_edges: one wavefront per workgroup.  Collision-free edges cost far
+// more than colliding ones, so edges are handed out dynamically: the batch is
+// split into one contiguous range per XCD (workgroup ids are dealt to the 8
+// XCDs round-robin) and each wave takes chunks of kEdgeChunk edges from its
+// XCD's counter, keeping the atomics off a single shared address.  The next
+// chunk's first endpoints are fetched while the current edge is checked.  The
+// last wave to finish resets the counters for the next launch.
+#ifndef PRRTC_EDGE_CHUNK
+#define PRRTC_EDGE_CHUNK 8
+#endif
+#ifndef PRRTC_EDGE_SCHED
+#define PRRTC_EDGE_SCHED 2  // 0: static stride, 1: one counter, 2: per-XCD chunked counters
+#endif
+constexpr int kEdgeChunk = PRRTC_EDGE_CHUNK;
+constexpr int kXcds = 8;
+
+struct EdgeCounter {
+    unsigned long long next[kXcds * 8];  // one 64-byte line per XCD
+    unsigned int done;
+    unsigned int pad[15];
+};
+
 template <int TP, int B>
 __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
                                                        const float* __restrict__ A,
                                                        const float* __restrict__ Bv,
                                                        long long n_edges, float res,
-                                                       uint8_t* __restrict__ valid) {
+                                                       uint8_t* __restrict__ valid,
+                                                       EdgeCounter* ctr) {
     extern __shared__ float4 lds4[];
     const int lane = threadIdx.x;
     const int dof = R.dof;
+    float4* sph = lds4;
+    int* slot3 = reinterpret_cast<int*>(sph + R.n_move);
     WaveWs ws;
-    ws.frames = lds4;
-    float* wp = reinterpret_cast<float*>(lds4 + TP * 3 * R.n_frames);
+    ws.frames = reinterpret_cast<float4*>(slot3 + ((R.n_move + 3) & ~3));
+    ws.sph = sph;
+    ws.slot3 = slot3;
+    float* wp = reinterpret_cast<float*>(ws.frames + TP * 3 * R.n_slots);
     ws.pk = reinterpret_cast<int*>(wp + 2 * kMaxDof);
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + 2;
-    const bool fixed_hit = static_collision(R, S, nullptr);
-    for (long long e = blockIdx.x; e < n_edges; e += gridDim.x) {
-        int ok = 0;
-        if (!fixed_hit) {
+    stage_spheres(R, sph, slot3);
+    const bool fixed_hit = static_collision(R, S);
+    __syncthreads();
+#if PRRTC_EDGE_SCHED == 2
+    const int xcd = blockIdx.x % kXcds;
+    const long long lo = n_edges * xcd / kXcds, hi = n_edges * (xcd + 1) / kXcds;
+    unsigned long long* my_ctr = &ctr->next[xcd * 8];
+    auto grab = [&]() {
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(my_ctr, (unsigned long long)kEdgeChunk);
+        return lo + (long long)__shfl(v, 0, kWave);
+    };
+    const long long stride = 1, end = hi;
+#elif PRRTC_EDGE_SCHED == 1
+    auto grab = [&]() {
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(&ctr->next[0], (unsigned long long)kEdgeChunk);
+        return (long long)__shfl(v, 0, kWave);
+    };
+    const long long stride = 1, end = n_edges;
+#else
+    long long cursor = (long long)blockIdx.x * kEdgeChunk;
+    auto grab = [&]() {
+        const long long v = cursor;
+        cursor += (long long)gridDim.x * kEdgeChunk;
+        return v;
+    };
+    const long long stride = 1, end = n_edges;
+#endif
+    long long c0 = grab();
+    float ra = 0.0f, rb = 0.0f;
+    if (c0 < end && lane < dof) {
+        ra = A[c0 * dof + lane];
+        rb = Bv[c0 * dof + lane];
+    }
+    while (c0 < end) {
+        const long long c1 = grab();
+        const long long cend = min(c0 + (long long)kEdgeChunk, end);
+        for (long long e = c0; e < cend; e += stride) {
             if (lane < dof) {
-                wp[lane] = A[e * dof + lane];
-                wp[dof + lane] = Bv[e * dof + lane];
+                wp[lane] = ra;
+                wp[dof + lane] = rb;
+            }
+            // prefetch the next edge (next in this chunk, else the next chunk's first)
+            const long long nx = e + 1 < cend ? e + 1 : c1;
+            if (nx < end && lane < dof) {
+                ra = A[nx * dof + lane];
+                rb = Bv[nx * dof + lane];
             }
             __syncthreads();
-            ok = wave_check<TP, B, false>(R, S, wp, 1, 0, res, ws) == 1;
+            const int ok = fixed_hit ? 0 : (wave_check<TP, B, false>(R, S, wp, 1, 0, res, ws) == 1);
+            if (lane == 0) valid[e] = (uint8_t)ok;
+            __syncthreads();
         }
-        if (lane == 0) valid[e] = (uint8_t)ok;
-        __syncthreads();
+        c0 = c1;
+    }
+    if (PRRTC_EDGE_SCHED != 0 && lane == 0) {
+        __threadfence();
+        if (atomicAdd(&ctr->done, 1u) == gridDim.x - 1) {
+            for (int x = 0; x < kXcds; ++x) atomicExch(&ctr->next[x * 8], 0ull);
+            atomicExch(&ctr->done, 0u);
+        }
     }
 }
 
@@ -62,7 +137,7 @@ __global__ __launch_bounds__(kWave) void k_fk_spheres(RobotArgs R, const float* 
     if (cfg >= n) return;
     float4* fr = lds4 + threadIdx.x * 3 * R.n_frames;
     const float* qc = q + cfg * R.dof;
-    fk_frames(R, [&](int j) { return qc[j]; }, fr);
+    fk_frames<true>(R, [&](int j) { return qc[j]; }, fr);
     const int ns = R.n_move + R.n_static;
     for (int s = 0; s < ns; ++s) {
         const float4 loc = R.sph[s];
@@ -102,8 +177,14 @@ struct prrtc_ctx {
     std::vector<RobotRec> robots;
     std::vector<SceneRec> scenes;
     PlannerBuffers plan;
+    EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
+    unsigned counter_next = 0;
+    int edge_grid = 0;                 // resident workgroups of k_check_edges (cached)
+    size_t edge_grid_lds = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
+
+constexpr int kCounterSlots = 256;
 
 namespace {
 
@@ -166,6 +247,8 @@ prrtc_status prrtc_create(prrtc_ctx** out, int device) {
     if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && wall_khz > 0)
         ctx->wall_khz = (double)wall_khz;
     PRRTC_HIP(ctx.get(), hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    PRRTC_HIP(ctx.get(), hipMalloc(&ctx->counters, sizeof(EdgeCounter) * kCounterSlots));
+    PRRTC_HIP(ctx.get(), hipMemset(ctx->counters, 0, sizeof(EdgeCounter) * kCounterSlots));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev0));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev1));
     *out = ctx.release();
@@ -179,6 +262,7 @@ void prrtc_destroy(prrtc_ctx* ctx) {
     for (auto& r : ctx->robots) hipFree(r.mem);
     for (auto& s : ctx->scenes) hipFree(s.mem);
     planner_free(ctx->plan);
+    if (ctx->counters) hipFree(ctx->counters);
     if (ctx->ev0) hipEventDestroy(ctx->ev0);
     if (ctx->ev1) hipEventDestroy(ctx->ev1);
     if (ctx->stream) hipStreamDestroy(ctx->stream);
@@ -243,13 +327,22 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
         if (is_fixed(k)) order.push_back(k);
     std::vector<int> new_of(ns);
     for (int k = 0; k < ns; ++k) new_of[order[k]] = k;
+    // LDS slots for the frames that carry moving spheres
+    int frame_slot[kMaxFrames];
+    for (int f = 0; f < kMaxFrames; ++f) frame_slot[f] = -1;
+    int n_slots = 0;
+    for (int k = 0; k < n_move; ++k) {
+        const int f = d->sphere_frame[order[k]];
+        if (frame_slot[f] < 0) frame_slot[f] = n_slots++;
+    }
     std::vector<float4> sph(ns);
-    std::vector<int> frame(ns), desc(ns);
+    std::vector<int> frame(ns), desc(ns), slot3(ns, 0);
     for (int k = 0; k < ns; ++k) {
         const float* p = d->sphere_xyzr + 4 * order[k];
         sph[k] = make_float4(p[0], p[1], p[2], p[3]);
         frame[k] = d->sphere_frame[order[k]];
         desc[k] = order[k];
+        if (k < n_move) slot3[k] = 3 * frame_slot[frame[k]];
     }
     std::vector<int2> pairs, spairs;
     for (int p = 0; p < np; ++p) {
@@ -259,7 +352,8 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     }
     const size_t o_sph = 0;
     const size_t o_frame = align_up<int>(o_sph + sizeof(float4) * ns);
-    const size_t o_desc = align_up<int>(o_frame + sizeof(int) * ns);
+    const size_t o_slot = align_up<int>(o_frame + sizeof(int) * ns);
+    const size_t o_desc = align_up<int>(o_slot + sizeof(int) * ns);
     const size_t o_pairs = align_up<int>(o_desc + sizeof(int) * ns);
     const size_t o_spairs = align_up<int>(o_pairs + sizeof(int2) * pairs.size());
     const size_t bytes = align_up<int>(o_spairs + sizeof(int2) * spairs.size());
@@ -270,6 +364,7 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     std::vector<char> host(bytes, 0);
     memcpy(host.data() + o_sph, sph.data(), sizeof(float4) * ns);
     memcpy(host.data() + o_frame, frame.data(), sizeof(int) * ns);
+    memcpy(host.data() + o_slot, slot3.data(), sizeof(int) * ns);
     memcpy(host.data() + o_desc, desc.data(), sizeof(int) * ns);
     if (!pairs.empty()) memcpy(host.data() + o_pairs, pairs.data(), sizeof(int2) * pairs.size());
     if (!spairs.empty()) memcpy(host.data() + o_spairs, spairs.data(), sizeof(int2) * spairs.size());
@@ -282,6 +377,8 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     A.n_chains = d->n_chains;
     A.dof = dof;
     A.n_frames = n_frames;
+    A.n_slots = n_slots;
+    for (int f = 0; f < kMaxFrames; ++f) A.frame_slot[f] = frame_slot[f];
     A.n_move = n_move;
     A.n_static = ns - n_move;
     A.n_pairs = (int)pairs.size();
@@ -304,6 +401,7 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     }
     A.sph = reinterpret_cast<const float4*>(base + o_sph);
     A.sph_frame = reinterpret_cast<const int*>(base + o_frame);
+    A.sph_slot = reinterpret_cast<const int*>(base + o_slot);
     A.desc_index = reinterpret_cast<const int*>(base + o_desc);
     A.pairs = reinterpret_cast<const int2*>(base + o_pairs);
     A.static_pairs = reinterpret_cast<const int2*>(base + o_spairs);
@@ -382,11 +480,22 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
 
 namespace {
 
-constexpr int kEdgeTile = 32;
-constexpr int kEdgeItems = 4;
+#ifndef PRRTC_EDGE_TILE
+#define PRRTC_EDGE_TILE 32
+#endif
+#ifndef PRRTC_EDGE_ITEMS
+#define PRRTC_EDGE_ITEMS 4
+#endif
+constexpr int kEdgeTile = PRRTC_EDGE_TILE;
+constexpr int kEdgeItems = PRRTC_EDGE_ITEMS;
+
+size_t sphere_lds_bytes(const RobotArgs& R) {
+    return sizeof(float4) * R.n_move + sizeof(int) * ((R.n_move + 3) & ~3);
+}
 
 size_t check_lds_bytes(const RobotArgs& R, int tp) {
-    return sizeof(float4) * tp * 3 * R.n_frames + sizeof(float) * 2 * kMaxDof + sizeof(int) * (tp + 4);
+    return sphere_lds_bytes(R) + sizeof(float4) * tp * 3 * R.n_slots + sizeof(float) * 2 * kMaxDof +
+           sizeof(int) * (tp + 4);
 }
 
 prrtc_status lookup(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const RobotRec** r,
@@ -419,12 +528,21 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
     if (!(res > 0.0f) || !std::isfinite(res)) return fail(ctx, PRRTC_E_ARG, "res must be finite and > 0");
     if (n_edges == 0) return PRRTC_OK;
     if (!a || !b || !valid) return fail(ctx, PRRTC_E_ARG, "null buffer");
-    hipStream_t sm = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    hipStream_t sm = static_cast<hipStream_t>(stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    const long long grid = std::min<long long>(n_edges, (long long)ctx->n_cu * 16);
     const size_t lds = check_lds_bytes(r->args, kEdgeTile);
+    if (ctx->edge_grid == 0 || ctx->edge_grid_lds != lds) {
+        int per_cu = 0;
+        PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &per_cu, reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems>), kWave, lds));
+        ctx->edge_grid = std::max(1, per_cu) * ctx->n_cu;
+        ctx->edge_grid_lds = lds;
+    }
+    // at least one workgroup per XCD range (empty ranges exit at once)
+    const long long grid = std::max<long long>(std::min<long long>(n_edges, ctx->edge_grid), kXcds);
+    EdgeCounter* ctr = ctx->counters + (ctx->counter_next++ % kCounterSlots);
     hipLaunchKernelGGL((k_check_edges<kEdgeTile, kEdgeItems>), dim3((unsigned)grid), dim3(kWave), lds, sm,
-                       r->args, s->args, a, b, (long long)n_edges, res, valid);
+                       r->args, s->args, a, b, (long long)n_edges, res, valid, ctr);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
 }
@@ -439,7 +557,7 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
     if (n < 0) return fail(ctx, PRRTC_E_ARG, "n < 0");
     if (n == 0) return PRRTC_OK;
     if (!q || !xyz) return fail(ctx, PRRTC_E_ARG, "null buffer");
-    hipStream_t sm = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    hipStream_t sm = static_cast<hipStream_t>(stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     const long long blocks = (n + kWave - 1) / kWave;
     const size_t lds = sizeof(float4) * kWave * 3 * r->args.n_frames;
@@ -543,8 +661,8 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     }
     char* m = static_cast<char*>(ctx->plan.mem);
     PlanArgs A;
-    A.R = RA;
-    A.S = s->args;
+    RobotArgs RA_arg = RA;
+    SceneArgs SA_arg = s->args;
     for (int j = 0; j < kMaxDof; ++j) {
         A.start[j] = j < dof ? start[j] : 0.0f;
         A.goal[j] = j < dof ? goal[j] : 0.0f;
@@ -576,12 +694,12 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     A.path = reinterpret_cast<float*>(m + L.path);
     A.path_idx = reinterpret_cast<int*>(m + L.path_idx);
     A.path_cap = path_cap_dev;
-    const size_t lds = sizeof(float4) * kPlanTile * 3 * RA.n_frames +
+    const size_t lds = sphere_lds_bytes(RA) + sizeof(float4) * kPlanTile * 3 * RA.n_slots +
                        sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) +
                        sizeof(int) * (kPlanTile + 2 * (stage_cap + 2));
     hipStream_t sm = ctx->stream;
     PRRTC_HIP(ctx, hipMemsetAsync(A.ctl, 0, sizeof(int) * kCtlWords, sm));
-    void* kargs[] = {&A};
+    void* kargs[] = {&RA_arg, &SA_arg, &A};
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
     PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
                                               dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));

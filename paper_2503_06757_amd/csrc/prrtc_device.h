@@ -5,10 +5,11 @@
 // steps of a greedy CONNECT, or the segments of a path), Alg. 2 / Sec. III-A.
 // Its lanes first run forward kinematics for a tile of interpolated
 // configurations (one configuration per lane, chain transforms in registers,
-// frames written to LDS), then sweep (configuration, sphere) items against
-// the obstacles.  Obstacle records are indexed only by loop counters, so the
-// compiler keeps them in scalar registers (wave-uniform operands of the
-// vector ALU); a ballot after every obstacle ends the sweep at the first hit.
+// the frames that carry moving spheres written to LDS), then sweep
+// (configuration, sphere) items, configuration-major, against the obstacles.
+// Obstacle records are indexed only by loop counters, so the compiler keeps
+// them in scalar registers (wave-uniform operands of the vector ALU); a ballot
+// after every obstacle ends the sweep at the first hit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,21 +20,32 @@ namespace prrtc {
 constexpr int kMaxDof = 16;
 constexpr int kMaxChains = 2;
 constexpr int kMaxFrames = kMaxDof + kMaxChains;
+constexpr int kMaxSpheres = 256;
 constexpr int kWave = 64;
+
+#ifndef PRRTC_OBS_GROUP
+#define PRRTC_OBS_GROUP 1   // obstacles tested between two ballots
+#endif
+#ifndef PRRTC_ITEM_ORDER
+#define PRRTC_ITEM_ORDER 0  // 0: configuration-major items, 1: sphere-major
+#endif
 
 // Robot tables.  Spheres are re-ordered on load: spheres that move come
 // first (their frame depends on some joint), spheres on a chain's base frame
-// (which never move) after them.
+// (which never move) after them.  Frames that carry a moving sphere get an
+// LDS slot; the others are computed but never stored.
 struct RobotArgs {
-    int n_chains, dof, n_frames;
+    int n_chains, dof, n_frames, n_slots;
     int n_move, n_static;          // spheres [0, n_move) move; [n_move, n_move + n_static) fixed
     int n_pairs, n_static_pairs;   // self pairs with a moving sphere / with two fixed spheres
     int chain_dof[kMaxChains], chain_q0[kMaxChains], chain_f0[kMaxChains];
+    int frame_slot[kMaxFrames];    // LDS slot of a frame, -1 if it carries no moving sphere
     float base[kMaxChains][12];
     float ca[kMaxDof], sa[kMaxDof], a[kMaxDof], d[kMaxDof];  // cos/sin(alpha), a, d per joint
     float lo[kMaxDof], hi[kMaxDof];
     const float4* sph;        // local centre + radius, re-ordered
     const int* sph_frame;     // global frame id, re-ordered
+    const int* sph_slot;      // 3 * frame slot of each moving sphere
     const int2* pairs;        // re-ordered indices
     const int2* static_pairs;
     const int* desc_index;    // re-ordered sphere -> descriptor order
@@ -76,6 +88,17 @@ __device__ inline int edge_count_f32(const float* a, const float* b, int dof, fl
     return (int)x;
 }
 
+// Element `idx` (lane-varying) of a small kernel-argument array, through
+// selects: indexing kernel arguments by a lane-varying value makes the
+// compiler copy the whole argument block to private memory.
+template <int N>
+__device__ inline float pick(const float (&arr)[N], int idx) {
+    float v = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v = (i == idx) ? arr[i] : v;
+    return v;
+}
+
 // ----------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11).
 // ----------------------------------------------------------------------------
@@ -109,12 +132,13 @@ __device__ inline float sample_joint(uint64_t seed, uint32_t query, uint32_t rou
 
 // ----------------------------------------------------------------------------
 // Forward kinematics of one configuration (one lane).  Frame j+1 = frame j *
-// Rx(alpha_j) Tx(a_j) Rz(q_j) Tz(d_j); every frame is written as three float4
-// rows [R | t].  With M = R Rx(alpha):  M0 = R0, M1 = ca R1 + sa R2,
-// M2 = ca R2 - sa R1; new R = (cq M0 + sq M1, cq M1 - sq M0, M2) and
-// new t = t + a R0 + d M2.
+// Rx(alpha_j) Tx(a_j) Rz(q_j) Tz(d_j); a frame is three float4 rows [R | t].
+// With M = R Rx(alpha):  M0 = R0, M1 = ca R1 + sa R2, M2 = ca R2 - sa R1;
+// new R = (cq M0 + sq M1, cq M1 - sq M0, M2) and new t = t + a R0 + d M2.
+// ALL = true stores every frame at 3 * f; otherwise only slotted frames, at
+// 3 * slot.
 // ----------------------------------------------------------------------------
-template <class QF>
+template <bool ALL, class QF>
 __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
     for (int c = 0; c < R.n_chains; ++c) {
         const float* B = R.base[c];
@@ -122,9 +146,15 @@ __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
         float r10 = B[4], r11 = B[5], r12 = B[6], t1 = B[7];
         float r20 = B[8], r21 = B[9], r22 = B[10], t2 = B[11];
         int f = R.chain_f0[c];
-        out[3 * f + 0] = make_float4(r00, r01, r02, t0);
-        out[3 * f + 1] = make_float4(r10, r11, r12, t1);
-        out[3 * f + 2] = make_float4(r20, r21, r22, t2);
+        auto store = [&](int fr) {
+            const int at = ALL ? fr : R.frame_slot[fr];
+            if (at >= 0) {
+                out[3 * at + 0] = make_float4(r00, r01, r02, t0);
+                out[3 * at + 1] = make_float4(r10, r11, r12, t1);
+                out[3 * at + 2] = make_float4(r20, r21, r22, t2);
+            }
+        };
+        store(f);
         const int q0 = R.chain_q0[c];
         for (int jj = 0; jj < R.chain_dof[c]; ++jj) {
             const int j = q0 + jj;
@@ -141,10 +171,7 @@ __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
             r00 = n00; r10 = n10; r20 = n20;
             r01 = n01; r11 = n11; r21 = n21;
             r02 = m0; r12 = m1; r22 = m2;
-            ++f;
-            out[3 * f + 0] = make_float4(r00, r01, r02, t0);
-            out[3 * f + 1] = make_float4(r10, r11, r12, t1);
-            out[3 * f + 2] = make_float4(r20, r21, r22, t2);
+            store(++f);
         }
     }
 }
@@ -192,48 +219,44 @@ __device__ inline bool hit_pair(float4 a, float4 b) {
     return dx * dx + dy * dy + dz * dz < rr * rr;
 }
 
-// Wave-wide minimum of a uniform-result integer.
+// Wave-wide minimum of an integer.
 __device__ inline int wave_min_int(int v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
     return v;
 }
 
+// World position (+ radius) of a sphere on a chain's base frame.
+// (The chain is selected per lane without indexing the kernel-argument
+// tables by a lane-varying value, which would force a private copy.)
+__device__ inline float4 fixed_world(const RobotArgs& R, int s) {
+    const int f = R.sph_frame[s];
+    const bool c1 = R.n_chains > 1 && f >= R.chain_f0[1];
+    float B[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) B[i] = c1 ? R.base[1][i] : R.base[0][i];
+    const float4 p = R.sph[s];
+    return make_float4(B[0] * p.x + B[1] * p.y + B[2] * p.z + B[3],
+                       B[4] * p.x + B[5] * p.y + B[6] * p.z + B[7],
+                       B[8] * p.x + B[9] * p.y + B[10] * p.z + B[11], p.w);
+}
+
 // Does any fixed sphere (or fixed-fixed self pair) collide?  Evaluated once
 // per wave: those spheres are at the same place in every configuration.
-__device__ inline bool static_collision(const RobotArgs& R, const SceneArgs& S, float4* fr_ws) {
+__device__ inline bool static_collision(const RobotArgs& R, const SceneArgs& S) {
     const int lane = threadIdx.x & (kWave - 1);
-    // fixed spheres use their chain's base pose
+    auto world = [&](int s) { return fixed_world(R, s); };
     bool hit = false;
     for (int k = lane; k < R.n_static; k += kWave) {
-        const int s = R.n_move + k;
-        const int f = R.sph_frame[s];
-        const int c = (R.n_chains > 1 && f >= R.chain_f0[1]) ? 1 : 0;
-        const float* B = R.base[c];
-        const float4 p = R.sph[s];
-        const float cx = B[0] * p.x + B[1] * p.y + B[2] * p.z + B[3];
-        const float cy = B[4] * p.x + B[5] * p.y + B[6] * p.z + B[7];
-        const float cz = B[8] * p.x + B[9] * p.y + B[10] * p.z + B[11];
-        for (int o = 0; o < S.n_sph; ++o) hit |= hit_sphere(cx, cy, cz, p.w, S.sph[o]);
-        for (int o = 0; o < S.n_box; ++o) hit |= hit_box(cx, cy, cz, p.w, S.box + 16 * o);
-        for (int o = 0; o < S.n_cyl; ++o) hit |= hit_cyl(cx, cy, cz, p.w, S.cyl + 8 * o);
+        const float4 c = world(R.n_move + k);
+        for (int o = 0; o < S.n_sph; ++o) hit |= hit_sphere(c.x, c.y, c.z, c.w, S.sph[o]);
+        for (int o = 0; o < S.n_box; ++o) hit |= hit_box(c.x, c.y, c.z, c.w, S.box + 16 * o);
+        for (int o = 0; o < S.n_cyl; ++o) hit |= hit_cyl(c.x, c.y, c.z, c.w, S.cyl + 8 * o);
     }
     for (int k = lane; k < R.n_static_pairs; k += kWave) {
         const int2 pr = R.static_pairs[k];
-        float4 cen[2];
-        const int idx[2] = {pr.x, pr.y};
-        for (int m = 0; m < 2; ++m) {
-            const int f = R.sph_frame[idx[m]];
-            const int c = (R.n_chains > 1 && f >= R.chain_f0[1]) ? 1 : 0;
-            const float* B = R.base[c];
-            const float4 p = R.sph[idx[m]];
-            cen[m] = make_float4(B[0] * p.x + B[1] * p.y + B[2] * p.z + B[3],
-                                 B[4] * p.x + B[5] * p.y + B[6] * p.z + B[7],
-                                 B[8] * p.x + B[9] * p.y + B[10] * p.z + B[11], p.w);
-        }
-        hit |= hit_pair(cen[0], cen[1]);
+        hit |= hit_pair(world(pr.x), world(pr.y));
     }
-    (void)fr_ws;
     return __any(hit);
 }
 
@@ -246,22 +269,33 @@ __device__ inline bool static_collision(const RobotArgs& R, const SceneArgs& S, 
 // the first sub-edge with a colliding point, or n_sub when none collides.
 // MULTI = false specialises the single-sub-edge case (any hit ends the call).
 //
-// Workspace (LDS, per wave): frames [TP][n_frames][3] float4, pk [TP] int,
-// sub_n / sub_off [n_sub + 1] int.
+// Workspace (LDS, per wave): frames [TP][n_slots][3] float4, the moving
+// spheres' local records and slot offsets, pk [TP], sub_n / sub_off
+// [n_sub + 1].
 // ----------------------------------------------------------------------------
 struct WaveWs {
     float4* frames;
+    const float4* sph;   // [n_move]
+    const int* slot3;    // [n_move] 3 * frame slot
     int* pk;
     int* sub_n;
     int* sub_off;
 };
 
+// Stage the moving spheres' records in LDS (once per workgroup).
+__device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3) {
+    for (int s = threadIdx.x; s < R.n_move; s += blockDim.x) {
+        sph[s] = R.sph[s];
+        slot3[s] = R.sph_slot[s];
+    }
+}
+
 template <int TP, int B, bool MULTI>
-__device__ int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
+__device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
                           int i_first, float res, const WaveWs& ws) {
     const int lane = threadIdx.x & (kWave - 1);
     const int dof = R.dof;
-    const int fstride = 3 * R.n_frames;
+    const int fstride = 3 * R.n_slots;
     // point counts and prefix offsets, in chunks of 64 sub-edges
     int total = 0;
     for (int k0 = 0; k0 < n_sub; k0 += kWave) {
@@ -272,7 +306,6 @@ __device__ int wave_check(const RobotArgs& R, const SceneArgs& S, const float* w
             ws.sub_n[k] = n;
             cnt = n - i_first + 1;
         }
-        // inclusive scan across the wave
         int incl = cnt;
 #pragma unroll
         for (int off = 1; off < kWave; off <<= 1) {
@@ -291,28 +324,35 @@ __device__ int wave_check(const RobotArgs& R, const SceneArgs& S, const float* w
         if (lane < np) {
             const int g = g0 + lane;
             int k = 0;
-            while (k + 1 < n_sub && ws.sub_off[k + 1] <= g) ++k;
+            if (MULTI)
+                while (k + 1 < n_sub && ws.sub_off[k + 1] <= g) ++k;
             const int i = i_first + (g - ws.sub_off[k]);
             const float t = (float)i / (float)ws.sub_n[k];
             const float* w0 = wp + k * dof;
             const float* w1 = w0 + dof;
             ws.pk[lane] = k;
-            fk_frames(R, [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); },
-                      ws.frames + lane * fstride);
+            fk_frames<false>(R, [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); },
+                             ws.frames + lane * fstride);
         }
         __syncthreads();
-        // ---- (point, sphere) items against the obstacles
+        // ---- (point, sphere) items, point-major, against the obstacles
         const int nitems = np * S_move;
-        for (int base = 0; base < nitems; base += kWave * B) {
+        bool stop = false;
+        for (int base = 0; base < nitems && !stop; base += kWave * B) {
             float cx[B], cy[B], cz[B], cr[B];
             int ck[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int it = min(base + lane + kWave * b, nitems - 1);
-                const int s = it / np;
+#if PRRTC_ITEM_ORDER == 1
+                const int s = it / np;          // sphere-major
                 const int p = it - s * np;
-                const float4 loc = R.sph[s];
-                const float3 c = frame_apply(ws.frames + p * fstride + 3 * R.sph_frame[s], loc.x, loc.y, loc.z);
+#else
+                const int p = it / S_move;      // point-major
+                const int s = it - p * S_move;
+#endif
+                const float4 loc = ws.sph[s];
+                const float3 c = frame_apply(ws.frames + p * fstride + ws.slot3[s], loc.x, loc.y, loc.z);
                 cx[b] = c.x; cy[b] = c.y; cz[b] = c.z; cr[b] = loc.w;
                 ck[b] = MULTI ? ws.pk[p] : 0;
             }
@@ -322,67 +362,87 @@ __device__ int wave_check(const RobotArgs& R, const SceneArgs& S, const float* w
                 for (int b = 0; b < B; ++b) alive |= ck[b] < kmin;
                 if (!__any(alive)) continue;
             }
-            bool done = false;
-            auto on_hit = [&](const bool* h) {
-                // returns true when nothing alive remains in this block
-                if (!MULTI) { kmin = 0; return true; }
+            // One obstacle against the lane's B items.  Returns true when the
+            // block (single sub-edge: the whole check) is decided.
+            auto test = [&](auto&& hit) -> bool {
+                bool any = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const bool h = hit(cx[b], cy[b], cz[b], cr[b]);
+                    any |= MULTI ? (h && ck[b] < kmin) : h;
+                }
+                if (!__any(any)) return false;
+                if (!MULTI) return true;
                 int mk = 0x7fffffff;
 #pragma unroll
                 for (int b = 0; b < B; ++b)
-                    if (h[b] && ck[b] < kmin) mk = min(mk, ck[b]);
+                    if (ck[b] < kmin && hit(cx[b], cy[b], cz[b], cr[b])) mk = min(mk, ck[b]);
                 kmin = min(kmin, wave_min_int(mk));
                 bool alive = false;
 #pragma unroll
                 for (int b = 0; b < B; ++b) alive |= ck[b] < kmin;
                 return !__any(alive);
             };
-            for (int o = 0; o < S.n_sph && !done; ++o) {
-                const float4 ob = S.sph[o];
-                bool h[B], any = false;
+            // obstacles in groups of U between ballots (a tail group re-tests
+            // its last obstacle, which cannot change the verdict)
+            constexpr int U = PRRTC_OBS_GROUP;
+            bool done = false;
+            for (int o = 0; o < S.n_sph && !done; o += U) {
+                float4 ob[U];
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    h[b] = hit_sphere(cx[b], cy[b], cz[b], cr[b], ob);
-                    any |= MULTI ? (h[b] && ck[b] < kmin) : h[b];
-                }
-                if (__any(any)) done = on_hit(h);
-            }
-            for (int o = 0; o < S.n_box && !done; ++o) {
-                const float* ob = S.box + 16 * o;
-                bool h[B], any = false;
+                for (int u = 0; u < U; ++u) ob[u] = S.sph[min(o + u, S.n_sph - 1)];
+                done = test([&](float x, float y, float z, float r) {
+                    bool h = false;
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    h[b] = hit_box(cx[b], cy[b], cz[b], cr[b], ob);
-                    any |= MULTI ? (h[b] && ck[b] < kmin) : h[b];
-                }
-                if (__any(any)) done = on_hit(h);
+                    for (int u = 0; u < U; ++u) h |= hit_sphere(x, y, z, r, ob[u]);
+                    return h;
+                });
             }
-            for (int o = 0; o < S.n_cyl && !done; ++o) {
-                const float* ob = S.cyl + 8 * o;
-                bool h[B], any = false;
+            for (int o = 0; o < S.n_box && !done; o += U) {
+                const float* ob[U];
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    h[b] = hit_cyl(cx[b], cy[b], cz[b], cr[b], ob);
-                    any |= MULTI ? (h[b] && ck[b] < kmin) : h[b];
-                }
-                if (__any(any)) done = on_hit(h);
+                for (int u = 0; u < U; ++u) ob[u] = S.box + 16 * min(o + u, S.n_box - 1);
+                done = test([&](float x, float y, float z, float r) {
+                    bool h = false;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) h |= hit_box(x, y, z, r, ob[u]);
+                    return h;
+                });
             }
-            if (!MULTI && done) break;
+            for (int o = 0; o < S.n_cyl && !done; o += U) {
+                const float* ob[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) ob[u] = S.cyl + 8 * min(o + u, S.n_cyl - 1);
+                done = test([&](float x, float y, float z, float r) {
+                    bool h = false;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) h |= hit_cyl(x, y, z, r, ob[u]);
+                    return h;
+                });
+            }
+            if (!MULTI && done) {
+                kmin = 0;
+                stop = true;
+            }
         }
-        // ---- self-collision pairs: (point, pair) items
+        // ---- self-collision pairs: (point, pair) items, point-major
         if (R.n_pairs > 0 && (MULTI || kmin == n_sub)) {
             const int npi = np * R.n_pairs;
             for (int base = 0; base < npi; base += kWave) {
                 const int it = min(base + lane, npi - 1);
-                const int pr_i = it / np;
-                const int p = it - pr_i * np;
+                const int p = it / R.n_pairs;
+                const int pr_i = it - p * R.n_pairs;
                 const int k = MULTI ? ws.pk[p] : 0;
                 const int2 pr = R.pairs[pr_i];
-                const float4 la = R.sph[pr.x], lb = R.sph[pr.y];
                 const float4* fp = ws.frames + p * fstride;
-                const float3 ca = frame_apply(fp + 3 * R.sph_frame[pr.x], la.x, la.y, la.z);
-                const float3 cb = frame_apply(fp + 3 * R.sph_frame[pr.y], lb.x, lb.y, lb.z);
-                const bool h = hit_pair(make_float4(ca.x, ca.y, ca.z, la.w), make_float4(cb.x, cb.y, cb.z, lb.w)) &&
-                               k < kmin;
+                auto centre = [&](int s) {
+                    if (s >= S_move) return fixed_world(R, s);
+                    const float4 l = ws.sph[s];
+                    const float3 c = frame_apply(fp + ws.slot3[s], l.x, l.y, l.z);
+                    return make_float4(c.x, c.y, c.z, l.w);
+                };
+                const float4 ca = centre(pr.x), cb = centre(pr.y);
+                const bool h = hit_pair(ca, cb) && k < kmin;
                 if (__any(h)) {
                     kmin = min(kmin, wave_min_int(h ? k : 0x7fffffff));
                     if (!MULTI) break;

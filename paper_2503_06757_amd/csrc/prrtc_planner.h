@@ -52,8 +52,6 @@ enum Ctl {
 constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInternal = -7;
 
 struct PlanArgs {
-    RobotArgs R;
-    SceneArgs S;
     float start[kMaxDof], goal[kMaxDof];
     unsigned long long seed;
     unsigned int query;
@@ -159,17 +157,20 @@ __device__ inline int wave_nearest(const float* tq, const unsigned char* blocked
 }
 
 template <int TP, int B>
-__global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
+__global__ __launch_bounds__(kWave) void k_plan(RobotArgs R, SceneArgs S, PlanArgs P) {
     extern __shared__ float4 lds4[];
     const int lane = threadIdx.x;
     const int w = blockIdx.x;
-    const RobotArgs& R = P.R;
     const int dof = R.dof;
     const int cap = P.cap;
     // ---- LDS carve-up
+    float4* sph = lds4;
+    int* slot3 = reinterpret_cast<int*>(sph + R.n_move);
     WaveWs ws;
-    ws.frames = lds4;
-    float* vec = reinterpret_cast<float*>(lds4 + TP * 3 * R.n_frames);
+    ws.frames = reinterpret_cast<float4*>(slot3 + ((R.n_move + 3) & ~3));
+    ws.sph = sph;
+    ws.slot3 = slot3;
+    float* vec = reinterpret_cast<float*>(ws.frames + TP * 3 * R.n_slots);
     float* c_rand = vec;
     float* c_nn = vec + kMaxDof;
     float* c_new = vec + 2 * kMaxDof;
@@ -184,8 +185,8 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
 
     // ---- prologue: roots, endpoint checks
     if (w == 0 && lane < dof) {
-        P.qa[(size_t)lane * cap] = P.start[lane];
-        P.qb[(size_t)lane * cap] = P.goal[lane];
+        P.qa[(size_t)lane * cap] = pick(P.start, lane);
+        P.qb[(size_t)lane * cap] = pick(P.goal, lane);
     }
     if (w == 0 && lane == 0) {
         P.pa[0] = -1;
@@ -195,16 +196,18 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
         ctl[kSizeA] = 1;
         ctl[kSizeB] = 1;
     }
-    const bool fixed_hit = static_collision(R, P.S, nullptr);
+    stage_spheres(R, sph, slot3);
+    const bool fixed_hit = static_collision(R, S);
+    __syncthreads();
     const int n_end_workers = P.W > 1 ? 2 : 1;
     for (int e = w; e < 2; e += n_end_workers) {
-        const float* q = e == 0 ? P.start : P.goal;
         if (lane < dof) {
-            wp[lane] = q[lane];
-            wp[dof + lane] = q[lane];
+            const float v = e == 0 ? pick(P.start, lane) : pick(P.goal, lane);
+            wp[lane] = v;
+            wp[dof + lane] = v;
         }
         __syncthreads();
-        const bool ok = !fixed_hit && wave_check<TP, B, false>(R, P.S, wp, 1, 0, P.res, ws) == 1;
+        const bool ok = !fixed_hit && wave_check<TP, B, false>(R, S, wp, 1, 0, P.res, ws) == 1;
         if (!ok && lane == 0) atomicOr(ctl + kEndpointBad, 1);
         __syncthreads();
     }
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
         const int ns = s_is_a ? na : nb, no = s_is_a ? nb : na;
         // ===== phase A: sample, nearest, extend, connect
         int count = 0, nn = -1, other = -1, conn = 0;
-        if (lane < dof) c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, lane, R.lo[lane], R.hi[lane]);
+        if (lane < dof) c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, lane, pick(R.lo, lane), pick(R.hi, lane));
         __syncthreads();
         nn = wave_nearest(qs, bs, cap, ns, c_rand, dof);
         if (nn >= 0) {
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
                 }
             }
             __syncthreads();
-            const bool ext_ok = wave_check<TP, B, false>(R, P.S, wp, 1, 1, P.res, ws) == 1;
+            const bool ext_ok = wave_check<TP, B, false>(R, S, wp, 1, 1, P.res, ws) == 1;
             my_edges += 1;
             if (ext_ok) {
                 count = 1;
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
                         wp[e] = v;
                     }
                     __syncthreads();
-                    const int K = wave_check<TP, B, true>(R, P.S, wp, n_ext, 1, P.res, ws);
+                    const int K = wave_check<TP, B, true>(R, S, wp, n_ext, 1, P.res, ws);
                     my_edges += min(K + 1, n_ext);
                     count = 1 + min(K, n_ext - 1);
                     conn = K == n_ext;
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(kWave) void k_plan(PlanArgs P) {
                 for (int k = w; k + 1 < len; k += P.W) {
                     if (lane < 2 * dof) wp[lane] = P.path[(size_t)k * dof + lane];
                     __syncthreads();
-                    const bool ok = wave_check<TP, B, false>(R, P.S, wp, 1, 0, P.res_v, ws) == 1;
+                    const bool ok = wave_check<TP, B, false>(R, S, wp, 1, 0, P.res_v, ws) == 1;
                     my_edges += 1;
                     if (!ok && lane == 0) {
                         ctl[kValBad] = 1;
