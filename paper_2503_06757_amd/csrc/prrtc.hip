@@ -65,6 +65,7 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + 2;
     stage_spheres(R, sph, slot3);
+    load_bounds(S, ws);
     const bool fixed_hit = static_collision(R, S);
     __syncthreads();
 #if PRRTC_EDGE_SCHED == 2
@@ -417,8 +418,12 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     ctx->err.clear();
     if (!scene_id || n < 0 || n > PRRTC_MAX_PRIMS || (n > 0 && !p))
         return fail(ctx, PRRTC_E_ARG, "bad scene arguments (n must be in 0..%d)", PRRTC_MAX_PRIMS);
-    std::vector<float4> sph;
+    std::vector<float4> sph, sph_b, box_b, cyl_b;
     std::vector<float> box, cyl;
+    const float margin = 1e-4f;
+    auto bound = [&](const prrtc_prim& q, double rad) {
+        return make_float4(q.c[0], q.c[1], q.c[2], (float)(rad * (1.0 + 1e-6)) + margin);
+    };
     for (int i = 0; i < n; ++i) {
         const prrtc_prim& q = p[i];
         if (!finite_all(q.c, 3) || !finite_all(q.rot, 9) || !finite_all(q.dims, 3))
@@ -426,6 +431,7 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
         if (q.type == 0) {
             if (!(q.dims[0] > 0.0f)) return fail(ctx, PRRTC_E_ARG, "primitive %d: radius <= 0", i);
             sph.push_back(make_float4(q.c[0], q.c[1], q.c[2], q.dims[0]));
+            sph_b.push_back(bound(q, q.dims[0]));
         } else if (q.type == 1 || q.type == 2) {
             if (!orthonormal(q.rot, 3)) return fail(ctx, PRRTC_E_ARG, "primitive %d: rotation not orthonormal", i);
             if (q.type == 1) {
@@ -437,11 +443,14 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
                                        q.rot[2], q.rot[5], q.rot[8],
                                        q.dims[0], q.dims[1], q.dims[2]};
                 box.insert(box.end(), rec, rec + 16);
+                box_b.push_back(bound(q, std::sqrt((double)q.dims[0] * q.dims[0] + (double)q.dims[1] * q.dims[1] +
+                                                   (double)q.dims[2] * q.dims[2])));
             } else {
                 if (!(q.dims[0] > 0.0f && q.dims[1] > 0.0f))
                     return fail(ctx, PRRTC_E_ARG, "primitive %d: cylinder radius/half-height <= 0", i);
                 const float rec[8] = {q.c[0], q.c[1], q.c[2], q.rot[2], q.rot[5], q.rot[8], q.dims[0], q.dims[1]};
                 cyl.insert(cyl.end(), rec, rec + 8);
+                cyl_b.push_back(bound(q, std::sqrt((double)q.dims[0] * q.dims[0] + (double)q.dims[1] * q.dims[1])));
             }
         } else {
             return fail(ctx, PRRTC_E_ARG, "primitive %d: unknown type %d", i, q.type);
@@ -450,7 +459,10 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     const size_t o_sph = 0;
     const size_t o_box = align_up<int>(sizeof(float4) * sph.size());
     const size_t o_cyl = align_up<int>(o_box + sizeof(float) * box.size());
-    const size_t bytes = std::max<size_t>(256, align_up<int>(o_cyl + sizeof(float) * cyl.size()));
+    const size_t o_sb = align_up<int>(o_cyl + sizeof(float) * cyl.size());
+    const size_t o_bb = align_up<int>(o_sb + sizeof(float4) * sph_b.size());
+    const size_t o_cb = align_up<int>(o_bb + sizeof(float4) * box_b.size());
+    const size_t bytes = std::max<size_t>(256, align_up<int>(o_cb + sizeof(float4) * cyl_b.size()));
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     SceneRec rec;
     PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
@@ -458,6 +470,9 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     if (!sph.empty()) memcpy(host.data() + o_sph, sph.data(), sizeof(float4) * sph.size());
     if (!box.empty()) memcpy(host.data() + o_box, box.data(), sizeof(float) * box.size());
     if (!cyl.empty()) memcpy(host.data() + o_cyl, cyl.data(), sizeof(float) * cyl.size());
+    if (!sph_b.empty()) memcpy(host.data() + o_sb, sph_b.data(), sizeof(float4) * sph_b.size());
+    if (!box_b.empty()) memcpy(host.data() + o_bb, box_b.data(), sizeof(float4) * box_b.size());
+    if (!cyl_b.empty()) memcpy(host.data() + o_cb, cyl_b.data(), sizeof(float4) * cyl_b.size());
     hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(rec.mem);
@@ -470,6 +485,9 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     rec.args.sph = reinterpret_cast<const float4*>(base + o_sph);
     rec.args.box = reinterpret_cast<const float*>(base + o_box);
     rec.args.cyl = reinterpret_cast<const float*>(base + o_cyl);
+    rec.args.sph_bnd = reinterpret_cast<const float4*>(base + o_sb);
+    rec.args.box_bnd = reinterpret_cast<const float4*>(base + o_bb);
+    rec.args.cyl_bnd = reinterpret_cast<const float4*>(base + o_cb);
     rec.n = n;
     ctx->scenes.push_back(rec);
     *scene_id = (int32_t)ctx->scenes.size() - 1;
@@ -481,10 +499,10 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
 namespace {
 
 #ifndef PRRTC_EDGE_TILE
-#define PRRTC_EDGE_TILE 32
+#define PRRTC_EDGE_TILE 16
 #endif
 #ifndef PRRTC_EDGE_ITEMS
-#define PRRTC_EDGE_ITEMS 4
+#define PRRTC_EDGE_ITEMS 2
 #endif
 constexpr int kEdgeTile = PRRTC_EDGE_TILE;
 constexpr int kEdgeItems = PRRTC_EDGE_ITEMS;

@@ -27,7 +27,10 @@ constexpr int kWave = 64;
 #define PRRTC_OBS_GROUP 1   // obstacles tested between two ballots
 #endif
 #ifndef PRRTC_ITEM_ORDER
-#define PRRTC_ITEM_ORDER 0  // 0: configuration-major items, 1: sphere-major
+#define PRRTC_ITEM_ORDER 1  // 0: configuration-major items, 1: sphere-major
+#endif
+#ifndef PRRTC_CULL
+#define PRRTC_CULL 1        // block bounding-box culling of obstacles
 #endif
 
 // Robot tables.  Spheres are re-ordered on load: spheres that move come
@@ -55,11 +58,15 @@ struct RobotArgs {
 //   sph: (cx, cy, cz, R)
 //   box: 16 floats: c(3), pad, axis0(3), axis1(3), axis2(3), half-extents(3)
 //   cyl: 8 floats: c(3), unit axis(3), R, half-height
+//   *_bnd: bounding sphere of each primitive, (centre, radius + 1e-4 m)
 struct SceneArgs {
     int n_sph, n_box, n_cyl;
     const float4* sph;
     const float* box;
     const float* cyl;
+    const float4* sph_bnd;
+    const float4* box_bnd;
+    const float4* cyl_bnd;
 };
 
 // ----------------------------------------------------------------------------
@@ -192,24 +199,42 @@ __device__ inline bool hit_sphere(float cx, float cy, float cz, float r, float4 
     return dx * dx + dy * dy + dz * dz < rr * rr;
 }
 
-__device__ inline bool hit_box(float cx, float cy, float cz, float r, const float* o) {
-    const float vx = cx - o[0], vy = cy - o[1], vz = cz - o[2];
-    const float l0 = o[4] * vx + o[5] * vy + o[6] * vz;
-    const float l1 = o[7] * vx + o[8] * vy + o[9] * vz;
-    const float l2 = o[10] * vx + o[11] * vy + o[12] * vz;
-    const float e0 = fmaxf(fabsf(l0) - o[13], 0.0f);
-    const float e1 = fmaxf(fabsf(l1) - o[14], 0.0f);
-    const float e2 = fmaxf(fabsf(l2) - o[15], 0.0f);
+// The scene tables are read-only for the whole launch: reading them through
+// the constant address space lets wave-uniform reads become scalar loads.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const v4f cv4f;
+__device__ inline float4 ld4(const void* base, int i) {
+    const v4f v = ((cv4f*)base)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+struct Box { float4 a, b, c, d; };   // see SceneArgs::box
+struct Cyl { float4 a, b; };         // see SceneArgs::cyl
+__device__ inline float4 ld_sph(const SceneArgs& S, int o) { return ld4(S.sph, o); }
+__device__ inline Box ld_box(const SceneArgs& S, int o) {
+    return Box{ld4(S.box, 4 * o), ld4(S.box, 4 * o + 1), ld4(S.box, 4 * o + 2), ld4(S.box, 4 * o + 3)};
+}
+__device__ inline Cyl ld_cyl(const SceneArgs& S, int o) { return Cyl{ld4(S.cyl, 2 * o), ld4(S.cyl, 2 * o + 1)}; }
+
+__device__ inline bool hit_box(float cx, float cy, float cz, float r, const Box& o) {
+    // o.a = (c, pad), o.b = (ax0, ax1.x), o.c = (ax1.yz, ax2.xy), o.d = (ax2.z, h)
+    const float vx = cx - o.a.x, vy = cy - o.a.y, vz = cz - o.a.z;
+    const float l0 = o.b.x * vx + o.b.y * vy + o.b.z * vz;
+    const float l1 = o.b.w * vx + o.c.x * vy + o.c.y * vz;
+    const float l2 = o.c.z * vx + o.c.w * vy + o.d.x * vz;
+    const float e0 = fmaxf(fabsf(l0) - o.d.y, 0.0f);
+    const float e1 = fmaxf(fabsf(l1) - o.d.z, 0.0f);
+    const float e2 = fmaxf(fabsf(l2) - o.d.w, 0.0f);
     return e0 * e0 + e1 * e1 + e2 * e2 < r * r;
 }
 
-__device__ inline bool hit_cyl(float cx, float cy, float cz, float r, const float* o) {
-    const float vx = cx - o[0], vy = cy - o[1], vz = cz - o[2];
-    const float z = o[3] * vx + o[4] * vy + o[5] * vz;
-    const float wx = vx - z * o[3], wy = vy - z * o[4], wz = vz - z * o[5];
+__device__ inline bool hit_cyl(float cx, float cy, float cz, float r, const Cyl& o) {
+    // o.a = (c, u.x), o.b = (u.yz, R, H)
+    const float vx = cx - o.a.x, vy = cy - o.a.y, vz = cz - o.a.z;
+    const float z = o.a.w * vx + o.b.x * vy + o.b.y * vz;
+    const float wx = vx - z * o.a.w, wy = vy - z * o.b.x, wz = vz - z * o.b.y;
     const float rho = __builtin_amdgcn_sqrtf(wx * wx + wy * wy + wz * wz);
-    const float dr = fmaxf(rho - o[6], 0.0f);
-    const float dz = fmaxf(fabsf(z) - o[7], 0.0f);
+    const float dr = fmaxf(rho - o.b.z, 0.0f);
+    const float dz = fmaxf(fabsf(z) - o.b.w, 0.0f);
     return dr * dr + dz * dz < r * r;
 }
 
@@ -217,6 +242,27 @@ __device__ inline bool hit_pair(float4 a, float4 b) {
     const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
     const float rr = a.w + b.w;
     return dx * dx + dy * dy + dz * dz < rr * rr;
+}
+
+__device__ inline float wave_min_f(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ inline float wave_max_f(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Does an obstacle's bounding sphere b reach the box [lo, hi]?
+__device__ inline bool sphere_meets_box(float4 b, float lx, float ly, float lz, float hx, float hy,
+                                        float hz) {
+    const float dx = fmaxf(fmaxf(lx - b.x, b.x - hx), 0.0f);
+    const float dy = fmaxf(fmaxf(ly - b.y, b.y - hy), 0.0f);
+    const float dz = fmaxf(fmaxf(lz - b.z, b.z - hz), 0.0f);
+    return dx * dx + dy * dy + dz * dz < b.w * b.w;
 }
 
 // Wave-wide minimum of an integer.
@@ -249,9 +295,9 @@ __device__ inline bool static_collision(const RobotArgs& R, const SceneArgs& S) 
     bool hit = false;
     for (int k = lane; k < R.n_static; k += kWave) {
         const float4 c = world(R.n_move + k);
-        for (int o = 0; o < S.n_sph; ++o) hit |= hit_sphere(c.x, c.y, c.z, c.w, S.sph[o]);
-        for (int o = 0; o < S.n_box; ++o) hit |= hit_box(c.x, c.y, c.z, c.w, S.box + 16 * o);
-        for (int o = 0; o < S.n_cyl; ++o) hit |= hit_cyl(c.x, c.y, c.z, c.w, S.cyl + 8 * o);
+        for (int o = 0; o < S.n_sph; ++o) hit |= hit_sphere(c.x, c.y, c.z, c.w, ld_sph(S, o));
+        for (int o = 0; o < S.n_box; ++o) hit |= hit_box(c.x, c.y, c.z, c.w, ld_box(S, o));
+        for (int o = 0; o < S.n_cyl; ++o) hit |= hit_cyl(c.x, c.y, c.z, c.w, ld_cyl(S, o));
     }
     for (int k = lane; k < R.n_static_pairs; k += kWave) {
         const int2 pr = R.static_pairs[k];
@@ -280,7 +326,17 @@ struct WaveWs {
     int* pk;
     int* sub_n;
     int* sub_off;
+    float4 bnd_sph, bnd_box, bnd_cyl;  // per lane: bounds of obstacle `lane` of each type
 };
+
+// Load each lane's first-chunk obstacle bounds (kept in registers).
+__device__ inline void load_bounds(const SceneArgs& S, WaveWs& ws) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    ws.bnd_sph = lane < S.n_sph ? S.sph_bnd[lane] : z;
+    ws.bnd_box = lane < S.n_box ? S.box_bnd[lane] : z;
+    ws.bnd_cyl = lane < S.n_cyl ? S.cyl_bnd[lane] : z;
+}
 
 // Stage the moving spheres' records in LDS (once per workgroup).
 __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3) {
@@ -383,6 +439,47 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 for (int b = 0; b < B; ++b) alive |= ck[b] < kmin;
                 return !__any(alive);
             };
+#if PRRTC_CULL
+            // Axis-aligned box around the block's item spheres; every lane
+            // tests one obstacle's bounding sphere against it, and only the
+            // obstacles that reach the box get exact tests.  The 1e-4 m margin
+            // on the bounding radii keeps culling from changing any verdict.
+            float lx = 3.0e38f, ly = 3.0e38f, lz = 3.0e38f;
+            float hx = -3.0e38f, hy = -3.0e38f, hz = -3.0e38f;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (!MULTI || ck[b] < kmin) {
+                    lx = fminf(lx, cx[b] - cr[b]); hx = fmaxf(hx, cx[b] + cr[b]);
+                    ly = fminf(ly, cy[b] - cr[b]); hy = fmaxf(hy, cy[b] + cr[b]);
+                    lz = fminf(lz, cz[b] - cr[b]); hz = fmaxf(hz, cz[b] + cr[b]);
+                }
+            }
+            lx = wave_min_f(lx); ly = wave_min_f(ly); lz = wave_min_f(lz);
+            hx = wave_max_f(hx); hy = wave_max_f(hy); hz = wave_max_f(hz);
+            bool done = false;
+            auto sweep = [&](int n, const float4* bnd, float4 first, auto&& exact) {
+                for (int c0 = 0; c0 < n && !done; c0 += kWave) {
+                    const int o = c0 + lane;
+                    bool keep = false;
+                    if (o < n) keep = sphere_meets_box(c0 == 0 ? first : bnd[o], lx, ly, lz, hx, hy, hz);
+                    unsigned long long m = __ballot(keep);
+                    while (m && !done) {
+                        const int oi = c0 + (int)__builtin_ctzll(m);
+                        m &= m - 1;
+                        done = test([&](float x, float y, float z, float r) { return exact(x, y, z, r, oi); });
+                    }
+                }
+            };
+            sweep(S.n_sph, S.sph_bnd, ws.bnd_sph, [&](float x, float y, float z, float r, int oi) {
+                return hit_sphere(x, y, z, r, ld_sph(S, oi));
+            });
+            sweep(S.n_box, S.box_bnd, ws.bnd_box, [&](float x, float y, float z, float r, int oi) {
+                return hit_box(x, y, z, r, ld_box(S, oi));
+            });
+            sweep(S.n_cyl, S.cyl_bnd, ws.bnd_cyl, [&](float x, float y, float z, float r, int oi) {
+                return hit_cyl(x, y, z, r, ld_cyl(S, oi));
+            });
+#else
             // obstacles in groups of U between ballots (a tail group re-tests
             // its last obstacle, which cannot change the verdict)
             constexpr int U = PRRTC_OBS_GROUP;
@@ -390,7 +487,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             for (int o = 0; o < S.n_sph && !done; o += U) {
                 float4 ob[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) ob[u] = S.sph[min(o + u, S.n_sph - 1)];
+                for (int u = 0; u < U; ++u) ob[u] = ld_sph(S, min(o + u, S.n_sph - 1));
                 done = test([&](float x, float y, float z, float r) {
                     bool h = false;
 #pragma unroll
@@ -399,9 +496,9 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 });
             }
             for (int o = 0; o < S.n_box && !done; o += U) {
-                const float* ob[U];
+                Box ob[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) ob[u] = S.box + 16 * min(o + u, S.n_box - 1);
+                for (int u = 0; u < U; ++u) ob[u] = ld_box(S, min(o + u, S.n_box - 1));
                 done = test([&](float x, float y, float z, float r) {
                     bool h = false;
 #pragma unroll
@@ -410,9 +507,9 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 });
             }
             for (int o = 0; o < S.n_cyl && !done; o += U) {
-                const float* ob[U];
+                Cyl ob[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) ob[u] = S.cyl + 8 * min(o + u, S.n_cyl - 1);
+                for (int u = 0; u < U; ++u) ob[u] = ld_cyl(S, min(o + u, S.n_cyl - 1));
                 done = test([&](float x, float y, float z, float r) {
                     bool h = false;
 #pragma unroll
@@ -420,6 +517,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     return h;
                 });
             }
+#endif
             if (!MULTI && done) {
                 kmin = 0;
                 stop = true;

@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kWave) void k_plan(RobotArgs R, SceneArgs S, PlanAr
         ctl[kSizeB] = 1;
     }
     stage_spheres(R, sph, slot3);
+    load_bounds(S, ws);
     const bool fixed_hit = static_collision(R, S);
     __syncthreads();
     const int n_end_workers = P.W > 1 ? 2 : 1;
