@@ -157,12 +157,14 @@ namespace {
 
 struct RobotRec {
     RobotArgs args{};
+    RobotArgs* dev_args = nullptr;  // copy of args in device memory
     void* mem = nullptr;
     int dof = 0, n_spheres = 0;
 };
 
 struct SceneRec {
     SceneArgs args{};
+    SceneArgs* dev_args = nullptr;  // copy of args in device memory
     void* mem = nullptr;
     int n = 0;
 };
@@ -260,8 +262,14 @@ void prrtc_destroy(prrtc_ctx* ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    for (auto& r : ctx->robots) hipFree(r.mem);
-    for (auto& s : ctx->scenes) hipFree(s.mem);
+    for (auto& r : ctx->robots) {
+        hipFree(r.mem);
+        hipFree(r.dev_args);
+    }
+    for (auto& s : ctx->scenes) {
+        hipFree(s.mem);
+        hipFree(s.dev_args);
+    }
     planner_free(ctx->plan);
     if (ctx->counters) hipFree(ctx->counters);
     if (ctx->ev0) hipEventDestroy(ctx->ev0);
@@ -351,13 +359,42 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
         if (i >= n_move && j >= n_move) spairs.push_back(make_int2(i, j));
         else pairs.push_back(make_int2(i, j));
     }
+    // Is the whole pair list the complete bipartite set A x B of two disjoint
+    // sphere groups?  Then the kernels test it group against group.
+    std::vector<int> bip_a, bip_b;
+    {
+        std::vector<char> in_a(ns, 0), in_b(ns, 0);
+        std::vector<std::pair<int, int>> all;
+        for (int p = 0; p < np; ++p) {
+            const int i = new_of[d->self_pairs[2 * p]], j = new_of[d->self_pairs[2 * p + 1]];
+            in_a[i] = 1;
+            in_b[j] = 1;
+            all.emplace_back(i, j);
+        }
+        std::sort(all.begin(), all.end());
+        const bool unique = std::adjacent_find(all.begin(), all.end()) == all.end();
+        bool disjoint = true;
+        for (int k = 0; k < ns; ++k) {
+            if (in_a[k] && in_b[k]) disjoint = false;
+            if (in_a[k]) bip_a.push_back(k);
+            if (in_b[k]) bip_b.push_back(k);
+        }
+        if (!(np > 0 && unique && disjoint && (size_t)np == bip_a.size() * bip_b.size())) {
+            bip_a.clear();
+            bip_b.clear();
+        } else {
+            pairs.clear();  // covered group against group
+        }
+    }
     const size_t o_sph = 0;
     const size_t o_frame = align_up<int>(o_sph + sizeof(float4) * ns);
     const size_t o_slot = align_up<int>(o_frame + sizeof(int) * ns);
     const size_t o_desc = align_up<int>(o_slot + sizeof(int) * ns);
     const size_t o_pairs = align_up<int>(o_desc + sizeof(int) * ns);
     const size_t o_spairs = align_up<int>(o_pairs + sizeof(int2) * pairs.size());
-    const size_t bytes = align_up<int>(o_spairs + sizeof(int2) * spairs.size());
+    const size_t o_bipa = align_up<int>(o_spairs + sizeof(int2) * spairs.size());
+    const size_t o_bipb = align_up<int>(o_bipa + sizeof(int) * bip_a.size());
+    const size_t bytes = align_up<int>(o_bipb + sizeof(int) * bip_b.size());
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     RobotRec rec;
     PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
@@ -369,6 +406,8 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     memcpy(host.data() + o_desc, desc.data(), sizeof(int) * ns);
     if (!pairs.empty()) memcpy(host.data() + o_pairs, pairs.data(), sizeof(int2) * pairs.size());
     if (!spairs.empty()) memcpy(host.data() + o_spairs, spairs.data(), sizeof(int2) * spairs.size());
+    if (!bip_a.empty()) memcpy(host.data() + o_bipa, bip_a.data(), sizeof(int) * bip_a.size());
+    if (!bip_b.empty()) memcpy(host.data() + o_bipb, bip_b.data(), sizeof(int) * bip_b.size());
     hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(rec.mem);
@@ -406,8 +445,19 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     A.desc_index = reinterpret_cast<const int*>(base + o_desc);
     A.pairs = reinterpret_cast<const int2*>(base + o_pairs);
     A.static_pairs = reinterpret_cast<const int2*>(base + o_spairs);
+    A.n_bip_a = (int)bip_a.size();
+    A.n_bip_b = (int)bip_b.size();
+    A.bip_a = reinterpret_cast<const int*>(base + o_bipa);
+    A.bip_b = reinterpret_cast<const int*>(base + o_bipb);
     rec.dof = dof;
     rec.n_spheres = ns;
+    e = hipMalloc(&rec.dev_args, sizeof(RobotArgs));
+    if (e == hipSuccess) e = hipMemcpy(rec.dev_args, &rec.args, sizeof(RobotArgs), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(rec.mem);
+        hipFree(rec.dev_args);
+        return fail(ctx, PRRTC_E_HIP, "robot tables: %s", hipGetErrorString(e));
+    }
     ctx->robots.push_back(rec);
     *robot_id = (int32_t)ctx->robots.size() - 1;
     return PRRTC_OK;
@@ -489,6 +539,13 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     rec.args.box_bnd = reinterpret_cast<const float4*>(base + o_bb);
     rec.args.cyl_bnd = reinterpret_cast<const float4*>(base + o_cb);
     rec.n = n;
+    e = hipMalloc(&rec.dev_args, sizeof(SceneArgs));
+    if (e == hipSuccess) e = hipMemcpy(rec.dev_args, &rec.args, sizeof(SceneArgs), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(rec.mem);
+        hipFree(rec.dev_args);
+        return fail(ctx, PRRTC_E_HIP, "scene tables: %s", hipGetErrorString(e));
+    }
     ctx->scenes.push_back(rec);
     *scene_id = (int32_t)ctx->scenes.size() - 1;
     return PRRTC_OK;
@@ -591,8 +648,14 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
 // ----------------------------------------------------------------------------
 namespace {
 
-constexpr int kPlanTile = 32;
-constexpr int kPlanItems = 4;
+#ifndef PRRTC_PLAN_TILE
+#define PRRTC_PLAN_TILE 16
+#endif
+#ifndef PRRTC_PLAN_ITEMS
+#define PRRTC_PLAN_ITEMS 2
+#endif
+constexpr int kPlanTile = PRRTC_PLAN_TILE;
+constexpr int kPlanItems = PRRTC_PLAN_ITEMS;
 
 struct PlanLayout {
     size_t qa, pa, ba, qb, pb, bb, ctl, stage, st, path, path_idx, bytes;
@@ -679,8 +742,8 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     }
     char* m = static_cast<char*>(ctx->plan.mem);
     PlanArgs A;
-    RobotArgs RA_arg = RA;
-    SceneArgs SA_arg = s->args;
+    const RobotArgs* RA_arg = r->dev_args;
+    const SceneArgs* SA_arg = s->dev_args;
     for (int j = 0; j < kMaxDof; ++j) {
         A.start[j] = j < dof ? start[j] : 0.0f;
         A.goal[j] = j < dof ? goal[j] : 0.0f;

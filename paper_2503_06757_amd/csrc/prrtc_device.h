@@ -52,6 +52,11 @@ struct RobotArgs {
     const int2* pairs;        // re-ordered indices
     const int2* static_pairs;
     const int* desc_index;    // re-ordered sphere -> descriptor order
+    // Self pairs forming a complete bipartite set A x B (e.g. all pairs
+    // between two arms) are kept as the two groups instead of a pair list.
+    int n_bip_a, n_bip_b;
+    const int* bip_a;         // re-ordered sphere indices of group A
+    const int* bip_b;
 };
 
 // Scene tables, one array per primitive type.
@@ -521,6 +526,51 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             if (!MULTI && done) {
                 kmin = 0;
                 stop = true;
+            }
+        }
+        // ---- self collision, bipartite groups: per configuration, lanes
+        // hold group A's spheres; group B's spheres (one per lane) are culled
+        // against A's bounding box and the survivors tested against all of A.
+        if (R.n_bip_a > 0 && (MULTI || kmin == n_sub)) {
+            for (int p = 0; p < np; ++p) {
+                const int k = MULTI ? ws.pk[p] : 0;
+                if (k >= kmin) continue;
+                const float4* fp = ws.frames + p * fstride;
+                auto centre = [&](int s) {
+                    if (s >= S_move) return fixed_world(R, s);
+                    const float4 l = ws.sph[s];
+                    const float3 c = frame_apply(fp + ws.slot3[s], l.x, l.y, l.z);
+                    return make_float4(c.x, c.y, c.z, l.w);
+                };
+                bool hit = false;
+                for (int a0 = 0; a0 < R.n_bip_a && !hit; a0 += kWave) {
+                    const bool va = a0 + lane < R.n_bip_a;
+                    const float4 ca = va ? centre(R.bip_a[a0 + lane]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float lx = wave_min_f(va ? ca.x - ca.w : 3.0e38f);
+                    const float ly = wave_min_f(va ? ca.y - ca.w : 3.0e38f);
+                    const float lz = wave_min_f(va ? ca.z - ca.w : 3.0e38f);
+                    const float hx = wave_max_f(va ? ca.x + ca.w : -3.0e38f);
+                    const float hy = wave_max_f(va ? ca.y + ca.w : -3.0e38f);
+                    const float hz = wave_max_f(va ? ca.z + ca.w : -3.0e38f);
+                    for (int b0 = 0; b0 < R.n_bip_b && !hit; b0 += kWave) {
+                        const bool vb = b0 + lane < R.n_bip_b;
+                        const float4 cb = vb ? centre(R.bip_b[b0 + lane]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        const bool keep =
+                            vb && sphere_meets_box(make_float4(cb.x, cb.y, cb.z, cb.w + 1e-4f), lx, ly, lz, hx, hy, hz);
+                        unsigned long long m = __ballot(keep);
+                        while (m && !hit) {
+                            const int j = (int)__builtin_ctzll(m);
+                            m &= m - 1;
+                            const float4 c = make_float4(__shfl(cb.x, j, kWave), __shfl(cb.y, j, kWave),
+                                                         __shfl(cb.z, j, kWave), __shfl(cb.w, j, kWave));
+                            hit = __any(va && hit_pair(ca, c));
+                        }
+                    }
+                }
+                if (hit) {
+                    kmin = k;
+                    if (!MULTI) break;
+                }
             }
         }
         // ---- self-collision pairs: (point, pair) items, point-major

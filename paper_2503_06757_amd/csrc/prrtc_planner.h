@@ -157,7 +157,10 @@ __device__ inline int wave_nearest(const float* tq, const unsigned char* blocked
 }
 
 template <int TP, int B>
-__global__ __launch_bounds__(kWave) void k_plan(RobotArgs R, SceneArgs S, PlanArgs P) {
+__global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp,
+                                                const SceneArgs* __restrict__ Sp, PlanArgs P) {
+    const RobotArgs& R = *Rp;   // resident in device memory: uniform reads are scalar loads
+    const SceneArgs& S = *Sp;
     extern __shared__ float4 lds4[];
     const int lane = threadIdx.x;
     const int w = blockIdx.x;
