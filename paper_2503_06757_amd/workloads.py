@@ -131,6 +131,15 @@ def robot_r14(seed: int = SEED_R7_SPHERES) -> dict:
     )
 
 
+def robot_r14_arm(arm: int, seed: int = SEED_R7_SPHERES) -> dict:
+    """One arm of the dual-arm robot on its own (chain ``arm`` at its base), for
+    per-arm goal sampling."""
+    r7 = robot_r7(seed)
+    r7["name"] = f"R14-arm{arm}"
+    r7["base_pose"] = robot_r14(seed)["base_pose"][arm:arm + 1].copy()
+    return r7
+
+
 def robot_dof(robot: dict) -> int:
     return int(sum(robot["chain_dof"]))
 
@@ -358,3 +367,34 @@ def query_candidates(robot: dict, seed: int, n: int, min_dist: float = 1.0):
         if np.linalg.norm(g - s) >= min_dist:
             out.append((s.astype(np.float32), g.astype(np.float32)))
     return out
+
+
+# ---- shelf queries (14-DoF workload) ------------------------------------------------
+HAND_SPHERES = slice(52, 60)   # the 8 hand-bar spheres of one arm (R7 sphere order)
+SHELF_MARGIN = 0.03
+
+
+def hand_cell(hand_xyz: np.ndarray, margin: float = SHELF_MARGIN) -> int:
+    """Index of the shelf cell whose interior (shrunk by ``margin``) holds the
+    centre of the hand bar (the mean of the hand spheres' centres), or -1.
+    Positions come from the caller's own forward kinematics; whether the hand
+    then fits between the walls is left to the caller's collision check."""
+    centre = np.mean(np.asarray(hand_xyz, np.float64), axis=0)
+    for k, (lo, hi) in enumerate(shelf_cells()):
+        if np.all(centre >= lo + SHELF_WALL / 2 + margin) and np.all(centre <= hi - SHELF_WALL / 2 - margin):
+            return k
+    return -1
+
+
+def shelf_query_candidates(seed: int, n: int, dof_arm: int = 7, limit: float = R7_LIMIT):
+    """Per-arm candidate configurations for one 14-DoF shelf query: ``n``
+    uniform start candidates for the whole robot and ``n`` uniform goal
+    candidates for each arm.  The caller keeps a start whose hands are outside
+    the shelf and, per arm, the first goal candidate whose hand is inside a
+    cell on the arm's own side (y < 0 for arm A, y > 0 for arm B), then checks
+    the combined configurations with its own collision checker."""
+    rng = np.random.default_rng(seed)
+    starts = rng.uniform(-limit, limit, (n, 2 * dof_arm)).astype(np.float32)
+    goals_a = rng.uniform(-limit, limit, (n, dof_arm)).astype(np.float32)
+    goals_b = rng.uniform(-limit, limit, (n, dof_arm)).astype(np.float32)
+    return starts, goals_a, goals_b
