@@ -160,6 +160,11 @@ typedef struct {
     int32_t tree_capacity;   /* nodes per tree, >= 2 */
     float time_budget_ms;    /* <= 0: none.  Checked between rounds on the GPU clock */
     int32_t validate_factor; /* 0 disables the final re-check (default 4) */
+    float dds_radius;        /* dynamic-domain sampling (Sec. III, after Yershova et
+                                al.): a failed extension sets its start node's
+                                sampling radius to this; 0 (default) turns it off */
+    int32_t dds_tries;       /* samples a worker draws per round until one lies
+                                within its nearest node's radius (1..64, default 1) */
 } prrtc_plan_params;
 
 typedef struct {
@@ -172,7 +177,7 @@ typedef struct {
 } prrtc_plan_stats;
 
 /* Fill *p with the defaults above (seed 1, 256 workers, 0.5 rad, 32/rad,
- * 1000 rounds, 65536 nodes, no time budget, factor 4). */
+ * 1000 rounds, 65536 nodes, no time budget, factor 4, no dynamic domain). */
 void prrtc_plan_params_default(prrtc_plan_params *p);
 
 /*

@@ -56,6 +56,8 @@ class PlanParams(C.Structure):
         ("max_rounds", C.c_int32),
         ("tree_capacity", C.c_int32),
         ("validate_factor", C.c_int32),
+        ("dds_radius", C.c_float),
+        ("dds_tries", C.c_int32),
     ]
 
 
@@ -101,6 +103,8 @@ def lib():
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_sample_config.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P, P,
                                         C.c_int32, P]
+        L.orc_sample_config_try.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                            P, P, C.c_int32, P]
         L.orc_plan.argtypes = [P, P, C.c_int32, P, P, P, P, C.c_int32, P, P, C.c_int32]
         L.orc_plan.restype = C.c_int32
         L.orc_path_clearance.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_float, P]
@@ -243,14 +247,15 @@ def sample_config(seed: int, query: int, rnd: int, worker: int, lo, hi) -> np.nd
 
 
 def plan(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=256, delta=0.5, res=32.0,
-         max_rounds=200, tree_capacity=1 << 16, validate_factor=4, n_threads=0):
+         max_rounds=200, tree_capacity=1 << 16, validate_factor=4, dds_radius=0.0, dds_tries=1,
+         n_threads=0):
     """Round replay of the planner.  Returns (status, path (K, dof) or None, stats dict)."""
     p = _prims(prims)
     s = np.ascontiguousarray(start, np.float32)
     g = np.ascontiguousarray(goal, np.float32)
     pp = PlanParams(seed=seed, query=query, workers=workers, delta=delta, res=res,
                     max_rounds=max_rounds, tree_capacity=tree_capacity,
-                    validate_factor=validate_factor)
+                    validate_factor=validate_factor, dds_radius=dds_radius, dds_tries=dds_tries)
     st = PlanStats()
     cap = 4096
     path = np.zeros((cap, rob.dof), np.float32)

@@ -343,12 +343,15 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 /* RANDOM_CONFIG: key = seed (low word, high word); counter = (draw, worker,
- * round, query); u = (word >> 8) * 2^-24; q_j = fmaf(u, hi_j - lo_j, lo_j). */
-void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
-                       const float *lo, const float *hi, int32_t dof, float *out) {
+ * round, query) with draw = attempt * ceil(dof / 4) + block; u = (word >> 8) *
+ * 2^-24; q_j = fmaf(u, hi_j - lo_j, lo_j), joint j from word j % 4 of block
+ * j / 4. */
+void orc_sample_config_try(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
+                           uint32_t attempt, const float *lo, const float *hi, int32_t dof, float *out) {
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t nblk = (uint32_t)(dof + 3) / 4;
     for (int32_t draw = 0; draw * 4 < dof; draw++) {
-        const uint32_t ctr[4] = {(uint32_t)draw, worker, round, query};
+        const uint32_t ctr[4] = {attempt * nblk + (uint32_t)draw, worker, round, query};
         uint32_t w[4];
         orc_philox4x32_10(ctr, key, w);
         for (int m = 0; m < 4 && draw * 4 + m < dof; m++) {
@@ -357,6 +360,11 @@ void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t w
             out[j] = fmaf(u, hi[j] - lo[j], lo[j]);
         }
     }
+}
+
+void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
+                       const float *lo, const float *hi, int32_t dof, float *out) {
+    orc_sample_config_try(seed, query, round, worker, 0, lo, hi, dof, out);
 }
 
 /* ---------------------------------------------------------------------------
@@ -374,6 +382,12 @@ void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t w
  *    the grown tree; the trees connect iff all n_ext steps are valid.
  *  - Staged nodes are appended in worker order.  A worker whose nodes do not
  *    all fit in the tree loses its connection.
+ *  - Dynamic-domain sampling (Yershova et al.; the paper uses it, Sec. III):
+ *    every node carries a radius, infinite at first.  A sample farther from
+ *    its nearest node than that node's radius is rejected and the worker
+ *    draws again (up to dds_tries samples per round); a failed extension sets
+ *    its start node's radius to dds_radius at the commit.  dds_radius = 0
+ *    turns this off.
  *  - The lowest-numbered connected worker gives the path.  Its segments are
  *    re-checked at validate_factor x res (points i = 0..n); on a failure the
  *    failing segment's deeper node is blocked (excluded from nearest
@@ -383,6 +397,7 @@ typedef struct {
     float *q; /* [dof][cap] */
     int32_t *parent;
     uint8_t *blocked;
+    float *radius; /* dynamic-domain radius */
     int32_t size, cap;
 } orc_tree;
 
@@ -390,7 +405,9 @@ static int tree_init(orc_tree *T, int dof, int cap, const float *root) {
     T->q = (float *)calloc((size_t)dof * cap, sizeof(float));
     T->parent = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
     T->blocked = (uint8_t *)calloc((size_t)cap, 1);
-    if (!T->q || !T->parent || !T->blocked) return -1;
+    T->radius = (float *)malloc(sizeof(float) * (size_t)cap);
+    if (!T->q || !T->parent || !T->blocked || !T->radius) return -1;
+    for (int32_t i = 0; i < cap; i++) T->radius[i] = INFINITY;
     T->cap = cap;
     for (int j = 0; j < dof; j++) T->q[(int64_t)j * cap] = root[j];
     T->parent[0] = -1;
@@ -402,6 +419,7 @@ static void tree_free(orc_tree *T) {
     free(T->q);
     free(T->parent);
     free(T->blocked);
+    free(T->radius);
 }
 
 static void tree_get(const orc_tree *T, int dof, int32_t i, float *out) {
@@ -411,6 +429,7 @@ static void tree_get(const orc_tree *T, int dof, int32_t i, float *out) {
 typedef struct {
     float *nodes; /* [stage_cap][dof] */
     int32_t count, nn, other, connected, edges, flagged;
+    int32_t fail_nn; /* node whose extension failed this round, or -1 */
     int32_t last; /* tree index of the last committed node */
 } orc_stage;
 
@@ -426,15 +445,28 @@ static void worker_round(const orc_robot *R, const orc_prim *prims, int32_t n_pr
     st->connected = 0;
     st->edges = 0;
     st->flagged = 0;
-    orc_sample_config(p->seed, p->query, round, w, R->q_lo, R->q_hi, dof, c_rand);
-    st->nn = orc_nearest(Ts->q, Ts->cap, ns, Ts->blocked, c_rand, dof);
+    st->fail_nn = -1;
+    st->nn = -1;
+    const int tries = p->dds_tries > 0 ? p->dds_tries : 1;
+    for (int t = 0; t < tries; t++) {
+        orc_sample_config_try(p->seed, p->query, round, w, (uint32_t)t, R->q_lo, R->q_hi, dof, c_rand);
+        const int32_t nn = orc_nearest(Ts->q, Ts->cap, ns, Ts->blocked, c_rand, dof);
+        if (nn < 0) return;
+        tree_get(Ts, dof, nn, c_nn);
+        /* dynamic domain: reject samples beyond the nearest node's radius */
+        if (p->dds_radius > 0.0f && !(f32_norm_diff(c_nn, c_rand, dof) <= Ts->radius[nn])) continue;
+        st->nn = nn;
+        break;
+    }
     if (st->nn < 0) return;
-    tree_get(Ts, dof, st->nn, c_nn);
     orc_steer(c_nn, c_rand, dof, p->delta, c_new);
     double m = orc_edge_clearance(R, prims, n_prims, c_nn, c_new, p->res, 1, 1);
     st->edges++;
     st->flagged += is_flag(m);
-    if (m < 0.0) return;
+    if (m < 0.0) {
+        st->fail_nn = st->nn;
+        return;
+    }
     memcpy(st->nodes, c_new, sizeof(float) * dof);
     st->count = 1;
     st->other = orc_nearest(To->q, To->cap, no, To->blocked, c_new, dof);
@@ -543,6 +575,7 @@ int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, con
             orc_stage *sw = &stages[w];
             st.edges_checked += sw->edges;
             st.flagged_edges += sw->flagged;
+            if (p->dds_radius > 0.0f && sw->fail_nn >= 0) Ts->radius[sw->fail_nn] = p->dds_radius;
             if (sw->count == 0) continue;
             const int32_t room = Ts->cap - Ts->size;
             const int32_t c = sw->count < room ? sw->count : room;
@@ -552,6 +585,7 @@ int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, con
                     Ts->q[(int64_t)j * Ts->cap + idx] = sw->nodes[(size_t)k * dof + j];
                 Ts->parent[idx] = k == 0 ? sw->nn : idx - 1;
                 Ts->blocked[idx] = 0;
+                Ts->radius[idx] = INFINITY;
             }
             Ts->size += c;
             if (c < sw->count) sw->connected = 0;

@@ -64,6 +64,8 @@ typedef struct {
     int32_t max_rounds;
     int32_t tree_capacity;
     int32_t validate_factor;
+    float dds_radius;  /* dynamic-domain radius after a failed extension; 0 = off */
+    int32_t dds_tries; /* samples drawn per worker and round before giving up */
 } orc_plan_params;
 
 typedef struct {
@@ -113,6 +115,9 @@ void orc_steer(const float *from, const float *to, int32_t dof, float delta, flo
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
                        const float *lo, const float *hi, int32_t dof, float *out);
+/* Sample number `attempt` of a worker in a round (attempt 0 = the above). */
+void orc_sample_config_try(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
+                           uint32_t attempt, const float *lo, const float *hi, int32_t dof, float *out);
 
 int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, const float *start,
                  const float *goal, const orc_plan_params *p, float *path, int32_t path_cap,

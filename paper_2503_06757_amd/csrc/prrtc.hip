@@ -658,7 +658,7 @@ constexpr int kPlanTile = PRRTC_PLAN_TILE;
 constexpr int kPlanItems = PRRTC_PLAN_ITEMS;
 
 struct PlanLayout {
-    size_t qa, pa, ba, qb, pb, bb, ctl, stage, st, path, path_idx, bytes;
+    size_t qa, pa, ba, ra, qb, pb, bb, rb, ctl, stage, st, path, path_idx, bytes;
 };
 
 PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
@@ -668,12 +668,14 @@ PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
     L.qa = take(sizeof(float) * (size_t)dof * cap);
     L.pa = take(sizeof(int) * (size_t)cap);
     L.ba = take((size_t)cap);
+    L.ra = take(sizeof(float) * (size_t)cap);
     L.qb = take(sizeof(float) * (size_t)dof * cap);
     L.pb = take(sizeof(int) * (size_t)cap);
     L.bb = take((size_t)cap);
+    L.rb = take(sizeof(float) * (size_t)cap);
     L.ctl = take(sizeof(int) * kCtlWords);
     L.stage = take(sizeof(float) * (size_t)W * stage_cap * dof);
-    L.st = take(sizeof(int) * 4 * (size_t)W);
+    L.st = take(sizeof(int) * 5 * (size_t)W);
     L.path = take(sizeof(float) * (size_t)path_cap * dof);
     L.path_idx = take(sizeof(int) * (size_t)path_cap);
     L.bytes = o;
@@ -695,6 +697,8 @@ void prrtc_plan_params_default(prrtc_plan_params* p) {
     p->tree_capacity = 65536;
     p->time_budget_ms = 0.0f;
     p->validate_factor = 4;
+    p->dds_radius = 0.0f;
+    p->dds_tries = 1;
 }
 
 prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const float* start,
@@ -720,6 +724,9 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
         return fail(ctx, PRRTC_E_ARG, "tree_capacity must be in 2..2^24");
     if (p.validate_factor < 0 || p.validate_factor > 1024)
         return fail(ctx, PRRTC_E_ARG, "validate_factor must be in 0..1024");
+    if (!(p.dds_radius >= 0.0f) || !std::isfinite(p.dds_radius))
+        return fail(ctx, PRRTC_E_ARG, "dds_radius must be finite and >= 0");
+    if (p.dds_tries < 1 || p.dds_tries > 64) return fail(ctx, PRRTC_E_ARG, "dds_tries must be in 1..64");
     if (!finite_all(start, dof) || !finite_all(goal, dof))
         return fail(ctx, PRRTC_E_ARG, "start/goal not finite");
     const RobotArgs& RA = r->args;
@@ -758,13 +765,17 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     A.cap = cap;
     A.stage_cap = stage_cap;
     A.validate = p.validate_factor;
+    A.dds_radius = p.dds_radius;
+    A.dds_tries = p.dds_tries;
     A.budget_ticks = p.time_budget_ms > 0.0f ? (long long)((double)p.time_budget_ms * ctx->wall_khz) : 0;
     A.qa = reinterpret_cast<float*>(m + L.qa);
     A.pa = reinterpret_cast<int*>(m + L.pa);
     A.ba = reinterpret_cast<unsigned char*>(m + L.ba);
+    A.ra = reinterpret_cast<float*>(m + L.ra);
     A.qb = reinterpret_cast<float*>(m + L.qb);
     A.pb = reinterpret_cast<int*>(m + L.pb);
     A.bb = reinterpret_cast<unsigned char*>(m + L.bb);
+    A.rb = reinterpret_cast<float*>(m + L.rb);
     A.ctl = reinterpret_cast<int*>(m + L.ctl);
     A.stage = reinterpret_cast<float*>(m + L.stage);
     int* sti = reinterpret_cast<int*>(m + L.st);
@@ -772,6 +783,7 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     A.st_nn = sti + W;
     A.st_other = sti + 2 * W;
     A.st_conn = sti + 3 * W;
+    A.st_fail = sti + 4 * W;
     A.path = reinterpret_cast<float*>(m + L.path);
     A.path_idx = reinterpret_cast<int*>(m + L.path_idx);
     A.path_cap = path_cap_dev;

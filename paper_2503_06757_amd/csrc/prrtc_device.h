@@ -128,12 +128,14 @@ __device__ inline uint4 philox4x32_10(uint4 c, uint2 k) {
     return c;
 }
 
-// RANDOM_CONFIG joint j: counter (draw = j / 4, worker, round, query), word j % 4,
+// RANDOM_CONFIG joint j of sample `attempt`: counter (draw, worker, round,
+// query) with draw = attempt * ceil(dof / 4) + j / 4, word j % 4,
 // u = (word >> 8) * 2^-24, q_j = fmaf(u, hi_j - lo_j, lo_j).
 __device__ inline float sample_joint(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
-                                     int j, float lo, float hi) {
+                                     uint32_t attempt, int dof, int j, float lo, float hi) {
 #pragma clang fp contract(off)
-    const uint4 w = philox4x32_10(make_uint4((uint32_t)(j >> 2), worker, round, query),
+    const uint32_t draw = attempt * (uint32_t)((dof + 3) >> 2) + (uint32_t)(j >> 2);
+    const uint4 w = philox4x32_10(make_uint4(draw, worker, round, query),
                                   make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
     const int m = j & 3;
     const uint32_t word = m == 0 ? w.x : (m == 1 ? w.y : (m == 2 ? w.z : w.w));

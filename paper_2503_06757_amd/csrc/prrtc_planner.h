@@ -58,12 +58,14 @@ struct PlanArgs {
     int W;
     float delta, res, res_v;
     int max_rounds, cap, stage_cap, validate;
+    float dds_radius;         // dynamic-domain radius after a failed extension (0: off)
+    int dds_tries;            // samples per worker and round
     long long budget_ticks;   // <= 0: none
-    float* qa; int* pa; unsigned char* ba;
-    float* qb; int* pb; unsigned char* bb;
+    float* qa; int* pa; unsigned char* ba; float* ra;
+    float* qb; int* pb; unsigned char* bb; float* rb;
     int* ctl;
     float* stage;             // [W][stage_cap][dof]
-    int* st_count; int* st_nn; int* st_other; int* st_conn;
+    int* st_count; int* st_nn; int* st_other; int* st_conn; int* st_fail;
     float* path;              // [path_cap][dof]
     int* path_idx;            // [path_cap] tree node index; tree = (k < na ? A : B)
     int path_cap;
@@ -196,6 +198,8 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
         P.pb[0] = -1;
         P.ba[0] = 0;
         P.bb[0] = 0;
+        P.ra[0] = __builtin_inff();
+        P.rb[0] = __builtin_inff();
         ctl[kSizeA] = 1;
         ctl[kSizeB] = 1;
     }
@@ -230,17 +234,28 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
         float* qs = s_is_a ? P.qa : P.qb;
         int* ps = s_is_a ? P.pa : P.pb;
         unsigned char* bs = s_is_a ? P.ba : P.bb;
+        float* rs = s_is_a ? P.ra : P.rb;
         const float* qo = s_is_a ? P.qb : P.qa;
         const unsigned char* bo = s_is_a ? P.bb : P.ba;
         const int ns = s_is_a ? na : nb, no = s_is_a ? nb : na;
         // ===== phase A: sample, nearest, extend, connect
-        int count = 0, nn = -1, other = -1, conn = 0;
-        if (lane < dof) c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, lane, pick(R.lo, lane), pick(R.hi, lane));
-        __syncthreads();
-        nn = wave_nearest(qs, bs, cap, ns, c_rand, dof);
-        if (nn >= 0) {
-            if (lane < dof) c_nn[lane] = qs[(size_t)lane * cap + nn];
+        int count = 0, nn = -1, other = -1, conn = 0, fail = -1;
+        // RANDOM_CONFIG + NEAREST_NEIGHBOR; with dynamic-domain sampling a sample
+        // farther from its nearest node than that node's radius is redrawn
+        for (int t = 0; t < P.dds_tries; ++t) {
+            if (lane < dof)
+                c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof, lane,
+                                            pick(R.lo, lane), pick(R.hi, lane));
             __syncthreads();
+            const int cand = wave_nearest(qs, bs, cap, ns, c_rand, dof);
+            if (cand < 0) break;
+            if (lane < dof) c_nn[lane] = qs[(size_t)lane * cap + cand];
+            __syncthreads();
+            if (P.dds_radius > 0.0f && !(norm_diff_f32(c_nn, c_rand, dof) <= rs[cand])) continue;
+            nn = cand;
+            break;
+        }
+        if (nn >= 0) {
             {
 #pragma clang fp contract(off)
                 const float L = norm_diff_f32(c_nn, c_rand, dof);
@@ -258,6 +273,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
             __syncthreads();
             const bool ext_ok = wave_check<TP, B, false>(R, S, wp, 1, 1, P.res, ws) == 1;
             my_edges += 1;
+            if (!ext_ok) fail = nn;
             if (ext_ok) {
                 count = 1;
                 other = wave_nearest(qo, bo, cap, no, c_new, dof);
@@ -306,6 +322,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
             P.st_nn[w] = nn;
             P.st_other[w] = other;
             P.st_conn[w] = conn;
+            P.st_fail[w] = fail;
         }
         if (!grid_barrier(ctl, P.W)) break;
         // ===== phase B: ordered commit
@@ -346,7 +363,11 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
             for (int k = lane; k < c; k += kWave) {
                 ps[my_base + k] = k == 0 ? nn : my_base + k - 1;
                 bs[my_base + k] = 0;
+                rs[my_base + k] = __builtin_inff();
             }
+            // a failed extension shrinks its start node's domain (same value
+            // from every worker, so the order of these writes does not matter)
+            if (lane == 0 && fail >= 0 && P.dds_radius > 0.0f) rs[fail] = P.dds_radius;
         }
         if (w == 0 && lane == 0) {
             const int new_size = min(cap, ns + running);

@@ -55,6 +55,8 @@ class prrtc_plan_params(C.Structure):
         ("tree_capacity", C.c_int32),
         ("time_budget_ms", C.c_float),
         ("validate_factor", C.c_int32),
+        ("dds_radius", C.c_float),
+        ("dds_tries", C.c_int32),
     ]
 
 

@@ -132,6 +132,33 @@ def test_plan_r14_replay(gpu, orc, r14, k):
     replay_equal(orc, r14, prims, s, g, st, path, stats, seed=7 + k, max_rounds=100)
 
 
+@pytest.mark.parametrize("instance,radius,tries", [(1, 0.1, 4), (4, 0.2, 2), (3, 0.05, 8)])
+def test_plan_r7_dynamic_domain_replay(gpu, orc, r7, instance, radius, tries):
+    P, ctx, _ = gpu
+    prims = W.scene_s12(r7, instance)
+    rid, sid = P.prrtc_load_robot(ctx, r7), P.prrtc_load_scene(ctx, prims)
+    s, g = free_query(orc, orc.OracleRobot(r7), prims, r7, W.SEED_QUERY + instance)
+    say("dynamic domain", instance, radius, tries)
+    kw = dict(seed=21 + instance, max_rounds=300, dds_radius=radius, dds_tries=tries)
+    st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
+    assert st == 0, (st, stats)
+    path_ok(orc, r7, prims, path, s, g)
+    replay_equal(orc, r7, prims, s, g, st, path, stats, **kw)
+
+
+def test_plan_r14_dynamic_domain_replay(gpu, orc, r14):
+    P, ctx, _ = gpu
+    prims = W.scene_mixed(0x53140000, r14, 12)
+    rid, sid = P.prrtc_load_robot(ctx, r14), P.prrtc_load_scene(ctx, prims)
+    s, g = free_query(orc, orc.OracleRobot(r14), prims, r14, W.SEED_QUERY + 100, n=3000)
+    say("dynamic domain R14")
+    kw = dict(seed=7, max_rounds=60, dds_radius=0.15, dds_tries=4)
+    st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
+    if st == 0:
+        path_ok(orc, r14, prims, path, s, g)
+    replay_equal(orc, r14, prims, s, g, st, path, stats, **kw)
+
+
 def test_plan_status_codes(gpu, orc, r7):
     P, ctx, _ = gpu
     prims = W.scene_s12(r7, 0)
@@ -153,7 +180,7 @@ def test_plan_status_codes(gpu, orc, r7):
     assert st2 == 0 and path2.shape[0] == stats["path_len"]
     # argument errors are raised by the binding
     for kw in (dict(workers=0), dict(delta=0.0), dict(res=-1.0), dict(tree_capacity=1),
-               dict(max_rounds=-1)):
+               dict(max_rounds=-1), dict(dds_tries=0), dict(dds_radius=-1.0)):
         with pytest.raises(P.PrrtcError):
             P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
     # a tiny tree fills up; the planner stops cleanly

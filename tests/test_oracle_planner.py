@@ -105,3 +105,32 @@ def test_round_structure_balanced_growth(orc, r7):
             break
         assert stats["rounds"] == rounds
         assert stats["nodes_a"] >= 1 and stats["nodes_b"] >= 1
+
+
+def test_dynamic_domain_off_is_plain_and_on_is_valid(orc, r7):
+    """With the dynamic domain off, extra draws are never used, so any number
+    of tries reproduces the plain planner exactly; with it on, paths stay
+    valid."""
+    rob = orc.OracleRobot(r7)
+    prims = W.scene_s12(r7, 4)
+    s, g = _first_free_query(orc, rob, prims, r7, W.SEED_QUERY + 4)
+    base = orc.plan(rob, prims, s, g, seed=8, workers=32, max_rounds=300)
+    same = orc.plan(rob, prims, s, g, seed=8, workers=32, max_rounds=300, dds_radius=0.0, dds_tries=5)
+    assert base[0] == same[0] == 0 and np.array_equal(base[1], same[1]) and base[2] == same[2]
+    st, path, stats = orc.plan(rob, prims, s, g, seed=8, workers=32, max_rounds=300, dds_radius=0.1,
+                               dds_tries=4)
+    assert st == 0
+    _check_path_properties(orc, rob, prims, path, s, g, 0.5, 32.0)
+
+
+def test_dynamic_domain_shrinks_extensions(orc, r7):
+    """Once a node's radius is set, accepted samples lie within it, so after
+    failures near an enclosed goal the extensions get shorter: with a tiny
+    radius and one try per round, far fewer samples are accepted than drawn."""
+    rob = orc.OracleRobot(r7)
+    prims = W.scene_s64(r7)
+    s, g = _first_free_query(orc, rob, prims, r7, 5)
+    _, _, plain = orc.plan(rob, prims, s, g, seed=4, workers=32, max_rounds=20)
+    _, _, dds = orc.plan(rob, prims, s, g, seed=4, workers=32, max_rounds=20, dds_radius=0.01, dds_tries=1)
+    # rejected samples check no edge
+    assert dds["edges_checked"] < plain["edges_checked"]
