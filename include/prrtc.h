@@ -105,6 +105,10 @@ typedef struct {
 prrtc_status prrtc_load_scene(prrtc_ctx *ctx, const prrtc_prim *prims, int32_t n,
                               int32_t *scene_id);
 
+/* Release a scene's device memory (waits for all work on the device first).
+ * Its id stays retired: later calls naming it return E_STATE. */
+prrtc_status prrtc_unload_scene(prrtc_ctx *ctx, int32_t scene_id);
+
 /*
  * check_edges (Alg. 2 / Sec. III-A).  For edge e with endpoints a_e, b_e:
  *     L = |b_e - a_e| (FP32, squares summed in joint order, no fused
@@ -165,6 +169,10 @@ typedef struct {
                                 sampling radius to this; 0 (default) turns it off */
     int32_t dds_tries;       /* samples a worker draws per round until one lies
                                 within its nearest node's radius (1..64, default 1) */
+    int32_t sampler;         /* 0: uniform (default); 1: learned proposal, see below */
+    int32_t model_id;        /* proposal model for sampler 1; its dof must match */
+    float mix;               /* sampler 1: probability that a draw comes from the
+                                mixture (0..1, default 0.5); 0 gives the uniform plan */
 } prrtc_plan_params;
 
 typedef struct {
@@ -173,11 +181,15 @@ typedef struct {
     int64_t edges_checked;
     int32_t validation_failures;
     int32_t connect_worker;
-    float gpu_ms;            /* device time of the planner launch */
+    float gpu_ms;            /* device time of the launch(es), proposal inference included */
+    int32_t fallback;        /* 1: the proposal's mixture was not finite; uniform draws only */
+    int32_t pad;
+    int64_t learned_samples; /* draws taken from the mixture */
 } prrtc_plan_stats;
 
 /* Fill *p with the defaults above (seed 1, 256 workers, 0.5 rad, 32/rad,
- * 1000 rounds, 65536 nodes, no time budget, factor 4, no dynamic domain). */
+ * 1000 rounds, 65536 nodes, no time budget, factor 4, no dynamic domain,
+ * uniform sampler, model -1, mix 0.5). */
 void prrtc_plan_params_default(prrtc_plan_params *p);
 
 /*
@@ -191,6 +203,84 @@ void prrtc_plan_params_default(prrtc_plan_params *p);
 prrtc_status prrtc_plan(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, const float *start,
                         const float *goal, const prrtc_plan_params *params, float *path,
                         int32_t path_cap, int32_t *path_len, prrtc_plan_stats *stats);
+
+/*
+ * Learned sampling proposal (not in the paper, which samples uniformly; an
+ * addition whose definition follows).  A 16^3 occupancy grid of the scene
+ * (cells of 0.1 m over [-0.8, 0.8]^3; a cell is occupied iff an obstacle lies
+ * closer than its half diagonal to its centre) is embedded linearly to 256
+ * values; with the start and goal scaled to [-1, 1] by the joint limits it
+ * feeds three Linear(256) + GELU layers and a head giving an 8-component
+ * diagonal Gaussian mixture over scaled configurations: per sample
+ * [8 logits | 8 x dof means | 8 x dof log sigmas clamped to [-5, 2]].
+ * Every matrix product rounds its operands to bfloat16 (nearest even) and
+ * accumulates in FP32 on the matrix cores.
+ *
+ * Blob layout (little endian): header {uint32 magic 0x31505250 "PRP1",
+ * uint32 version 1, int32 dof, int32 hidden 256, int32 components 8,
+ * int32 voxels per side 16, int64 adam steps, int32 has_adam, int32 pad},
+ * then the FP32 parameters W_v [4096][256], b_v, W_1 [2 dof + 256][256], b_1,
+ * W_2 [256][256], b_2, W_3, b_3, W_4 [256][8 (1 + 2 dof)], b_4 (weights
+ * [in][out] row-major), then, if has_adam, Adam's first and second moments
+ * in the same layout.
+ */
+/* Copy a proposal to the device.  Non-finite weights are accepted (plans
+ * with such a model fall back to uniform sampling). */
+prrtc_status prrtc_load_proposal(prrtc_ctx *ctx, const void *blob, size_t bytes, int32_t *model_id);
+/* Write the model (with Adam state) to blob.  E_CAPACITY if cap is too small;
+ * *bytes is always set to the size needed.  Synchronises the device. */
+prrtc_status prrtc_save_proposal(prrtc_ctx *ctx, int32_t model_id, void *blob, size_t cap, size_t *bytes);
+/* Occupancy grid of a scene: vox = device uint8 [4096], x fastest.  Async. */
+prrtc_status prrtc_voxelize(prrtc_ctx *ctx, int32_t scene_id, uint8_t *vox, void *stream);
+/* Mixture parameters for n (start, goal) pairs: vox device uint8 [n_scenes][4096],
+ * scene_of device int32 [n] (row of vox per sample), start/goal device float32
+ * [n][dof] in joint units (scaled with robot_id's limits), gmm device float32
+ * [n][8 (1 + 2 dof)].  Async on stream. */
+prrtc_status prrtc_proposal_forward(prrtc_ctx *ctx, int32_t model_id, int32_t robot_id, const uint8_t *vox,
+                                    int32_t n_scenes, const int32_t *scene_of, const float *start,
+                                    const float *goal, int32_t n, float *gmm, void *stream);
+
+/* One training step on a batch whose samples are grouped by scene: samples
+ * scene_start[s] .. scene_start[s+1]-1 belong to scene s (scene_of repeats
+ * that mapping per sample).  All pointers are device memory; waypoint is the
+ * target configuration (joint units). */
+typedef struct {
+    const uint8_t *vox;         /* [n_scenes][4096] */
+    int32_t n_scenes;
+    const int32_t *scene_start; /* [n_scenes + 1] */
+    const int32_t *scene_of;    /* [n] */
+    const float *start, *goal, *waypoint; /* [n][dof] */
+    int32_t n;
+} prrtc_train_batch;
+
+/*
+ * Drawing from a mixture (the planner's learned RANDOM_CONFIG).  All
+ * uniforms are Philox4x32-10 words (key = seed) with counter
+ * (c0, worker, round, query), c0 = 0x80000000 | attempt << 8 | slot, a
+ * range the uniform sampler never uses; u(x) = (x >> 8) 2^-24.  Slot 255:
+ * word 0 decides mixture vs uniform (u < mix, taken at attempt 4t for the
+ * t-th draw of a round) and word 1 picks the component by inverse CDF of
+ * softmax(logits); slot 1 + j/2 gives Box-Muller normals for joints j, j+1
+ * (u1 = ((x >> 8) + 1) 2^-24, u2 = u(y); z = sqrt(-2 ln u1) cos or sin
+ * (2 pi u2) for even or odd j).  Scaled draw x = mu + exp(log sigma) z,
+ * q = lo + (x + 1)(hi - lo) / 2.  The planner tries attempts 4t..4t+3 and
+ * keeps the first draw inside the joint limits, else draws uniformly.
+ *
+ * Test hook: n draws of one (query, round, attempt), draw i as worker i.
+ * gmm: device float32 [8 (1 + 2 dof)] (one row of prrtc_proposal_forward's
+ * output); q: device float32 [n][dof]; inside: device uint8 [n], 1 iff the
+ * draw lies inside the limits.  attempt < 2^23.  Async on stream.
+ */
+prrtc_status prrtc_proposal_sample(prrtc_ctx *ctx, int32_t robot_id, const float *gmm, uint64_t seed,
+                                   uint32_t query, uint32_t round, uint32_t attempt, int32_t n, float *q,
+                                   uint8_t *inside, void *stream);
+
+/* Forward, backward of the batch-mean negative log-likelihood and one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.  loss:
+ * device float32 [1], the batch-mean NLL before the step.  Async; one model
+ * must not be trained on two streams at once. */
+prrtc_status prrtc_train_proposal(prrtc_ctx *ctx, int32_t model_id, int32_t robot_id,
+                                  const prrtc_train_batch *batch, float lr, float *loss, void *stream);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,12 @@ here and implemented identically on the GPU:
   * every matrix product rounds both operands to bfloat16 (round to nearest
     even) and accumulates in high precision, as the kernels do;
   * loss: negative log-likelihood of a scaled waypoint under the mixture,
-    averaged over the batch; Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8).
+    averaged over the batch; Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8);
+  * drawing from the mixture (the learned RANDOM_CONFIG): Philox4x32-10 words
+    with counter (0x80000000 | attempt << 8 | slot, worker, round, query) and
+    key = seed; slot 255 word 0 decides mixture against uniform, word 1 picks
+    the component by inverse CDF of the softmax weights; slot 1 + j // 2 gives
+    the Box-Muller pair of joints j, j + 1.
 """
 from __future__ import annotations
 
@@ -25,6 +30,7 @@ import math
 import numpy as np
 
 from . import clearance as _clearance
+from . import philox as _philox
 
 N_COMP = 8
 HIDDEN = 256
@@ -181,3 +187,45 @@ def mixture_moments(gmm_one):
     mean = np.sum(w[:, None] * mu, axis=0)
     second = np.sum(w[:, None] * (np.exp(2 * logsig) + mu * mu), axis=0)
     return mean, second - mean * mean
+
+
+def _unit(word) -> float:
+    return float(int(word) >> 8) * 2.0 ** -24
+
+
+def _words(seed, query, rnd, worker, attempt, slot):
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    return _philox([0x80000000 | (attempt << 8) | slot, worker, rnd, query], key)
+
+
+def mix_uniform(seed, query, rnd, worker, attempt) -> float:
+    """The uniform compared with the mixing probability (slot 255, word 0)."""
+    return _unit(_words(seed, query, rnd, worker, attempt, 255)[0])
+
+
+def mixture_draw(gmm_row, dof, lo, hi, seed, query, rnd, worker, attempt):
+    """One draw from one sample's mixture, in FP64 after the Philox words.
+    gmm_row = [K logits | K x dof means | K x dof log sigmas] (scaled
+    coordinates).  Returns (q in joint units, component, distance of the
+    component uniform from the nearest inner CDF boundary)."""
+    g = np.asarray(gmm_row, np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    logits = g[:N_COMP]
+    mu = g[N_COMP:N_COMP * (1 + dof)].reshape(N_COMP, dof)
+    ls = g[N_COMP * (1 + dof):N_COMP * (1 + 2 * dof)].reshape(N_COMP, dof)
+    w = np.exp(logits - logits.max())
+    cdf = np.cumsum(w / w.sum())
+    uc = _unit(_words(seed, query, rnd, worker, attempt, 255)[1])
+    comp = next((k for k in range(N_COMP) if uc < cdf[k]), N_COMP - 1)
+    gap = float(np.min(np.abs(uc - cdf[:-1])))
+    q = np.empty(dof)
+    for j in range(dof):
+        wn = _words(seed, query, rnd, worker, attempt, 1 + j // 2)
+        u1 = (float(int(wn[0]) >> 8) + 1.0) * 2.0 ** -24
+        u2 = _unit(wn[1])
+        r = math.sqrt(-2.0 * math.log(u1))
+        z = r * (math.sin(2.0 * math.pi * u2) if j % 2 else math.cos(2.0 * math.pi * u2))
+        x = mu[comp, j] + math.exp(ls[comp, j]) * z
+        q[j] = lo[j] + 0.5 * (x + 1.0) * (hi[j] - lo[j])
+    return q, comp, gap

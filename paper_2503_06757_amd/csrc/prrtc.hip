@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,7 @@
 #include "prrtc.h"
 #include "prrtc_device.h"
 #include "prrtc_planner.h"
+#include "prrtc_proposal.h"
 
 using namespace prrtc;
 
@@ -166,10 +168,57 @@ struct SceneRec {
     SceneArgs args{};
     SceneArgs* dev_args = nullptr;  // copy of args in device memory
     void* mem = nullptr;
+    uint8_t* vox = nullptr;         // occupancy grid, made by the first learned plan
     int n = 0;
 };
 
 }  // namespace
+
+namespace {
+
+constexpr uint32_t kPropMagic = 0x31505250u;  // "PRP1"
+constexpr uint32_t kPropVersion = 1;
+
+struct PropHeader {
+    uint32_t magic, version;
+    int32_t dof, hidden, n_comp, vox;
+    int64_t adam_t;
+    int32_t has_adam, pad;
+};
+
+enum { pWv, pbv, pW1, pb1, pW2, pb2, pW3, pb3, pW4, pb4, pCount };
+
+struct PropLayout {
+    size_t off[pCount + 1];
+    int dof, D0, Cw;
+};
+
+PropLayout prop_layout(int dof) {
+    PropLayout L{};
+    L.dof = dof;
+    L.D0 = 2 * dof + kHidden;
+    L.Cw = kComp * (1 + 2 * dof);
+    const size_t sz[pCount] = {(size_t)kVoxCells * kHidden, kHidden, (size_t)L.D0 * kHidden, kHidden,
+                               (size_t)kHidden * kHidden, kHidden, (size_t)kHidden * kHidden, kHidden,
+                               (size_t)kHidden * L.Cw, (size_t)L.Cw};
+    L.off[0] = 0;
+    for (int i = 0; i < pCount; ++i) L.off[i + 1] = L.off[i] + sz[i];
+    return L;
+}
+
+}  // namespace
+
+struct ModelRec {
+    PropLayout L{};
+    float* mem = nullptr;      // params | grads | adam m | adam v, each L.off[pCount] floats
+    long long adam_t = 0;
+    void* ws = nullptr;        // activation workspace
+    size_t ws_bytes = 0;
+    size_t n() const { return L.off[pCount]; }
+    float* p(int i) { return mem + L.off[i]; }
+    float* g(int i) { return mem + n() + L.off[i]; }
+};
+
 
 struct prrtc_ctx {
     int device = 0;
@@ -180,12 +229,16 @@ struct prrtc_ctx {
     std::vector<RobotRec> robots;
     std::vector<SceneRec> scenes;
     PlannerBuffers plan;
+    std::vector<ModelRec> models;
     EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
     unsigned counter_next = 0;
     int edge_grid = 0;                 // resident workgroups of k_check_edges (cached)
     size_t edge_grid_lds = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float* pinned = nullptr;           // kPinnedFloats of pinned host staging
 };
+
+constexpr int kPinnedFloats = 1024;
 
 constexpr int kCounterSlots = 256;
 
@@ -254,6 +307,7 @@ prrtc_status prrtc_create(prrtc_ctx** out, int device) {
     PRRTC_HIP(ctx.get(), hipMemset(ctx->counters, 0, sizeof(EdgeCounter) * kCounterSlots));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev0));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev1));
+    PRRTC_HIP(ctx.get(), hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), sizeof(float) * kPinnedFloats));
     *out = ctx.release();
     return PRRTC_OK;
 }
@@ -267,13 +321,20 @@ void prrtc_destroy(prrtc_ctx* ctx) {
         hipFree(r.dev_args);
     }
     for (auto& s : ctx->scenes) {
+        if (!s.mem) continue;
         hipFree(s.mem);
         hipFree(s.dev_args);
+        if (s.vox) hipFree(s.vox);
     }
     planner_free(ctx->plan);
+    for (auto& m : ctx->models) {
+        hipFree(m.mem);
+        if (m.ws) hipFree(m.ws);
+    }
     if (ctx->counters) hipFree(ctx->counters);
     if (ctx->ev0) hipEventDestroy(ctx->ev0);
     if (ctx->ev1) hipEventDestroy(ctx->ev1);
+    if (ctx->pinned) hipHostFree(ctx->pinned);
     if (ctx->stream) hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -551,6 +612,21 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     return PRRTC_OK;
 }
 
+prrtc_status prrtc_unload_scene(prrtc_ctx* ctx, int32_t scene_id) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
+        return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
+    SceneRec& rec = ctx->scenes[scene_id];
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    PRRTC_HIP(ctx, hipDeviceSynchronize());
+    PRRTC_HIP(ctx, hipFree(rec.mem));
+    PRRTC_HIP(ctx, hipFree(rec.dev_args));
+    if (rec.vox) PRRTC_HIP(ctx, hipFree(rec.vox));
+    rec = SceneRec{};
+    return PRRTC_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -579,8 +655,8 @@ prrtc_status lookup(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const Ro
         return fail(ctx, PRRTC_E_STATE, "unknown robot id %d", robot_id);
     *r = &ctx->robots[robot_id];
     if (s) {
-        if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size())
-            return fail(ctx, PRRTC_E_STATE, "unknown scene id %d", scene_id);
+        if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
+            return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
         *s = &ctx->scenes[scene_id];
     }
     return PRRTC_OK;
@@ -658,7 +734,7 @@ constexpr int kPlanTile = PRRTC_PLAN_TILE;
 constexpr int kPlanItems = PRRTC_PLAN_ITEMS;
 
 struct PlanLayout {
-    size_t qa, pa, ba, ra, qb, pb, bb, rb, ctl, stage, st, path, path_idx, bytes;
+    size_t qa, pa, ba, ra, qb, pb, bb, rb, ctl, stage, st, path, path_idx, qin, gmm, bytes;
 };
 
 PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
@@ -678,9 +754,17 @@ PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
     L.st = take(sizeof(int) * 5 * (size_t)W);
     L.path = take(sizeof(float) * (size_t)path_cap * dof);
     L.path_idx = take(sizeof(int) * (size_t)path_cap);
+    L.qin = take(sizeof(float) * 2 * kMaxDof + sizeof(int));
+    L.gmm = take(sizeof(float) * kComp * (1 + 2 * kMaxDof));
     L.bytes = o;
     return L;
 }
+
+// Mixture of the learned proposal for one (scene, start, goal): the scene's
+// occupancy grid (made once per scene) and a batch-of-one forward pass, all
+// enqueued on sm.  qin: device staging of [start | goal] and scene row 0.
+prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, SceneRec& s, const float* start,
+                           const float* goal, float* qin, float* gmm, hipStream_t sm);
 
 }  // namespace
 
@@ -699,6 +783,9 @@ void prrtc_plan_params_default(prrtc_plan_params* p) {
     p->validate_factor = 4;
     p->dds_radius = 0.0f;
     p->dds_tries = 1;
+    p->sampler = 0;
+    p->model_id = -1;
+    p->mix = 0.5f;
 }
 
 prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const float* start,
@@ -727,6 +814,14 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     if (!(p.dds_radius >= 0.0f) || !std::isfinite(p.dds_radius))
         return fail(ctx, PRRTC_E_ARG, "dds_radius must be finite and >= 0");
     if (p.dds_tries < 1 || p.dds_tries > 64) return fail(ctx, PRRTC_E_ARG, "dds_tries must be in 1..64");
+    if (p.sampler != 0 && p.sampler != 1) return fail(ctx, PRRTC_E_ARG, "sampler must be 0 or 1");
+    if (p.sampler == 1) {
+        if (!(p.mix >= 0.0f && p.mix <= 1.0f)) return fail(ctx, PRRTC_E_ARG, "mix must be in [0, 1]");
+        if (p.model_id < 0 || p.model_id >= (int32_t)ctx->models.size())
+            return fail(ctx, PRRTC_E_STATE, "unknown model id %d", p.model_id);
+        if (ctx->models[p.model_id].L.dof != r->dof)
+            return fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", ctx->models[p.model_id].L.dof, r->dof);
+    }
     if (!finite_all(start, dof) || !finite_all(goal, dof))
         return fail(ctx, PRRTC_E_ARG, "start/goal not finite");
     const RobotArgs& RA = r->args;
@@ -767,6 +862,8 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     A.validate = p.validate_factor;
     A.dds_radius = p.dds_radius;
     A.dds_tries = p.dds_tries;
+    A.gmm = nullptr;
+    A.mix = p.mix;
     A.budget_ticks = p.time_budget_ms > 0.0f ? (long long)((double)p.time_budget_ms * ctx->wall_khz) : 0;
     A.qa = reinterpret_cast<float*>(m + L.qa);
     A.pa = reinterpret_cast<int*>(m + L.pa);
@@ -791,9 +888,16 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
                        sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) +
                        sizeof(int) * (kPlanTile + 2 * (stage_cap + 2));
     hipStream_t sm = ctx->stream;
+    PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
+    if (p.sampler == 1) {
+        float* gmm = reinterpret_cast<float*>(m + L.gmm);
+        st = plan_proposal(ctx, p.model_id, *r, ctx->scenes[scene_id], start, goal,
+                           reinterpret_cast<float*>(m + L.qin), gmm, sm);
+        if (st != PRRTC_OK) return st;
+        A.gmm = gmm;
+    }
     PRRTC_HIP(ctx, hipMemsetAsync(A.ctl, 0, sizeof(int) * kCtlWords, sm));
     void* kargs[] = {&RA_arg, &SA_arg, &A};
-    PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
     PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
                                               dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
@@ -811,6 +915,9 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
         stats->validation_failures = ctl[kValFails];
         stats->connect_worker = ctl[kStatus] == kStOk ? ctl[kConnWorker] : -1;
         stats->gpu_ms = ms;
+        stats->fallback = ctl[kFallback];
+        stats->learned_samples = (int64_t)((unsigned long long)(unsigned)ctl[kLearnedLo] |
+                                           ((unsigned long long)(unsigned)ctl[kLearnedHi] << 32));
     }
     const int status = ctl[kStatus];
     if (status == kStInternal)
@@ -822,6 +929,286 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     if (len > path_cap) return fail(ctx, PRRTC_E_CAPACITY, "path needs %d nodes, buffer holds %d", len, path_cap);
     PRRTC_HIP(ctx, hipMemcpyAsync(path, A.path, sizeof(float) * (size_t)len * dof, hipMemcpyDeviceToHost, sm));
     PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    return PRRTC_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Learned sampling proposal: model storage, forward, training
+// ----------------------------------------------------------------------------
+struct PropWs {
+    float *E, *dE, *X0, *dX0, *Z1, *H1, *Z2, *H2, *Z3, *H3, *O, *dO, *dZ, *dH, *qh, *nll;
+};
+
+namespace {
+
+std::vector<ModelRec>& models_of(prrtc_ctx* ctx) { return ctx->models; }
+
+prrtc_status prop_workspace(prrtc_ctx* ctx, ModelRec& M, int n, int S, PropWs& W) {
+    const PropLayout& L = M.L;
+    size_t o = 0;
+    size_t offs[16];
+    const size_t cnt[16] = {(size_t)S * kHidden, (size_t)S * kHidden, (size_t)n * L.D0, (size_t)n * L.D0,
+                            (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * kHidden,
+                            (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * L.Cw, (size_t)n * L.Cw,
+                            (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * L.dof, (size_t)n};
+    for (int i = 0; i < 16; ++i) {
+        offs[i] = o;
+        o = align_up<int>(o + sizeof(float) * cnt[i]);
+    }
+    if (M.ws_bytes < o) {
+        if (M.ws) (void)hipFree(M.ws);
+        M.ws = nullptr;
+        M.ws_bytes = 0;
+        PRRTC_HIP(ctx, hipMalloc(&M.ws, o));
+        M.ws_bytes = o;
+    }
+    char* b = static_cast<char*>(M.ws);
+    float** f[16] = {&W.E, &W.dE, &W.X0, &W.dX0, &W.Z1, &W.H1, &W.Z2, &W.H2, &W.Z3, &W.H3, &W.O, &W.dO,
+                     &W.dZ, &W.dH, &W.qh, &W.nll};
+    for (int i = 0; i < 16; ++i) *f[i] = reinterpret_cast<float*>(b + offs[i]);
+    return PRRTC_OK;
+}
+
+inline unsigned blocks(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename TA, bool TA_, bool TB_, bool GELU>
+void gemm(hipStream_t sm, const TA* A, int lda, const float* B, int ldb, const float* bias, float* C, float* Z,
+          int ldc, int M, int N, int K) {
+    dim3 grid(blocks(N, kGemmBN), blocks(M, kGemmBM));
+    hipLaunchKernelGGL((k_gemm_bf16<TA, TA_, TB_, GELU>), grid, dim3(256), 0, sm, A, lda, B, ldb, bias, C, Z, ldc, M,
+                       N, K);
+}
+
+// Forward pass for n samples over S scenes; with q (training) also the NLL
+// and the head gradient.  Returns the mixture in W.O.
+void prop_forward(hipStream_t sm, ModelRec& M, const PropWs& W, const RobotArgs* R_dev, const uint8_t* vox, int S,
+                  const int* scene_of, const float* s, const float* g, const float* q, int n, float* gmm_out) {
+    const PropLayout& L = M.L;
+    // the joint limits inside the device copy of the robot's arguments
+    const char* rb = reinterpret_cast<const char*>(R_dev);
+    const float* lo = reinterpret_cast<const float*>(rb + offsetof(RobotArgs, lo));
+    const float* hi = reinterpret_cast<const float*>(rb + offsetof(RobotArgs, hi));
+    gemm<uint8_t, false, false, false>(sm, vox, kVoxCells, M.p(pWv), kHidden, M.p(pbv), W.E, nullptr, kHidden, S,
+                                       kHidden, kVoxCells);
+    hipLaunchKernelGGL(k_build_x0, dim3(blocks((size_t)n * L.D0, 256)), dim3(256), 0, sm, s, g, q, scene_of, W.E,
+                       lo, hi, n, L.dof, W.X0, W.qh);
+    gemm<float, false, false, true>(sm, W.X0, L.D0, M.p(pW1), kHidden, M.p(pb1), W.H1, W.Z1, kHidden, n, kHidden, L.D0);
+    gemm<float, false, false, true>(sm, W.H1, kHidden, M.p(pW2), kHidden, M.p(pb2), W.H2, W.Z2, kHidden, n, kHidden,
+                                    kHidden);
+    gemm<float, false, false, true>(sm, W.H2, kHidden, M.p(pW3), kHidden, M.p(pb3), W.H3, W.Z3, kHidden, n, kHidden,
+                                    kHidden);
+    gemm<float, false, false, false>(sm, W.H3, kHidden, M.p(pW4), L.Cw, M.p(pb4), W.O, nullptr, L.Cw, n, L.Cw,
+                                     kHidden);
+    hipLaunchKernelGGL(k_gmm_head, dim3(blocks(n, 128)), dim3(128), 0, sm, W.O, n, L.dof, q ? W.qh : nullptr,
+                       gmm_out, W.nll, W.dO, 1.0f / (float)n);
+}
+
+void prop_backward(hipStream_t sm, ModelRec& M, const PropWs& W, const uint8_t* vox, int S, const int* scene_start,
+                   int n) {
+    const PropLayout& L = M.L;
+    // head
+    gemm<float, true, false, false>(sm, W.H3, kHidden, W.dO, L.Cw, nullptr, M.g(pW4), nullptr, L.Cw, kHidden, L.Cw, n);
+    hipLaunchKernelGGL(k_col_sum, dim3(blocks(L.Cw, 128)), dim3(128), 0, sm, W.dO, n, L.Cw, L.Cw, 0, M.g(pb4));
+    gemm<float, false, true, false>(sm, W.dO, L.Cw, M.p(pW4), L.Cw, nullptr, W.dH, nullptr, kHidden, n, kHidden, L.Cw);
+    // hidden layers 3, 2
+    const float* Zs[3] = {W.Z1, W.Z2, W.Z3};
+    const float* Hin[3] = {W.X0, W.H1, W.H2};
+    const int pw[3] = {pW1, pW2, pW3}, pb[3] = {pb1, pb2, pb3};
+    for (int l = 2; l >= 0; --l) {
+        hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks((size_t)n * kHidden, 256)), dim3(256), 0, sm, W.dH, Zs[l], W.dZ,
+                           n * kHidden);
+        const int din = l == 0 ? L.D0 : kHidden;
+        gemm<float, true, false, false>(sm, Hin[l], din, W.dZ, kHidden, nullptr, M.g(pw[l]), nullptr, kHidden, din,
+                                        kHidden, n);
+        hipLaunchKernelGGL(k_col_sum, dim3(blocks(kHidden, 128)), dim3(128), 0, sm, W.dZ, n, kHidden, kHidden, 0,
+                           M.g(pb[l]));
+        float* dIn = l == 0 ? W.dX0 : W.dH;
+        gemm<float, false, true, false>(sm, W.dZ, kHidden, M.p(pw[l]), kHidden, nullptr, dIn, nullptr, din, n, din,
+                                        kHidden);
+    }
+    // embedding of the voxel grid
+    hipLaunchKernelGGL(k_scene_sum, dim3(blocks((size_t)S * kHidden, 256)), dim3(256), 0, sm, W.dX0, L.D0, 2 * L.dof,
+                       scene_start, S, W.dE);
+    gemm<uint8_t, true, false, false>(sm, vox, kVoxCells, W.dE, kHidden, nullptr, M.g(pWv), nullptr, kHidden,
+                                      kVoxCells, kHidden, S);
+    hipLaunchKernelGGL(k_col_sum, dim3(blocks(kHidden, 128)), dim3(128), 0, sm, W.dE, S, kHidden, kHidden, 0,
+                       M.g(pbv));
+}
+
+prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, SceneRec& s, const float* start,
+                           const float* goal, float* qin, float* gmm, hipStream_t sm) {
+    ModelRec& M = ctx->models[model_id];
+    const int dof = r.dof;
+    if (!s.vox) {
+        PRRTC_HIP(ctx, hipMalloc(&s.vox, kVoxCells));
+        hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, sm, s.args, s.vox);
+    }
+    PropWs W;
+    prrtc_status st = prop_workspace(ctx, M, 1, 1, W);
+    if (st != PRRTC_OK) return st;
+    float* host = ctx->pinned;   // the plan synchronises before the staging is reused
+    for (int j = 0; j < dof; ++j) {
+        host[j] = start[j];
+        host[dof + j] = goal[j];
+    }
+    const int zero = 0;
+    memcpy(&host[2 * dof], &zero, sizeof zero);
+    PRRTC_HIP(ctx, hipMemcpyAsync(qin, host, sizeof(float) * (2 * dof + 1), hipMemcpyHostToDevice, sm));
+    prop_forward(sm, M, W, r.dev_args, s.vox, 1, reinterpret_cast<const int*>(qin + 2 * dof), qin, qin + dof, nullptr, 1, gmm);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+prrtc_status prrtc_load_proposal(prrtc_ctx* ctx, const void* blob, size_t bytes, int32_t* model_id) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (!blob || !model_id || bytes < sizeof(PropHeader)) return fail(ctx, PRRTC_E_ARG, "blob too small");
+    PropHeader h;
+    memcpy(&h, blob, sizeof h);
+    if (h.magic != kPropMagic || h.version != kPropVersion) return fail(ctx, PRRTC_E_ARG, "not a proposal blob");
+    if (h.hidden != kHidden || h.n_comp != kComp || h.vox != kVox || h.dof < 1 || h.dof > PRRTC_MAX_DOF)
+        return fail(ctx, PRRTC_E_ARG, "unsupported proposal dimensions");
+    ModelRec M;
+    M.L = prop_layout(h.dof);
+    const size_t n = M.n();
+    const size_t need = sizeof(PropHeader) + sizeof(float) * n * (h.has_adam ? 3 : 1);
+    if (bytes < need) return fail(ctx, PRRTC_E_ARG, "blob holds %zu bytes, needs %zu", bytes, need);
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    PRRTC_HIP(ctx, hipMalloc(&M.mem, sizeof(float) * n * 4));
+    const char* src = static_cast<const char*>(blob) + sizeof(PropHeader);
+    hipError_t e = hipMemcpy(M.mem, src, sizeof(float) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(M.mem + n, 0, sizeof(float) * n * 3);
+    if (e == hipSuccess && h.has_adam)
+        e = hipMemcpy(M.mem + 2 * n, src + sizeof(float) * n, sizeof(float) * n * 2, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(M.mem);
+        return fail(ctx, PRRTC_E_HIP, "proposal upload: %s", hipGetErrorString(e));
+    }
+    M.adam_t = h.has_adam ? h.adam_t : 0;
+    models_of(ctx).push_back(M);
+    *model_id = (int32_t)models_of(ctx).size() - 1;
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_save_proposal(prrtc_ctx* ctx, int32_t model_id, void* blob, size_t cap, size_t* bytes) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (model_id < 0 || model_id >= (int32_t)models_of(ctx).size())
+        return fail(ctx, PRRTC_E_STATE, "unknown model id %d", model_id);
+    if (!bytes) return fail(ctx, PRRTC_E_ARG, "null size");
+    ModelRec& M = models_of(ctx)[model_id];
+    const size_t n = M.n();
+    *bytes = sizeof(PropHeader) + sizeof(float) * n * 3;
+    if (!blob || cap < *bytes) return fail(ctx, PRRTC_E_CAPACITY, "blob needs %zu bytes", *bytes);
+    PropHeader h{kPropMagic, kPropVersion, M.L.dof, kHidden, kComp, kVox, M.adam_t, 1, 0};
+    memcpy(blob, &h, sizeof h);
+    char* dst = static_cast<char*>(blob) + sizeof h;
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    PRRTC_HIP(ctx, hipDeviceSynchronize());
+    PRRTC_HIP(ctx, hipMemcpy(dst, M.mem, sizeof(float) * n, hipMemcpyDeviceToHost));
+    PRRTC_HIP(ctx, hipMemcpy(dst + sizeof(float) * n, M.mem + 2 * n, sizeof(float) * n * 2, hipMemcpyDeviceToHost));
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_voxelize(prrtc_ctx* ctx, int32_t scene_id, uint8_t* vox, void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
+        return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
+    if (!vox) return fail(ctx, PRRTC_E_ARG, "null buffer");
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       ctx->scenes[scene_id].args, vox);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+static prrtc_status prop_common(prrtc_ctx* ctx, int32_t model_id, int32_t robot_id, ModelRec** M,
+                                const RobotArgs** R) {
+    if (model_id < 0 || model_id >= (int32_t)models_of(ctx).size())
+        return fail(ctx, PRRTC_E_STATE, "unknown model id %d", model_id);
+    if (robot_id < 0 || robot_id >= (int32_t)ctx->robots.size())
+        return fail(ctx, PRRTC_E_STATE, "unknown robot id %d", robot_id);
+    *M = &models_of(ctx)[model_id];
+    *R = &ctx->robots[robot_id].args;
+    if ((*R)->dof != (*M)->L.dof) return fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", (*M)->L.dof, (*R)->dof);
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_proposal_forward(prrtc_ctx* ctx, int32_t model_id, int32_t robot_id, const uint8_t* vox,
+                                    int32_t n_scenes, const int32_t* scene_of, const float* start,
+                                    const float* goal, int32_t n, float* gmm, void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    ModelRec* M;
+    const RobotArgs* R;
+    prrtc_status st = prop_common(ctx, model_id, robot_id, &M, &R);
+    if (st != PRRTC_OK) return st;
+    if (n < 0 || n_scenes < 1) return fail(ctx, PRRTC_E_ARG, "bad sizes");
+    if (n == 0) return PRRTC_OK;
+    if (!vox || !scene_of || !start || !goal || !gmm) return fail(ctx, PRRTC_E_ARG, "null buffer");
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = static_cast<hipStream_t>(stream);
+    PropWs W;
+    st = prop_workspace(ctx, *M, n, n_scenes, W);
+    if (st != PRRTC_OK) return st;
+    prop_forward(sm, *M, W, ctx->robots[robot_id].dev_args, vox, n_scenes, scene_of, start, goal, nullptr, n, gmm);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_proposal_sample(prrtc_ctx* ctx, int32_t robot_id, const float* gmm, uint64_t seed,
+                                   uint32_t query, uint32_t round, uint32_t attempt, int32_t n, float* q,
+                                   uint8_t* inside, void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (robot_id < 0 || robot_id >= (int32_t)ctx->robots.size())
+        return fail(ctx, PRRTC_E_STATE, "unknown robot id %d", robot_id);
+    if (n < 0 || attempt > 0x7FFFFFu) return fail(ctx, PRRTC_E_ARG, "bad sizes");
+    if (n == 0) return PRRTC_OK;
+    if (!gmm || !q || !inside) return fail(ctx, PRRTC_E_ARG, "null buffer");
+    const RobotRec& r = ctx->robots[robot_id];
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_gmm_sample, dim3((unsigned)n), dim3(kWave), 0, static_cast<hipStream_t>(stream), gmm,
+                       r.dev_args, seed, query, round, attempt, n, q, inside);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_train_proposal(prrtc_ctx* ctx, int32_t model_id, int32_t robot_id, const prrtc_train_batch* b,
+                                  float lr, float* loss, void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    ModelRec* M;
+    const RobotArgs* R;
+    prrtc_status st = prop_common(ctx, model_id, robot_id, &M, &R);
+    if (st != PRRTC_OK) return st;
+    if (!b || b->n < 1 || b->n_scenes < 1 || !b->vox || !b->scene_start || !b->scene_of || !b->start || !b->goal ||
+        !b->waypoint || !loss)
+        return fail(ctx, PRRTC_E_ARG, "bad training batch");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(ctx, PRRTC_E_ARG, "lr must be > 0");
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t sm = static_cast<hipStream_t>(stream);
+    PropWs W;
+    st = prop_workspace(ctx, *M, b->n, b->n_scenes, W);
+    if (st != PRRTC_OK) return st;
+    prop_forward(sm, *M, W, ctx->robots[robot_id].dev_args, b->vox, b->n_scenes, b->scene_of, b->start, b->goal, b->waypoint, b->n, nullptr);
+    prop_backward(sm, *M, W, b->vox, b->n_scenes, b->scene_start, b->n);
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(kWave), 0, sm, W.nll, b->n, loss);
+    M->adam_t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)M->adam_t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)M->adam_t)));
+    const size_t n = M->n();
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n, 256)), dim3(256), 0, sm, M->mem, M->mem + n, M->mem + 2 * n,
+                       M->mem + 3 * n, n, lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+    PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
 }
 

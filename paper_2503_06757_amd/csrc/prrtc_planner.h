@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "prrtc_device.h"
+#include "prrtc_proposal.h"
 
 namespace prrtc {
 
@@ -45,8 +46,12 @@ enum Ctl {
     kNa,
     kEdgesLo,          // 64-bit edge counter (two words)
     kEdgesHi,
+    kLearnedLo,        // 64-bit count of draws taken from the learned mixture
+    kLearnedHi,
+    kFallback,         // 1: the mixture was not finite, uniform sampling used         // 1: the mixture was not finite, uniform sampling used
     kCtlWords = 96
 };
+static_assert(kEdgesLo % 2 == 0 && kLearnedLo % 2 == 0, "64-bit counters need 8-byte alignment");
 
 // Status codes written by the kernel (mirror prrtc_status).
 constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInternal = -7;
@@ -60,6 +65,8 @@ struct PlanArgs {
     int max_rounds, cap, stage_cap, validate;
     float dds_radius;         // dynamic-domain radius after a failed extension (0: off)
     int dds_tries;            // samples per worker and round
+    const float* gmm;         // learned mixture [K (1 + 2 dof)] or null (uniform sampling)
+    float mix;                // probability of drawing from the mixture
     long long budget_ticks;   // <= 0: none
     float* qa; int* pa; unsigned char* ba; float* ra;
     float* qb; int* pb; unsigned char* bb; float* rb;
@@ -187,6 +194,8 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
     __shared__ int sh_i[8];
     int* ctl = P.ctl;
     long long my_edges = 0;
+    long long my_learned = 0;
+    __shared__ float gmm_s[kComp * (1 + 2 * kMaxDof)];
 
     // ---- prologue: roots, endpoint checks
     if (w == 0 && lane < dof) {
@@ -205,6 +214,13 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
     }
     stage_spheres(R, sph, slot3);
     load_bounds(S, ws);
+    bool use_gmm = false;
+    if (P.gmm) {
+        for (int t = lane; t < kComp * (1 + 2 * dof); t += kWave) gmm_s[t] = P.gmm[t];
+        __syncthreads();
+        use_gmm = gmm_finite(gmm_s, dof);
+        if (!use_gmm && w == 0 && lane == 0) ctl[kFallback] = 1;
+    }
     const bool fixed_hit = static_collision(R, S);
     __syncthreads();
     const int n_end_workers = P.W > 1 ? 2 : 1;
@@ -243,7 +259,21 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
         // RANDOM_CONFIG + NEAREST_NEIGHBOR; with dynamic-domain sampling a sample
         // farther from its nearest node than that node's radius is redrawn
         for (int t = 0; t < P.dds_tries; ++t) {
-            if (lane < dof)
+            // learned: with probability mix, up to 4 mixture draws (attempts
+            // 4t..4t+3) until one lies inside the limits, else the uniform draw
+            bool drawn = false;
+            if (use_gmm && mix_uniform(P.seed, P.query, (unsigned)round, (unsigned)w, 4u * t) < P.mix) {
+                const float lo_j = lane < dof ? pick(R.lo, lane) : 0.0f;
+                const float hi_j = lane < dof ? pick(R.hi, lane) : 0.0f;
+                for (int a = 0; a < 4 && !drawn; ++a) {
+                    float v = 0.0f;
+                    drawn = gmm_draw(gmm_s, dof, lo_j, hi_j, P.seed, P.query, (unsigned)round, (unsigned)w,
+                                     4u * t + a, lane, &v);
+                    if (drawn && lane < dof) c_rand[lane] = v;
+                }
+                my_learned += drawn;
+            }
+            if (!drawn && lane < dof)
                 c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof, lane,
                                             pick(R.lo, lane), pick(R.hi, lane));
             __syncthreads();
@@ -450,6 +480,8 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
         }
     }
     if (lane == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
+    if (lane == 0 && my_learned)
+        atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kLearnedLo), (unsigned long long)my_learned);
     if (w == 0 && lane == 0) {
         ctl[kRounds] = round;
         if (ctl[kAbort]) ctl[kStatus] = kStInternal;

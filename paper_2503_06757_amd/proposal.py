@@ -1,0 +1,325 @@
+"""Learned sampling proposal: weight initialisation, blob packing and the
+training driver.  Every arithmetic step of the model runs in libprrtc's
+kernels; this module only prepares arrays and calls the C ABI."""
+from __future__ import annotations
+
+import math
+import struct
+import time
+
+import numpy as np
+
+N_COMP = 8
+HIDDEN = 256
+VOX = 16
+MAGIC, VERSION = 0x31505250, 1
+PARAM_ORDER = ("Wv", "bv", "W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+HEADER = struct.Struct("<IIiiiiqii")
+
+
+def param_shapes(dof: int) -> dict:
+    c = N_COMP * (1 + 2 * dof)
+    return dict(Wv=(VOX ** 3, HIDDEN), bv=(HIDDEN,), W1=(2 * dof + HIDDEN, HIDDEN), b1=(HIDDEN,),
+                W2=(HIDDEN, HIDDEN), b2=(HIDDEN,), W3=(HIDDEN, HIDDEN), b3=(HIDDEN,), W4=(HIDDEN, c), b4=(c,))
+
+
+def init_params(dof: int, seed: int) -> dict:
+    """He-normal hidden weights (GELU), a small head, zero biases; seeded."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for k, shp in param_shapes(dof).items():
+        if len(shp) == 1:
+            out[k] = np.zeros(shp, np.float32)
+        else:
+            std = math.sqrt(2.0 / shp[0]) * (0.1 if k == "W4" else 1.0)
+            if k == "Wv":
+                std = math.sqrt(1.0 / 64.0)  # sparse binary input: ~64 occupied cells
+            out[k] = (rng.standard_normal(shp) * std).astype(np.float32)
+    return out
+
+
+def pack(params: dict, dof: int, m: dict | None = None, v: dict | None = None, adam_t: int = 0) -> bytes:
+    has = m is not None and v is not None
+    parts = [HEADER.pack(MAGIC, VERSION, dof, HIDDEN, N_COMP, VOX, adam_t, int(has), 0)]
+    for group in ([params] + ([m, v] if has else [])):
+        for k in PARAM_ORDER:
+            parts.append(np.ascontiguousarray(group[k], np.float32).tobytes())
+    return b"".join(parts)
+
+
+def unpack(blob: bytes):
+    magic, ver, dof, hid, nc, vox, adam_t, has, _ = HEADER.unpack_from(blob, 0)
+    assert magic == MAGIC and ver == VERSION and hid == HIDDEN and nc == N_COMP and vox == VOX
+    shapes = param_shapes(dof)
+    off = HEADER.size
+    groups = []
+    for _ in range(3 if has else 1):
+        g = {}
+        for k in PARAM_ORDER:
+            n = int(np.prod(shapes[k]))
+            g[k] = np.frombuffer(blob, np.float32, n, off).reshape(shapes[k]).copy()
+            off += 4 * n
+        groups.append(g)
+    return dof, adam_t, groups
+
+
+def resample_path(path: np.ndarray, step: float = 0.25) -> np.ndarray:
+    """Waypoints every `step` rad of arclength along a path, endpoints excluded
+    (training targets)."""
+    p = np.asarray(path, np.float64)
+    seg = np.linalg.norm(np.diff(p, axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    total = cum[-1]
+    out = []
+    t = step
+    while t < total - 1e-9:
+        i = min(int(np.searchsorted(cum, t, side="right")) - 1, len(seg) - 1)
+        f = (t - cum[i]) / seg[i] if seg[i] > 0 else 0.0
+        out.append(p[i] + f * (p[i + 1] - p[i]))
+        t += step
+    return np.array(out, np.float32).reshape(-1, p.shape[1])
+
+
+# ---- training data, training and evaluation (drives the C ABI; needs a GPU) ----------
+SEED_TRAIN = 0x54000000      # + scene index: training scenes
+SEED_EVAL = 0x55000000       # + scene index: held-out scenes
+
+
+def scene(robot: dict, index: int, base: int = SEED_TRAIN) -> np.ndarray:
+    """Scene `index` of a family: U{8..128} obstacles, spheres/cuboids/cylinders 6:4:2."""
+    from . import workloads as W
+    n = int(np.random.default_rng(base + index).integers(8, 129))
+    return W.scene_mixed(base + index, robot, n)
+
+
+def free_query(P, ctx, torch, rid: int, sid: int, robot: dict, seed: int, n_cand: int = 64):
+    """First generated (start, goal) whose endpoints the GPU collision check
+    accepts (each configuration checked as a zero-length edge), or None."""
+    from . import workloads as W
+    cands = W.query_candidates(robot, seed, n_cand)
+    q = torch.from_numpy(np.stack([c for pair in cands for c in pair]).astype(np.float32)).cuda()
+    ok = torch.zeros(q.shape[0], dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, q.data_ptr(), q.data_ptr(), q.shape[0], 32.0, ok.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    ok = ok.cpu().numpy().reshape(-1, 2)
+    for (s, g), (a, b) in zip(cands, ok):
+        if a and b:
+            return s, g
+    return None
+
+
+class Dataset:
+    """Waypoint targets grouped by scene: vox [S][4096] (host uint8), and per
+    sample scene index, start, goal and waypoint."""
+
+    def __init__(self, dof):
+        self.dof = dof
+        self.vox, self.queries, self.paths = [], [], []
+        self.scene_of, self.start, self.goal, self.waypoint = [], [], [], []
+
+    def finish(self):
+        d = self.dof
+        self.vox = np.stack(self.vox) if self.vox else np.zeros((0, VOX ** 3), np.uint8)
+        self.scene_of = np.asarray(self.scene_of, np.int32)
+        self.start = np.asarray(self.start, np.float32).reshape(-1, d)
+        self.goal = np.asarray(self.goal, np.float32).reshape(-1, d)
+        self.waypoint = np.asarray(self.waypoint, np.float32).reshape(-1, d)
+        return self
+
+
+def generate(P, ctx, torch, rid: int, robot: dict, n_scenes: int, base: int = SEED_TRAIN, max_rounds: int = 2000,
+             log=None) -> Dataset:
+    """Solve one query per scene with the uniform planner and keep the path's
+    waypoints every 0.25 rad (endpoints excluded).  Scenes without a free
+    query or a solution contribute no samples."""
+    dof = int(np.asarray(robot["q_lo"]).shape[0])
+    ds = Dataset(dof)
+    vox = torch.zeros(VOX ** 3, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for i in range(n_scenes):
+        prims = scene(robot, i, base)
+        sid = P.prrtc_load_scene(ctx, prims)
+        q = free_query(P, ctx, torch, rid, sid, robot, base + i)
+        path = None
+        if q is not None:
+            p = P.prrtc_plan_params_default()
+            p.seed, p.max_rounds = base + i, max_rounds
+            st, path, _ = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
+            if st != P.PRRTC_OK:
+                path = None
+        if path is not None:
+            P.prrtc_voxelize(ctx, sid, vox.data_ptr(), stream)
+            k = len(ds.vox)
+            ds.vox.append(vox.cpu().numpy().copy())
+            ds.queries.append(q)
+            ds.paths.append(path)
+            for w in resample_path(path):
+                ds.scene_of.append(k)
+                ds.start.append(q[0])
+                ds.goal.append(q[1])
+                ds.waypoint.append(w)
+        P.prrtc_unload_scene(ctx, sid)
+        if log and (i + 1) % 1000 == 0:
+            log("  %d/%d scenes, %d solved, %d samples" % (i + 1, n_scenes, len(ds.vox), len(ds.scene_of)))
+    return ds.finish()
+
+
+def train(P, ctx, torch, mid: int, rid: int, ds: Dataset, epochs: int, batch: int = 256, lr: float = 1e-3,
+          seed: int = 0, log=None) -> np.ndarray:
+    """Adam on the mean NLL.  Each epoch shuffles the scenes and cuts them into
+    batches of whole scenes holding at least `batch` samples; every batch is
+    a contiguous slice of arrays uploaded once per epoch.  Returns the mean
+    loss of each epoch."""
+    rng = np.random.default_rng(seed)
+    n_sc = ds.vox.shape[0]
+    counts = np.bincount(ds.scene_of, minlength=n_sc)
+    first = np.concatenate([[0], np.cumsum(counts)])
+    order_in = np.argsort(ds.scene_of, kind="stable")
+    stream = torch.cuda.current_stream().cuda_stream
+    out = []
+    for ep in range(epochs):
+        perm = rng.permutation(np.nonzero(counts)[0])
+        idx = np.concatenate([order_in[first[s]:first[s + 1]] for s in perm])
+        # batches: consecutive scenes of perm
+        cuts, acc = [0], 0
+        for j, s in enumerate(perm):
+            acc += counts[s]
+            if acc >= batch:
+                cuts.append(j + 1)
+                acc = 0
+        if cuts[-1] != len(perm):
+            cuts.append(len(perm))
+        local = np.empty(len(idx), np.int32)
+        starts = []
+        pos = 0
+        for b in range(len(cuts) - 1):
+            cs = counts[perm[cuts[b]:cuts[b + 1]]]
+            local[pos:pos + cs.sum()] = np.repeat(np.arange(len(cs), dtype=np.int32), cs)
+            starts.append(np.concatenate([[0], np.cumsum(cs)]).astype(np.int32))
+            pos += cs.sum()
+        dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in dict(
+            vox=ds.vox[perm], local=local, s=ds.start[idx], g=ds.goal[idx], w=ds.waypoint[idx],
+            starts=np.concatenate(starts)).items()}
+        losses = torch.zeros(len(cuts) - 1, dtype=torch.float32, device="cuda")
+        a0, st0 = 0, 0
+        for b in range(len(cuts) - 1):
+            n_sb = cuts[b + 1] - cuts[b]
+            n_b = int(starts[b][-1])
+            tb = P.prrtc_train_batch(
+                vox=dev["vox"].data_ptr() + cuts[b] * VOX ** 3, n_scenes=n_sb,
+                scene_start=dev["starts"].data_ptr() + 4 * st0, scene_of=dev["local"].data_ptr() + 4 * a0,
+                start=dev["s"].data_ptr() + 4 * a0 * ds.dof, goal=dev["g"].data_ptr() + 4 * a0 * ds.dof,
+                waypoint=dev["w"].data_ptr() + 4 * a0 * ds.dof, n=n_b)
+            P.prrtc_train_proposal(ctx, mid, rid, tb, lr, losses.data_ptr() + 4 * b, stream)
+            a0 += n_b
+            st0 += n_sb + 1
+        l = losses.cpu().numpy()
+        out.append(float(l.mean()))
+        if log:
+            log("  epoch %d: %d steps, mean NLL %.4f" % (ep, len(l), out[-1]))
+    return np.asarray(out)
+
+
+def mean_nll(P, ctx, torch, mid: int, rid: int, ds: Dataset, lo, hi) -> float:
+    """Held-out mean NLL of the waypoints (mixture from the GPU forward pass;
+    the log-sum-exp is evaluated here in FP64)."""
+    if len(ds.scene_of) == 0:
+        return float("nan")
+    d = ds.dof
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in dict(
+        vox=ds.vox, so=ds.scene_of, s=ds.start, g=ds.goal).items()}
+    n = len(ds.scene_of)
+    gmm = torch.zeros((n, N_COMP * (1 + 2 * d)), dtype=torch.float32, device="cuda")
+    P.prrtc_proposal_forward(ctx, mid, rid, dev["vox"].data_ptr(), ds.vox.shape[0], dev["so"].data_ptr(),
+                             dev["s"].data_ptr(), dev["g"].data_ptr(), n, gmm.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    o = gmm.cpu().numpy().astype(np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    x = 2.0 * (ds.waypoint.astype(np.float64) - lo) / (hi - lo) - 1.0
+    logits = o[:, :N_COMP]
+    mu = o[:, N_COMP:N_COMP * (1 + d)].reshape(n, N_COMP, d)
+    ls = o[:, N_COMP * (1 + d):].reshape(n, N_COMP, d)
+    z = (x[:, None, :] - mu) * np.exp(-ls)
+    a = logits - logits.max(1, keepdims=True)
+    a = a - np.log(np.exp(a).sum(1, keepdims=True))
+    a = a + np.sum(-0.5 * z * z - ls - 0.5 * math.log(2 * math.pi), axis=2)
+    m = a.max(1, keepdims=True)
+    return float(-(m[:, 0] + np.log(np.exp(a - m).sum(1))).mean())
+
+
+def compare(P, ctx, torch, mid: int, rid: int, robot: dict, n_scenes: int, base: int = SEED_EVAL,
+            mix: float = 0.5, max_rounds: int = 2000, log=None) -> dict:
+    """Uniform against learned sampling on held-out scenes, one query each,
+    same seed and budget: wall time of the prrtc_plan call and success."""
+    res = {"plain": [], "learned": []}
+    for i in range(n_scenes):
+        sid = P.prrtc_load_scene(ctx, scene(robot, i, base))
+        q = free_query(P, ctx, torch, rid, sid, robot, base + i)
+        if q is not None:
+            for name, sampler in (("plain", 0), ("learned", 1)):
+                p = P.prrtc_plan_params_default()
+                p.seed, p.max_rounds, p.sampler, p.model_id, p.mix = base + i, max_rounds, sampler, mid, mix
+                t0 = time.perf_counter()
+                st, _, stats = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
+                ms = (time.perf_counter() - t0) * 1e3
+                res[name].append((st == P.PRRTC_OK, ms, stats["rounds"], stats["gpu_ms"]))
+        P.prrtc_unload_scene(ctx, sid)
+    out = {}
+    for name, rows in res.items():
+        a = np.array(rows, np.float64).reshape(-1, 4)
+        ok = a[:, 0] > 0
+        out[name] = dict(queries=int(len(a)), success=float(ok.mean()) if len(a) else 0.0,
+                         p50_ms=float(np.median(a[ok, 1])) if ok.any() else None,
+                         p99_ms=float(np.percentile(a[ok, 1], 99)) if ok.any() else None,
+                         p50_rounds=float(np.median(a[ok, 2])) if ok.any() else None,
+                         p50_gpu_ms=float(np.median(a[ok, 3])) if ok.any() else None)
+        if log:
+            log("  %s: %s" % (name, out[name]))
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import sys
+    import torch
+    from . import prrtc as P
+    from . import workloads as W
+    ap = argparse.ArgumentParser(description="Generate data with the uniform planner, train the 7-DoF "
+                                             "proposal, compare learned and uniform sampling")
+    ap.add_argument("--scenes", type=int, default=10000)
+    ap.add_argument("--eval-scenes", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--mix", type=float, default=0.5)
+    ap.add_argument("--out", default=None, help="write the trained model blob here")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    robot = W.robot_r7()
+    ctx = P.prrtc_create(0)
+    rid = P.prrtc_load_robot(ctx, robot)
+    t0 = time.perf_counter()
+    ds = generate(P, ctx, torch, rid, robot, a.scenes, log=log)
+    log("data: %d scenes solved, %d samples, %.1f s" % (ds.vox.shape[0], len(ds.scene_of), time.perf_counter() - t0))
+    ev = generate(P, ctx, torch, rid, robot, a.eval_scenes, base=SEED_EVAL)
+    mid = P.prrtc_load_proposal(ctx, pack(init_params(7, 1), 7))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = train(P, ctx, torch, mid, rid, ds, a.epochs, a.batch, a.lr, log=log)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("train: %.1f s, %.0f samples/s" % (dt, a.epochs * len(ds.scene_of) / dt))
+    log("held-out NLL %.4f" % mean_nll(P, ctx, torch, mid, rid, ev, robot["q_lo"], robot["q_hi"]))
+    compare(P, ctx, torch, mid, rid, robot, a.eval_scenes, mix=a.mix, log=log)
+    if a.out:
+        with open(a.out, "wb") as f:
+            f.write(P.prrtc_save_proposal(ctx, mid))
+    P.prrtc_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

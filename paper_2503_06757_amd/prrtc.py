@@ -57,6 +57,9 @@ class prrtc_plan_params(C.Structure):
         ("validate_factor", C.c_int32),
         ("dds_radius", C.c_float),
         ("dds_tries", C.c_int32),
+        ("sampler", C.c_int32),
+        ("model_id", C.c_int32),
+        ("mix", C.c_float),
     ]
 
 
@@ -69,6 +72,22 @@ class prrtc_plan_stats(C.Structure):
         ("validation_failures", C.c_int32),
         ("connect_worker", C.c_int32),
         ("gpu_ms", C.c_float),
+        ("fallback", C.c_int32),
+        ("pad", C.c_int32),
+        ("learned_samples", C.c_int64),
+    ]
+
+
+class prrtc_train_batch(C.Structure):
+    _fields_ = [
+        ("vox", C.c_void_p),
+        ("n_scenes", C.c_int32),
+        ("scene_start", C.c_void_p),
+        ("scene_of", C.c_void_p),
+        ("start", C.c_void_p),
+        ("goal", C.c_void_p),
+        ("waypoint", C.c_void_p),
+        ("n", C.c_int32),
     ]
 
 
@@ -94,10 +113,25 @@ def _load():
     L.prrtc_load_robot.restype = I32
     L.prrtc_load_scene.argtypes = [P, VP, I32, C.POINTER(I32)]
     L.prrtc_load_scene.restype = I32
+    L.prrtc_unload_scene.argtypes = [P, I32]
+    L.prrtc_unload_scene.restype = I32
     L.prrtc_check_edges.argtypes = [P, I32, I32, VP, VP, I64, F, VP, VP]
     L.prrtc_check_edges.restype = I32
     L.prrtc_fk_spheres.argtypes = [P, I32, VP, I64, VP, VP]
     L.prrtc_fk_spheres.restype = I32
+    L.prrtc_load_proposal.argtypes = [P, VP, C.c_size_t, C.POINTER(I32)]
+    L.prrtc_load_proposal.restype = I32
+    L.prrtc_save_proposal.argtypes = [P, I32, VP, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.prrtc_save_proposal.restype = I32
+    L.prrtc_voxelize.argtypes = [P, I32, VP, VP]
+    L.prrtc_voxelize.restype = I32
+    L.prrtc_proposal_forward.argtypes = [P, I32, I32, VP, I32, VP, VP, VP, I32, VP, VP]
+    L.prrtc_proposal_forward.restype = I32
+    L.prrtc_train_proposal.argtypes = [P, I32, I32, C.POINTER(prrtc_train_batch), F, VP, VP]
+    L.prrtc_train_proposal.restype = I32
+    L.prrtc_proposal_sample.argtypes = [P, I32, VP, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, I32, VP, VP,
+                                        VP]
+    L.prrtc_proposal_sample.restype = I32
     if hasattr(L, "prrtc_plan"):
         L.prrtc_plan_params_default.argtypes = [C.POINTER(prrtc_plan_params)]
         L.prrtc_plan_params_default.restype = None
@@ -111,8 +145,9 @@ lib = _load()
 
 # the symbols include/prrtc.h declares (checked by the CPU test-suite)
 EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
-            "prrtc_load_scene", "prrtc_check_edges", "prrtc_fk_spheres",
-            "prrtc_plan_params_default", "prrtc_plan")
+            "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_fk_spheres",
+            "prrtc_plan_params_default", "prrtc_plan", "prrtc_load_proposal", "prrtc_save_proposal",
+            "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_sample", "prrtc_train_proposal")
 
 
 # ---- C-named wrappers ------------------------------------------------------------
@@ -184,6 +219,10 @@ def prrtc_load_scene(ctx: int, prims: np.ndarray) -> int:
     return sid.value
 
 
+def prrtc_unload_scene(ctx: int, scene_id: int) -> None:
+    _check(ctx, lib.prrtc_unload_scene(ctx, int(scene_id)))
+
+
 def prrtc_check_edges(ctx: int, robot_id: int, scene_id: int, a_dev: int, b_dev: int, n_edges: int,
                       res: float, valid_dev: int, stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_check_edges(ctx, robot_id, scene_id, a_dev, b_dev, int(n_edges),
@@ -217,3 +256,44 @@ def prrtc_plan(ctx: int, robot_id: int, scene_id: int, start: np.ndarray, goal: 
     stats = {f: getattr(st, f) for f, _ in prrtc_plan_stats._fields_}
     stats["path_len"] = ln.value
     return status, (path[: ln.value].copy() if status == PRRTC_OK else None), stats
+
+
+# ---- learned proposal ---------------------------------------------------------------
+def prrtc_load_proposal(ctx: int, blob: bytes) -> int:
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    mid = C.c_int32(-1)
+    _check(ctx, lib.prrtc_load_proposal(ctx, C.cast(buf, C.c_void_p), len(blob), C.byref(mid)))
+    return mid.value
+
+
+def prrtc_save_proposal(ctx: int, model_id: int) -> bytes:
+    need = C.c_size_t(0)
+    st = lib.prrtc_save_proposal(ctx, model_id, None, 0, C.byref(need))
+    if st != PRRTC_E_CAPACITY:
+        _check(ctx, st)
+    buf = C.create_string_buffer(need.value)
+    _check(ctx, lib.prrtc_save_proposal(ctx, model_id, C.cast(buf, C.c_void_p), need.value, C.byref(need)))
+    return buf.raw[: need.value]
+
+
+def prrtc_voxelize(ctx: int, scene_id: int, vox_dev: int, stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_voxelize(ctx, scene_id, vox_dev, stream))
+
+
+def prrtc_proposal_forward(ctx: int, model_id: int, robot_id: int, vox_dev: int, n_scenes: int,
+                           scene_of_dev: int, start_dev: int, goal_dev: int, n: int, gmm_dev: int,
+                           stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_proposal_forward(ctx, model_id, robot_id, vox_dev, n_scenes, scene_of_dev,
+                                                  start_dev, goal_dev, n, gmm_dev, stream))
+
+
+def prrtc_train_proposal(ctx: int, model_id: int, robot_id: int, batch: prrtc_train_batch, lr: float,
+                         loss_dev: int, stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_train_proposal(ctx, model_id, robot_id, C.byref(batch), float(lr), loss_dev,
+                                                stream))
+
+
+def prrtc_proposal_sample(ctx: int, robot_id: int, gmm_dev: int, seed: int, query: int, rnd: int, attempt: int,
+                          n: int, q_dev: int, inside_dev: int, stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_proposal_sample(ctx, robot_id, gmm_dev, int(seed), int(query), int(rnd),
+                                                 int(attempt), int(n), q_dev, inside_dev, stream))

@@ -1,0 +1,301 @@
+"""GPU parity of the learned proposal (voxel grid, BF16 MFMA MLP, mixture
+head, gradients, Adam) against the numpy oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_06757_amd import proposal as PR
+from paper_2503_06757_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def prop():
+    from oracle import proposal
+    return proposal
+
+
+def gpu_vox(gpu, prims_list):
+    P, ctx, torch = gpu
+    out = torch.zeros((len(prims_list), 4096), dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    for i, prims in enumerate(prims_list):
+        sid = P.prrtc_load_scene(ctx, prims)
+        P.prrtc_voxelize(ctx, sid, out[i].data_ptr(), st)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_voxel_grid_parity(gpu, orc, prop, r7):
+    say("voxel parity")
+    scenes = [W.scene_s12(r7, 0), W.scene_s64(r7), W.scene_shelf(r7), W.scene_mixed(77, r7, 128)]
+    got = gpu_vox(gpu, scenes).cpu().numpy()
+    for prims, g in zip(scenes, got):
+        occ, margin = prop.voxelize(prims)
+        flagged = np.abs(margin) <= orc.FLAG_BAND
+        assert np.array_equal(g[~flagged], occ[~flagged])
+        assert 0 < occ.sum() < 4096
+
+
+def _batch(rng, robot, n_scenes, per_scene):
+    dof = W.robot_dof(robot)
+    scene_of = np.repeat(np.arange(n_scenes), per_scene).astype(np.int32)
+    n = scene_of.size
+    lo, hi = robot["q_lo"], robot["q_hi"]
+    s = rng.uniform(lo, hi, (n, dof)).astype(np.float32)
+    g = rng.uniform(lo, hi, (n, dof)).astype(np.float32)
+    q = rng.uniform(lo * 0.8, hi * 0.8, (n, dof)).astype(np.float32)
+    start = np.concatenate([[0], np.cumsum([per_scene] * n_scenes)]).astype(np.int32)
+    return scene_of, start, s, g, q
+
+
+def _forward_gpu(gpu, mid, rid, vox_t, scene_of, s, g):
+    P, ctx, torch = gpu
+    dof = s.shape[1]
+    n = s.shape[0]
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in
+         dict(scene_of=scene_of, s=s, g=g).items()}
+    out = torch.zeros((n, 8 * (1 + 2 * dof)), dtype=torch.float32, device="cuda")
+    P.prrtc_proposal_forward(ctx, mid, rid, vox_t.data_ptr(), vox_t.shape[0], t["scene_of"].data_ptr(),
+                             t["s"].data_ptr(), t["g"].data_ptr(), n, out.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def test_forward_parity(gpu, prop, r7):
+    P, ctx, torch = gpu
+    say("proposal forward parity")
+    rng = np.random.default_rng(3)
+    dof = 7
+    params = PR.init_params(dof, 11)
+    # non-trivial biases so every path is exercised
+    for k in ("bv", "b1", "b2", "b3", "b4"):
+        params[k] = (rng.standard_normal(params[k].shape) * 0.1).astype(np.float32)
+    mid = P.prrtc_load_proposal(ctx, PR.pack(params, dof))
+    rid = P.prrtc_load_robot(ctx, r7)
+    scenes = [W.scene_s12(r7, i) for i in range(3)]
+    vox_t = gpu_vox(gpu, scenes)
+    vox = vox_t.cpu().numpy().astype(np.float64)
+    scene_of, _, s, g, _ = _batch(rng, r7, 3, 13)          # 39 samples: ragged against 64-row tiles
+    got = _forward_gpu(gpu, mid, rid, vox_t, scene_of, s, g)
+    (logits, mu, logsig), cache = prop.forward(params, vox, scene_of, s, g, r7["q_lo"], r7["q_hi"])
+    ref = np.concatenate([logits, mu.reshape(len(s), -1), logsig.reshape(len(s), -1)], axis=1)
+    # bound: the head's |w x| sum at BF16, 4 x 2^-8 (both sides round the same operands;
+    # differences come from accumulation order and rare rounding flips upstream)
+    mag = np.abs(prop.bf16(cache["h3"])) @ np.abs(prop.bf16(params["W4"])) + np.abs(params["b4"])
+    mag = np.concatenate([mag[:, :8], mag[:, 8:8 + 8 * dof], mag[:, 8 + 8 * dof:]], axis=1)
+    err = np.abs(got - ref)
+    say("  max err %.3g, max err/bound %.3g" % (err.max(), (err / (4 * 2 ** -8 * mag + 1e-12)).max()))
+    assert np.all(err <= 4 * 2 ** -8 * mag + 1e-7)
+
+
+def test_gradient_parity_and_roundtrip(gpu, prop, r7):
+    """One training step from a fresh Adam state: the first moment is
+    (1 - beta1) g, so the GPU gradient is recovered from the saved blob."""
+    P, ctx, torch = gpu
+    say("proposal gradient parity")
+    rng = np.random.default_rng(5)
+    dof = 7
+    params = PR.init_params(dof, 12)
+    mid = P.prrtc_load_proposal(ctx, PR.pack(params, dof))
+    rid = P.prrtc_load_robot(ctx, r7)
+    scenes = [W.scene_s12(r7, i) for i in range(4)]
+    vox_t = gpu_vox(gpu, scenes)
+    vox = vox_t.cpu().numpy().astype(np.float64)
+    scene_of, start, s, g, q = _batch(rng, r7, 4, 24)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in
+           dict(scene_of=scene_of, start=start, s=s, g=g, q=q).items()}
+    loss = torch.zeros(1, device="cuda")
+    b = P.prrtc_train_batch(vox=vox_t.data_ptr(), n_scenes=4, scene_start=dev["start"].data_ptr(),
+                            scene_of=dev["scene_of"].data_ptr(), start=dev["s"].data_ptr(),
+                            goal=dev["g"].data_ptr(), waypoint=dev["q"].data_ptr(), n=len(s))
+    P.prrtc_train_proposal(ctx, mid, rid, b, 1e-6, loss.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    _, adam_t, (p1, m1, v1) = PR.unpack(P.prrtc_save_proposal(ctx, mid))
+    assert adam_t == 1
+    gm, cache = prop.forward(params, vox, scene_of, s, g, r7["q_lo"], r7["q_hi"])
+    qh = prop.scale(q, r7["q_lo"], r7["q_hi"])
+    ref_loss = prop.nll(gm, qh).mean()
+    say("  loss gpu %.6f oracle %.6f" % (loss.item(), ref_loss))
+    assert loss.item() == pytest.approx(ref_loss, rel=2e-3)
+    G = prop.backward(params, cache, gm, qh)
+    for k in PR.PARAM_ORDER:
+        g_gpu = m1[k].astype(np.float64) / 0.1
+        rel = np.linalg.norm(g_gpu - G[k]) / max(np.linalg.norm(G[k]), 1e-30)
+        say("  %s rel L2 %.2e" % (k, rel))
+        assert rel <= 2e-2, k
+    # blob round trip: reload and evaluate identically
+    blob = P.prrtc_save_proposal(ctx, mid)
+    mid2 = P.prrtc_load_proposal(ctx, blob)
+    a = _forward_gpu(gpu, mid, rid, vox_t, scene_of, s, g)
+    c = _forward_gpu(gpu, mid2, rid, vox_t, scene_of, s, g)
+    assert np.array_equal(a, c)
+
+
+def test_training_reduces_loss(gpu, r7):
+    """Waypoints drawn around a per-scene mean: 300 Adam steps must cut the
+    mean NLL substantially (the model can read the scene from the grid)."""
+    P, ctx, torch = gpu
+    say("proposal training")
+    rng = np.random.default_rng(9)
+    dof = 7
+    mid = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(dof, 13), dof))
+    rid = P.prrtc_load_robot(ctx, r7)
+    scenes = [W.scene_s12(r7, i) for i in range(8)]
+    vox_t = gpu_vox(gpu, scenes)
+    scene_of, start, s, g, _ = _batch(rng, r7, 8, 32)
+    centres = rng.uniform(-1.5, 1.5, (8, dof))
+    q = (centres[scene_of] + rng.normal(0, 0.2, (len(s), dof))).astype(np.float32)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in
+           dict(scene_of=scene_of, start=start, s=s, g=g, q=q).items()}
+    loss = torch.zeros(1, device="cuda")
+    b = P.prrtc_train_batch(vox=vox_t.data_ptr(), n_scenes=8, scene_start=dev["start"].data_ptr(),
+                            scene_of=dev["scene_of"].data_ptr(), start=dev["s"].data_ptr(),
+                            goal=dev["g"].data_ptr(), waypoint=dev["q"].data_ptr(), n=len(s))
+    losses = []
+    for it in range(300):
+        P.prrtc_train_proposal(ctx, mid, rid, b, 2e-3, loss.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        if it % 50 == 0 or it == 299:
+            torch.cuda.synchronize()
+            losses.append(loss.item())
+    say("  losses", ["%.3f" % x for x in losses])
+    assert np.isfinite(losses).all()
+    assert losses[-1] < losses[0] - 3.0
+
+
+def test_bad_blobs_rejected(gpu):
+    P, ctx, _ = gpu
+    blob = bytearray(PR.pack(PR.init_params(7, 1), 7))
+    with pytest.raises(P.PrrtcError):
+        P.prrtc_load_proposal(ctx, bytes(blob[:100]))
+    blob[0] ^= 0xFF
+    with pytest.raises(P.PrrtcError):
+        P.prrtc_load_proposal(ctx, bytes(blob))
+
+
+def test_mixture_draw_parity(gpu, prop, r7):
+    """prrtc_proposal_sample against the oracle's FP64 draw from the same
+    Philox words.  Where the component uniform sits within 1e-5 of a CDF
+    boundary the component may differ (FP32 against FP64 weights): skipped."""
+    P, ctx, torch = gpu
+    say("mixture draw parity")
+    rng = np.random.default_rng(21)
+    dof = 7
+    rid = P.prrtc_load_robot(ctx, r7)
+    lo, hi = r7["q_lo"].astype(np.float64), r7["q_hi"].astype(np.float64)
+    row = np.concatenate([rng.normal(0, 1.5, 8), rng.uniform(-0.8, 0.8, 8 * dof),
+                          rng.uniform(-3.0, 0.3, 8 * dof)]).astype(np.float32)
+    g_dev = torch.from_numpy(row).cuda()
+    n = 700
+    for (query, rnd, attempt) in ((0, 0, 0), (3, 17, 5), (9, 123456, 0x7FFFFF)):
+        q = torch.zeros((n, dof), dtype=torch.float32, device="cuda")
+        ins = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        P.prrtc_proposal_sample(ctx, rid, g_dev.data_ptr(), 0x1234ABCD5678, query, rnd, attempt, n, q.data_ptr(),
+                                ins.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        qg, ig = q.cpu().numpy().astype(np.float64), ins.cpu().numpy()
+        checked = 0
+        for w in range(n):
+            qo, k, gap = prop.mixture_draw(row, dof, lo, hi, 0x1234ABCD5678, query, rnd, w, attempt)
+            if gap <= 1e-5:
+                continue
+            checked += 1
+            x = 2.0 * (qo - lo) / (hi - lo) - 1.0
+            tol = 4e-6 * (1.0 + np.abs(x)) * (hi - lo)
+            assert np.all(np.abs(qg[w] - qo) <= tol), (w, qg[w], qo)
+            near = np.any(np.minimum(np.abs(qo - lo), np.abs(qo - hi)) <= tol)
+            if not near:
+                assert bool(ig[w]) == bool(np.all((qo >= lo) & (qo <= hi))), w
+        say("  (%d, %d, %d): %d of %d draws compared, %.0f%% inside" % (query, rnd, attempt, checked, n,
+                                                                       100 * ig.mean()))
+        assert checked >= n - 5
+
+
+def _learned_model(P, ctx, dof, seed, poison=False):
+    params = PR.init_params(dof, seed)
+    if poison:
+        params["b4"] = params["b4"].copy()
+        params["b4"][3] = np.nan
+    return P.prrtc_load_proposal(ctx, PR.pack(params, dof))
+
+
+def test_plan_learned_mix0_equals_plain_and_nan_fallback(gpu, orc, r7):
+    from conftest import free_query
+    P, ctx, _ = gpu
+    say("learned plan: mix 0 and non-finite model equal the uniform plan")
+    prims = W.scene_s12(r7, 2)
+    rid, sid = P.prrtc_load_robot(ctx, r7), P.prrtc_load_scene(ctx, prims)
+    s, g = free_query(orc, orc.OracleRobot(r7), prims, r7, W.SEED_QUERY + 2)
+    good = _learned_model(P, ctx, 7, 31)
+    bad = _learned_model(P, ctx, 7, 31, poison=True)
+
+    def run(**kw):
+        p = P.prrtc_plan_params_default()
+        p.seed, p.max_rounds = 5, 300
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return P.prrtc_plan(ctx, rid, sid, s, g, p)
+
+    st0, path0, stats0 = run()
+    assert st0 == 0
+    for kw in (dict(sampler=1, model_id=good, mix=0.0), dict(sampler=1, model_id=bad, mix=1.0)):
+        st, path, stats = run(**kw)
+        assert st == st0 and np.array_equal(path, path0), kw
+        for k in ("rounds", "nodes_a", "nodes_b", "edges_checked", "connect_worker"):
+            assert stats[k] == stats0[k], (kw, k)
+        assert stats["learned_samples"] == 0
+        assert stats["fallback"] == (1 if kw["model_id"] == bad else 0)
+
+
+@pytest.mark.parametrize("mix", [0.5, 1.0])
+def test_plan_learned_valid_and_reproducible(gpu, orc, r7, mix):
+    """Learned plans: no oracle replay exists (the draws come from FP32
+    transcendentals), so every path is checked against the oracle at 4x the
+    resolution, and two runs must agree bit for bit."""
+    from conftest import free_query
+    P, ctx, _ = gpu
+    say("learned plan, mix", mix)
+    model = _learned_model(P, ctx, 7, 32)
+    rid = P.prrtc_load_robot(ctx, r7)
+    for inst in range(4):
+        prims = W.scene_s12(r7, inst)
+        sid = P.prrtc_load_scene(ctx, prims)
+        s, g = free_query(orc, orc.OracleRobot(r7), prims, r7, W.SEED_QUERY + inst)
+        p = P.prrtc_plan_params_default()
+        p.seed, p.max_rounds, p.sampler, p.model_id, p.mix = 40 + inst, 1000, 1, model, mix
+        st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, p)
+        say("  instance", inst, st, stats["rounds"], stats["learned_samples"], "%.3f ms" % stats["gpu_ms"])
+        assert st == 0, stats
+        assert stats["fallback"] == 0 and stats["learned_samples"] > 0
+        rob = orc.OracleRobot(r7)
+        assert np.array_equal(path[0], s) and np.array_equal(path[-1], g)
+        seg = np.linalg.norm(np.diff(path.astype(np.float64), axis=0), axis=1)
+        assert np.all(seg <= 0.5 * (1 + 1e-6))
+        m, _ = orc.path_clearance(rob, prims, path, 4 * 32.0)
+        assert m >= -orc.FLAG_BAND
+        st2, path2, stats2 = P.prrtc_plan(ctx, rid, sid, s, g, p)
+        assert st2 == st and np.array_equal(path2, path) and stats2["rounds"] == stats["rounds"]
+        assert stats2["learned_samples"] == stats["learned_samples"]
+
+
+def test_plan_learned_bad_arguments(gpu, r7):
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    sid = P.prrtc_load_scene(ctx, W.scene_s12(r7, 0))
+    m14 = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(14, 1), 14))
+    s = np.zeros(7, np.float32)
+    for kw in (dict(sampler=2), dict(sampler=1, model_id=99), dict(sampler=1, model_id=m14),
+               dict(sampler=1, model_id=0, mix=1.5)):
+        p = P.prrtc_plan_params_default()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        with pytest.raises(P.PrrtcError):
+            P.prrtc_plan(ctx, rid, sid, s, s, p)

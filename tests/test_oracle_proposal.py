@@ -145,3 +145,47 @@ def test_voxel_grid_box_aligned_with_cells(prop):
     assert np.all(np.abs(margin) > 1e-3)
     idx = (8 * 16 + 8) * 16 + 8          # cell (8, 8, 8) holds the box corner region
     assert occ[idx] == 1
+
+
+def _row(prop, dof, logits, mu, ls):
+    return np.concatenate([logits, np.broadcast_to(mu, (prop.N_COMP, dof)).ravel(),
+                           np.broadcast_to(ls, (prop.N_COMP, dof)).ravel()])
+
+
+def test_mixture_draw_normals(prop):
+    """One component at mu = 0, sigma = 1 over [-1, 1] limits: q is a standard
+    normal draw (Box-Muller); mean, variance, an independence check across the
+    pair and a Kolmogorov-Smirnov test against the normal CDF."""
+    from scipy import stats
+    dof = 4
+    logits = np.full(prop.N_COMP, -1e30)
+    logits[2] = 0.0
+    row = _row(prop, dof, logits, 0.0, 0.0)
+    lo, hi = -np.ones(dof), np.ones(dof)
+    Z = np.array([prop.mixture_draw(row, dof, lo, hi, 7, 1, 2, w, 0)[0] for w in range(6000)])
+    assert abs(Z.mean()) < 0.05
+    np.testing.assert_allclose(Z.var(axis=0), 1.0, atol=0.08)
+    assert abs(np.corrcoef(Z[:, 0], Z[:, 1])[0, 1]) < 0.05
+    for j in range(dof):
+        assert stats.kstest(Z[:, j], "norm").pvalue > 1e-3
+
+
+def test_mixture_draw_components_and_scaling(prop):
+    """Component frequencies follow softmax(logits) (chi-square); a component
+    with sigma ~ 0 lands exactly on lo + (mu + 1)(hi - lo) / 2."""
+    from scipy import stats
+    dof = 3
+    pw = np.array([0.4, 0.2, 0.1, 0.1, 0.05, 0.05, 0.05, 0.05])
+    mu = np.linspace(-0.7, 0.7, prop.N_COMP)[:, None] * np.ones(dof)
+    row = _row(prop, dof, np.log(pw) + 1.3, mu, -60.0)
+    lo, hi = np.array([-2.0, 0.0, -1.0]), np.array([2.0, 3.0, 0.5])
+    n = 8000
+    counts = np.zeros(prop.N_COMP)
+    for w in range(n):
+        q, k, _ = prop.mixture_draw(row, dof, lo, hi, 3, 0, 0, w, 5)
+        counts[k] += 1
+        np.testing.assert_allclose(q, lo + 0.5 * (mu[k] + 1.0) * (hi - lo), atol=1e-12)
+    assert stats.chisquare(counts, pw * n).pvalue > 1e-3
+    # the mixing uniform and the component uniform are distinct words
+    us = [prop.mix_uniform(3, 0, 0, w, 5) for w in range(2000)]
+    assert 0.45 < np.mean(us) < 0.55 and min(us) >= 0.0 and max(us) < 1.0
