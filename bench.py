@@ -160,10 +160,140 @@ def bench_plan(P, ctx, n_instances=100, n_seeds=50):
             fails += 1
             times.append(float("inf"))
     t = np.array(times)
+
+    def pct(q):
+        # failures count as infinitely slow; a percentile they reach is reported as null
+        v = float(np.percentile(t, q))
+        return v if np.isfinite(v) else None
+
+    ok = t[np.isfinite(t)]
     return {"workload": "plan_r7_s12", "queries": len(jobs), "success": float(np.mean(np.isfinite(t))),
-            "p50_ms": float(np.percentile(t, 50)), "p95_ms": float(np.percentile(t, 95)),
-            "max_ms": float(np.max(t)), "mean_rounds": float(np.mean(rounds)) if rounds else None,
+            "p50_ms": pct(50), "p95_ms": pct(95), "p99_ms": pct(99),
+            "max_solved_ms": float(ok.max()) if ok.size else None, "mean_rounds": float(np.mean(rounds)) if rounds else None,
             "mean_cost": float(np.mean(costs)) if costs else None, "workers": prm.workers}
+
+
+def query_pool(P, ctx, torch, n_scenes=32, per_scene=4, seed=0x56000000):
+    """Served workload pool: scenes with U{8..128} obstacles (6:4:2 mix) for
+    the 7-DoF arm and the dual arm alternately, `per_scene` free queries each
+    (endpoints checked by prrtc_check_edges)."""
+    from paper_2503_06757_amd import proposal as PR
+    robots = [W.robot_r7(), W.robot_r14()]
+    rids = [P.prrtc_load_robot(ctx, r) for r in robots]
+    pool = []
+    for i in range(n_scenes):
+        kind = i % 2
+        rng = np.random.default_rng(seed + i)
+        prims = W.scene_mixed(seed + i, robots[kind], int(rng.integers(8, 129)))
+        sid = P.prrtc_load_scene(ctx, prims)
+        for j in range(per_scene):
+            q = PR.free_query(P, ctx, torch, rids[kind], sid, robots[kind], seed + 1000 * j + i)
+            if q is not None:
+                pool.append((rids[kind], sid, q[0], q[1], kind))
+    return pool
+
+
+def bench_serve(P, ctx, torch, n_queries=10000, rate=2000.0, workers=128, slots=256, max_pending=1024,
+                budget=2 << 30, max_rounds=2000, seed=0x56000000):
+    """The served workload through the library's serving thread: queries
+    arrive as a Poisson stream (exponential gaps) and are submitted at their
+    arrival time (refused submissions are retried: admission); the thread
+    batches whatever is queued into one launch at a time.  Latency =
+    completion seen by polling - arrival, on the host clock."""
+    pool = query_pool(P, ctx, torch)
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_queries))
+    picks = rng.integers(0, len(pool), n_queries)
+    prm = P.prrtc_plan_params_default()
+    prm.workers, prm.max_rounds = workers, max_rounds
+    done = np.full(n_queries, np.nan)
+    status = np.zeros(n_queries, np.int32)
+    refused = 0
+    outstanding = {}
+    nxt = 0
+    P.prrtc_serve_start(ctx, prm, slots=slots, max_pending=max_pending, memory_budget=budget, path_cap=128)
+    t0 = time.perf_counter()
+    try:
+        while nxt < n_queries or outstanding:
+            now = time.perf_counter() - t0
+            while nxt < n_queries and arrivals[nxt] <= now:
+                rid, sid, s, g, kind = pool[picks[nxt]]
+                t = P.prrtc_submit(ctx, rid, sid, s, g, seed + nxt, 0)
+                if t is None:
+                    refused += 1
+                    break
+                outstanding[t] = (nxt, len(s))
+                nxt += 1
+            for t in list(outstanding):
+                k, dof = outstanding[t]
+                r = P.prrtc_poll(ctx, t, dof, 128)
+                if r is not None:
+                    done[k] = time.perf_counter() - t0
+                    status[k] = r[0]
+                    del outstanding[t]
+    finally:
+        launches = P.prrtc_serve_stop(ctx)
+    lat = (done - arrivals) * 1e3
+    ok = status == P.PRRTC_OK
+    span = float(np.nanmax(done))
+    return {"workload": "serve_mixed_r7_r14", "queries": n_queries, "rate_per_s": rate, "workers": workers,
+            "slots": slots, "max_pending": max_pending, "memory_budget_bytes": budget, "success": float(ok.mean()),
+            "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+            "queries_per_s": n_queries / span, "launches": launches, "mean_batch": n_queries / max(launches, 1),
+            "refused_submissions": refused, "pool": len(pool)}
+
+
+def bench_throughput(P, ctx, torch, n_queries=2048, workers=(32, 64, 128, 256), max_rounds=2000):
+    """Queries/s of one prrtc_plan_batch launch over the served pool for each
+    worker count (the planner's launch-shape tuning)."""
+    pool = query_pool(P, ctx, torch)
+    rows = []
+    for wk in workers:
+        prm = P.prrtc_plan_params_default()
+        prm.workers, prm.max_rounds = wk, max_rounds
+        qs = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
+               7 + k, 0) for k in range(n_queries)]
+        t0 = time.perf_counter()
+        used, out = P.prrtc_plan_batch(ctx, qs, prm, groups=0, path_cap=128)
+        dt = time.perf_counter() - t0
+        ok = np.mean([o[0] == P.PRRTC_OK for o in out])
+        rows.append({"workers": wk, "groups": used, "queries_per_s": n_queries / dt, "success": float(ok)})
+    return rows
+
+
+def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
+    """The learned proposal end to end on the 7-DoF arm: data from the
+    uniform planner on generated scenes, training (throughput against the
+    BF16 matrix-core peak), held-out NLL, then uniform against learned
+    sampling on held-out scenes (same seeds and budgets)."""
+    from paper_2503_06757_amd import proposal as PR
+    robot = W.robot_r7()
+    rid = P.prrtc_load_robot(ctx, robot)
+    t0 = time.perf_counter()
+    ds = PR.generate(P, ctx, torch, rid, robot, n_train, log=log)
+    gen_s = time.perf_counter() - t0
+    ev = PR.generate(P, ctx, torch, rid, robot, n_eval, base=PR.SEED_EVAL)
+    mid = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(7, 1), 7))
+    nll0 = PR.mean_nll(P, ctx, torch, mid, rid, ev, robot["q_lo"], robot["q_hi"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = PR.train(P, ctx, torch, mid, rid, ds, epochs, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    n_samples = len(ds.scene_of)
+    dof, hid, cw = 7, 256, 8 * 15
+    fwd_sample = 2 * ((2 * dof + hid) * hid + 2 * hid * hid + hid * cw)
+    fwd_scene = 2 * 4096 * hid
+    flop = 3 * epochs * (n_samples * fwd_sample + ds.vox.shape[0] * fwd_scene)
+    nll = PR.mean_nll(P, ctx, torch, mid, rid, ev, robot["q_lo"], robot["q_hi"])
+    cmp = PR.compare(P, ctx, torch, mid, rid, robot, n_eval, log=log)
+    return {"workload": "learned_r7_mixed_scenes", "train_scenes": n_train, "solved_scenes": int(ds.vox.shape[0]),
+            "samples": n_samples, "epochs": epochs, "datagen_s": gen_s, "train_s": train_s,
+            "train_samples_per_s": epochs * n_samples / train_s,
+            "train_tflops": flop / train_s / 1e12, "bf16_peak_tflops": 2500.0,
+            "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+            "heldout_nll_init": nll0, "heldout_nll": nll, "eval_scenes": n_eval,
+            "plain": cmp["plain"], "learned": cmp["learned"]}
 
 
 def cpu_baseline(ce, budget_s=12.0):
@@ -183,6 +313,19 @@ def cpu_baseline(ce, budget_s=12.0):
             "sample": f"first {n} edges of the 2^20-edge batch, early-exit boolean mode, 1 thread, {t:.1f} s"}
 
 
+def finite_or_null(x):
+    """Plain JSON: numpy scalars to Python numbers, non-finite floats to null."""
+    if isinstance(x, dict):
+        return {k: finite_or_null(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite_or_null(v) for v in x]
+    if isinstance(x, (np.integer,)):
+        return int(x)
+    if isinstance(x, (float, np.floating)):
+        return float(x) if np.isfinite(x) else None
+    return x
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +333,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle CPU baseline")
     ap.add_argument("--skip-plan", action="store_true", help="omit the planner ms-to-solution run")
+    ap.add_argument("--skip-learned", action="store_true", help="omit the learned-proposal leg")
+    ap.add_argument("--learned-scenes", type=int, default=2000, help="training scenes (10000 for the full set)")
+    ap.add_argument("--learned-eval", type=int, default=200, help="held-out scenes")
+    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--skip-serve", action="store_true", help="omit the batched / served planner legs")
+    ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +357,20 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     plan = None if args.skip_plan else bench_plan(P, ctx)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    serve = batch = None
+    if not args.skip_serve:
+        log("batched planner: launch shapes")
+        batch = bench_throughput(P, ctx, torch)
+        log("served planner: Poisson arrivals")
+        serve = bench_serve(P, ctx, torch, n_queries=args.serve_queries)
+    learned = None
+    if not args.skip_learned:
+        log("learned proposal")
+        learned = bench_learned(P, ctx, torch, args.learned_scenes, args.learned_eval, args.learned_epochs, log)
     ms_per_step = ce["wall_s"] * 1e3 / args.steps
     value = N_EDGES / (ce["wall_s"] / args.steps)
     achieved = ce["alg_flop"] / (ce["kernel_ms"] * 1e-3) / 1e12
@@ -234,11 +397,14 @@ def main():
                      "kernel": "k_check_edges", "kernel_ms": ce["kernel_ms"],
                      "flop_per_launch": ce["alg_flop"], "flop_per_point": ce["flop_per_point"]},
         "ms_to_solution": plan,
+        "batched": batch,
+        "served": serve,
+        "learned": learned,
     }
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(ce)
     P.prrtc_destroy(ctx)
-    print(json.dumps(out, default=float), flush=True)
+    print(json.dumps(finite_or_null(out)), flush=True)
 
 
 if __name__ == "__main__":

@@ -205,6 +205,77 @@ prrtc_status prrtc_plan(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, cons
                         int32_t path_cap, int32_t *path_len, prrtc_plan_stats *stats);
 
 /*
+ * Batched planning: many independent queries in one persistent launch (the
+ * paper's high-level parallelism, one query per group of workers instead of
+ * one query per launch).  The launch holds G groups of params->workers
+ * workgroups; group g runs queries g, g + G, g + 2G, ... one after another,
+ * each exactly as prrtc_plan would with the same parameters, seed and query
+ * word (identical trees, path and statistics).  Queries may mix robots and
+ * scenes; all share *params (its seed and query fields are ignored).  With
+ * sampler 1 every query must use the same robot.
+ *
+ * groups: G, or 0 for as many as are resident at once (capped at n).  More
+ *   than fit on the device at once is E_CAPACITY.
+ * memory_budget: bytes of device memory the launch may use for trees and
+ *   per-query buffers (0: no limit); G shrinks to fit (admission by tree
+ *   memory), E_CAPACITY if not even one group fits.
+ * paths: host float32 [n][path_cap][PRRTC_MAX_DOF]; query k's path is the
+ *   row-major [path_len][dof] block at paths + k path_cap PRRTC_MAX_DOF.
+ * results: host [n]; status per query (OK, E_CAPACITY with path_len = nodes
+ *   needed, E_INVALID_ENDPOINT, E_NO_SOLUTION, E_STATE/E_ARG for a query
+ *   rejected on the host (not launched), E_HIP if its group aborted);
+ *   stats.gpu_ms is the whole launch.
+ * groups_used: may be NULL.  Synchronous.  The return value is OK when the
+ * launch ran, whatever the queries' outcomes.
+ */
+typedef struct {
+    int32_t robot_id, scene_id;
+    float start[PRRTC_MAX_DOF], goal[PRRTC_MAX_DOF];
+    uint64_t seed;
+    uint32_t query;
+    int32_t pad;
+} prrtc_query;
+
+typedef struct {
+    int32_t status;
+    int32_t path_len;
+    prrtc_plan_stats stats;
+} prrtc_query_result;
+
+prrtc_status prrtc_plan_batch(prrtc_ctx *ctx, const prrtc_query *queries, int32_t n,
+                              const prrtc_plan_params *params, int32_t groups, int64_t memory_budget,
+                              float *paths, int32_t path_cap, prrtc_query_result *results,
+                              int32_t *groups_used);
+
+/*
+ * Serving: a thread owned by the context gathers submitted queries into
+ * prrtc_plan_batch launches (up to `slots` queries per launch, groups sized
+ * by memory_budget as in prrtc_plan_batch), so queries arriving over time
+ * are planned as they come (continuous batching at launch granularity).
+ * While serving, the context accepts only prrtc_submit, prrtc_poll,
+ * prrtc_serve_stop and prrtc_last_error (everything else: E_STATE).
+ *
+ * prrtc_serve_start: params as for prrtc_plan_batch; slots >= 1;
+ *   max_pending >= slots bounds the queries admitted and not yet polled;
+ *   path_cap >= 1 nodes kept per query.
+ * prrtc_submit: copies *query and returns a ticket; E_BUSY (admission
+ *   refused) when max_pending queries are queued, running or unpolled.
+ * prrtc_poll: E_BUSY while the ticket is queued or running; OK with *result
+ *   (its status is the query's outcome) and, for a solved query, the path in
+ *   path (host float32 [path_cap][dof]) once done — the ticket is then
+ *   released; E_CAPACITY if path_cap < result->path_len (ticket kept);
+ *   E_STATE for an unknown or released ticket.
+ * prrtc_serve_stop: plans everything still queued, joins the thread, drops
+ *   unpolled results; *launches (may be NULL) = batched launches made.
+ */
+prrtc_status prrtc_serve_start(prrtc_ctx *ctx, const prrtc_plan_params *params, int32_t slots,
+                               int32_t max_pending, int64_t memory_budget, int32_t path_cap);
+prrtc_status prrtc_submit(prrtc_ctx *ctx, const prrtc_query *query, uint64_t *ticket);
+prrtc_status prrtc_poll(prrtc_ctx *ctx, uint64_t ticket, prrtc_query_result *result, float *path,
+                        int32_t path_cap);
+prrtc_status prrtc_serve_stop(prrtc_ctx *ctx, int64_t *launches);
+
+/*
  * Learned sampling proposal (not in the paper, which samples uniformly; an
  * addition whose definition follows).  A 16^3 occupancy grid of the scene
  * (cells of 0.1 m over [-0.8, 0.8]^3; a cell is occupied iff an obstacle lies

@@ -4,7 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cstddef>
 #include <cstdarg>
 #include <cstdio>
@@ -220,6 +226,28 @@ struct ModelRec {
 };
 
 
+// Serving state of a context (see prrtc_serve_start).
+struct ServeDone {
+    prrtc_query_result res;
+    std::vector<float> path;   // [path_len][dof]
+};
+
+struct Server {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    prrtc_plan_params params{};
+    int slots = 0, max_pending = 0, path_cap = 0;
+    int64_t budget = 0;
+    uint64_t next_ticket = 1;
+    std::deque<std::pair<uint64_t, prrtc_query>> queue;
+    std::unordered_map<uint64_t, int> running;
+    std::unordered_map<uint64_t, ServeDone> done;
+    long long launches = 0;
+    size_t in_flight() const { return queue.size() + running.size() + done.size(); }
+};
+
 struct prrtc_ctx {
     int device = 0;
     int n_cu = 256;
@@ -228,7 +256,9 @@ struct prrtc_ctx {
     std::string err;
     std::vector<RobotRec> robots;
     std::vector<SceneRec> scenes;
-    PlannerBuffers plan;
+    PlannerBuffers plan;               // single-query launches
+    PlannerBuffers batch;              // batched launches
+    std::vector<float> stage_host;     // host staging of batched proposal inputs
     std::vector<ModelRec> models;
     EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
     unsigned counter_next = 0;
@@ -236,6 +266,8 @@ struct prrtc_ctx {
     size_t edge_grid_lds = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float* pinned = nullptr;           // kPinnedFloats of pinned host staging
+    std::unique_ptr<struct Server> server;
+    std::atomic<bool> serving{false};  // while set, only submit/poll/serve_stop are accepted
 };
 
 constexpr int kPinnedFloats = 1024;
@@ -263,6 +295,13 @@ prrtc_status fail(prrtc_ctx* ctx, prrtc_status st, const char* fmt, ...) {
             return fail((ctx), PRRTC_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Entry points other than submit / poll / serve_stop are refused while the
+// context's serving thread owns its stream and buffers.
+#define PRRTC_NOT_SERVING(ctx)                                                          \
+    do {                                                                                \
+        if ((ctx)->serving.load()) return fail((ctx), PRRTC_E_STATE, "context is serving"); \
+    } while (0)
+
 bool finite_all(const float* p, int n) {
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -284,6 +323,10 @@ size_t align_up(size_t x) {
     return (x + 255) & ~size_t(255);
 }
 
+}  // namespace
+
+namespace {
+void serve_shutdown(prrtc_ctx* ctx);   // stops and joins a context's serving thread
 }  // namespace
 
 extern "C" {
@@ -314,6 +357,7 @@ prrtc_status prrtc_create(prrtc_ctx** out, int device) {
 
 void prrtc_destroy(prrtc_ctx* ctx) {
     if (!ctx) return;
+    serve_shutdown(ctx);
     hipSetDevice(ctx->device);
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     for (auto& r : ctx->robots) {
@@ -327,6 +371,7 @@ void prrtc_destroy(prrtc_ctx* ctx) {
         if (s.vox) hipFree(s.vox);
     }
     planner_free(ctx->plan);
+    planner_free(ctx->batch);
     for (auto& m : ctx->models) {
         hipFree(m.mem);
         if (m.ws) hipFree(m.ws);
@@ -344,6 +389,7 @@ const char* prrtc_last_error(const prrtc_ctx* ctx) { return ctx ? ctx->err.c_str
 prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t* robot_id) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (!d || !robot_id) return fail(ctx, PRRTC_E_ARG, "null descriptor or id");
     if (d->n_chains < 1 || d->n_chains > PRRTC_MAX_CHAINS)
         return fail(ctx, PRRTC_E_ARG, "n_chains must be 1 or 2");
@@ -527,6 +573,7 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
 prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, int32_t* scene_id) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (!scene_id || n < 0 || n > PRRTC_MAX_PRIMS || (n > 0 && !p))
         return fail(ctx, PRRTC_E_ARG, "bad scene arguments (n must be in 0..%d)", PRRTC_MAX_PRIMS);
     std::vector<float4> sph, sph_b, box_b, cyl_b;
@@ -615,6 +662,7 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
 prrtc_status prrtc_unload_scene(prrtc_ctx* ctx, int32_t scene_id) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
         return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
     SceneRec& rec = ctx->scenes[scene_id];
@@ -671,6 +719,7 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
                                void* stream) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     const RobotRec* r = nullptr;
     const SceneRec* s = nullptr;
     prrtc_status st = lookup(ctx, robot_id, scene_id, &r, &s);
@@ -702,6 +751,7 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
                               void* stream) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     const RobotRec* r = nullptr;
     prrtc_status st = lookup(ctx, robot_id, 0, &r, nullptr);
     if (st != PRRTC_OK) return st;
@@ -733,14 +783,16 @@ namespace {
 constexpr int kPlanTile = PRRTC_PLAN_TILE;
 constexpr int kPlanItems = PRRTC_PLAN_ITEMS;
 
-struct PlanLayout {
-    size_t qa, pa, ba, ra, qb, pb, bb, rb, ctl, stage, st, path, path_idx, qin, gmm, bytes;
+// Device buffers of one worker group (reused by every query the group runs).
+struct GroupLayout {
+    size_t qa, pa, ba, ra, qb, pb, bb, rb, bar, stage, st, path, path_idx, bytes;
 };
 
-PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
-    PlanLayout L{};
+GroupLayout group_layout(int dof, int cap, int W, int stage_cap) {
+    GroupLayout L{};
     size_t o = 0;
     auto take = [&](size_t n) { const size_t at = o; o = align_up<int>(o + n); return at; };
+    const int path_cap = 2 * cap;
     L.qa = take(sizeof(float) * (size_t)dof * cap);
     L.pa = take(sizeof(int) * (size_t)cap);
     L.ba = take((size_t)cap);
@@ -749,15 +801,129 @@ PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
     L.pb = take(sizeof(int) * (size_t)cap);
     L.bb = take((size_t)cap);
     L.rb = take(sizeof(float) * (size_t)cap);
-    L.ctl = take(sizeof(int) * kCtlWords);
+    L.bar = take(sizeof(int) * kBarWords);
     L.stage = take(sizeof(float) * (size_t)W * stage_cap * dof);
     L.st = take(sizeof(int) * 5 * (size_t)W);
     L.path = take(sizeof(float) * (size_t)path_cap * dof);
     L.path_idx = take(sizeof(int) * (size_t)path_cap);
-    L.qin = take(sizeof(float) * 2 * kMaxDof + sizeof(int));
-    L.gmm = take(sizeof(float) * kComp * (1 + 2 * kMaxDof));
     L.bytes = o;
     return L;
+}
+
+void group_args(PlanArgs& A, char* m, const GroupLayout& L, int W, int cap) {
+    A.qa = reinterpret_cast<float*>(m + L.qa);
+    A.pa = reinterpret_cast<int*>(m + L.pa);
+    A.ba = reinterpret_cast<unsigned char*>(m + L.ba);
+    A.ra = reinterpret_cast<float*>(m + L.ra);
+    A.qb = reinterpret_cast<float*>(m + L.qb);
+    A.pb = reinterpret_cast<int*>(m + L.pb);
+    A.bb = reinterpret_cast<unsigned char*>(m + L.bb);
+    A.rb = reinterpret_cast<float*>(m + L.rb);
+    A.bar = reinterpret_cast<int*>(m + L.bar);
+    A.stage = reinterpret_cast<float*>(m + L.stage);
+    int* sti = reinterpret_cast<int*>(m + L.st);
+    A.st_count = sti;
+    A.st_nn = sti + W;
+    A.st_other = sti + 2 * W;
+    A.st_conn = sti + 3 * W;
+    A.st_fail = sti + 4 * W;
+    A.path = reinterpret_cast<float*>(m + L.path);
+    A.path_idx = reinterpret_cast<int*>(m + L.path_idx);
+    A.path_cap = 2 * cap;
+}
+
+// Longest greedy connect, ceil(|hi - lo| / delta) steps (+ margin for
+// rounding); -1 if it exceeds the staging limit.
+int stage_cap_for(const RobotArgs& RA, float delta) {
+    double diag = 0.0;
+    for (int j = 0; j < RA.dof; ++j) diag += (double)(RA.hi[j] - RA.lo[j]) * (double)(RA.hi[j] - RA.lo[j]);
+    const int sc = (int)std::ceil(std::sqrt(diag) / (double)delta * (1.0 + 1e-6)) + 2;
+    return sc > 4096 ? -1 : sc;
+}
+
+size_t plan_lds_bytes(const RobotArgs& RA, int stage_cap, int dof) {
+    return sphere_lds_bytes(RA) + sizeof(float4) * kPlanTile * 3 * RA.n_slots +
+           sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) + sizeof(int) * (kPlanTile + 2 * (stage_cap + 2));
+}
+
+prrtc_status check_plan_params(prrtc_ctx* ctx, const prrtc_plan_params& p) {
+    if (p.workers < 1 || p.workers > 4096) return fail(ctx, PRRTC_E_ARG, "workers must be in 1..4096");
+    if (!(p.delta > 0.0f) || !std::isfinite(p.delta)) return fail(ctx, PRRTC_E_ARG, "delta must be > 0");
+    if (!(p.res > 0.0f) || !std::isfinite(p.res)) return fail(ctx, PRRTC_E_ARG, "res must be > 0");
+    if (p.max_rounds < 0) return fail(ctx, PRRTC_E_ARG, "max_rounds < 0");
+    if (p.tree_capacity < 2 || p.tree_capacity > (1 << 24))
+        return fail(ctx, PRRTC_E_ARG, "tree_capacity must be in 2..2^24");
+    if (p.validate_factor < 0 || p.validate_factor > 1024)
+        return fail(ctx, PRRTC_E_ARG, "validate_factor must be in 0..1024");
+    if (!(p.dds_radius >= 0.0f) || !std::isfinite(p.dds_radius))
+        return fail(ctx, PRRTC_E_ARG, "dds_radius must be finite and >= 0");
+    if (p.dds_tries < 1 || p.dds_tries > 64) return fail(ctx, PRRTC_E_ARG, "dds_tries must be in 1..64");
+    if (p.sampler != 0 && p.sampler != 1) return fail(ctx, PRRTC_E_ARG, "sampler must be 0 or 1");
+    if (p.sampler == 1) {
+        if (!(p.mix >= 0.0f && p.mix <= 1.0f)) return fail(ctx, PRRTC_E_ARG, "mix must be in [0, 1]");
+        if (p.model_id < 0 || p.model_id >= (int32_t)ctx->models.size())
+            return fail(ctx, PRRTC_E_STATE, "unknown model id %d", p.model_id);
+    }
+    return PRRTC_OK;
+}
+
+// Per-query fields of A (everything but the group buffers, ctl and out_path).
+void query_args(prrtc_ctx* ctx, PlanArgs& A, const prrtc_plan_params& p, const RobotRec& r, const SceneRec& s,
+                const float* start, const float* goal, uint64_t seed, uint32_t query, int stage_cap) {
+    const int dof = r.dof;
+    A.R = r.dev_args;
+    A.S = s.dev_args;
+    for (int j = 0; j < kMaxDof; ++j) {
+        A.start[j] = j < dof ? start[j] : 0.0f;
+        A.goal[j] = j < dof ? goal[j] : 0.0f;
+    }
+    A.seed = seed;
+    A.query = query;
+    A.W = p.workers;
+    A.delta = p.delta;
+    A.res = p.res;
+    A.res_v = p.res * (float)p.validate_factor;
+    A.max_rounds = p.max_rounds;
+    A.cap = p.tree_capacity;
+    A.stage_cap = stage_cap;
+    A.validate = p.validate_factor;
+    A.dds_radius = p.dds_radius;
+    A.dds_tries = p.dds_tries;
+    A.gmm = nullptr;
+    A.mix = p.mix;
+    A.budget_ticks = p.time_budget_ms > 0.0f ? (long long)((double)p.time_budget_ms * ctx->wall_khz) : 0;
+}
+
+prrtc_status endpoints_ok(prrtc_ctx* ctx, const RobotArgs& RA, const float* start, const float* goal) {
+    if (!finite_all(start, RA.dof) || !finite_all(goal, RA.dof))
+        return fail(ctx, PRRTC_E_ARG, "start/goal not finite");
+    for (int j = 0; j < RA.dof; ++j)
+        if (!(start[j] >= RA.lo[j] && start[j] <= RA.hi[j] && goal[j] >= RA.lo[j] && goal[j] <= RA.hi[j]))
+            return fail(ctx, PRRTC_E_INVALID_ENDPOINT, "start/goal joint %d outside the limits", j);
+    return PRRTC_OK;
+}
+
+void fill_stats(const int* c, float ms, prrtc_plan_stats* st) {
+    st->rounds = c[kRounds];
+    st->nodes_a = c[kSizeA];
+    st->nodes_b = c[kSizeB];
+    st->edges_checked =
+        (int64_t)((unsigned long long)(unsigned)c[kEdgesLo] | ((unsigned long long)(unsigned)c[kEdgesHi] << 32));
+    st->validation_failures = c[kValFails];
+    st->connect_worker = c[kStatus] == kStOk ? c[kConnWorker] : -1;
+    st->gpu_ms = ms;
+    st->fallback = c[kFallback];
+    st->learned_samples =
+        (int64_t)((unsigned long long)(unsigned)c[kLearnedLo] | ((unsigned long long)(unsigned)c[kLearnedHi] << 32));
+}
+
+prrtc_status status_of(int device_status) {
+    switch (device_status) {
+        case kStOk: return PRRTC_OK;
+        case kStInvalidEndpoint: return PRRTC_E_INVALID_ENDPOINT;
+        case kStNoSolution: return PRRTC_E_NO_SOLUTION;
+        default: return PRRTC_E_HIP;
+    }
 }
 
 // Mixture of the learned proposal for one (scene, start, goal): the scene's
@@ -765,6 +931,13 @@ PlanLayout plan_layout(int dof, int cap, int W, int stage_cap, int path_cap) {
 // enqueued on sm.  qin: device staging of [start | goal] and scene row 0.
 prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, SceneRec& s, const float* start,
                            const float* goal, float* qin, float* gmm, hipStream_t sm);
+
+// Mixtures for a batch: grids of the distinct scenes into vox, one forward
+// pass over all queries.  qin: [n][2 dof_max + 1] device staging.
+prrtc_status batch_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, const std::vector<int>& scene_ids,
+                            const std::vector<int>& scene_row, const std::vector<const float*>& starts,
+                            const std::vector<const float*>& goals, uint8_t* vox, float* qin, float* gmm,
+                            hipStream_t sm);
 
 }  // namespace
 
@@ -793,6 +966,7 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
                         int32_t* path_len, prrtc_plan_stats* stats) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (path_len) *path_len = 0;
     if (stats) memset(stats, 0, sizeof *stats);
     const RobotRec* r = nullptr;
@@ -801,103 +975,52 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     if (st != PRRTC_OK) return st;
     if (!start || !goal || !prm || !path_len) return fail(ctx, PRRTC_E_ARG, "null argument");
     if (path_cap < 0 || (path_cap > 0 && !path)) return fail(ctx, PRRTC_E_ARG, "bad path buffer");
-    const int dof = r->dof;
     const prrtc_plan_params& p = *prm;
-    if (p.workers < 1 || p.workers > 4096) return fail(ctx, PRRTC_E_ARG, "workers must be in 1..4096");
-    if (!(p.delta > 0.0f) || !std::isfinite(p.delta)) return fail(ctx, PRRTC_E_ARG, "delta must be > 0");
-    if (!(p.res > 0.0f) || !std::isfinite(p.res)) return fail(ctx, PRRTC_E_ARG, "res must be > 0");
-    if (p.max_rounds < 0) return fail(ctx, PRRTC_E_ARG, "max_rounds < 0");
-    if (p.tree_capacity < 2 || p.tree_capacity > (1 << 24))
-        return fail(ctx, PRRTC_E_ARG, "tree_capacity must be in 2..2^24");
-    if (p.validate_factor < 0 || p.validate_factor > 1024)
-        return fail(ctx, PRRTC_E_ARG, "validate_factor must be in 0..1024");
-    if (!(p.dds_radius >= 0.0f) || !std::isfinite(p.dds_radius))
-        return fail(ctx, PRRTC_E_ARG, "dds_radius must be finite and >= 0");
-    if (p.dds_tries < 1 || p.dds_tries > 64) return fail(ctx, PRRTC_E_ARG, "dds_tries must be in 1..64");
-    if (p.sampler != 0 && p.sampler != 1) return fail(ctx, PRRTC_E_ARG, "sampler must be 0 or 1");
-    if (p.sampler == 1) {
-        if (!(p.mix >= 0.0f && p.mix <= 1.0f)) return fail(ctx, PRRTC_E_ARG, "mix must be in [0, 1]");
-        if (p.model_id < 0 || p.model_id >= (int32_t)ctx->models.size())
-            return fail(ctx, PRRTC_E_STATE, "unknown model id %d", p.model_id);
-        if (ctx->models[p.model_id].L.dof != r->dof)
-            return fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", ctx->models[p.model_id].L.dof, r->dof);
-    }
-    if (!finite_all(start, dof) || !finite_all(goal, dof))
-        return fail(ctx, PRRTC_E_ARG, "start/goal not finite");
-    const RobotArgs& RA = r->args;
-    for (int j = 0; j < dof; ++j)
-        if (!(start[j] >= RA.lo[j] && start[j] <= RA.hi[j] && goal[j] >= RA.lo[j] && goal[j] <= RA.hi[j]))
-            return fail(ctx, PRRTC_E_INVALID_ENDPOINT, "start/goal joint %d outside the limits", j);
-    // longest greedy connect: ceil(|hi - lo| / delta) steps (+ margin for rounding)
-    double diag = 0.0;
-    for (int j = 0; j < dof; ++j) diag += (double)(RA.hi[j] - RA.lo[j]) * (double)(RA.hi[j] - RA.lo[j]);
-    const int stage_cap = (int)std::ceil(std::sqrt(diag) / (double)p.delta * (1.0 + 1e-6)) + 2;
-    if (stage_cap > 4096) return fail(ctx, PRRTC_E_ARG, "delta too small for the joint range");
+    st = check_plan_params(ctx, p);
+    if (st != PRRTC_OK) return st;
+    if (p.sampler == 1 && ctx->models[p.model_id].L.dof != r->dof)
+        return fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", ctx->models[p.model_id].L.dof, r->dof);
+    st = endpoints_ok(ctx, r->args, start, goal);
+    if (st != PRRTC_OK) return st;
+    const int dof = r->dof;
+    const int stage_cap = stage_cap_for(r->args, p.delta);
+    if (stage_cap < 0) return fail(ctx, PRRTC_E_ARG, "delta too small for the joint range");
     const int W = p.workers, cap = p.tree_capacity;
-    const int path_cap_dev = 2 * cap;
-    const PlanLayout L = plan_layout(dof, cap, W, stage_cap, path_cap_dev);
+    const GroupLayout L = group_layout(dof, cap, W, stage_cap);
+    // after the group: query words, the query's arguments, proposal staging
+    const size_t o_ctl = L.bytes;
+    const size_t o_args = align_up<int>(o_ctl + sizeof(int) * kCtlWords);
+    const size_t o_qin = align_up<int>(o_args + sizeof(PlanArgs));
+    const size_t o_gmm = align_up<int>(o_qin + sizeof(float) * 2 * kMaxDof + sizeof(int));
+    const size_t bytes = align_up<int>(o_gmm + sizeof(float) * kComp * (1 + 2 * kMaxDof));
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    if (ctx->plan.bytes < L.bytes) {
+    if (ctx->plan.bytes < bytes) {
         planner_free(ctx->plan);
-        PRRTC_HIP(ctx, hipMalloc(&ctx->plan.mem, L.bytes));
-        ctx->plan.bytes = L.bytes;
+        PRRTC_HIP(ctx, hipMalloc(&ctx->plan.mem, bytes));
+        ctx->plan.bytes = bytes;
     }
     char* m = static_cast<char*>(ctx->plan.mem);
-    PlanArgs A;
-    const RobotArgs* RA_arg = r->dev_args;
-    const SceneArgs* SA_arg = s->dev_args;
-    for (int j = 0; j < kMaxDof; ++j) {
-        A.start[j] = j < dof ? start[j] : 0.0f;
-        A.goal[j] = j < dof ? goal[j] : 0.0f;
-    }
-    A.seed = p.seed;
-    A.query = p.query;
-    A.W = W;
-    A.delta = p.delta;
-    A.res = p.res;
-    A.res_v = p.res * (float)p.validate_factor;
-    A.max_rounds = p.max_rounds;
-    A.cap = cap;
-    A.stage_cap = stage_cap;
-    A.validate = p.validate_factor;
-    A.dds_radius = p.dds_radius;
-    A.dds_tries = p.dds_tries;
-    A.gmm = nullptr;
-    A.mix = p.mix;
-    A.budget_ticks = p.time_budget_ms > 0.0f ? (long long)((double)p.time_budget_ms * ctx->wall_khz) : 0;
-    A.qa = reinterpret_cast<float*>(m + L.qa);
-    A.pa = reinterpret_cast<int*>(m + L.pa);
-    A.ba = reinterpret_cast<unsigned char*>(m + L.ba);
-    A.ra = reinterpret_cast<float*>(m + L.ra);
-    A.qb = reinterpret_cast<float*>(m + L.qb);
-    A.pb = reinterpret_cast<int*>(m + L.pb);
-    A.bb = reinterpret_cast<unsigned char*>(m + L.bb);
-    A.rb = reinterpret_cast<float*>(m + L.rb);
-    A.ctl = reinterpret_cast<int*>(m + L.ctl);
-    A.stage = reinterpret_cast<float*>(m + L.stage);
-    int* sti = reinterpret_cast<int*>(m + L.st);
-    A.st_count = sti;
-    A.st_nn = sti + W;
-    A.st_other = sti + 2 * W;
-    A.st_conn = sti + 3 * W;
-    A.st_fail = sti + 4 * W;
-    A.path = reinterpret_cast<float*>(m + L.path);
-    A.path_idx = reinterpret_cast<int*>(m + L.path_idx);
-    A.path_cap = path_cap_dev;
-    const size_t lds = sphere_lds_bytes(RA) + sizeof(float4) * kPlanTile * 3 * RA.n_slots +
-                       sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) +
-                       sizeof(int) * (kPlanTile + 2 * (stage_cap + 2));
+    PlanArgs A{};
+    query_args(ctx, A, p, *r, *s, start, goal, p.seed, p.query, stage_cap);
+    group_args(A, m, L, W, cap);
+    A.ctl = reinterpret_cast<int*>(m + o_ctl);
+    A.out_path = A.path;
+    A.out_path_cap = A.path_cap;
+    PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
+    const size_t lds = plan_lds_bytes(r->args, stage_cap, dof);
     hipStream_t sm = ctx->stream;
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
     if (p.sampler == 1) {
-        float* gmm = reinterpret_cast<float*>(m + L.gmm);
+        float* gmm = reinterpret_cast<float*>(m + o_gmm);
         st = plan_proposal(ctx, p.model_id, *r, ctx->scenes[scene_id], start, goal,
-                           reinterpret_cast<float*>(m + L.qin), gmm, sm);
+                           reinterpret_cast<float*>(m + o_qin), gmm, sm);
         if (st != PRRTC_OK) return st;
         A.gmm = gmm;
     }
-    PRRTC_HIP(ctx, hipMemsetAsync(A.ctl, 0, sizeof(int) * kCtlWords, sm));
-    void* kargs[] = {&RA_arg, &SA_arg, &A};
+    hipLaunchKernelGGL(k_plan_init, dim3(1), dim3(256), 0, sm, A.bar, 1, (size_t)0, A.ctl, 1, A, Pq);
+    PRRTC_HIP(ctx, hipGetLastError());
+    int n_q = 1, n_g = 1;
+    void* kargs[] = {&Pq, &n_q, &n_g};
     PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
                                               dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
@@ -906,22 +1029,9 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PRRTC_HIP(ctx, hipStreamSynchronize(sm));
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    if (stats) {
-        stats->rounds = ctl[kRounds];
-        stats->nodes_a = ctl[kSizeA];
-        stats->nodes_b = ctl[kSizeB];
-        stats->edges_checked = (int64_t)((unsigned long long)(unsigned)ctl[kEdgesLo] |
-                                         ((unsigned long long)(unsigned)ctl[kEdgesHi] << 32));
-        stats->validation_failures = ctl[kValFails];
-        stats->connect_worker = ctl[kStatus] == kStOk ? ctl[kConnWorker] : -1;
-        stats->gpu_ms = ms;
-        stats->fallback = ctl[kFallback];
-        stats->learned_samples = (int64_t)((unsigned long long)(unsigned)ctl[kLearnedLo] |
-                                           ((unsigned long long)(unsigned)ctl[kLearnedHi] << 32));
-    }
+    if (stats) fill_stats(ctl, ms, stats);
     const int status = ctl[kStatus];
-    if (status == kStInternal)
-        return fail(ctx, PRRTC_E_HIP, "planner aborted on the device (code %d)", ctl[kAbort]);
+    if (status == kStInternal) return fail(ctx, PRRTC_E_HIP, "planner aborted on the device");
     if (status == kStInvalidEndpoint) return fail(ctx, PRRTC_E_INVALID_ENDPOINT, "start or goal in collision");
     if (status == kStNoSolution) return fail(ctx, PRRTC_E_NO_SOLUTION, "no connection within the round/time budget");
     const int len = ctl[kPathLen];
@@ -929,6 +1039,323 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     if (len > path_cap) return fail(ctx, PRRTC_E_CAPACITY, "path needs %d nodes, buffer holds %d", len, path_cap);
     PRRTC_HIP(ctx, hipMemcpyAsync(path, A.path, sizeof(float) * (size_t)len * dof, hipMemcpyDeviceToHost, sm));
     PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    return PRRTC_OK;
+}
+
+static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n,
+                                    const prrtc_plan_params* prm, int32_t groups, int64_t memory_budget,
+                                    float* paths, int32_t path_cap, prrtc_query_result* results,
+                                    int32_t* groups_used) {
+    ctx->err.clear();
+    if (groups_used) *groups_used = 0;
+    if (n < 0 || !prm || (n > 0 && (!queries || !results)) || path_cap < 0 || (path_cap > 0 && !paths) ||
+        groups < 0 || memory_budget < 0)
+        return fail(ctx, PRRTC_E_ARG, "bad batch arguments");
+    if (n == 0) return PRRTC_OK;
+    const prrtc_plan_params& p = *prm;
+    prrtc_status st = check_plan_params(ctx, p);
+    if (st != PRRTC_OK) return st;
+    const int W = p.workers, cap = p.tree_capacity;
+    // host-side checks per query; rejected queries are not launched
+    std::vector<int> live;
+    int dof_max = 1, stage_max = 1;
+    size_t lds = 0;
+    for (int k = 0; k < n; ++k) {
+        prrtc_query_result& res = results[k];
+        memset(&res, 0, sizeof res);
+        const RobotRec* r = nullptr;
+        const SceneRec* s = nullptr;
+        res.status = lookup(ctx, queries[k].robot_id, queries[k].scene_id, &r, &s);
+        if (res.status == PRRTC_OK) res.status = endpoints_ok(ctx, r->args, queries[k].start, queries[k].goal);
+        if (res.status == PRRTC_OK && p.sampler == 1 && ctx->models[p.model_id].L.dof != r->dof)
+            res.status = fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", ctx->models[p.model_id].L.dof,
+                              r->dof);
+        if (p.sampler == 1 && queries[k].robot_id != queries[0].robot_id)
+            return fail(ctx, PRRTC_E_ARG, "a learned batch must use one robot");
+        int sc = 0;
+        if (res.status == PRRTC_OK) {
+            sc = stage_cap_for(r->args, p.delta);
+            if (sc < 0) res.status = fail(ctx, PRRTC_E_ARG, "delta too small for the joint range");
+        }
+        if (res.status != PRRTC_OK) continue;
+        live.push_back(k);
+        dof_max = std::max(dof_max, r->dof);
+        stage_max = std::max(stage_max, sc);
+        lds = std::max(lds, plan_lds_bytes(r->args, sc, r->dof));
+    }
+    ctx->err.clear();
+    const int n_live = (int)live.size();
+    if (n_live == 0) return PRRTC_OK;
+    const GroupLayout L = group_layout(dof_max, cap, W, stage_max);
+    // co-residency bound of the cooperative launch, then the memory budget
+    int per_cu = 0;
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &per_cu, reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>), kWave, lds));
+    const int g_resident = per_cu * ctx->n_cu / W;
+    if (g_resident < 1) return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once", W);
+    int G = groups > 0 ? groups : std::min(n_live, g_resident);
+    if (G > g_resident) return fail(ctx, PRRTC_E_CAPACITY, "%d groups of %d workers exceed the %d resident",
+                                    G, W, g_resident);
+    G = std::min(G, n_live);
+    const size_t per_query = align_up<int>(sizeof(int) * kCtlWords) + sizeof(PlanArgs) +
+                             sizeof(float) * (size_t)path_cap * kMaxDof;
+    if (memory_budget > 0) {
+        const long long fit = (memory_budget - (long long)(per_query * n_live)) / (long long)L.bytes;
+        if (fit < 1) return fail(ctx, PRRTC_E_CAPACITY, "memory budget below one worker group");
+        G = (int)std::min<long long>(G, fit);
+    }
+    if (groups_used) *groups_used = G;
+    // device memory: groups | query words | arguments | paths | proposal staging
+    const int Cw = kComp * (1 + 2 * kMaxDof);
+    const size_t o_ctl = (size_t)G * L.bytes;
+    const size_t o_args = align_up<int>(o_ctl + sizeof(int) * kCtlWords * (size_t)n_live);
+    const size_t o_path = align_up<int>(o_args + sizeof(PlanArgs) * (size_t)n_live);
+    const size_t o_vox = align_up<int>(o_path + sizeof(float) * (size_t)path_cap * kMaxDof * n_live);
+    const size_t o_qin = align_up<int>(o_vox + (p.sampler == 1 ? (size_t)kVoxCells * n_live : 0));
+    const size_t o_gmm = align_up<int>(o_qin + (p.sampler == 1 ? sizeof(float) * (2 * kMaxDof + 1) * n_live : 0));
+    const size_t bytes = align_up<int>(o_gmm + (p.sampler == 1 ? sizeof(float) * Cw * (size_t)n_live : 0));
+    if (ctx->batch.bytes < bytes) {
+        planner_free(ctx->batch);
+        PRRTC_HIP(ctx, hipMalloc(&ctx->batch.mem, bytes));
+        ctx->batch.bytes = bytes;
+    }
+    char* m = static_cast<char*>(ctx->batch.mem);
+    hipStream_t sm = ctx->stream;
+    PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
+    float* gmm = reinterpret_cast<float*>(m + o_gmm);
+    if (p.sampler == 1) {
+        // one forward pass over all launched queries (they share the model, hence the robot's dof)
+        std::vector<int> scene_ids, scene_row;
+        std::vector<const float*> starts, goals;
+        for (int i = 0; i < n_live; ++i) {
+            const prrtc_query& q = queries[live[i]];
+            int row = -1;
+            for (size_t t = 0; t < scene_ids.size(); ++t)
+                if (scene_ids[t] == q.scene_id) row = (int)t;
+            if (row < 0) {
+                row = (int)scene_ids.size();
+                scene_ids.push_back(q.scene_id);
+            }
+            scene_row.push_back(row);
+            starts.push_back(q.start);
+            goals.push_back(q.goal);
+        }
+        st = batch_proposal(ctx, p.model_id, ctx->robots[queries[live[0]].robot_id], scene_ids, scene_row, starts,
+                            goals, reinterpret_cast<uint8_t*>(m + o_vox), reinterpret_cast<float*>(m + o_qin), gmm,
+                            sm);
+        if (st != PRRTC_OK) return st;
+    }
+    std::vector<PlanArgs> args(n_live);
+    for (int i = 0; i < n_live; ++i) {
+        const prrtc_query& q = queries[live[i]];
+        const RobotRec& r = ctx->robots[q.robot_id];
+        PlanArgs& A = args[i];
+        query_args(ctx, A, p, r, ctx->scenes[q.scene_id], q.start, q.goal, q.seed, q.query,
+                   stage_cap_for(r.args, p.delta));
+        group_args(A, m + (size_t)(i % G) * L.bytes, L, W, cap);
+        A.ctl = reinterpret_cast<int*>(m + o_ctl) + (size_t)kCtlWords * i;
+        A.out_path = reinterpret_cast<float*>(m + o_path) + (size_t)path_cap * kMaxDof * i;
+        A.out_path_cap = path_cap;
+        if (p.sampler == 1) A.gmm = gmm + (size_t)ctx->models[p.model_id].L.Cw * i;
+    }
+    PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
+    PRRTC_HIP(ctx, hipMemcpyAsync(Pq, args.data(), sizeof(PlanArgs) * n_live, hipMemcpyHostToDevice, sm));
+    // every group's barrier words (blocks L.bytes apart) and every query's words
+    const int init_threads = std::max(kBarWords * G, kCtlWords * n_live);
+    hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((init_threads + 255) / 256)), dim3(256), 0, sm, args[0].bar, G,
+                       L.bytes / sizeof(int), args[0].ctl, n_live, args[0], (PlanArgs*)nullptr);
+    PRRTC_HIP(ctx, hipGetLastError());
+    int n_q = n_live, n_g = G;
+    void* kargs[] = {&Pq, &n_q, &n_g};
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
+                                              dim3((unsigned)(G * W)), dim3(kWave), kargs, (unsigned)lds, sm));
+    PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
+    std::vector<int> ctl((size_t)kCtlWords * n_live);
+    PRRTC_HIP(ctx, hipMemcpyAsync(ctl.data(), args[0].ctl, sizeof(int) * ctl.size(), hipMemcpyDeviceToHost, sm));
+    PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    // paths: one copy of the whole block when every query was launched (the
+    // host and device layouts then agree), else one copy per solved query
+    const bool bulk = n_live == n && n > 64 && path_cap > 0;
+    if (bulk)
+        PRRTC_HIP(ctx, hipMemcpyAsync(paths, m + o_path, sizeof(float) * (size_t)path_cap * kMaxDof * n,
+                                      hipMemcpyDeviceToHost, sm));
+    for (int i = 0; i < n_live; ++i) {
+        const int* c = ctl.data() + (size_t)kCtlWords * i;
+        prrtc_query_result& res = results[live[i]];
+        fill_stats(c, ms, &res.stats);
+        res.status = status_of(c[kStatus]);
+        if (res.status == PRRTC_OK) {
+            res.path_len = c[kPathLen];
+            if (res.path_len > path_cap) {
+                res.status = PRRTC_E_CAPACITY;
+            } else if (!bulk) {
+                const int dof = ctx->robots[queries[live[i]].robot_id].dof;
+                PRRTC_HIP(ctx, hipMemcpyAsync(paths + (size_t)live[i] * path_cap * kMaxDof, args[i].out_path,
+                                              sizeof(float) * (size_t)res.path_len * dof, hipMemcpyDeviceToHost, sm));
+            }
+        }
+    }
+    PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_plan_batch(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n,
+                              const prrtc_plan_params* prm, int32_t groups, int64_t memory_budget,
+                              float* paths, int32_t path_cap, prrtc_query_result* results,
+                              int32_t* groups_used) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
+    return plan_batch_impl(ctx, queries, n, prm, groups, memory_budget, paths, path_cap, results, groups_used);
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Serving: a thread owned by the context gathers submitted queries into
+// batched launches (continuous batching at launch granularity).
+// ----------------------------------------------------------------------------
+namespace {
+
+void serve_loop(prrtc_ctx* ctx) {
+    Server& S = *ctx->server;
+    (void)hipSetDevice(ctx->device);
+    std::vector<prrtc_query> qs;
+    std::vector<uint64_t> tickets;
+    std::vector<prrtc_query_result> res;
+    std::vector<float> paths;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.cv.wait(lk, [&] { return S.stop || !S.queue.empty(); });
+            if (S.queue.empty()) return;   // stop requested and drained
+            qs.clear();
+            tickets.clear();
+            while (!S.queue.empty() && (int)qs.size() < S.slots) {
+                tickets.push_back(S.queue.front().first);
+                qs.push_back(S.queue.front().second);
+                S.queue.pop_front();
+            }
+            for (uint64_t t : tickets) S.running[t] = 1;
+        }
+        const int n = (int)qs.size();
+        res.assign(n, prrtc_query_result{});
+        paths.assign((size_t)n * S.path_cap * kMaxDof, 0.0f);
+        const prrtc_status st = plan_batch_impl(ctx, qs.data(), n, &S.params, 0, S.budget, paths.data(), S.path_cap,
+                                                res.data(), nullptr);
+        std::lock_guard<std::mutex> lk(S.mu);
+        for (int i = 0; i < n; ++i) {
+            ServeDone d;
+            d.res = res[i];
+            if (st != PRRTC_OK) {
+                d.res = prrtc_query_result{};
+                d.res.status = st;
+            }
+            if (d.res.status == PRRTC_OK) {
+                const int dof = ctx->robots[qs[i].robot_id].dof;
+                const float* src = paths.data() + (size_t)i * S.path_cap * kMaxDof;
+                d.path.assign(src, src + (size_t)d.res.path_len * dof);
+            }
+            S.done[tickets[i]] = std::move(d);
+            S.running.erase(tickets[i]);
+        }
+        ++S.launches;
+    }
+}
+
+void serve_shutdown(prrtc_ctx* ctx) {
+    if (!ctx->server) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->server->mu);
+        ctx->server->stop = true;
+    }
+    ctx->server->cv.notify_all();
+    if (ctx->server->th.joinable()) ctx->server->th.join();
+    ctx->server.reset();
+    ctx->serving.store(false);
+}
+
+}  // namespace
+
+extern "C" {
+
+prrtc_status prrtc_serve_start(prrtc_ctx* ctx, const prrtc_plan_params* params, int32_t slots, int32_t max_pending,
+                               int64_t memory_budget, int32_t path_cap) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
+    if (!params || slots < 1 || slots > 65536 || max_pending < slots || memory_budget < 0 || path_cap < 1 ||
+        path_cap > (1 << 20))
+        return fail(ctx, PRRTC_E_ARG, "bad serving arguments");
+    prrtc_status st = check_plan_params(ctx, *params);
+    if (st != PRRTC_OK) return st;
+    std::unique_ptr<Server> S(new Server());
+    S->params = *params;
+    S->slots = slots;
+    S->max_pending = max_pending;
+    S->budget = memory_budget;
+    S->path_cap = path_cap;
+    ctx->server = std::move(S);
+    ctx->serving.store(true);
+    try {
+        ctx->server->th = std::thread(serve_loop, ctx);
+    } catch (...) {
+        ctx->server.reset();
+        ctx->serving.store(false);
+        return fail(ctx, PRRTC_E_STATE, "cannot start the serving thread");
+    }
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_submit(prrtc_ctx* ctx, const prrtc_query* query, uint64_t* ticket) {
+    if (!ctx || !query || !ticket) return PRRTC_E_ARG;
+    if (!ctx->serving.load() || !ctx->server) return PRRTC_E_STATE;
+    Server& S = *ctx->server;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if ((int)S.in_flight() >= S.max_pending) return PRRTC_E_BUSY;
+        *ticket = S.next_ticket++;
+        S.queue.emplace_back(*ticket, *query);
+    }
+    S.cv.notify_one();
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_poll(prrtc_ctx* ctx, uint64_t ticket, prrtc_query_result* result, float* path,
+                        int32_t path_cap) {
+    if (!ctx || !result || path_cap < 0 || (path_cap > 0 && !path)) return PRRTC_E_ARG;
+    if (!ctx->serving.load() || !ctx->server) return PRRTC_E_STATE;
+    Server& S = *ctx->server;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.done.find(ticket);
+    if (it == S.done.end()) {
+        if (S.running.count(ticket)) return PRRTC_E_BUSY;
+        for (const auto& q : S.queue)
+            if (q.first == ticket) return PRRTC_E_BUSY;
+        return PRRTC_E_STATE;
+    }
+    *result = it->second.res;
+    if (result->status == PRRTC_OK) {
+        const int dof = (int)(it->second.path.size() / std::max(1, result->path_len));
+        if (result->path_len > path_cap) return PRRTC_E_CAPACITY;   // kept: poll again with a larger buffer
+        if (!it->second.path.empty()) memcpy(path, it->second.path.data(), sizeof(float) * it->second.path.size());
+        (void)dof;
+    }
+    S.done.erase(it);
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_serve_stop(prrtc_ctx* ctx, int64_t* launches) {
+    if (!ctx) return PRRTC_E_ARG;
+    if (!ctx->serving.load() || !ctx->server) return PRRTC_E_STATE;
+    if (launches) {
+        std::lock_guard<std::mutex> lk(ctx->server->mu);
+        *launches = ctx->server->launches;
+    }
+    serve_shutdown(ctx);
     return PRRTC_OK;
 }
 
@@ -1061,6 +1488,35 @@ prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, 
     return PRRTC_OK;
 }
 
+prrtc_status batch_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, const std::vector<int>& scene_ids,
+                            const std::vector<int>& scene_row, const std::vector<const float*>& starts,
+                            const std::vector<const float*>& goals, uint8_t* vox, float* qin, float* gmm,
+                            hipStream_t sm) {
+    ModelRec& M = ctx->models[model_id];
+    const int dof = r.dof;
+    const int n = (int)starts.size(), S = (int)scene_ids.size();
+    for (int t = 0; t < S; ++t)
+        hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, sm, ctx->scenes[scene_ids[t]].args,
+                           vox + (size_t)t * kVoxCells);
+    PropWs W;
+    prrtc_status st = prop_workspace(ctx, M, n, S, W);
+    if (st != PRRTC_OK) return st;
+    // [n][dof] starts | [n][dof] goals | [n] scene rows; the host staging
+    // stays untouched until the batch has synchronised
+    std::vector<float>& h = ctx->stage_host;
+    h.assign((size_t)2 * n * dof + n, 0.0f);
+    for (int i = 0; i < n; ++i) {
+        memcpy(&h[(size_t)i * dof], starts[i], sizeof(float) * dof);
+        memcpy(&h[(size_t)(n + i) * dof], goals[i], sizeof(float) * dof);
+        memcpy(&h[(size_t)2 * n * dof + i], &scene_row[i], sizeof(int));
+    }
+    PRRTC_HIP(ctx, hipMemcpyAsync(qin, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, sm));
+    prop_forward(sm, M, W, r.dev_args, vox, S, reinterpret_cast<const int*>(qin + (size_t)2 * n * dof), qin,
+                 qin + (size_t)n * dof, nullptr, n, gmm);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1068,6 +1524,7 @@ extern "C" {
 prrtc_status prrtc_load_proposal(prrtc_ctx* ctx, const void* blob, size_t bytes, int32_t* model_id) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (!blob || !model_id || bytes < sizeof(PropHeader)) return fail(ctx, PRRTC_E_ARG, "blob too small");
     PropHeader h;
     memcpy(&h, blob, sizeof h);
@@ -1099,6 +1556,7 @@ prrtc_status prrtc_load_proposal(prrtc_ctx* ctx, const void* blob, size_t bytes,
 prrtc_status prrtc_save_proposal(prrtc_ctx* ctx, int32_t model_id, void* blob, size_t cap, size_t* bytes) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (model_id < 0 || model_id >= (int32_t)models_of(ctx).size())
         return fail(ctx, PRRTC_E_STATE, "unknown model id %d", model_id);
     if (!bytes) return fail(ctx, PRRTC_E_ARG, "null size");
@@ -1119,6 +1577,7 @@ prrtc_status prrtc_save_proposal(prrtc_ctx* ctx, int32_t model_id, void* blob, s
 prrtc_status prrtc_voxelize(prrtc_ctx* ctx, int32_t scene_id, uint8_t* vox, void* stream) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
         return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
     if (!vox) return fail(ctx, PRRTC_E_ARG, "null buffer");
@@ -1146,6 +1605,7 @@ prrtc_status prrtc_proposal_forward(prrtc_ctx* ctx, int32_t model_id, int32_t ro
                                     const float* goal, int32_t n, float* gmm, void* stream) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     ModelRec* M;
     const RobotArgs* R;
     prrtc_status st = prop_common(ctx, model_id, robot_id, &M, &R);
@@ -1168,6 +1628,7 @@ prrtc_status prrtc_proposal_sample(prrtc_ctx* ctx, int32_t robot_id, const float
                                    uint8_t* inside, void* stream) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     if (robot_id < 0 || robot_id >= (int32_t)ctx->robots.size())
         return fail(ctx, PRRTC_E_STATE, "unknown robot id %d", robot_id);
     if (n < 0 || attempt > 0x7FFFFFu) return fail(ctx, PRRTC_E_ARG, "bad sizes");
@@ -1185,6 +1646,7 @@ prrtc_status prrtc_train_proposal(prrtc_ctx* ctx, int32_t model_id, int32_t robo
                                   float lr, float* loss, void* stream) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
     ModelRec* M;
     const RobotArgs* R;
     prrtc_status st = prop_common(ctx, model_id, robot_id, &M, &R);

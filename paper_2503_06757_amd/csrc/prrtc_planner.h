@@ -28,12 +28,15 @@
 
 namespace prrtc {
 
-// Control words (int32) in device memory; zeroed before each launch.
+// Barrier words (int32) of one worker group in device memory, zeroed before
+// each launch: arrival counter, generation and the group's sticky abort word
+// on separate cache lines.
+enum Bar { kBarCount = 0, kBarGen = 32, kAbort = 64, kBarWords = 96 };
+
+// Control and result words (int32) of one query, set up before each launch
+// (status = internal error, everything else 0).
 enum Ctl {
-    kBarCount = 0,
-    kBarGen = 32,      // separate cache line from the arrival counter
-    kAbort = 64,
-    kSizeA,
+    kSizeA = 0,
     kSizeB,
     kStatus,
     kPathLen,
@@ -44,19 +47,23 @@ enum Ctl {
     kEndpointBad,
     kValBad,
     kNa,
+    kFallback,         // 1: the mixture was not finite, uniform sampling used
     kEdgesLo,          // 64-bit edge counter (two words)
     kEdgesHi,
     kLearnedLo,        // 64-bit count of draws taken from the learned mixture
     kLearnedHi,
-    kFallback,         // 1: the mixture was not finite, uniform sampling used         // 1: the mixture was not finite, uniform sampling used
-    kCtlWords = 96
+    kCtlWords = 32
 };
 static_assert(kEdgesLo % 2 == 0 && kLearnedLo % 2 == 0, "64-bit counters need 8-byte alignment");
 
 // Status codes written by the kernel (mirror prrtc_status).
 constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInternal = -7;
 
+// One query of a launch.  Trees, staging, path and barrier words belong to
+// the worker group that runs the query; ctl and out_path to the query.
 struct PlanArgs {
+    const RobotArgs* R;       // device copies of the robot and scene tables
+    const SceneArgs* S;
     float start[kMaxDof], goal[kMaxDof];
     unsigned long long seed;
     unsigned int query;
@@ -70,13 +77,18 @@ struct PlanArgs {
     long long budget_ticks;   // <= 0: none
     float* qa; int* pa; unsigned char* ba; float* ra;
     float* qb; int* pb; unsigned char* bb; float* rb;
-    int* ctl;
+    int* bar;                 // group barrier words [kBarWords]
+    int* ctl;                 // query words [kCtlWords]
     float* stage;             // [W][stage_cap][dof]
     int* st_count; int* st_nn; int* st_other; int* st_conn; int* st_fail;
     float* path;              // [path_cap][dof]
     int* path_idx;            // [path_cap] tree node index; tree = (k < na ? A : B)
     int path_cap;
+    float* out_path;          // [out_path_cap][dof]: the query's path (may equal path)
+    int out_path_cap;
 };
+static_assert(sizeof(PlanArgs) % sizeof(int) == 0 && sizeof(PlanArgs) <= 256 * sizeof(int),
+              "k_plan_init copies PlanArgs with one block of 256 threads");
 
 // Device memory owned by a context for planner launches (grown on demand).
 struct PlannerBuffers {
@@ -96,13 +108,13 @@ inline void planner_free(PlannerBuffers& b) {
 // A wait longer than ~2 s (the GPU wall clock) raises the abort word, and
 // every workgroup leaves its round loop on abort, so the grid always drains.
 // ----------------------------------------------------------------------------
-__device__ inline bool grid_barrier(int* ctl, int nblocks) {
+__device__ inline bool grid_barrier(int* bar, int nblocks) {
     __shared__ int ok_s;
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        unsigned* cnt = reinterpret_cast<unsigned*>(ctl + kBarCount);
-        unsigned* gen = reinterpret_cast<unsigned*>(ctl + kBarGen);
+        unsigned* cnt = reinterpret_cast<unsigned*>(bar + kBarCount);
+        unsigned* gen = reinterpret_cast<unsigned*>(bar + kBarGen);
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -113,19 +125,19 @@ __device__ inline bool grid_barrier(int* ctl, int nblocks) {
             const unsigned long long t0 = wall_clock64();
             while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
-                if (__hip_atomic_load(ctl + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
                     break;
                 }
                 if (wall_clock64() - t0 > 200000000ull) {  // 2 s at the 100 MHz wall clock
-                    __hip_atomic_store(ctl + kAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(bar + kAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
                 }
             }
         }
         __threadfence();
-        if (__hip_atomic_load(ctl + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
         ok_s = ok;
     }
     __syncthreads();
@@ -165,14 +177,18 @@ __device__ inline int wave_nearest(const float* tq, const unsigned char* blocked
     return bi == 0x7fffffff ? -1 : bi;
 }
 
+// One query on the W workers of a group (worker w); false if the group
+// aborted (a barrier timed out or an internal limit was hit).
+// The query's arguments are read through the constant address space: they
+// never change during the launch, so the compiler may reload them instead of
+// keeping every field live in registers.
+typedef __attribute__((address_space(4))) const PlanArgs CPlanArgs;
+
 template <int TP, int B>
-__global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp,
-                                                const SceneArgs* __restrict__ Sp, PlanArgs P) {
-    const RobotArgs& R = *Rp;   // resident in device memory: uniform reads are scalar loads
-    const SceneArgs& S = *Sp;
-    extern __shared__ float4 lds4[];
+__device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, float4* lds4) {
+    const RobotArgs& R = *P.R;   // device memory: uniform reads are scalar loads
+    const SceneArgs& S = *P.S;
     const int lane = threadIdx.x;
-    const int w = blockIdx.x;
     const int dof = R.dof;
     const int cap = P.cap;
     // ---- LDS carve-up
@@ -199,8 +215,8 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
 
     // ---- prologue: roots, endpoint checks
     if (w == 0 && lane < dof) {
-        P.qa[(size_t)lane * cap] = pick(P.start, lane);
-        P.qb[(size_t)lane * cap] = pick(P.goal, lane);
+        P.qa[(size_t)lane * cap] = P.start[lane];
+        P.qb[(size_t)lane * cap] = P.goal[lane];
     }
     if (w == 0 && lane == 0) {
         P.pa[0] = -1;
@@ -226,7 +242,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
     const int n_end_workers = P.W > 1 ? 2 : 1;
     for (int e = w; e < 2; e += n_end_workers) {
         if (lane < dof) {
-            const float v = e == 0 ? pick(P.start, lane) : pick(P.goal, lane);
+            const float v = e == 0 ? P.start[lane] : P.goal[lane];
             wp[lane] = v;
             wp[dof + lane] = v;
         }
@@ -235,10 +251,10 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
         if (!ok && lane == 0) atomicOr(ctl + kEndpointBad, 1);
         __syncthreads();
     }
-    if (!grid_barrier(ctl, P.W)) return;
+    if (!grid_barrier(P.bar, P.W)) return false;
     if (ctl[kEndpointBad]) {
         if (w == 0 && lane == 0) ctl[kStatus] = kStInvalidEndpoint;
-        return;
+        return true;
     }
     const unsigned long long t_start = wall_clock64();
     int status = kStNoSolution;
@@ -320,7 +336,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
                     }
                     if (n_ext > P.stage_cap) {
                         // cannot happen for nodes inside the joint limits
-                        if (lane == 0) atomicExch(ctl + kAbort, 2);
+                        if (lane == 0) atomicExch(P.bar + kAbort, 2);
                         n_ext = P.stage_cap;
                     }
                     // waypoints t_0 = c_new, t_k = fmaf(k / n_ext, c_nno - c_new, c_new), t_n = c_nno
@@ -354,7 +370,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
             P.st_conn[w] = conn;
             P.st_fail[w] = fail;
         }
-        if (!grid_barrier(ctl, P.W)) break;
+        if (!grid_barrier(P.bar, P.W)) break;
         // ===== phase B: ordered commit
         int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1;
         for (int c0 = 0; c0 < P.W; c0 += kWave) {
@@ -404,7 +420,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
             ctl[s_is_a ? kSizeA : kSizeB] = new_size;
             if (P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks) ctl[kStop] = 1;
         }
-        if (!grid_barrier(ctl, P.W)) break;
+        if (!grid_barrier(P.bar, P.W)) break;
         // ===== phase C: path and re-check
         if (first != 0x7fffffff) {
             const int xa = s_is_a ? first_last : first_other;
@@ -422,7 +438,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
                         for (int x = xb; x >= 0; x = P.pb[x]) P.path_idx[m++] = x;
                     } else {
                         bad = 1;
-                        atomicExch(ctl + kAbort, 3);
+                        atomicExch(P.bar + kAbort, 3);
                     }
                     if (P.validate <= 0) bad = len > P.path_cap;  // no re-check: blocked nodes cannot exist
                     ctl[kNa] = la;
@@ -448,7 +464,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
                     }
                 }
             }
-            if (!grid_barrier(ctl, P.W)) break;
+            if (!grid_barrier(P.bar, P.W)) break;
             const int la = ctl[kNa], len = ctl[kPathLen];
             if (P.validate > 0) {
                 for (int k = w; k + 1 < len; k += P.W) {
@@ -465,7 +481,7 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
                     __syncthreads();
                 }
             }
-            if (!grid_barrier(ctl, P.W)) break;
+            if (!grid_barrier(P.bar, P.W)) break;
             if (!ctl[kValBad]) {
                 status = kStOk;
                 if (w == 0 && lane == 0) ctl[kConnWorker] = first;
@@ -482,11 +498,43 @@ __global__ __launch_bounds__(kWave) void k_plan(const RobotArgs* __restrict__ Rp
     if (lane == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
     if (lane == 0 && my_learned)
         atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kLearnedLo), (unsigned long long)my_learned);
-    if (w == 0 && lane == 0) {
-        ctl[kRounds] = round;
-        if (ctl[kAbort]) ctl[kStatus] = kStInternal;
-        else ctl[kStatus] = status;
+    const bool aborted = __hip_atomic_load(P.bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (w == 0) {
+        // hand the path to the query's own buffer (the group's is reused)
+        const int len = ctl[kPathLen];
+        if (!aborted && status == kStOk && P.out_path != P.path && len <= P.out_path_cap)
+            for (int e = lane; e < len * dof; e += kWave) P.out_path[e] = P.path[e];
+        if (lane == 0) {
+            ctl[kRounds] = round;
+            ctl[kStatus] = aborted ? kStInternal : status;
+        }
     }
+    return !aborted;
+}
+
+// Prepare a launch: zero the barrier words of n_groups groups (bar_stride
+// ints apart) and set every query's words to (status = internal error,
+// rest 0); with Pq, the single query's arguments (by value) are stored there.
+__global__ void k_plan_init(int* bar, int n_groups, size_t bar_stride, int* ctl, int n_queries, PlanArgs one_query,
+                            PlanArgs* Pq) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_groups * kBarWords) bar[(size_t)(t / kBarWords) * bar_stride + t % kBarWords] = 0;
+    if (t < n_queries * kCtlWords) ctl[t] = (t % kCtlWords) == kStatus ? kStInternal : 0;
+    if (Pq && t < (int)(sizeof(PlanArgs) / sizeof(int)))
+        reinterpret_cast<int*>(Pq)[t] = reinterpret_cast<const int*>(&one_query)[t];
+}
+
+// Persistent planner: n_groups groups of W one-wave workgroups; group g runs
+// queries g, g + n_groups, ... one after another.  All queries of a launch
+// share W.  A group that aborts leaves its remaining queries at "internal".
+template <int TP, int B>
+__global__ __launch_bounds__(kWave) void k_plan(const PlanArgs* __restrict__ Pq, int n_queries, int n_groups) {
+    extern __shared__ float4 lds4[];
+    const int W = Pq[0].W;
+    const int g = blockIdx.x / W;
+    const int w = blockIdx.x - g * W;
+    for (int k = g; k < n_queries; k += n_groups)
+        if (!plan_query<TP, B>(((CPlanArgs*)Pq)[k], w, lds4)) break;
 }
 
 }  // namespace prrtc

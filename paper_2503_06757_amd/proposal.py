@@ -127,11 +127,12 @@ class Dataset:
         return self
 
 
-def generate(P, ctx, torch, rid: int, robot: dict, n_scenes: int, base: int = SEED_TRAIN, max_rounds: int = 2000,
-             log=None) -> Dataset:
+def generate(P, ctx, torch, rid: int, robot: dict, n_scenes: int, base: int = SEED_TRAIN, max_rounds: int = 1000,
+             budget_ms: float = 50.0, log=None) -> Dataset:
     """Solve one query per scene with the uniform planner and keep the path's
     waypoints every 0.25 rad (endpoints excluded).  Scenes without a free
-    query or a solution contribute no samples."""
+    query or a solution within the round and time budget contribute no
+    samples."""
     dof = int(np.asarray(robot["q_lo"]).shape[0])
     ds = Dataset(dof)
     vox = torch.zeros(VOX ** 3, dtype=torch.uint8, device="cuda")
@@ -143,7 +144,7 @@ def generate(P, ctx, torch, rid: int, robot: dict, n_scenes: int, base: int = SE
         path = None
         if q is not None:
             p = P.prrtc_plan_params_default()
-            p.seed, p.max_rounds = base + i, max_rounds
+            p.seed, p.max_rounds, p.time_budget_ms = base + i, max_rounds, budget_ms
             st, path, _ = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
             if st != P.PRRTC_OK:
                 path = None
@@ -159,7 +160,7 @@ def generate(P, ctx, torch, rid: int, robot: dict, n_scenes: int, base: int = SE
                 ds.goal.append(q[1])
                 ds.waypoint.append(w)
         P.prrtc_unload_scene(ctx, sid)
-        if log and (i + 1) % 1000 == 0:
+        if log and (i + 1) % 100 == 0:
             log("  %d/%d scenes, %d solved, %d samples" % (i + 1, n_scenes, len(ds.vox), len(ds.scene_of)))
     return ds.finish()
 
@@ -249,9 +250,10 @@ def mean_nll(P, ctx, torch, mid: int, rid: int, ds: Dataset, lo, hi) -> float:
 
 
 def compare(P, ctx, torch, mid: int, rid: int, robot: dict, n_scenes: int, base: int = SEED_EVAL,
-            mix: float = 0.5, max_rounds: int = 2000, log=None) -> dict:
+            mix: float = 0.5, max_rounds: int = 2000, budget_ms: float = 100.0, log=None) -> dict:
     """Uniform against learned sampling on held-out scenes, one query each,
-    same seed and budget: wall time of the prrtc_plan call and success."""
+    same seed, round limit and time budget: wall time of the prrtc_plan call
+    and success."""
     res = {"plain": [], "learned": []}
     for i in range(n_scenes):
         sid = P.prrtc_load_scene(ctx, scene(robot, i, base))
@@ -260,11 +262,14 @@ def compare(P, ctx, torch, mid: int, rid: int, robot: dict, n_scenes: int, base:
             for name, sampler in (("plain", 0), ("learned", 1)):
                 p = P.prrtc_plan_params_default()
                 p.seed, p.max_rounds, p.sampler, p.model_id, p.mix = base + i, max_rounds, sampler, mid, mix
+                p.time_budget_ms = budget_ms
                 t0 = time.perf_counter()
                 st, _, stats = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
                 ms = (time.perf_counter() - t0) * 1e3
                 res[name].append((st == P.PRRTC_OK, ms, stats["rounds"], stats["gpu_ms"]))
         P.prrtc_unload_scene(ctx, sid)
+        if log and (i + 1) % 50 == 0:
+            log("  compared %d/%d scenes" % (i + 1, n_scenes))
     out = {}
     for name, rows in res.items():
         a = np.array(rows, np.float64).reshape(-1, 4)

@@ -78,6 +78,26 @@ class prrtc_plan_stats(C.Structure):
     ]
 
 
+class prrtc_query(C.Structure):
+    _fields_ = [
+        ("robot_id", C.c_int32),
+        ("scene_id", C.c_int32),
+        ("start", C.c_float * 16),
+        ("goal", C.c_float * 16),
+        ("seed", C.c_uint64),
+        ("query", C.c_uint32),
+        ("pad", C.c_int32),
+    ]
+
+
+class prrtc_query_result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32),
+        ("path_len", C.c_int32),
+        ("stats", prrtc_plan_stats),
+    ]
+
+
 class prrtc_train_batch(C.Structure):
     _fields_ = [
         ("vox", C.c_void_p),
@@ -138,6 +158,17 @@ def _load():
         L.prrtc_plan.argtypes = [P, I32, I32, VP, VP, C.POINTER(prrtc_plan_params), VP, I32,
                                  C.POINTER(I32), C.POINTER(prrtc_plan_stats)]
         L.prrtc_plan.restype = I32
+        L.prrtc_plan_batch.argtypes = [P, C.POINTER(prrtc_query), I32, C.POINTER(prrtc_plan_params), I32, I64,
+                                       VP, I32, C.POINTER(prrtc_query_result), C.POINTER(I32)]
+        L.prrtc_plan_batch.restype = I32
+        L.prrtc_serve_start.argtypes = [P, C.POINTER(prrtc_plan_params), I32, I32, I64, I32]
+        L.prrtc_serve_start.restype = I32
+        L.prrtc_submit.argtypes = [P, C.POINTER(prrtc_query), C.POINTER(C.c_uint64)]
+        L.prrtc_submit.restype = I32
+        L.prrtc_poll.argtypes = [P, C.c_uint64, C.POINTER(prrtc_query_result), VP, I32]
+        L.prrtc_poll.restype = I32
+        L.prrtc_serve_stop.argtypes = [P, C.POINTER(I64)]
+        L.prrtc_serve_stop.restype = I32
     return L
 
 
@@ -146,7 +177,8 @@ lib = _load()
 # the symbols include/prrtc.h declares (checked by the CPU test-suite)
 EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
             "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_fk_spheres",
-            "prrtc_plan_params_default", "prrtc_plan", "prrtc_load_proposal", "prrtc_save_proposal",
+            "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch",
+            "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
             "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_sample", "prrtc_train_proposal")
 
 
@@ -256,6 +288,88 @@ def prrtc_plan(ctx: int, robot_id: int, scene_id: int, start: np.ndarray, goal: 
     stats = {f: getattr(st, f) for f, _ in prrtc_plan_stats._fields_}
     stats["path_len"] = ln.value
     return status, (path[: ln.value].copy() if status == PRRTC_OK else None), stats
+
+
+_QUERY_DT = np.dtype(prrtc_query)
+_RESULT_DT = np.dtype(prrtc_query_result)
+
+
+def prrtc_plan_batch(ctx: int, queries, params, groups: int = 0, memory_budget: int = 0, path_cap: int = 256):
+    """queries: list of (robot_id, scene_id, start, goal, seed, query).  Returns
+    (groups used, [(status, path or None, stats dict)])."""
+    n = len(queries)
+    arr = np.zeros(max(n, 1), _QUERY_DT)
+    if n:
+        arr["robot_id"][:n] = [q[0] for q in queries]
+        arr["scene_id"][:n] = [q[1] for q in queries]
+        arr["seed"][:n] = [q[4] for q in queries]
+        arr["query"][:n] = [q[5] for q in queries]
+        for k, q in enumerate(queries):
+            d = len(q[2])
+            arr["start"][k, :d] = q[2]
+            arr["goal"][k, :d] = q[3]
+    paths = np.zeros((max(n, 1), path_cap, 16), np.float32)
+    res = np.zeros(max(n, 1), _RESULT_DT)
+    used = C.c_int32(0)
+    _check(ctx, lib.prrtc_plan_batch(ctx, arr.ctypes.data_as(C.POINTER(prrtc_query)), n, C.byref(params),
+                                     int(groups), int(memory_budget), paths.ctypes.data, int(path_cap),
+                                     res.ctypes.data_as(C.POINTER(prrtc_query_result)), C.byref(used)))
+    out = []
+    names = [f for f, _ in prrtc_plan_stats._fields_]
+    for k, q in enumerate(queries):
+        r = res[k]
+        dof = len(q[2])
+        stats = {f: r["stats"][f].item() for f in names}
+        stats["path_len"] = int(r["path_len"])
+        path = None
+        st = int(r["status"])
+        if st == PRRTC_OK:
+            path = paths[k].reshape(-1)[: stats["path_len"] * dof].reshape(-1, dof).copy()
+        out.append((st, path, stats))
+    return used.value, out
+
+
+def prrtc_serve_start(ctx: int, params, slots: int = 256, max_pending: int = 1024, memory_budget: int = 0,
+                      path_cap: int = 256) -> None:
+    _check(ctx, lib.prrtc_serve_start(ctx, C.byref(params), int(slots), int(max_pending), int(memory_budget),
+                                      int(path_cap)))
+
+
+def prrtc_submit(ctx: int, robot_id: int, scene_id: int, start, goal, seed: int, query: int = 0):
+    """Ticket, or None when admission is refused (E_BUSY)."""
+    q = prrtc_query()
+    q.robot_id, q.scene_id, q.seed, q.query = int(robot_id), int(scene_id), int(seed), int(query)
+    for j, v in enumerate(np.asarray(start, np.float32)):
+        q.start[j] = float(v)
+    for j, v in enumerate(np.asarray(goal, np.float32)):
+        q.goal[j] = float(v)
+    t = C.c_uint64(0)
+    st = lib.prrtc_submit(ctx, C.byref(q), C.byref(t))
+    if st == PRRTC_E_BUSY:
+        return None
+    if st != PRRTC_OK:   # the serving thread owns the error text: not read here
+        raise PrrtcError(st, "prrtc_submit refused")
+    return t.value
+
+
+def prrtc_poll(ctx: int, ticket: int, dof: int, path_cap: int = 256):
+    """None while the query is queued or running, else (status, path or None, stats)."""
+    r = prrtc_query_result()
+    path = np.zeros((path_cap, dof), np.float32)
+    st = lib.prrtc_poll(ctx, int(ticket), C.byref(r), path.ctypes.data, int(path_cap))
+    if st == PRRTC_E_BUSY:
+        return None
+    if st != PRRTC_OK:
+        raise PrrtcError(st, "prrtc_poll failed")
+    stats = {f: getattr(r.stats, f) for f, _ in prrtc_plan_stats._fields_}
+    stats["path_len"] = r.path_len
+    return r.status, (path[: r.path_len].copy() if r.status == PRRTC_OK else None), stats
+
+
+def prrtc_serve_stop(ctx: int) -> int:
+    n = C.c_int64(0)
+    _check(ctx, lib.prrtc_serve_stop(ctx, C.byref(n)))
+    return n.value
 
 
 # ---- learned proposal ---------------------------------------------------------------

@@ -1,0 +1,164 @@
+"""GPU tests of prrtc_plan_batch: many queries in one persistent launch,
+one group of workers per query.  Every query must come out exactly as the
+single-query planner returns it with the same parameters, seed and query
+word (the oracle parity of that planner is covered by its own tests)."""
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import free_query
+from paper_2503_06757_amd import proposal as PR
+from paper_2503_06757_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("rounds", "nodes_a", "nodes_b", "edges_checked", "validation_failures", "connect_worker",
+        "learned_samples", "fallback")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def params(P, **kw):
+    p = P.prrtc_plan_params_default()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.fixture(scope="module")
+def mixed(gpu, orc, r7, r14):
+    """12 R7 queries over 6 S12 scenes and 4 R14 queries on S12 scenes."""
+    P, ctx, _ = gpu
+    rid7, rid14 = P.prrtc_load_robot(ctx, r7), P.prrtc_load_robot(ctx, r14)
+    qs = []
+    for inst in range(6):
+        prims = W.scene_s12(r7, inst)
+        sid = P.prrtc_load_scene(ctx, prims)
+        rob = orc.OracleRobot(r7)
+        for j in range(2):
+            s, g = free_query(orc, rob, prims, r7, W.SEED_QUERY + 100 * j + inst)
+            qs.append((rid7, sid, s, g, 70 + 10 * inst + j, j))
+    for inst in range(4):
+        prims = W.scene_s12(r14, inst)
+        sid = P.prrtc_load_scene(ctx, prims)
+        s, g = free_query(orc, orc.OracleRobot(r14), prims, r14, W.SEED_QUERY + 500 + inst)
+        qs.append((rid14, sid, s, g, 900 + inst, 3))
+    return qs
+
+
+def _single(P, ctx, q, prm):
+    rid, sid, s, g, seed, qw = q
+    prm.seed, prm.query = seed, qw
+    return P.prrtc_plan(ctx, rid, sid, s, g, prm)
+
+
+@pytest.mark.parametrize("groups,workers", [(4, 64), (16, 32), (0, 128)])
+def test_batch_equals_single(gpu, mixed, groups, workers):
+    P, ctx, _ = gpu
+    say("batch of %d queries, groups %d, workers %d" % (len(mixed), groups, workers))
+    prm = params(P, workers=workers, max_rounds=500)
+    used, out = P.prrtc_plan_batch(ctx, mixed, prm, groups=groups, path_cap=512)
+    say("  groups used", used)
+    assert used == (groups if groups else len(mixed))
+    for k, q in enumerate(mixed):
+        st, path, stats = out[k]
+        st1, path1, stats1 = _single(P, ctx, q, params(P, workers=workers, max_rounds=500))
+        assert st == st1, (k, st, st1)
+        for key in KEYS:
+            assert stats[key] == stats1[key], (k, key, stats[key], stats1[key])
+        if st == 0:
+            assert np.array_equal(path, path1), k
+
+
+def test_batch_rejections_and_budget(gpu, mixed, r7):
+    P, ctx, _ = gpu
+    say("batch rejections and memory budget")
+    rid, sid = mixed[0][0], mixed[0][1]
+    bad_limits = (rid, sid, np.full(7, 9.0, np.float32), mixed[0][3], 1, 0)
+    bad_scene = (rid, 10_000, mixed[0][2], mixed[0][3], 1, 0)
+    qs = [mixed[0], bad_limits, mixed[1], bad_scene, mixed[2]]
+    prm = params(P, workers=32, max_rounds=500, tree_capacity=4096)
+    used, out = P.prrtc_plan_batch(ctx, qs, prm, groups=0, path_cap=256)
+    assert [o[0] for o in out][1] == P.PRRTC_E_INVALID_ENDPOINT
+    assert [o[0] for o in out][3] == P.PRRTC_E_STATE
+    for k in (0, 2, 4):
+        st1, path1, _ = _single(P, ctx, qs[k], params(P, workers=32, max_rounds=500, tree_capacity=4096))
+        assert out[k][0] == st1 and (st1 != 0 or np.array_equal(out[k][1], path1))
+    # a budget for about one group: the launch runs everything on fewer groups
+    used1, out1 = P.prrtc_plan_batch(ctx, [mixed[0], mixed[1], mixed[2]], prm, groups=0,
+                                     memory_budget=1_000_000, path_cap=256)
+    say("  groups under the budget:", used1)
+    assert used1 >= 1 and used1 < 3
+    for k in range(3):
+        assert out1[k][0] == out[[0, 2, 4][k]][0]
+    with pytest.raises(P.PrrtcError):
+        P.prrtc_plan_batch(ctx, [mixed[0]], prm, memory_budget=1000, path_cap=256)
+    # capacity: a path longer than path_cap is reported, not written
+    used2, out2 = P.prrtc_plan_batch(ctx, [mixed[0]], params(P, workers=32, max_rounds=500), path_cap=1)
+    if out[0][0] == 0:
+        assert out2[0][0] == P.PRRTC_E_CAPACITY and out2[0][2]["path_len"] > 1
+
+
+def test_batch_learned_equals_single(gpu, mixed):
+    P, ctx, _ = gpu
+    say("learned batch")
+    mid = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(7, 77), 7))
+    qs = [q for q in mixed if q[2].shape[0] == 7][:8]
+    prm = params(P, workers=64, max_rounds=500, sampler=1, model_id=mid, mix=0.7)
+    used, out = P.prrtc_plan_batch(ctx, qs, prm, groups=3, path_cap=512)
+    for k, q in enumerate(qs):
+        st1, path1, stats1 = _single(P, ctx, q, params(P, workers=64, max_rounds=500, sampler=1, model_id=mid,
+                                                       mix=0.7))
+        st, path, stats = out[k]
+        assert st == st1
+        for key in KEYS:
+            assert stats[key] == stats1[key], (k, key)
+        assert stats["learned_samples"] > 0
+        if st == 0:
+            assert np.array_equal(path, path1)
+
+
+def test_serving_submit_poll(gpu, mixed):
+    """Queries submitted to the serving thread come out as single launches
+    plan them; admission refuses submissions beyond max_pending until
+    results are polled; other calls are refused while serving."""
+    import time
+    P, ctx, _ = gpu
+    say("serving: submit / poll")
+    prm = params(P, workers=64, max_rounds=500)
+    P.prrtc_serve_start(ctx, prm, slots=6, max_pending=len(mixed), memory_budget=0, path_cap=512)
+    try:
+        with pytest.raises(P.PrrtcError):
+            P.prrtc_plan(ctx, mixed[0][0], mixed[0][1], mixed[0][2], mixed[0][3], prm)
+        tickets = [P.prrtc_submit(ctx, *q) for q in mixed]
+        assert all(t is not None for t in tickets)
+        assert P.prrtc_submit(ctx, *mixed[0]) is None          # admission: max_pending reached
+        got = {}
+        t0 = time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 60:
+            for t, q in zip(tickets, mixed):
+                if t not in got:
+                    r = P.prrtc_poll(ctx, t, len(q[2]), 512)
+                    if r is not None:
+                        got[t] = r
+            time.sleep(0.001)
+        assert len(got) == len(tickets)
+        with pytest.raises(P.PrrtcError):
+            P.prrtc_poll(ctx, tickets[0], 7, 512)                # released
+        assert P.prrtc_submit(ctx, *mixed[0]) is not None
+    finally:
+        launches = P.prrtc_serve_stop(ctx)
+    say("  launches", launches)
+    assert 1 <= launches <= len(mixed) + 1
+    for t, q in zip(tickets, mixed):
+        st, path, stats = got[t]
+        st1, path1, stats1 = _single(P, ctx, q, params(P, workers=64, max_rounds=500))
+        assert st == st1
+        for key in KEYS:
+            assert stats[key] == stats1[key], key
+        if st == 0:
+            assert np.array_equal(path, path1)
