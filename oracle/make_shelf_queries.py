@@ -1,5 +1,5 @@
 """Write the dual-arm shelf queries (start, goal) used by the tests and the
-benchmark: ``python oracle/make_shelf_queries.py N OUT``.
+benchmark: ``python oracle/make_shelf_queries.py N OUT [JOBS]``.
 
 Calls only the oracle (FK and clearances) and the seeded generators.  Query i
 uses numpy seed SEED_QUERY + 1000 + i:
@@ -8,8 +8,9 @@ uses numpy seed SEED_QUERY + 1000 + i:
   * goal, per arm: uniform arm configurations whose hand-bar centre lies in a
     shelf cell on the arm's side (arm 0: y < 0, arm 1: y > 0), the eight with
     the largest clearance (arm alone) refined by a seeded random hill climb on
-    that clearance until it exceeds 2e-3 m; the two arms' goals together must
-    be collision-free (including the inter-arm pairs) with clearance > 1e-3 m.
+    that clearance until it exceeds GOAL_CLEARANCE; the two arms' goals
+    together must be collision-free (including the inter-arm pairs) with
+    clearance > 1e-3 m.
 Rows are written as float32 with 9 significant digits (exact round trip).
 """
 from __future__ import annotations
@@ -24,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 import oracle as O  # noqa: E402
 from paper_2503_06757_amd import workloads as W  # noqa: E402
+
+
+GOAL_CLEARANCE = 0.02   # m: a grasp pose with room around the hand, not a jammed one
 
 
 def _arm_goal(rng, rob_arm, prims, arm):
@@ -46,7 +50,7 @@ def _arm_goal(rng, rob_arm, prims, arm):
     for s, q in cands[:8]:
         step = 0.1
         for it in range(600):
-            if s > 2e-3:
+            if s > GOAL_CLEARANCE:
                 return q
             qn = np.clip(q + rng.normal(0.0, step, 7).astype(np.float32), -W.R7_LIMIT, W.R7_LIMIT)
             sn = score(qn)
@@ -76,18 +80,29 @@ def make_query(i, rob14, arms, prims):
             return start, goal
 
 
+_STATE = {}
+
+
+def _one(i):
+    if not _STATE:
+        r14 = W.robot_r14()
+        _STATE["rob14"] = O.OracleRobot(r14)
+        _STATE["arms"] = [O.OracleRobot(W.robot_r14_arm(a)) for a in (0, 1)]
+        _STATE["prims"] = W.scene_shelf(r14)
+    s, g = make_query(i, _STATE["rob14"], _STATE["arms"], _STATE["prims"])
+    return np.concatenate([s, g])
+
+
 def main():
+    import multiprocessing as mp
     n = int(sys.argv[1]) if len(sys.argv) > 1 else 500
     out = sys.argv[2] if len(sys.argv) > 2 else os.path.join(ROOT, "tests", "golden", "shelf_queries_r14.txt")
-    r14 = W.robot_r14()
-    rob14 = O.OracleRobot(r14)
-    arms = [O.OracleRobot(W.robot_r14_arm(a)) for a in (0, 1)]
-    prims = W.scene_shelf(r14)
-    rows = []
-    for i in range(n):
-        s, g = make_query(i, rob14, arms, prims)
-        rows.append(np.concatenate([s, g]))
-        print(i, flush=True)
+    jobs = int(sys.argv[3]) if len(sys.argv) > 3 else min(8, os.cpu_count() or 1)
+    with mp.Pool(jobs) as pool:
+        rows = []
+        for i, r in enumerate(pool.imap(_one, range(n))):   # query i depends on i only
+            rows.append(r)
+            print(i, flush=True)
     with open(out, "w") as fh:
         fh.write("# Dual-arm shelf queries: 14 start joints then 14 goal joints (rad), float32.\n")
         fh.write("# Written by oracle/make_shelf_queries.py %d (oracle FK and clearances only).\n" % n)

@@ -45,6 +45,7 @@ R7_LIMIT = 2.8
 R7_LINK_SPHERES = 52
 R7_HAND_SPHERES = 8
 R7_RADIUS = (0.03, 0.08)
+R7_HAND_HALF_WIDTH = 0.05      # the hand bar (with its spheres) fits a 0.28 m shelf cell
 
 SCENE_HALF = 0.8            # scenes live in the cube [-0.8, 0.8]^3
 BASE_BALL = 0.25            # keep-out ball around each chain base
@@ -61,7 +62,8 @@ def _segment_offsets(alpha, a, d):
 
 
 def _r7_sphere_layout(radii):
-    """52 spheres evenly by arc length along the link polyline + 8 on a hand bar.
+    """52 spheres evenly by arc length along the link polyline + 8 on a hand bar
+    (y in [-0.05, 0.05] m at z = 0.06 m in the flange frame).
 
     Returns (frame ids 0..7 within the chain, local xyz (60,3) float64).
     """
@@ -82,7 +84,7 @@ def _r7_sphere_layout(radii):
             frames.append(6)
             xyz.append(segs[6].copy())
     for k in range(R7_HAND_SPHERES):
-        y = -0.10 + 0.20 * k / (R7_HAND_SPHERES - 1)
+        y = -R7_HAND_HALF_WIDTH + 2.0 * R7_HAND_HALF_WIDTH * k / (R7_HAND_SPHERES - 1)
         frames.append(7)
         xyz.append(np.array([0.0, y, 0.06]))
     return np.array(frames, np.int32), np.array(xyz)
@@ -96,7 +98,8 @@ def _pose(t):
 
 
 def robot_r7(seed: int = SEED_R7_SPHERES) -> dict:
-    """Synthetic 7-DoF revolute arm with 60 collision spheres (single chain)."""
+    """Synthetic 7-DoF revolute arm with 60 collision spheres (single chain),
+    radii ~ U[0.03, 0.08]."""
     rng = np.random.default_rng(seed)
     radii = rng.uniform(*R7_RADIUS, R7_LINK_SPHERES + R7_HAND_SPHERES)
     frames, xyz = _r7_sphere_layout(radii)
