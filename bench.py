@@ -194,7 +194,7 @@ def query_pool(P, ctx, torch, n_scenes=32, per_scene=4, seed=0x56000000):
 
 
 def bench_serve(P, ctx, torch, n_queries=10000, rate=2000.0, workers=128, slots=256, max_pending=1024,
-                budget=2 << 30, max_rounds=2000, seed=0x56000000):
+                budget=2 << 30, max_rounds=2000, budget_ms=50.0, seed=0x56000000):
     """The served workload through the library's serving thread: queries
     arrive as a Poisson stream (exponential gaps) and are submitted at their
     arrival time (refused submissions are retried: admission); the thread
@@ -205,7 +205,7 @@ def bench_serve(P, ctx, torch, n_queries=10000, rate=2000.0, workers=128, slots=
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_queries))
     picks = rng.integers(0, len(pool), n_queries)
     prm = P.prrtc_plan_params_default()
-    prm.workers, prm.max_rounds = workers, max_rounds
+    prm.workers, prm.max_rounds, prm.time_budget_ms = workers, max_rounds, budget_ms
     done = np.full(n_queries, np.nan)
     status = np.zeros(n_queries, np.int32)
     refused = 0
@@ -243,22 +243,56 @@ def bench_serve(P, ctx, torch, n_queries=10000, rate=2000.0, workers=128, slots=
             "refused_submissions": refused, "pool": len(pool)}
 
 
-def bench_throughput(P, ctx, torch, n_queries=2048, workers=(32, 64, 128, 256), max_rounds=2000):
+def bench_throughput(P, ctx, torch, n_queries=2048, workers=(32, 64, 128, 256), max_rounds=2000, budget_ms=50.0,
+                     log=None):
     """Queries/s of one prrtc_plan_batch launch over the served pool for each
     worker count (the planner's launch-shape tuning)."""
     pool = query_pool(P, ctx, torch)
     rows = []
     for wk in workers:
         prm = P.prrtc_plan_params_default()
-        prm.workers, prm.max_rounds = wk, max_rounds
+        prm.workers, prm.max_rounds, prm.time_budget_ms = wk, max_rounds, budget_ms
         qs = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
                7 + k, 0) for k in range(n_queries)]
         t0 = time.perf_counter()
         used, out = P.prrtc_plan_batch(ctx, qs, prm, groups=0, path_cap=128)
         dt = time.perf_counter() - t0
         ok = np.mean([o[0] == P.PRRTC_OK for o in out])
-        rows.append({"workers": wk, "groups": used, "queries_per_s": n_queries / dt, "success": float(ok)})
+        rows.append({"workers": wk, "groups": used, "queries_per_s": n_queries / dt, "success": float(ok),
+                     "time_budget_ms": budget_ms})
+        if log:
+            log("  workers %d: %s" % (wk, rows[-1]))
     return rows
+
+
+SHELF_QUERIES = os.path.join(ROOT, "tests", "golden", "shelf_queries_r14.txt")
+
+
+def bench_shelf(P, ctx, n_queries=500, max_rounds=4000, budget_ms=200.0, workers=256):
+    """ms-to-solution of the dual arm (14-DoF, 3600 inter-arm pairs) reaching
+    into the 5x3 shelf with 24 random spheres: the stored generated queries
+    (start in front of the shelf, each hand in a cell on its side)."""
+    robot = W.robot_r14()
+    rid = P.prrtc_load_robot(ctx, robot)
+    sid = P.prrtc_load_scene(ctx, W.scene_shelf(robot))
+    Q = np.loadtxt(SHELF_QUERIES, dtype=np.float32)[:n_queries]
+    prm = P.prrtc_plan_params_default()
+    prm.max_rounds, prm.time_budget_ms, prm.workers = max_rounds, budget_ms, workers
+    rows = []
+    for k, row in enumerate(Q):
+        prm.seed = W.SEED_QUERY + k
+        t0 = time.perf_counter()
+        st, _, stats = P.prrtc_plan(ctx, rid, sid, row[:14], row[14:], prm)
+        dt = (time.perf_counter() - t0) * 1e3
+        rows.append((st == P.PRRTC_OK, dt, stats["rounds"], stats["edges_checked"], stats["gpu_ms"]))
+    a = np.array(rows, np.float64)
+    ok = a[:, 0] > 0
+    t = np.where(ok, a[:, 1], np.inf)
+    return {"workload": "plan_r14_shelf", "queries": len(a), "success": float(ok.mean()),
+            "p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)),
+            "mean_rounds": float(a[ok, 2].mean()) if ok.any() else None,
+            "edge_checks_per_s": float(a[:, 3].sum() / (a[:, 4].sum() * 1e-3)),
+            "max_rounds": max_rounds, "time_budget_ms": budget_ms, "workers": workers}
 
 
 def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
@@ -334,6 +368,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle CPU baseline")
     ap.add_argument("--skip-plan", action="store_true", help="omit the planner ms-to-solution run")
     ap.add_argument("--skip-learned", action="store_true", help="omit the learned-proposal leg")
+    ap.add_argument("--skip-shelf", action="store_true", help="omit the 14-DoF shelf leg")
+    ap.add_argument("--shelf-queries", type=int, default=500)
     ap.add_argument("--learned-scenes", type=int, default=2000, help="training scenes (10000 for the full set)")
     ap.add_argument("--learned-eval", type=int, default=200, help="held-out scenes")
     ap.add_argument("--learned-epochs", type=int, default=8)
@@ -361,16 +397,23 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    shelf = None
+    if not args.skip_shelf:
+        log("14-DoF shelf")
+        shelf = bench_shelf(P, ctx, args.shelf_queries)
+        log("  " + json.dumps(finite_or_null(shelf)))
     serve = batch = None
     if not args.skip_serve:
         log("batched planner: launch shapes")
-        batch = bench_throughput(P, ctx, torch)
+        batch = bench_throughput(P, ctx, torch, log=log)
         log("served planner: Poisson arrivals")
         serve = bench_serve(P, ctx, torch, n_queries=args.serve_queries)
+        log("  " + json.dumps(finite_or_null(serve)))
     learned = None
     if not args.skip_learned:
         log("learned proposal")
         learned = bench_learned(P, ctx, torch, args.learned_scenes, args.learned_eval, args.learned_epochs, log)
+        log("  " + json.dumps(finite_or_null(learned)))
     ms_per_step = ce["wall_s"] * 1e3 / args.steps
     value = N_EDGES / (ce["wall_s"] / args.steps)
     achieved = ce["alg_flop"] / (ce["kernel_ms"] * 1e-3) / 1e12
@@ -397,6 +440,7 @@ def main():
                      "kernel": "k_check_edges", "kernel_ms": ce["kernel_ms"],
                      "flop_per_launch": ce["alg_flop"], "flop_per_point": ce["flop_per_point"]},
         "ms_to_solution": plan,
+        "ms_to_solution_r14_shelf": shelf,
         "batched": batch,
         "served": serve,
         "learned": learned,

@@ -595,7 +595,12 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
             if (q.type == 1) {
                 if (!(q.dims[0] > 0.0f && q.dims[1] > 0.0f && q.dims[2] > 0.0f))
                     return fail(ctx, PRRTC_E_ARG, "primitive %d: half-extent <= 0", i);
-                const float rec[16] = {q.c[0], q.c[1], q.c[2], 0.0f,
+                // axis k is column k of rot; the record keeps -(axis_k . c)
+                double off[3];
+                for (int k = 0; k < 3; ++k)
+                    off[k] = -((double)q.rot[k] * q.c[0] + (double)q.rot[3 + k] * q.c[1] +
+                               (double)q.rot[6 + k] * q.c[2]);
+                const float rec[16] = {(float)off[0], (float)off[1], (float)off[2], 0.0f,
                                        q.rot[0], q.rot[3], q.rot[6],
                                        q.rot[1], q.rot[4], q.rot[7],
                                        q.rot[2], q.rot[5], q.rot[8],
@@ -988,8 +993,11 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     const int W = p.workers, cap = p.tree_capacity;
     const GroupLayout L = group_layout(dof, cap, W, stage_cap);
     // after the group: query words, the query's arguments, proposal staging
+    // after the group: the query's words followed directly by its path (one
+    // copy brings both back), its arguments, proposal staging
     const size_t o_ctl = L.bytes;
-    const size_t o_args = align_up<int>(o_ctl + sizeof(int) * kCtlWords);
+    const size_t o_out = o_ctl + sizeof(int) * kCtlWords;
+    const size_t o_args = align_up<int>(o_out + sizeof(float) * (size_t)2 * cap * dof);
     const size_t o_qin = align_up<int>(o_args + sizeof(PlanArgs));
     const size_t o_gmm = align_up<int>(o_qin + sizeof(float) * 2 * kMaxDof + sizeof(int));
     const size_t bytes = align_up<int>(o_gmm + sizeof(float) * kComp * (1 + 2 * kMaxDof));
@@ -1004,7 +1012,7 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     query_args(ctx, A, p, *r, *s, start, goal, p.seed, p.query, stage_cap);
     group_args(A, m, L, W, cap);
     A.ctl = reinterpret_cast<int*>(m + o_ctl);
-    A.out_path = A.path;
+    A.out_path = reinterpret_cast<float*>(m + o_out);
     A.out_path_cap = A.path_cap;
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
     const size_t lds = plan_lds_bytes(r->args, stage_cap, dof);
@@ -1024,9 +1032,13 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
                                               dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
-    int ctl[kCtlWords];
-    PRRTC_HIP(ctx, hipMemcpyAsync(ctl, A.ctl, sizeof ctl, hipMemcpyDeviceToHost, sm));
+    // the words and the first nodes of the path in one copy to pinned memory
+    const int prefix = std::min(std::min(path_cap, 2 * cap), (kPinnedFloats - kCtlWords) / dof);
+    PRRTC_HIP(ctx, hipMemcpyAsync(ctx->pinned, A.ctl, sizeof(int) * kCtlWords + sizeof(float) * (size_t)prefix * dof,
+                                  hipMemcpyDeviceToHost, sm));
     PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    int ctl[kCtlWords];
+    memcpy(ctl, ctx->pinned, sizeof ctl);
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     if (stats) fill_stats(ctl, ms, stats);
@@ -1037,8 +1049,12 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     const int len = ctl[kPathLen];
     *path_len = len;
     if (len > path_cap) return fail(ctx, PRRTC_E_CAPACITY, "path needs %d nodes, buffer holds %d", len, path_cap);
-    PRRTC_HIP(ctx, hipMemcpyAsync(path, A.path, sizeof(float) * (size_t)len * dof, hipMemcpyDeviceToHost, sm));
-    PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    if (len <= prefix) {
+        memcpy(path, ctx->pinned + kCtlWords, sizeof(float) * (size_t)len * dof);
+    } else {
+        PRRTC_HIP(ctx, hipMemcpyAsync(path, A.out_path, sizeof(float) * (size_t)len * dof, hipMemcpyDeviceToHost, sm));
+        PRRTC_HIP(ctx, hipStreamSynchronize(sm));
+    }
     return PRRTC_OK;
 }
 

@@ -61,7 +61,9 @@ struct RobotArgs {
 
 // Scene tables, one array per primitive type.
 //   sph: (cx, cy, cz, R)
-//   box: 16 floats: c(3), pad, axis0(3), axis1(3), axis2(3), half-extents(3)
+//   box: 16 floats: -(axis_k . c) for k = 0..2, pad, axis0(3), axis1(3),
+//        axis2(3), half-extents(3) (box frame coordinates of a point p are
+//        axis_k . p - axis_k . c, three FMAs each)
 //   cyl: 8 floats: c(3), unit axis(3), R, half-height
 //   *_bnd: bounding sphere of each primitive, (centre, radius + 1e-4 m)
 struct SceneArgs {
@@ -223,11 +225,11 @@ __device__ inline Box ld_box(const SceneArgs& S, int o) {
 __device__ inline Cyl ld_cyl(const SceneArgs& S, int o) { return Cyl{ld4(S.cyl, 2 * o), ld4(S.cyl, 2 * o + 1)}; }
 
 __device__ inline bool hit_box(float cx, float cy, float cz, float r, const Box& o) {
-    // o.a = (c, pad), o.b = (ax0, ax1.x), o.c = (ax1.yz, ax2.xy), o.d = (ax2.z, h)
-    const float vx = cx - o.a.x, vy = cy - o.a.y, vz = cz - o.a.z;
-    const float l0 = o.b.x * vx + o.b.y * vy + o.b.z * vz;
-    const float l1 = o.b.w * vx + o.c.x * vy + o.c.y * vz;
-    const float l2 = o.c.z * vx + o.c.w * vy + o.d.x * vz;
+    // o.a = (-ax0.c, -ax1.c, -ax2.c, pad), o.b = (ax0, ax1.x), o.c = (ax1.yz, ax2.xy),
+    // o.d = (ax2.z, h)
+    const float l0 = fmaf(o.b.x, cx, fmaf(o.b.y, cy, fmaf(o.b.z, cz, o.a.x)));
+    const float l1 = fmaf(o.b.w, cx, fmaf(o.c.x, cy, fmaf(o.c.y, cz, o.a.y)));
+    const float l2 = fmaf(o.c.z, cx, fmaf(o.c.w, cy, fmaf(o.d.x, cz, o.a.z)));
     const float e0 = fmaxf(fabsf(l0) - o.d.y, 0.0f);
     const float e1 = fmaxf(fabsf(l1) - o.d.z, 0.0f);
     const float e2 = fmaxf(fabsf(l2) - o.d.w, 0.0f);
@@ -251,17 +253,37 @@ __device__ inline bool hit_pair(float4 a, float4 b) {
     return dx * dx + dy * dy + dz * dz < rr * rr;
 }
 
-__device__ inline float wave_min_f(float v) {
+// Wave-wide min / max (all 64 lanes active), returned to every lane as a
+// wave-uniform value.  Data-parallel-primitive (DPP) moves fuse into the
+// min/max instructions: pairs and quads by quad permutes, rows of 16 by the
+// half-row and row mirrors, then row broadcasts 15 and 31 carry the partial
+// results up so that lane 63 holds the wave's value.
+#ifndef PRRTC_DPP_REDUCE
+#define PRRTC_DPP_REDUCE 1
+#endif
+template <bool MAX>
+__device__ inline float wave_reduce_f(float v) {
+#if PRRTC_DPP_REDUCE
+#define PRRTC_DPP(x, ctrl, rows) \
+    __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), ctrl, rows, 0xF, false))
+    auto op = [](float a, float b) { return MAX ? fmaxf(a, b) : fminf(a, b); };
+    v = op(v, PRRTC_DPP(v, 0xB1, 0xF));    // quad_perm [1, 0, 3, 2]
+    v = op(v, PRRTC_DPP(v, 0x4E, 0xF));    // quad_perm [2, 3, 0, 1]
+    v = op(v, PRRTC_DPP(v, 0x141, 0xF));   // row_half_mirror
+    v = op(v, PRRTC_DPP(v, 0x140, 0xF));   // row_mirror
+    v = op(v, PRRTC_DPP(v, 0x142, 0xA));   // row_bcast:15 into rows 1 and 3
+    v = op(v, PRRTC_DPP(v, 0x143, 0xC));   // row_bcast:31 into rows 2 and 3
+#undef PRRTC_DPP
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+#else
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+    for (int off = 32; off >= 1; off >>= 1) v = MAX ? fmaxf(v, __shfl_xor(v, off, kWave)) : fminf(v, __shfl_xor(v, off, kWave));
     return v;
+#endif
 }
 
-__device__ inline float wave_max_f(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
-    return v;
-}
+__device__ inline float wave_min_f(float v) { return wave_reduce_f<false>(v); }
+__device__ inline float wave_max_f(float v) { return wave_reduce_f<true>(v); }
 
 // Does an obstacle's bounding sphere b reach the box [lo, hi]?
 __device__ inline bool sphere_meets_box(float4 b, float lx, float ly, float lz, float hx, float hy,

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libprrtc.so")
+# PRRTC_LIB may name another build of the same library (same ABI)
+LIB_PATH = os.environ.get("PRRTC_LIB") or os.path.join(_HERE, "libprrtc.so")
 
 PRRTC_OK = 0
 PRRTC_E_ARG = -1
