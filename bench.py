@@ -57,12 +57,18 @@ def point_flops(robot, prims):
 
 
 def kernel_source_hash():
+    """Hash of the source text that decides what k_check_edges executes: the
+    shared device header, the device part of prrtc.hip and its launch
+    configuration (planner, proposal and other host code are excluded)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_06757_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
+    with open(os.path.join(csrc, "prrtc_device.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "prrtc.hip")) as fh:
+        text = fh.read()
+    h.update(text[:text.index("// Host side")].encode())
+    a = text.index("#ifndef PRRTC_EDGE_TILE")
+    h.update(text[a:text.index("prrtc_status prrtc_fk_spheres(", a)].encode())
     return h.hexdigest()[:16]
 
 
@@ -173,14 +179,18 @@ def bench_plan(P, ctx, n_instances=100, n_seeds=50):
             "mean_cost": float(np.mean(costs)) if costs else None, "workers": prm.workers}
 
 
-def query_pool(P, ctx, torch, n_scenes=32, per_scene=4, seed=0x56000000):
+def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, budget_ms=100.0):
     """Served workload pool: scenes with U{8..128} obstacles (6:4:2 mix) for
-    the 7-DoF arm and the dual arm alternately, `per_scene` free queries each
-    (endpoints checked by prrtc_check_edges)."""
+    the 7-DoF arm and the dual arm alternately, up to `per_scene` free
+    queries each (endpoints checked by prrtc_check_edges), kept when the
+    uniform planner solves them within budget_ms (many generated queries in
+    dense scenes have no solution; serving them measures only the budget)."""
     from paper_2503_06757_amd import proposal as PR
     robots = [W.robot_r7(), W.robot_r14()]
     rids = [P.prrtc_load_robot(ctx, r) for r in robots]
-    pool = []
+    prm = P.prrtc_plan_params_default()
+    prm.max_rounds, prm.time_budget_ms = 4000, budget_ms
+    pool, tried = [], 0
     for i in range(n_scenes):
         kind = i % 2
         rng = np.random.default_rng(seed + i)
@@ -188,24 +198,38 @@ def query_pool(P, ctx, torch, n_scenes=32, per_scene=4, seed=0x56000000):
         sid = P.prrtc_load_scene(ctx, prims)
         for j in range(per_scene):
             q = PR.free_query(P, ctx, torch, rids[kind], sid, robots[kind], seed + 1000 * j + i)
-            if q is not None:
+            if q is None:
+                continue
+            tried += 1
+            prm.seed = seed + 1000 * j + i
+            st, _, _ = P.prrtc_plan(ctx, rids[kind], sid, q[0], q[1], prm)
+            if st == P.PRRTC_OK:
                 pool.append((rids[kind], sid, q[0], q[1], kind))
-    return pool
+    return pool, tried
 
 
-def bench_serve(P, ctx, torch, n_queries=10000, rate=2000.0, workers=128, slots=256, max_pending=1024,
-                budget=2 << 30, max_rounds=2000, budget_ms=50.0, seed=0x56000000):
+def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None, slots=256, max_pending=1024,
+                budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None):
     """The served workload through the library's serving thread: queries
     arrive as a Poisson stream (exponential gaps) and are submitted at their
     arrival time (refused submissions are retried: admission); the thread
     batches whatever is queued into one launch at a time.  Latency =
     completion seen by polling - arrival, on the host clock."""
-    pool = query_pool(P, ctx, torch)
+    pool, tried = pool
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_queries))
     picks = rng.integers(0, len(pool), n_queries)
     prm = P.prrtc_plan_params_default()
-    prm.workers, prm.max_rounds, prm.time_budget_ms = workers, max_rounds, budget_ms
+    prm.max_rounds, prm.time_budget_ms = max_rounds, budget_ms
+    tune = None
+    if workers is None:
+        # launch shape from the autotuner on a sample of the pool
+        sample = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
+                   seed + 777 + k, 0) for k in range(slots)]
+        workers, tune = P.prrtc_tune_workers(ctx, sample, prm, memory_budget=budget)
+        if log:
+            log("  tuned workers per query: %d %s" % (workers, tune))
+    prm.workers = workers
     done = np.full(n_queries, np.nan)
     status = np.zeros(n_queries, np.int32)
     refused = 0
@@ -240,14 +264,15 @@ def bench_serve(P, ctx, torch, n_queries=10000, rate=2000.0, workers=128, slots=
             "slots": slots, "max_pending": max_pending, "memory_budget_bytes": budget, "success": float(ok.mean()),
             "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
             "queries_per_s": n_queries / span, "launches": launches, "mean_batch": n_queries / max(launches, 1),
-            "refused_submissions": refused, "pool": len(pool)}
+            "refused_submissions": refused, "pool": len(pool), "pool_tried": tried, "tuning": tune,
+            "time_budget_ms": budget_ms}
 
 
-def bench_throughput(P, ctx, torch, n_queries=2048, workers=(32, 64, 128, 256), max_rounds=2000, budget_ms=50.0,
-                     log=None):
+def bench_throughput(P, ctx, torch, pool, n_queries=2048, workers=(16, 32, 64, 128, 256), max_rounds=4000,
+                     budget_ms=100.0, log=None):
     """Queries/s of one prrtc_plan_batch launch over the served pool for each
     worker count (the planner's launch-shape tuning)."""
-    pool = query_pool(P, ctx, torch)
+    pool, _ = pool
     rows = []
     for wk in workers:
         prm = P.prrtc_plan_params_default()
@@ -405,9 +430,11 @@ def main():
     serve = batch = None
     if not args.skip_serve:
         log("batched planner: launch shapes")
-        batch = bench_throughput(P, ctx, torch, log=log)
+        pool = query_pool(P, ctx, torch)
+        log("  pool: %d solvable of %d free queries" % (len(pool[0]), pool[1]))
+        batch = bench_throughput(P, ctx, torch, pool, log=log)
         log("served planner: Poisson arrivals")
-        serve = bench_serve(P, ctx, torch, n_queries=args.serve_queries)
+        serve = bench_serve(P, ctx, torch, pool, n_queries=args.serve_queries, log=log)
         log("  " + json.dumps(finite_or_null(serve)))
     learned = None
     if not args.skip_learned:

@@ -248,6 +248,18 @@ prrtc_status prrtc_plan_batch(prrtc_ctx *ctx, const prrtc_query *queries, int32_
                               int32_t *groups_used);
 
 /*
+ * Launch-shape tuning for batched planning: the queries are planned once per
+ * candidate worker count (each pass a complete prrtc_plan_batch with the
+ * largest resident group count and memory_budget), timed on the host clock.
+ * rates (may be NULL): host float [n_cand], queries per second of each
+ * candidate (0 if it cannot launch).  *best = the fastest candidate.
+ * Synchronous; E_CAPACITY if no candidate can launch.
+ */
+prrtc_status prrtc_tune_workers(prrtc_ctx *ctx, const prrtc_query *queries, int32_t n,
+                                const prrtc_plan_params *params, const int32_t *candidates, int32_t n_cand,
+                                int64_t memory_budget, float *rates, int32_t *best);
+
+/*
  * Serving: a thread owned by the context gathers submitted queries into
  * prrtc_plan_batch launches (up to `slots` queries per launch, groups sized
  * by memory_budget as in prrtc_plan_batch), so queries arriving over time

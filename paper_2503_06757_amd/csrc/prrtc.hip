@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -1228,6 +1229,35 @@ prrtc_status prrtc_plan_batch(prrtc_ctx* ctx, const prrtc_query* queries, int32_
     return plan_batch_impl(ctx, queries, n, prm, groups, memory_budget, paths, path_cap, results, groups_used);
 }
 
+prrtc_status prrtc_tune_workers(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n,
+                                const prrtc_plan_params* params, const int32_t* candidates, int32_t n_cand,
+                                int64_t memory_budget, float* rates, int32_t* best) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
+    if (n < 1 || !queries || !params || !candidates || n_cand < 1 || !best || memory_budget < 0)
+        return fail(ctx, PRRTC_E_ARG, "bad tuning arguments");
+    std::vector<prrtc_query_result> res(n);
+    std::vector<float> path((size_t)n * kMaxDof);
+    float best_rate = -1.0f;
+    *best = 0;
+    for (int c = 0; c < n_cand; ++c) {
+        prrtc_plan_params p = *params;
+        p.workers = candidates[c];
+        const auto t0 = std::chrono::steady_clock::now();
+        prrtc_status st = plan_batch_impl(ctx, queries, n, &p, 0, memory_budget, path.data(), 1, res.data(), nullptr);
+        const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const float rate = st == PRRTC_OK ? (float)(n / s) : 0.0f;   // a shape that cannot launch rates 0
+        if (rates) rates[c] = rate;
+        if (rate > best_rate) {
+            best_rate = rate;
+            *best = candidates[c];
+        }
+    }
+    ctx->err.clear();
+    return best_rate > 0.0f ? PRRTC_OK : fail(ctx, PRRTC_E_CAPACITY, "no candidate could launch");
+}
+
 }  // extern "C"
 
 // ----------------------------------------------------------------------------
@@ -1381,7 +1411,7 @@ prrtc_status prrtc_serve_stop(prrtc_ctx* ctx, int64_t* launches) {
 // Learned sampling proposal: model storage, forward, training
 // ----------------------------------------------------------------------------
 struct PropWs {
-    float *E, *dE, *X0, *dX0, *Z1, *H1, *Z2, *H2, *Z3, *H3, *O, *dO, *dZ, *dH, *qh, *nll;
+    float *E, *dE, *X0, *dX0, *Z1, *H1, *Z2, *H2, *Z3, *H3, *O, *dO, *dZ, *dH, *qh, *nll, *part;
 };
 
 namespace {
@@ -1391,12 +1421,13 @@ std::vector<ModelRec>& models_of(prrtc_ctx* ctx) { return ctx->models; }
 prrtc_status prop_workspace(prrtc_ctx* ctx, ModelRec& M, int n, int S, PropWs& W) {
     const PropLayout& L = M.L;
     size_t o = 0;
-    size_t offs[16];
-    const size_t cnt[16] = {(size_t)S * kHidden, (size_t)S * kHidden, (size_t)n * L.D0, (size_t)n * L.D0,
+    size_t offs[17];
+    const size_t cnt[17] = {(size_t)S * kHidden, (size_t)S * kHidden, (size_t)n * L.D0, (size_t)n * L.D0,
                             (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * kHidden,
                             (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * L.Cw, (size_t)n * L.Cw,
-                            (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * L.dof, (size_t)n};
-    for (int i = 0; i < 16; ++i) {
+                            (size_t)n * kHidden, (size_t)n * kHidden, (size_t)n * L.dof, (size_t)n,
+                            (size_t)kEmbedSlices * kSmallRows * kHidden};
+    for (int i = 0; i < 17; ++i) {
         offs[i] = o;
         o = align_up<int>(o + sizeof(float) * cnt[i]);
     }
@@ -1408,9 +1439,9 @@ prrtc_status prop_workspace(prrtc_ctx* ctx, ModelRec& M, int n, int S, PropWs& W
         M.ws_bytes = o;
     }
     char* b = static_cast<char*>(M.ws);
-    float** f[16] = {&W.E, &W.dE, &W.X0, &W.dX0, &W.Z1, &W.H1, &W.Z2, &W.H2, &W.Z3, &W.H3, &W.O, &W.dO,
-                     &W.dZ, &W.dH, &W.qh, &W.nll};
-    for (int i = 0; i < 16; ++i) *f[i] = reinterpret_cast<float*>(b + offs[i]);
+    float** f[17] = {&W.E, &W.dE, &W.X0, &W.dX0, &W.Z1, &W.H1, &W.Z2, &W.H2, &W.Z3, &W.H3, &W.O, &W.dO,
+                     &W.dZ, &W.dH, &W.qh, &W.nll, &W.part};
+    for (int i = 0; i < 17; ++i) *f[i] = reinterpret_cast<float*>(b + offs[i]);
     return PRRTC_OK;
 }
 
@@ -1433,6 +1464,14 @@ void prop_forward(hipStream_t sm, ModelRec& M, const PropWs& W, const RobotArgs*
     const char* rb = reinterpret_cast<const char*>(R_dev);
     const float* lo = reinterpret_cast<const float*>(rb + offsetof(RobotArgs, lo));
     const float* hi = reinterpret_cast<const float*>(rb + offsetof(RobotArgs, hi));
+    if (!q && n <= kSmallRows && S <= kSmallRows) {
+        // a few queries: split embedding and one workgroup per row
+        hipLaunchKernelGGL(k_embed_partial, dim3(kEmbedSlices), dim3(256), 0, sm, vox, S, M.p(pWv), W.part);
+        hipLaunchKernelGGL(k_embed_reduce, dim3(S), dim3(256), 0, sm, W.part, M.p(pbv), W.E);
+        hipLaunchKernelGGL(k_mlp_rows, dim3(n), dim3(256), 0, sm, s, g, scene_of, W.E, lo, hi, L.dof, M.p(pW1),
+                           M.p(pb1), M.p(pW2), M.p(pb2), M.p(pW3), M.p(pb3), M.p(pW4), M.p(pb4), gmm_out);
+        return;
+    }
     gemm<uint8_t, false, false, false>(sm, vox, kVoxCells, M.p(pWv), kHidden, M.p(pbv), W.E, nullptr, kHidden, S,
                                        kHidden, kVoxCells);
     hipLaunchKernelGGL(k_build_x0, dim3(blocks((size_t)n * L.D0, 256)), dim3(256), 0, sm, s, g, q, scene_of, W.E,

@@ -204,6 +204,107 @@ __global__ void k_gmm_head(const float* __restrict__ O, int n, int dof, const fl
     }
 }
 
+// ---------------------------------------------------------------------------
+// Inference for a handful of queries (planning): the matrix-core GEMM's
+// 64-row tiles would be almost empty, and the 4096-deep embedding would run
+// on four workgroups.  Instead:
+//   k_embed_partial: grid (kEmbedSlices), 256 threads (one per output
+//     column); slice z sums bf16(W_v[k][col]) over its 64 cells k that are
+//     occupied, for every scene row (at most kSmallRows);
+//   k_embed_reduce: E[s][col] = b_v[col] + the slices' partial sums, in
+//     slice order;
+//   k_mlp_rows: one workgroup per query row, activations in LDS, each layer
+//     a BF16-operand FP32-accumulate dot product per output column, GELU,
+//     and the mixture head (log sigma clamped).
+// Same arithmetic as the GEMM path (BF16 operands, FP32 sums); only the
+// order of the sums differs.
+// ---------------------------------------------------------------------------
+constexpr int kEmbedSlices = 64;
+constexpr int kSmallRows = 16;
+
+__device__ inline float bf16_round(float x) { return __uint_as_float((unsigned)bf16_bits(x) << 16); }
+
+__global__ __launch_bounds__(256) void k_embed_partial(const uint8_t* __restrict__ vox, int S,
+                                                       const float* __restrict__ Wv, float* __restrict__ part) {
+    const int z = blockIdx.x, col = threadIdx.x;
+    constexpr int kCells = kVoxCells / kEmbedSlices;
+    float acc[kSmallRows];
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r) acc[r] = 0.0f;
+    for (int c = 0; c < kCells; ++c) {
+        const int k = z * kCells + c;
+        const float w = bf16_round(Wv[(size_t)k * kHidden + col]);
+#pragma unroll
+        for (int r = 0; r < kSmallRows; ++r)
+            if (r < S && vox[(size_t)r * kVoxCells + k]) acc[r] += w;
+    }
+    for (int r = 0; r < S; ++r) part[((size_t)z * kSmallRows + r) * kHidden + col] = acc[r];
+}
+
+__global__ __launch_bounds__(256) void k_embed_reduce(const float* __restrict__ part, const float* __restrict__ bv,
+                                                      float* __restrict__ E) {
+    const int r = blockIdx.x, col = threadIdx.x;
+    float e = 0.0f;
+    for (int z = 0; z < kEmbedSlices; ++z) e += part[((size_t)z * kSmallRows + r) * kHidden + col];
+    E[(size_t)r * kHidden + col] = e + bv[col];
+}
+
+// out[col] = act(sum_k bf16(x[k]) bf16(W[k][col]) + b[col]) for col < N (threads stride N)
+template <bool GELU>
+__device__ inline void row_layer(const float* __restrict__ x, int K, const float* __restrict__ W, int N,
+                                 const float* __restrict__ b, float* __restrict__ out) {
+    for (int col = threadIdx.x; col < N; col += blockDim.x) {
+        float acc = 0.0f;
+        for (int k = 0; k < K; ++k) acc = fmaf(x[k], bf16_round(W[(size_t)k * N + col]), acc);
+        float v = acc + b[col];
+        if (GELU) v = 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
+        out[col] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_rows(const float* __restrict__ s, const float* __restrict__ g,
+                                                  const int* __restrict__ scene_of, const float* __restrict__ E,
+                                                  const float* __restrict__ lo, const float* __restrict__ hi,
+                                                  int dof, const float* __restrict__ W1, const float* __restrict__ b1,
+                                                  const float* __restrict__ W2, const float* __restrict__ b2,
+                                                  const float* __restrict__ W3, const float* __restrict__ b3,
+                                                  const float* __restrict__ W4, const float* __restrict__ b4,
+                                                  float* __restrict__ gmm) {
+    __shared__ float xa[2 * kMaxDof + kHidden];
+    __shared__ float xb[kComp * (1 + 2 * kMaxDof) > kHidden ? kComp * (1 + 2 * kMaxDof) : kHidden];
+    const int row = blockIdx.x, t = threadIdx.x;
+    const int D0 = 2 * dof + kHidden, Cw = kComp * (1 + 2 * dof);
+    for (int c = t; c < D0; c += blockDim.x) {
+        float v;
+        if (c < 2 * dof) {
+            const int j = c % dof;
+            const float x = c < dof ? s[row * dof + j] : g[row * dof + j];
+            v = 2.0f * (x - lo[j]) / (hi[j] - lo[j]) - 1.0f;
+        } else {
+            v = E[(size_t)scene_of[row] * kHidden + (c - 2 * dof)];
+        }
+        xa[c] = bf16_round(v);
+    }
+    __syncthreads();
+    row_layer<true>(xa, D0, W1, kHidden, b1, xb);
+    __syncthreads();
+    for (int c = t; c < kHidden; c += blockDim.x) xa[c] = bf16_round(xb[c]);
+    __syncthreads();
+    row_layer<true>(xa, kHidden, W2, kHidden, b2, xb);
+    __syncthreads();
+    for (int c = t; c < kHidden; c += blockDim.x) xa[c] = bf16_round(xb[c]);
+    __syncthreads();
+    row_layer<true>(xa, kHidden, W3, kHidden, b3, xb);
+    __syncthreads();
+    for (int c = t; c < kHidden; c += blockDim.x) xa[c] = bf16_round(xb[c]);
+    __syncthreads();
+    row_layer<false>(xa, kHidden, W4, Cw, b4, xb);
+    __syncthreads();
+    float* out = gmm + (size_t)row * Cw;
+    for (int c = t; c < Cw; c += blockDim.x)
+        out[c] = c < kComp * (1 + dof) ? xb[c] : fminf(fmaxf(xb[c], kLogSigLo), kLogSigHi);
+}
+
 // dZ = dH * GELU'(Z)
 __global__ void k_gelu_bwd(const float* __restrict__ dH, const float* __restrict__ Z, float* __restrict__ dZ,
                            int n) {

@@ -162,6 +162,9 @@ def _load():
         L.prrtc_plan_batch.argtypes = [P, C.POINTER(prrtc_query), I32, C.POINTER(prrtc_plan_params), I32, I64,
                                        VP, I32, C.POINTER(prrtc_query_result), C.POINTER(I32)]
         L.prrtc_plan_batch.restype = I32
+        L.prrtc_tune_workers.argtypes = [P, C.POINTER(prrtc_query), I32, C.POINTER(prrtc_plan_params), VP, I32, I64,
+                                         VP, C.POINTER(I32)]
+        L.prrtc_tune_workers.restype = I32
         L.prrtc_serve_start.argtypes = [P, C.POINTER(prrtc_plan_params), I32, I32, I64, I32]
         L.prrtc_serve_start.restype = I32
         L.prrtc_submit.argtypes = [P, C.POINTER(prrtc_query), C.POINTER(C.c_uint64)]
@@ -178,7 +181,7 @@ lib = _load()
 # the symbols include/prrtc.h declares (checked by the CPU test-suite)
 EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
             "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_fk_spheres",
-            "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch",
+            "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_workers",
             "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
             "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_sample", "prrtc_train_proposal")
 
@@ -299,16 +302,7 @@ def prrtc_plan_batch(ctx: int, queries, params, groups: int = 0, memory_budget: 
     """queries: list of (robot_id, scene_id, start, goal, seed, query).  Returns
     (groups used, [(status, path or None, stats dict)])."""
     n = len(queries)
-    arr = np.zeros(max(n, 1), _QUERY_DT)
-    if n:
-        arr["robot_id"][:n] = [q[0] for q in queries]
-        arr["scene_id"][:n] = [q[1] for q in queries]
-        arr["seed"][:n] = [q[4] for q in queries]
-        arr["query"][:n] = [q[5] for q in queries]
-        for k, q in enumerate(queries):
-            d = len(q[2])
-            arr["start"][k, :d] = q[2]
-            arr["goal"][k, :d] = q[3]
+    arr = _query_array(queries)
     paths = np.zeros((max(n, 1), path_cap, 16), np.float32)
     res = np.zeros(max(n, 1), _RESULT_DT)
     used = C.c_int32(0)
@@ -328,6 +322,33 @@ def prrtc_plan_batch(ctx: int, queries, params, groups: int = 0, memory_budget: 
             path = paths[k].reshape(-1)[: stats["path_len"] * dof].reshape(-1, dof).copy()
         out.append((st, path, stats))
     return used.value, out
+
+
+def _query_array(queries):
+    n = len(queries)
+    arr = np.zeros(max(n, 1), _QUERY_DT)
+    if n:
+        arr["robot_id"][:n] = [q[0] for q in queries]
+        arr["scene_id"][:n] = [q[1] for q in queries]
+        arr["seed"][:n] = [q[4] for q in queries]
+        arr["query"][:n] = [q[5] for q in queries]
+        for k, q in enumerate(queries):
+            d = len(q[2])
+            arr["start"][k, :d] = q[2]
+            arr["goal"][k, :d] = q[3]
+    return arr
+
+
+def prrtc_tune_workers(ctx: int, queries, params, candidates=(16, 32, 64, 128, 256), memory_budget: int = 0):
+    """(best worker count, {candidate: queries/s})."""
+    arr = _query_array(queries)
+    cand = np.asarray(candidates, np.int32)
+    rates = np.zeros(len(cand), np.float32)
+    best = C.c_int32(0)
+    _check(ctx, lib.prrtc_tune_workers(ctx, arr.ctypes.data_as(C.POINTER(prrtc_query)), len(queries),
+                                       C.byref(params), cand.ctypes.data, len(cand), int(memory_budget),
+                                       rates.ctypes.data, C.byref(best)))
+    return best.value, {int(c): float(r) for c, r in zip(cand, rates)}
 
 
 def prrtc_serve_start(ctx: int, params, slots: int = 256, max_pending: int = 1024, memory_budget: int = 0,

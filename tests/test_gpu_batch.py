@@ -162,3 +162,17 @@ def test_serving_submit_poll(gpu, mixed):
             assert stats[key] == stats1[key], key
         if st == 0:
             assert np.array_equal(path, path1)
+
+
+def test_tune_workers(gpu, mixed):
+    P, ctx, _ = gpu
+    say("worker-count tuning")
+    best, rates = P.prrtc_tune_workers(ctx, mixed, params(P, max_rounds=300), candidates=(16, 32, 64))
+    say("  best", best, rates)
+    assert best in (16, 32, 64)
+    assert all(r > 0 for r in rates.values())
+    assert rates[best] == max(rates.values())
+    # a candidate that cannot be resident at all rates 0 and is never chosen
+    best2, rates2 = P.prrtc_tune_workers(ctx, mixed[:2], params(P, max_rounds=50, tree_capacity=4096),
+                                         candidates=(32, 4096), memory_budget=4 << 20)
+    assert best2 == 32 and rates2[4096] == 0.0

@@ -70,9 +70,11 @@ def _forward_gpu(gpu, mid, rid, vox_t, scene_of, s, g):
     return out.cpu().numpy().astype(np.float64)
 
 
-def test_forward_parity(gpu, prop, r7):
+@pytest.mark.parametrize("per_scene", [13, 1])
+def test_forward_parity(gpu, prop, r7, per_scene):
+    """39 rows run on the matrix-core GEMMs, 3 rows on the small-batch path."""
     P, ctx, torch = gpu
-    say("proposal forward parity")
+    say("proposal forward parity, %d rows per scene" % per_scene)
     rng = np.random.default_rng(3)
     dof = 7
     params = PR.init_params(dof, 11)
@@ -84,7 +86,7 @@ def test_forward_parity(gpu, prop, r7):
     scenes = [W.scene_s12(r7, i) for i in range(3)]
     vox_t = gpu_vox(gpu, scenes)
     vox = vox_t.cpu().numpy().astype(np.float64)
-    scene_of, _, s, g, _ = _batch(rng, r7, 3, 13)          # 39 samples: ragged against 64-row tiles
+    scene_of, _, s, g, _ = _batch(rng, r7, 3, per_scene)   # 39 samples: ragged against 64-row tiles
     got = _forward_gpu(gpu, mid, rid, vox_t, scene_of, s, g)
     (logits, mu, logsig), cache = prop.forward(params, vox, scene_of, s, g, r7["q_lo"], r7["q_hi"])
     ref = np.concatenate([logits, mu.reshape(len(s), -1), logsig.reshape(len(s), -1)], axis=1)
