@@ -226,9 +226,12 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
         # launch shape from the autotuner on a sample of the pool
         sample = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
                    seed + 777 + k, 0) for k in range(slots)]
-        workers, tune = P.prrtc_tune_workers(ctx, sample, prm, memory_budget=budget)
+        (workers, tile), rates = P.prrtc_tune_launch(ctx, sample, prm, memory_budget=budget)
+        tune = {"workers": workers, "tile": tile,
+                "queries_per_s": {"%d/%d" % k: v for k, v in rates.items()}}
         if log:
-            log("  tuned workers per query: %d %s" % (workers, tune))
+            log("  tuned launch shape: %d workers per query, tile %d" % (workers, tile))
+        prm.tile = tile
     prm.workers = workers
     done = np.full(n_queries, np.nan)
     status = np.zeros(n_queries, np.int32)

@@ -173,6 +173,10 @@ typedef struct {
     int32_t model_id;        /* proposal model for sampler 1; its dof must match */
     float mix;               /* sampler 1: probability that a draw comes from the
                                 mixture (0..1, default 0.5); 0 gives the uniform plan */
+    int32_t tile;            /* configurations per FK tile of the collision checks:
+                                64 (0 = default; lowest latency per query) or 16
+                                (a quarter of the LDS: more groups per batched
+                                launch); results do not depend on it */
 } prrtc_plan_params;
 
 typedef struct {
@@ -249,15 +253,16 @@ prrtc_status prrtc_plan_batch(prrtc_ctx *ctx, const prrtc_query *queries, int32_
 
 /*
  * Launch-shape tuning for batched planning: the queries are planned once per
- * candidate worker count (each pass a complete prrtc_plan_batch with the
+ * (worker count, tile) pair (each pass a complete prrtc_plan_batch with the
  * largest resident group count and memory_budget), timed on the host clock.
- * rates (may be NULL): host float [n_cand], queries per second of each
- * candidate (0 if it cannot launch).  *best = the fastest candidate.
- * Synchronous; E_CAPACITY if no candidate can launch.
+ * rates (may be NULL): host float [n_workers][n_tiles], queries per second
+ * of each pair (0 if it cannot launch).  *best_workers, *best_tile = the
+ * fastest pair.  Synchronous; E_CAPACITY if no pair can launch.
  */
-prrtc_status prrtc_tune_workers(prrtc_ctx *ctx, const prrtc_query *queries, int32_t n,
-                                const prrtc_plan_params *params, const int32_t *candidates, int32_t n_cand,
-                                int64_t memory_budget, float *rates, int32_t *best);
+prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32_t n,
+                               const prrtc_plan_params *params, const int32_t *workers, int32_t n_workers,
+                               const int32_t *tiles, int32_t n_tiles, int64_t memory_budget, float *rates,
+                               int32_t *best_workers, int32_t *best_tile);
 
 /*
  * Serving: a thread owned by the context gathers submitted queries into

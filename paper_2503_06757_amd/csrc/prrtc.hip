@@ -689,7 +689,7 @@ namespace {
 #define PRRTC_EDGE_TILE 16
 #endif
 #ifndef PRRTC_EDGE_ITEMS
-#define PRRTC_EDGE_ITEMS 2
+#define PRRTC_EDGE_ITEMS 3
 #endif
 constexpr int kEdgeTile = PRRTC_EDGE_TILE;
 constexpr int kEdgeItems = PRRTC_EDGE_ITEMS;
@@ -780,14 +780,25 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
 // ----------------------------------------------------------------------------
 namespace {
 
-#ifndef PRRTC_PLAN_TILE
-#define PRRTC_PLAN_TILE 16
-#endif
-#ifndef PRRTC_PLAN_ITEMS
-#define PRRTC_PLAN_ITEMS 2
-#endif
-constexpr int kPlanTile = PRRTC_PLAN_TILE;
-constexpr int kPlanItems = PRRTC_PLAN_ITEMS;
+// Planner launch shapes: the collision checks' FK tile (configurations per
+// wave tile) and items per lane.  A 64-configuration tile halves the latency
+// of a query's long connect checks; a 16-configuration tile needs a quarter
+// of the LDS, so more worker groups fit at once in batched launches.
+struct PlanShape {
+    int tile, items;
+    const void* kernel;
+};
+
+const PlanShape* plan_shape(int tile) {
+    static const PlanShape shapes[] = {
+        {64, 6, reinterpret_cast<const void*>(&k_plan<64, 6>)},
+        {16, 3, reinterpret_cast<const void*>(&k_plan<16, 3>)},
+    };
+    if (tile == 0) return &shapes[0];
+    for (const PlanShape& sh : shapes)
+        if (sh.tile == tile) return &sh;
+    return nullptr;
+}
 
 // Device buffers of one worker group (reused by every query the group runs).
 struct GroupLayout {
@@ -847,9 +858,9 @@ int stage_cap_for(const RobotArgs& RA, float delta) {
     return sc > 4096 ? -1 : sc;
 }
 
-size_t plan_lds_bytes(const RobotArgs& RA, int stage_cap, int dof) {
-    return sphere_lds_bytes(RA) + sizeof(float4) * kPlanTile * 3 * RA.n_slots +
-           sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) + sizeof(int) * (kPlanTile + 2 * (stage_cap + 2));
+size_t plan_lds_bytes(const RobotArgs& RA, int stage_cap, int dof, int tile) {
+    return sphere_lds_bytes(RA) + sizeof(float4) * tile * 3 * RA.n_slots +
+           sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) + sizeof(int) * (tile + 2 * (stage_cap + 2));
 }
 
 prrtc_status check_plan_params(prrtc_ctx* ctx, const prrtc_plan_params& p) {
@@ -865,6 +876,7 @@ prrtc_status check_plan_params(prrtc_ctx* ctx, const prrtc_plan_params& p) {
         return fail(ctx, PRRTC_E_ARG, "dds_radius must be finite and >= 0");
     if (p.dds_tries < 1 || p.dds_tries > 64) return fail(ctx, PRRTC_E_ARG, "dds_tries must be in 1..64");
     if (p.sampler != 0 && p.sampler != 1) return fail(ctx, PRRTC_E_ARG, "sampler must be 0 or 1");
+    if (!plan_shape(p.tile)) return fail(ctx, PRRTC_E_ARG, "tile must be 0, 16 or 64");
     if (p.sampler == 1) {
         if (!(p.mix >= 0.0f && p.mix <= 1.0f)) return fail(ctx, PRRTC_E_ARG, "mix must be in [0, 1]");
         if (p.model_id < 0 || p.model_id >= (int32_t)ctx->models.size())
@@ -965,6 +977,7 @@ void prrtc_plan_params_default(prrtc_plan_params* p) {
     p->sampler = 0;
     p->model_id = -1;
     p->mix = 0.5f;
+    p->tile = 0;
 }
 
 prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const float* start,
@@ -1016,7 +1029,8 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     A.out_path = reinterpret_cast<float*>(m + o_out);
     A.out_path_cap = A.path_cap;
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
-    const size_t lds = plan_lds_bytes(r->args, stage_cap, dof);
+    const PlanShape& shape = *plan_shape(p.tile);
+    const size_t lds = plan_lds_bytes(r->args, stage_cap, dof, shape.tile);
     hipStream_t sm = ctx->stream;
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
     if (p.sampler == 1) {
@@ -1030,8 +1044,7 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = 1, n_g = 1;
     void* kargs[] = {&Pq, &n_q, &n_g};
-    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
-                                              dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(shape.kernel, dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
     // the words and the first nodes of the path in one copy to pinned memory
     const int prefix = std::min(std::min(path_cap, 2 * cap), (kPinnedFloats - kCtlWords) / dof);
@@ -1098,7 +1111,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
         live.push_back(k);
         dof_max = std::max(dof_max, r->dof);
         stage_max = std::max(stage_max, sc);
-        lds = std::max(lds, plan_lds_bytes(r->args, sc, r->dof));
+        lds = std::max(lds, plan_lds_bytes(r->args, sc, r->dof, plan_shape(p.tile)->tile));
     }
     ctx->err.clear();
     const int n_live = (int)live.size();
@@ -1108,7 +1121,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     int per_cu = 0;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                       &per_cu, reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>), kWave, lds));
+                       &per_cu, plan_shape(p.tile)->kernel, kWave, lds));
     const int g_resident = per_cu * ctx->n_cu / W;
     if (g_resident < 1) return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once", W);
     int G = groups > 0 ? groups : std::min(n_live, g_resident);
@@ -1185,8 +1198,8 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = n_live, n_g = G;
     void* kargs[] = {&Pq, &n_q, &n_g};
-    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plan<kPlanTile, kPlanItems>),
-                                              dim3((unsigned)(G * W)), dim3(kWave), kargs, (unsigned)lds, sm));
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(plan_shape(p.tile)->kernel, dim3((unsigned)(G * W)), dim3(kWave),
+                                              kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
     std::vector<int> ctl((size_t)kCtlWords * n_live);
     PRRTC_HIP(ctx, hipMemcpyAsync(ctl.data(), args[0].ctl, sizeof(int) * ctl.size(), hipMemcpyDeviceToHost, sm));
@@ -1229,31 +1242,40 @@ prrtc_status prrtc_plan_batch(prrtc_ctx* ctx, const prrtc_query* queries, int32_
     return plan_batch_impl(ctx, queries, n, prm, groups, memory_budget, paths, path_cap, results, groups_used);
 }
 
-prrtc_status prrtc_tune_workers(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n,
-                                const prrtc_plan_params* params, const int32_t* candidates, int32_t n_cand,
-                                int64_t memory_budget, float* rates, int32_t* best) {
+prrtc_status prrtc_tune_launch(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n,
+                               const prrtc_plan_params* params, const int32_t* workers, int32_t n_workers,
+                               const int32_t* tiles, int32_t n_tiles, int64_t memory_budget, float* rates,
+                               int32_t* best_workers, int32_t* best_tile) {
     if (!ctx) return PRRTC_E_ARG;
     ctx->err.clear();
     PRRTC_NOT_SERVING(ctx);
-    if (n < 1 || !queries || !params || !candidates || n_cand < 1 || !best || memory_budget < 0)
+    if (n < 1 || !queries || !params || !workers || n_workers < 1 || !tiles || n_tiles < 1 || !best_workers ||
+        !best_tile || memory_budget < 0)
         return fail(ctx, PRRTC_E_ARG, "bad tuning arguments");
+    for (int t = 0; t < n_tiles; ++t)
+        if (!plan_shape(tiles[t])) return fail(ctx, PRRTC_E_ARG, "tile must be 0, 16 or 64");
     std::vector<prrtc_query_result> res(n);
     std::vector<float> path((size_t)n * kMaxDof);
     float best_rate = -1.0f;
-    *best = 0;
-    for (int c = 0; c < n_cand; ++c) {
-        prrtc_plan_params p = *params;
-        p.workers = candidates[c];
-        const auto t0 = std::chrono::steady_clock::now();
-        prrtc_status st = plan_batch_impl(ctx, queries, n, &p, 0, memory_budget, path.data(), 1, res.data(), nullptr);
-        const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        const float rate = st == PRRTC_OK ? (float)(n / s) : 0.0f;   // a shape that cannot launch rates 0
-        if (rates) rates[c] = rate;
-        if (rate > best_rate) {
-            best_rate = rate;
-            *best = candidates[c];
+    *best_workers = 0;
+    *best_tile = 0;
+    for (int c = 0; c < n_workers; ++c)
+        for (int t = 0; t < n_tiles; ++t) {
+            prrtc_plan_params p = *params;
+            p.workers = workers[c];
+            p.tile = tiles[t];
+            const auto t0 = std::chrono::steady_clock::now();
+            const prrtc_status st =
+                plan_batch_impl(ctx, queries, n, &p, 0, memory_budget, path.data(), 1, res.data(), nullptr);
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            const float rate = st == PRRTC_OK ? (float)(n / sec) : 0.0f;   // a shape that cannot launch rates 0
+            if (rates) rates[c * n_tiles + t] = rate;
+            if (rate > best_rate) {
+                best_rate = rate;
+                *best_workers = workers[c];
+                *best_tile = plan_shape(tiles[t])->tile;
+            }
         }
-    }
     ctx->err.clear();
     return best_rate > 0.0f ? PRRTC_OK : fail(ctx, PRRTC_E_CAPACITY, "no candidate could launch");
 }

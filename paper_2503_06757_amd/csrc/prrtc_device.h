@@ -258,6 +258,9 @@ __device__ inline bool hit_pair(float4 a, float4 b) {
 // min/max instructions: pairs and quads by quad permutes, rows of 16 by the
 // half-row and row mirrors, then row broadcasts 15 and 31 carry the partial
 // results up so that lane 63 holds the wave's value.
+#ifndef PRRTC_FASTDIV
+#define PRRTC_FASTDIV 1
+#endif
 #ifndef PRRTC_DPP_REDUCE
 #define PRRTC_DPP_REDUCE 1
 #endif
@@ -378,6 +381,7 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
 template <int TP, int B, bool MULTI>
 __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
                           int i_first, float res, const WaveWs& ws) {
+    static_assert(TP >= 1 && TP <= kWave, "one configuration per lane in the FK tile");
     const int lane = threadIdx.x & (kWave - 1);
     const int dof = R.dof;
     const int fstride = 3 * R.n_slots;
@@ -422,6 +426,11 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
         __syncthreads();
         // ---- (point, sphere) items, point-major, against the obstacles
         const int nitems = np * S_move;
+        // it / np as a multiply and shift: with m = ceil(2^20 / np), (it m) >> 20
+        // equals floor(it / np) for it < np * 256 and np <= 64 (the rounding
+        // excess it (m - 2^20 / np) / 2^20 stays below 1/64 <= 1/np), and
+        // it m < 2^32
+        const unsigned div_m = ((1u << 20) + (unsigned)np - 1u) / (unsigned)np;
         bool stop = false;
         for (int base = 0; base < nitems && !stop; base += kWave * B) {
             float cx[B], cy[B], cz[B], cr[B];
@@ -430,7 +439,11 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             for (int b = 0; b < B; ++b) {
                 const int it = min(base + lane + kWave * b, nitems - 1);
 #if PRRTC_ITEM_ORDER == 1
-                const int s = it / np;          // sphere-major
+#if PRRTC_FASTDIV
+                const int s = (int)(((unsigned)it * div_m) >> 20);   // sphere-major
+#else
+                const int s = it / np;
+#endif
                 const int p = it - s * np;
 #else
                 const int p = it / S_move;      // point-major

@@ -528,7 +528,10 @@ __global__ void k_plan_init(int* bar, int n_groups, size_t bar_stride, int* ctl,
 // queries g, g + n_groups, ... one after another.  All queries of a launch
 // share W.  A group that aborts leaves its remaining queries at "internal".
 template <int TP, int B>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_plan(
+#ifndef PRRTC_PLAN_WAVES_PER_EU
+#define PRRTC_PLAN_WAVES_PER_EU 3
+#endif
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(PRRTC_PLAN_WAVES_PER_EU))) void k_plan(
     const PlanArgs* __restrict__ Pq, int n_queries, int n_groups) {
     extern __shared__ float4 lds4[];
     const int W = Pq[0].W;

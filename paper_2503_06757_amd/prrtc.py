@@ -61,6 +61,7 @@ class prrtc_plan_params(C.Structure):
         ("sampler", C.c_int32),
         ("model_id", C.c_int32),
         ("mix", C.c_float),
+        ("tile", C.c_int32),
     ]
 
 
@@ -162,9 +163,9 @@ def _load():
         L.prrtc_plan_batch.argtypes = [P, C.POINTER(prrtc_query), I32, C.POINTER(prrtc_plan_params), I32, I64,
                                        VP, I32, C.POINTER(prrtc_query_result), C.POINTER(I32)]
         L.prrtc_plan_batch.restype = I32
-        L.prrtc_tune_workers.argtypes = [P, C.POINTER(prrtc_query), I32, C.POINTER(prrtc_plan_params), VP, I32, I64,
-                                         VP, C.POINTER(I32)]
-        L.prrtc_tune_workers.restype = I32
+        L.prrtc_tune_launch.argtypes = [P, C.POINTER(prrtc_query), I32, C.POINTER(prrtc_plan_params), VP, I32, VP,
+                                        I32, I64, VP, C.POINTER(I32), C.POINTER(I32)]
+        L.prrtc_tune_launch.restype = I32
         L.prrtc_serve_start.argtypes = [P, C.POINTER(prrtc_plan_params), I32, I32, I64, I32]
         L.prrtc_serve_start.restype = I32
         L.prrtc_submit.argtypes = [P, C.POINTER(prrtc_query), C.POINTER(C.c_uint64)]
@@ -181,7 +182,7 @@ lib = _load()
 # the symbols include/prrtc.h declares (checked by the CPU test-suite)
 EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
             "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_fk_spheres",
-            "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_workers",
+            "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_launch",
             "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
             "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_sample", "prrtc_train_proposal")
 
@@ -339,16 +340,19 @@ def _query_array(queries):
     return arr
 
 
-def prrtc_tune_workers(ctx: int, queries, params, candidates=(16, 32, 64, 128, 256), memory_budget: int = 0):
-    """(best worker count, {candidate: queries/s})."""
+def prrtc_tune_launch(ctx: int, queries, params, workers=(16, 32, 64, 128, 256), tiles=(16, 64),
+                      memory_budget: int = 0):
+    """((best workers, best tile), {(workers, tile): queries/s})."""
     arr = _query_array(queries)
-    cand = np.asarray(candidates, np.int32)
-    rates = np.zeros(len(cand), np.float32)
-    best = C.c_int32(0)
-    _check(ctx, lib.prrtc_tune_workers(ctx, arr.ctypes.data_as(C.POINTER(prrtc_query)), len(queries),
-                                       C.byref(params), cand.ctypes.data, len(cand), int(memory_budget),
-                                       rates.ctypes.data, C.byref(best)))
-    return best.value, {int(c): float(r) for c, r in zip(cand, rates)}
+    wk = np.asarray(workers, np.int32)
+    tl = np.asarray(tiles, np.int32)
+    rates = np.zeros((len(wk), len(tl)), np.float32)
+    bw, bt = C.c_int32(0), C.c_int32(0)
+    _check(ctx, lib.prrtc_tune_launch(ctx, arr.ctypes.data_as(C.POINTER(prrtc_query)), len(queries),
+                                      C.byref(params), wk.ctypes.data, len(wk), tl.ctypes.data, len(tl),
+                                      int(memory_budget), rates.ctypes.data, C.byref(bw), C.byref(bt)))
+    return (bw.value, bt.value), {(int(w), int(t)): float(rates[i, j]) for i, w in enumerate(wk)
+                                  for j, t in enumerate(tl)}
 
 
 def prrtc_serve_start(ctx: int, params, slots: int = 256, max_pending: int = 1024, memory_budget: int = 0,

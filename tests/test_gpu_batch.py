@@ -63,7 +63,8 @@ def test_batch_equals_single(gpu, mixed, groups, workers):
     prm = params(P, workers=workers, max_rounds=500)
     used, out = P.prrtc_plan_batch(ctx, mixed, prm, groups=groups, path_cap=512)
     say("  groups used", used)
-    assert used == (groups if groups else len(mixed))
+    # groups = 0: as many as are resident at once (LDS and registers decide), at most one per query
+    assert used == groups if groups else 1 <= used <= len(mixed)
     for k, q in enumerate(mixed):
         st, path, stats = out[k]
         st1, path1, stats1 = _single(P, ctx, q, params(P, workers=workers, max_rounds=500))
@@ -164,15 +165,26 @@ def test_serving_submit_poll(gpu, mixed):
             assert np.array_equal(path, path1)
 
 
-def test_tune_workers(gpu, mixed):
+def test_tune_launch_and_tiles(gpu, mixed):
+    """The tuner returns the fastest (workers, tile) pair; the FK tile changes
+    only speed: every query plans identically with tile 16 and tile 64."""
     P, ctx, _ = gpu
-    say("worker-count tuning")
-    best, rates = P.prrtc_tune_workers(ctx, mixed, params(P, max_rounds=300), candidates=(16, 32, 64))
-    say("  best", best, rates)
-    assert best in (16, 32, 64)
+    say("launch-shape tuning")
+    (bw, bt), rates = P.prrtc_tune_launch(ctx, mixed, params(P, max_rounds=300), workers=(16, 32, 64),
+                                          tiles=(16, 64))
+    say("  best", bw, bt, rates)
+    assert (bw, bt) in rates and rates[(bw, bt)] == max(rates.values())
     assert all(r > 0 for r in rates.values())
-    assert rates[best] == max(rates.values())
-    # a candidate that cannot be resident at all rates 0 and is never chosen
-    best2, rates2 = P.prrtc_tune_workers(ctx, mixed[:2], params(P, max_rounds=50, tree_capacity=4096),
-                                         candidates=(32, 4096), memory_budget=4 << 20)
-    assert best2 == 32 and rates2[4096] == 0.0
+    # a shape that cannot be resident at all rates 0 and is never chosen
+    (bw2, _), rates2 = P.prrtc_tune_launch(ctx, mixed[:2], params(P, max_rounds=50, tree_capacity=4096),
+                                           workers=(32, 4096), tiles=(16,), memory_budget=4 << 20)
+    assert bw2 == 32 and rates2[(4096, 16)] == 0.0
+    for q in mixed[:6] + mixed[-2:]:
+        outs = [_single(P, ctx, q, params(P, workers=64, max_rounds=500, tile=t)) for t in (16, 64)]
+        assert outs[0][0] == outs[1][0]
+        for key in KEYS:
+            assert outs[0][2][key] == outs[1][2][key], key
+        if outs[0][0] == 0:
+            assert np.array_equal(outs[0][1], outs[1][1])
+    with pytest.raises(P.PrrtcError):
+        _single(P, ctx, mixed[0], params(P, tile=32))
