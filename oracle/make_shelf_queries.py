@@ -8,9 +8,10 @@ uses numpy seed SEED_QUERY + 1000 + i:
   * goal, per arm: uniform arm configurations whose hand-bar centre lies in a
     shelf cell on the arm's side (arm 0: y < 0, arm 1: y > 0), the eight with
     the largest clearance (arm alone) refined by a seeded random hill climb on
-    that clearance until it exceeds GOAL_CLEARANCE; the two arms' goals
-    together must be collision-free (including the inter-arm pairs) with
-    clearance > 1e-3 m.
+    that clearance until it exceeds GOAL_CLEARANCE, kept if a straight
+    joint-space retreat of 0.5-2 rad leads, collision-free, to a configuration
+    with the arm in front of the shelf; the two arms' goals together must be
+    collision-free (including the inter-arm pairs) with clearance > 1e-3 m.
 Rows are written as float32 with 9 significant digits (exact round trip).
 """
 from __future__ import annotations
@@ -28,6 +29,25 @@ from paper_2503_06757_amd import workloads as W  # noqa: E402
 
 
 GOAL_CLEARANCE = 0.02   # m: a grasp pose with room around the hand, not a jammed one
+ESCAPE_TRIES = 256      # straight joint-space retreats tried per goal
+ESCAPE_STEP = (0.5, 2.0)  # rad: length of a retreat
+
+
+def _escapes(rng, rob_arm, prims, q):
+    """Is there a straight joint-space segment of ESCAPE_STEP length from q to
+    a configuration with every sphere in front of the shelf (x < 0.4 m) that
+    is collision-free at 32 points per rad?  (A grasp pose the arm can back
+    out of, as pick poses in a shelf are.)"""
+    d = rng.standard_normal((ESCAPE_TRIES, 7))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    b = np.clip(q[None, :] + rng.uniform(*ESCAPE_STEP, (ESCAPE_TRIES, 1)) * d, -W.R7_LIMIT, W.R7_LIMIT)
+    b = b.astype(np.float32)
+    out = [k for k in range(ESCAPE_TRIES) if np.all(O.fk_spheres(rob_arm, b[k])[:, 0] < 0.4)]
+    if not out:
+        return False
+    a = np.repeat(q[None, :], len(out), 0).astype(np.float32)
+    valid = O.check_edges(rob_arm, prims, a, b[out], 32.0, early_exit=True, n_threads=1)[0]
+    return bool(valid.any())
 
 
 def _arm_goal(rng, rob_arm, prims, arm):
@@ -51,7 +71,7 @@ def _arm_goal(rng, rob_arm, prims, arm):
         step = 0.1
         for it in range(600):
             if s > GOAL_CLEARANCE:
-                return q
+                return q if _escapes(rng, rob_arm, prims, q) else None
             qn = np.clip(q + rng.normal(0.0, step, 7).astype(np.float32), -W.R7_LIMIT, W.R7_LIMIT)
             sn = score(qn)
             if sn is not None and sn > s:
