@@ -818,7 +818,7 @@ GroupLayout group_layout(int dof, int cap, int W, int stage_cap) {
     L.pb = take(sizeof(int) * (size_t)cap);
     L.bb = take((size_t)cap);
     L.rb = take(sizeof(float) * (size_t)cap);
-    L.bar = take(sizeof(int) * kBarWords);
+    L.bar = take(sizeof(int) * ((size_t)kBarWords + W));
     L.stage = take(sizeof(float) * (size_t)W * stage_cap * dof);
     L.st = take(sizeof(int) * 5 * (size_t)W);
     L.path = take(sizeof(float) * (size_t)path_cap * dof);
@@ -1040,7 +1040,9 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
         if (st != PRRTC_OK) return st;
         A.gmm = gmm;
     }
-    hipLaunchKernelGGL(k_plan_init, dim3(1), dim3(256), 0, sm, A.bar, 1, (size_t)0, A.ctl, 1, A, Pq);
+    const int bar_words = kBarWords + W;
+    hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((std::max(bar_words, 256) + 255) / 256)), dim3(256), 0, sm, A.bar,
+                       1, bar_words, (size_t)0, A.ctl, 1, A, Pq);
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = 1, n_g = 1;
     void* kargs[] = {&Pq, &n_q, &n_g};
@@ -1192,9 +1194,10 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
     PRRTC_HIP(ctx, hipMemcpyAsync(Pq, args.data(), sizeof(PlanArgs) * n_live, hipMemcpyHostToDevice, sm));
     // every group's barrier words (blocks L.bytes apart) and every query's words
-    const int init_threads = std::max(kBarWords * G, kCtlWords * n_live);
+    const int bar_words = kBarWords + W;
+    const int init_threads = std::max(bar_words * G, kCtlWords * n_live);
     hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((init_threads + 255) / 256)), dim3(256), 0, sm, args[0].bar, G,
-                       L.bytes / sizeof(int), args[0].ctl, n_live, args[0], (PlanArgs*)nullptr);
+                       bar_words, L.bytes / sizeof(int), args[0].ctl, n_live, args[0], (PlanArgs*)nullptr);
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = n_live, n_g = G;
     void* kargs[] = {&Pq, &n_q, &n_g};

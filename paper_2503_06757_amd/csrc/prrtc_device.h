@@ -378,9 +378,11 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
     }
 }
 
+// With n_chunks > 1 (one sub-edge only) the points i_first..n are split into
+// n_chunks equal runs and only run `chunk` is checked.
 template <int TP, int B, bool MULTI>
 __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
-                          int i_first, float res, const WaveWs& ws) {
+                          int i_first, float res, const WaveWs& ws, int chunk = 0, int n_chunks = 1) {
     static_assert(TP >= 1 && TP <= kWave, "one configuration per lane in the FK tile");
     const int lane = threadIdx.x & (kWave - 1);
     const int dof = R.dof;
@@ -389,11 +391,15 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
     int total = 0;
     for (int k0 = 0; k0 < n_sub; k0 += kWave) {
         const int k = k0 + lane;
-        int cnt = 0;
+        int cnt = 0, lo = 0;
         if (k < n_sub) {
             const int n = edge_count_f32(wp + k * dof, wp + (k + 1) * dof, dof, res);
             ws.sub_n[k] = n;
             cnt = n - i_first + 1;
+            if (n_chunks > 1) {
+                lo = cnt * chunk / n_chunks;
+                cnt = cnt * (chunk + 1) / n_chunks - lo;
+            }
         }
         int incl = cnt;
 #pragma unroll
@@ -401,7 +407,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             const int v = __shfl_up(incl, off, kWave);
             if (lane >= off) incl += v;
         }
-        if (k < n_sub) ws.sub_off[k] = total + incl - cnt;
+        if (k < n_sub) ws.sub_off[k] = total + incl - cnt - lo;   // point i = i_first + g - sub_off
         total += __shfl(incl, kWave - 1, kWave);
     }
     __syncthreads();

@@ -56,6 +56,10 @@ enum Ctl {
 };
 static_assert(kEdgesLo % 2 == 0 && kLearnedLo % 2 == 0, "64-bit counters need 8-byte alignment");
 
+// The final re-check splits every path segment's points into this many
+// chunks, checked by different workers.
+constexpr int kValChunks = 4;
+
 // Status codes written by the kernel (mirror prrtc_status).
 constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInternal = -7;
 
@@ -77,7 +81,7 @@ struct PlanArgs {
     long long budget_ticks;   // <= 0: none
     float* qa; int* pa; unsigned char* ba; float* ra;
     float* qb; int* pb; unsigned char* bb; float* rb;
-    int* bar;                 // group barrier words [kBarWords]
+    int* bar;                 // group barrier words [kBarWords + W] (generation, abort, per-worker flags)
     int* ctl;                 // query words [kCtlWords]
     float* stage;             // [W][stage_cap][dof]
     int* st_count; int* st_nn; int* st_other; int* st_conn; int* st_fail;
@@ -142,6 +146,75 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
     }
     __syncthreads();
     return ok_s != 0;
+}
+
+// Group barrier without a shared counter: every workgroup w > 0 publishes its
+// arrival by storing the next generation number into its own flag word
+// (flags = bar + kBarWords, one int per worker) and then waits for the
+// generation word to advance; workgroup 0 polls all flags with its whole wave
+// and advances the generation once every flag shows it.  Release stores and
+// acquire loads at agent scope carry each workgroup's earlier writes through
+// workgroup 0 to everyone.  Flags and generation only grow, so nothing is
+// reset between barriers, queries or rounds.  Waits are bounded as above.
+#ifndef PRRTC_FLAG_BARRIER
+#define PRRTC_FLAG_BARRIER 1
+#endif
+__device__ inline bool group_barrier(int* bar, int w, int nblocks) {
+#if PRRTC_FLAG_BARRIER
+    __shared__ int ok_s;
+    __syncthreads();
+    unsigned* gen = reinterpret_cast<unsigned*>(bar + kBarGen);
+    unsigned* flags = reinterpret_cast<unsigned*>(bar + kBarWords);
+    int ok = 1;
+    if (w == 0) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const unsigned g = __shfl(threadIdx.x == 0 ? __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0u,
+                                  0, kWave);
+        const unsigned target = g + 1u;
+        const unsigned long long t0 = wall_clock64();
+        for (;;) {
+            bool arrived = true;
+            for (int i = 1 + lane; i < nblocks; i += kWave)
+                arrived &= __hip_atomic_load(flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == target;
+            if (__all(arrived)) break;
+            __builtin_amdgcn_s_sleep(1);
+            const bool abort = __hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            const bool late = wall_clock64() - t0 > 200000000ull;   // 2 s at the 100 MHz wall clock
+            if (abort || late) {
+                if (late && threadIdx.x == 0) __hip_atomic_store(bar + kAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);   // the flags' release stores happen before what follows
+        if (ok && threadIdx.x == 0) __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (threadIdx.x == 0) {
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(flags + w, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > 200000000ull) {
+                __hip_atomic_store(bar + kAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+#else
+    (void)w;
+    return grid_barrier(bar, nblocks);
+#endif
 }
 
 // Wave argmin of the FP32 squared distance (in joint order, no FMA) over
@@ -251,7 +324,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         if (!ok && lane == 0) atomicOr(ctl + kEndpointBad, 1);
         __syncthreads();
     }
-    if (!grid_barrier(P.bar, P.W)) return false;
+    if (!group_barrier(P.bar, w, P.W)) return false;
     if (ctl[kEndpointBad]) {
         if (w == 0 && lane == 0) ctl[kStatus] = kStInvalidEndpoint;
         return true;
@@ -370,7 +443,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             P.st_conn[w] = conn;
             P.st_fail[w] = fail;
         }
-        if (!grid_barrier(P.bar, P.W)) break;
+        if (!group_barrier(P.bar, w, P.W)) break;
         // ===== phase B: ordered commit
         int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1;
         for (int c0 = 0; c0 < P.W; c0 += kWave) {
@@ -420,24 +493,29 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             ctl[s_is_a ? kSizeA : kSizeB] = new_size;
             if (P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks) ctl[kStop] = 1;
         }
-        if (!grid_barrier(P.bar, P.W)) break;
+        if (!group_barrier(P.bar, w, P.W)) break;
         // ===== phase C: path and re-check
         if (first != 0x7fffffff) {
             const int xa = s_is_a ? first_last : first_other;
             const int xb = s_is_a ? first_other : first_last;
             if (w == 0) {
                 if (lane == 0) {
-                    int bad = 0, la = 0, lb = 0;
-                    for (int x = xa; x >= 0; x = P.pa[x]) { ++la; bad |= P.ba[x]; }
-                    for (int x = xb; x >= 0; x = P.pb[x]) { ++lb; bad |= P.bb[x]; }
-                    const int len = la + lb;
-                    if (len <= P.path_cap) {
-                        int m = la - 1;
-                        for (int x = xa; x >= 0; x = P.pa[x]) P.path_idx[m--] = x;
-                        m = la;
-                        for (int x = xb; x >= 0; x = P.pb[x]) P.path_idx[m++] = x;
-                    } else {
+                    // one walk per tree: A from the connection node up to its root
+                    // (stored reversed, flipped below), B from its node up to its root
+                    int bad = 0, la = 0, lb = 0, x = xa;
+                    for (; x >= 0 && la < cap; x = P.pa[x]) {
+                        P.path_idx[la++] = x;
+                        bad |= P.ba[x];
+                    }
+                    int y = xb;
+                    for (; y >= 0 && lb < cap; y = P.pb[y]) {
+                        P.path_idx[la + lb++] = y;
+                        bad |= P.bb[y];
+                    }
+                    int len = la + lb;
+                    if (x >= 0 || y >= 0) {           // a parent chain longer than the tree
                         bad = 1;
+                        len = P.path_cap + 1;
                         atomicExch(P.bar + kAbort, 3);
                     }
                     if (P.validate <= 0) bad = len > P.path_cap;  // no re-check: blocked nodes cannot exist
@@ -456,6 +534,13 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 __threadfence_block();
                 const int la = sh_i[1], len = sh_i[2];
                 if (len <= P.path_cap) {
+                    for (int m = lane; m < la / 2; m += kWave) {
+                        const int u = P.path_idx[m], v = P.path_idx[la - 1 - m];
+                        P.path_idx[m] = v;
+                        P.path_idx[la - 1 - m] = u;
+                    }
+                    __syncthreads();
+                    __threadfence_block();
                     for (int e = lane; e < len * dof; e += kWave) {
                         const int m = e / dof, j = e - m * dof;
                         const bool in_a = m < la;
@@ -464,14 +549,16 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     }
                 }
             }
-            if (!grid_barrier(P.bar, P.W)) break;
+            if (!group_barrier(P.bar, w, P.W)) break;
             const int la = ctl[kNa], len = ctl[kPathLen];
             if (P.validate > 0) {
-                for (int k = w; k + 1 < len; k += P.W) {
+                // each segment's points in kValChunks chunks, one per worker
+                for (int item = w; item < (len - 1) * kValChunks; item += P.W) {
+                    const int k = item / kValChunks, c = item - k * kValChunks;
                     if (lane < 2 * dof) wp[lane] = P.path[(size_t)k * dof + lane];
                     __syncthreads();
-                    const bool ok = wave_check<TP, B, false>(R, S, wp, 1, 0, P.res_v, ws) == 1;
-                    my_edges += 1;
+                    const bool ok = wave_check<TP, B, false>(R, S, wp, 1, 0, P.res_v, ws, c, kValChunks) == 1;
+                    if (c == 0) my_edges += 1;
                     if (!ok && lane == 0) {
                         ctl[kValBad] = 1;
                         if (k + 1 < la) P.ba[P.path_idx[k + 1]] = 1;
@@ -481,7 +568,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     __syncthreads();
                 }
             }
-            if (!grid_barrier(P.bar, P.W)) break;
+            if (!group_barrier(P.bar, w, P.W)) break;
             if (!ctl[kValBad]) {
                 status = kStOk;
                 if (w == 0 && lane == 0) ctl[kConnWorker] = first;
@@ -512,13 +599,14 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     return !aborted;
 }
 
-// Prepare a launch: zero the barrier words of n_groups groups (bar_stride
-// ints apart) and set every query's words to (status = internal error,
-// rest 0); with Pq, the single query's arguments (by value) are stored there.
-__global__ void k_plan_init(int* bar, int n_groups, size_t bar_stride, int* ctl, int n_queries, PlanArgs one_query,
-                            PlanArgs* Pq) {
+// Prepare a launch: zero the barrier words (bar_words each) of n_groups groups
+// (bar_stride ints apart) and set every query's words to (status = internal
+// error, rest 0); with Pq, the single query's arguments (by value) are stored
+// there.
+__global__ void k_plan_init(int* bar, int n_groups, int bar_words, size_t bar_stride, int* ctl, int n_queries,
+                            PlanArgs one_query, PlanArgs* Pq) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n_groups * kBarWords) bar[(size_t)(t / kBarWords) * bar_stride + t % kBarWords] = 0;
+    if (t < n_groups * bar_words) bar[(size_t)(t / bar_words) * bar_stride + t % bar_words] = 0;
     if (t < n_queries * kCtlWords) ctl[t] = (t % kCtlWords) == kStatus ? kStInternal : 0;
     if (Pq && t < (int)(sizeof(PlanArgs) / sizeof(int)))
         reinterpret_cast<int*>(Pq)[t] = reinterpret_cast<const int*>(&one_query)[t];
