@@ -73,6 +73,7 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
     ws.pk = reinterpret_cast<int*>(wp + 2 * kMaxDof);
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + 2;
+    ws.shared = nullptr;   // single-wave checks share nothing
     stage_spheres(R, sph, slot3);
     load_bounds(S, ws);
     const bool fixed_hit = static_collision(R, S);
@@ -781,18 +782,22 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
 namespace {
 
 // Planner launch shapes: the collision checks' FK tile (configurations per
-// wave tile) and items per lane.  A 64-configuration tile halves the latency
-// of a query's long connect checks; a 16-configuration tile needs a quarter
-// of the LDS, so more worker groups fit at once in batched launches.
+// tile), items per lane and waves per worker.  Four waves sharing a
+// 64-configuration tile cut the latency of a query's long connect checks; a
+// one-wave worker with a 16-configuration tile needs a quarter of the LDS and
+// a quarter of the waves, so more worker groups fit in batched launches.
+#ifndef PRRTC_PLAN_WAVES
+#define PRRTC_PLAN_WAVES 4
+#endif
 struct PlanShape {
-    int tile, items;
+    int tile, items, waves;
     const void* kernel;
 };
 
 const PlanShape* plan_shape(int tile) {
     static const PlanShape shapes[] = {
-        {64, 6, reinterpret_cast<const void*>(&k_plan<64, 6>)},
-        {16, 3, reinterpret_cast<const void*>(&k_plan<16, 3>)},
+        {64, 6, PRRTC_PLAN_WAVES, reinterpret_cast<const void*>(&k_plan<64, 6, PRRTC_PLAN_WAVES, 2>)},
+        {16, 3, 1, reinterpret_cast<const void*>(&k_plan<16, 3, 1, 3>)},
     };
     if (tile == 0) return &shapes[0];
     for (const PlanShape& sh : shapes)
@@ -1046,7 +1051,8 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = 1, n_g = 1;
     void* kargs[] = {&Pq, &n_q, &n_g};
-    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(shape.kernel, dim3(W), dim3(kWave), kargs, (unsigned)lds, sm));
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(shape.kernel, dim3(W), dim3(kWave * shape.waves), kargs, (unsigned)lds,
+                                              sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
     // the words and the first nodes of the path in one copy to pinned memory
     const int prefix = std::min(std::min(path_cap, 2 * cap), (kPinnedFloats - kCtlWords) / dof);
@@ -1123,7 +1129,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     int per_cu = 0;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                       &per_cu, plan_shape(p.tile)->kernel, kWave, lds));
+                       &per_cu, plan_shape(p.tile)->kernel, kWave * plan_shape(p.tile)->waves, lds));
     const int g_resident = per_cu * ctx->n_cu / W;
     if (g_resident < 1) return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once", W);
     int G = groups > 0 ? groups : std::min(n_live, g_resident);
@@ -1201,8 +1207,8 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = n_live, n_g = G;
     void* kargs[] = {&Pq, &n_q, &n_g};
-    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(plan_shape(p.tile)->kernel, dim3((unsigned)(G * W)), dim3(kWave),
-                                              kargs, (unsigned)lds, sm));
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(plan_shape(p.tile)->kernel, dim3((unsigned)(G * W)),
+                                              dim3(kWave * plan_shape(p.tile)->waves), kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
     std::vector<int> ctl((size_t)kCtlWords * n_live);
     PRRTC_HIP(ctx, hipMemcpyAsync(ctl.data(), args[0].ctl, sizeof(int) * ctl.size(), hipMemcpyDeviceToHost, sm));

@@ -358,6 +358,7 @@ struct WaveWs {
     int* pk;
     int* sub_n;
     int* sub_off;
+    int* shared;         // two ints: running minimum and stop flag (multi-wave checks only)
     float4 bnd_sph, bnd_box, bnd_cyl;  // per lane: bounds of obstacle `lane` of each type
 };
 
@@ -380,11 +381,20 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
 
 // With n_chunks > 1 (one sub-edge only) the points i_first..n are split into
 // n_chunks equal runs and only run `chunk` is checked.
-template <int TP, int B, bool MULTI>
+//
+// NW > 1: the NW waves of a workgroup check together.  Every wave runs the
+// same tile loop; the tile's FK is split into TP / NW configurations per
+// wave, its item blocks are dealt to the waves in turn, and at the end of
+// the tile the waves' results meet in LDS (ws.shared[0]: least colliding
+// sub-edge; ws.shared[1]: a wave found a hit, single sub-edge).
+template <int TP, int B, bool MULTI, int NW = 1>
 __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
                           int i_first, float res, const WaveWs& ws, int chunk = 0, int n_chunks = 1) {
     static_assert(TP >= 1 && TP <= kWave, "one configuration per lane in the FK tile");
+    static_assert(NW >= 1 && TP % NW == 0, "the FK tile splits evenly over the waves");
     const int lane = threadIdx.x & (kWave - 1);
+    const int wave = NW > 1 ? (int)(threadIdx.x / kWave) : 0;
+    volatile int* shared = ws.shared;
     const int dof = R.dof;
     const int fstride = 3 * R.n_slots;
     // point counts and prefix offsets, in chunks of 64 sub-edges
@@ -394,7 +404,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
         int cnt = 0, lo = 0;
         if (k < n_sub) {
             const int n = edge_count_f32(wp + k * dof, wp + (k + 1) * dof, dof, res);
-            ws.sub_n[k] = n;
+            if (wave == 0) ws.sub_n[k] = n;
             cnt = n - i_first + 1;
             if (n_chunks > 1) {
                 lo = cnt * chunk / n_chunks;
@@ -407,17 +417,23 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             const int v = __shfl_up(incl, off, kWave);
             if (lane >= off) incl += v;
         }
-        if (k < n_sub) ws.sub_off[k] = total + incl - cnt - lo;   // point i = i_first + g - sub_off
+        if (k < n_sub && wave == 0) ws.sub_off[k] = total + incl - cnt - lo;   // point i = i_first + g - sub_off
         total += __shfl(incl, kWave - 1, kWave);
+    }
+    if (NW > 1 && threadIdx.x == 0) {
+        shared[0] = n_sub;
+        shared[1] = 0;
     }
     __syncthreads();
     int kmin = n_sub;
     const int S_move = R.n_move;
     for (int g0 = 0; g0 < total; g0 += TP) {
         const int np = min(TP, total - g0);
-        // ---- FK of the tile's configurations: lane l takes point g0 + l
-        if (lane < np) {
-            const int g = g0 + lane;
+        // ---- FK of the tile's configurations: slot wave * TP / NW + lane takes
+        // point g0 + slot
+        const int slot = wave * (TP / NW) + lane;
+        if (lane < TP / NW && slot < np) {
+            const int g = g0 + slot;
             int k = 0;
             if (MULTI)
                 while (k + 1 < n_sub && ws.sub_off[k + 1] <= g) ++k;
@@ -425,9 +441,9 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             const float t = (float)i / (float)ws.sub_n[k];
             const float* w0 = wp + k * dof;
             const float* w1 = w0 + dof;
-            ws.pk[lane] = k;
+            ws.pk[slot] = k;
             fk_frames<false>(R, [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); },
-                             ws.frames + lane * fstride);
+                             ws.frames + slot * fstride);
         }
         __syncthreads();
         // ---- (point, sphere) items, point-major, against the obstacles
@@ -438,7 +454,8 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
         // it m < 2^32
         const unsigned div_m = ((1u << 20) + (unsigned)np - 1u) / (unsigned)np;
         bool stop = false;
-        for (int base = 0; base < nitems && !stop; base += kWave * B) {
+        for (int base = wave * kWave * B; base < nitems && !stop; base += NW * kWave * B) {
+            if (NW > 1 && !MULTI && shared[1]) break;   // another wave found a hit
             float cx[B], cy[B], cz[B], cr[B];
             int ck[B];
 #pragma unroll
@@ -569,13 +586,15 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             if (!MULTI && done) {
                 kmin = 0;
                 stop = true;
+                if (NW > 1 && lane == 0) shared[1] = 1;
             }
         }
         // ---- self collision, bipartite groups: per configuration, lanes
         // hold group A's spheres; group B's spheres (one per lane) are culled
         // against A's bounding box and the survivors tested against all of A.
         if (R.n_bip_a > 0 && (MULTI || kmin == n_sub)) {
-            for (int p = 0; p < np; ++p) {
+            for (int p = wave; p < np; p += NW) {
+                if (NW > 1 && !MULTI && shared[1]) break;
                 const int k = MULTI ? ws.pk[p] : 0;
                 if (k >= kmin) continue;
                 const float4* fp = ws.frames + p * fstride;
@@ -612,14 +631,17 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 }
                 if (hit) {
                     kmin = k;
-                    if (!MULTI) break;
+                    if (!MULTI) {
+                        if (NW > 1 && lane == 0) shared[1] = 1;
+                        break;
+                    }
                 }
             }
         }
         // ---- self-collision pairs: (point, pair) items, point-major
         if (R.n_pairs > 0 && (MULTI || kmin == n_sub)) {
             const int npi = np * R.n_pairs;
-            for (int base = 0; base < npi; base += kWave) {
+            for (int base = wave * kWave; base < npi; base += NW * kWave) {
                 const int it = min(base + lane, npi - 1);
                 const int p = it / R.n_pairs;
                 const int pr_i = it - p * R.n_pairs;
@@ -640,7 +662,14 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 }
             }
         }
-        __syncthreads();
+        if (NW > 1) {
+            if (lane == 0 && kmin < n_sub) atomicMin((int*)&shared[0], kmin);
+            __syncthreads();
+            kmin = shared[0];
+            __syncthreads();
+        } else {
+            __syncthreads();
+        }
         if (kmin < n_sub) return kmin;
     }
     return kmin;

@@ -168,7 +168,7 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks) {
     int ok = 1;
     if (w == 0) {
         const int lane = threadIdx.x & (kWave - 1);
-        const unsigned g = __shfl(threadIdx.x == 0 ? __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0u,
+        const unsigned g = __shfl(lane == 0 ? __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0u,
                                   0, kWave);
         const unsigned target = g + 1u;
         const unsigned long long t0 = wall_clock64();
@@ -257,11 +257,16 @@ __device__ inline int wave_nearest(const float* tq, const unsigned char* blocked
 // keeping every field live in registers.
 typedef __attribute__((address_space(4))) const PlanArgs CPlanArgs;
 
-template <int TP, int B>
+// A worker is a workgroup of NW waves: wave 0 ("lead") does the worker's
+// scalar bookkeeping and writes its small LDS vectors; every wave computes the
+// same samples and nearest neighbours and shares the collision checks.
+template <int TP, int B, int NW>
 __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, float4* lds4) {
     const RobotArgs& R = *P.R;   // device memory: uniform reads are scalar loads
     const SceneArgs& S = *P.S;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, nth = NW * kWave;
+    const int lane = tid & (kWave - 1);
+    const bool lead = tid < kWave;
     const int dof = R.dof;
     const int cap = P.cap;
     // ---- LDS carve-up
@@ -281,17 +286,19 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + P.stage_cap + 2;
     __shared__ int sh_i[8];
+    __shared__ int sh_check[2];
+    ws.shared = sh_check;
     int* ctl = P.ctl;
     long long my_edges = 0;
     long long my_learned = 0;
     __shared__ float gmm_s[kComp * (1 + 2 * kMaxDof)];
 
     // ---- prologue: roots, endpoint checks
-    if (w == 0 && lane < dof) {
+    if (w == 0 && lead && lane < dof) {
         P.qa[(size_t)lane * cap] = P.start[lane];
         P.qb[(size_t)lane * cap] = P.goal[lane];
     }
-    if (w == 0 && lane == 0) {
+    if (w == 0 && tid == 0) {
         P.pa[0] = -1;
         P.pb[0] = -1;
         P.ba[0] = 0;
@@ -305,28 +312,28 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     load_bounds(S, ws);
     bool use_gmm = false;
     if (P.gmm) {
-        for (int t = lane; t < kComp * (1 + 2 * dof); t += kWave) gmm_s[t] = P.gmm[t];
+        for (int t = tid; t < kComp * (1 + 2 * dof); t += nth) gmm_s[t] = P.gmm[t];
         __syncthreads();
         use_gmm = gmm_finite(gmm_s, dof);
-        if (!use_gmm && w == 0 && lane == 0) ctl[kFallback] = 1;
+        if (!use_gmm && w == 0 && tid == 0) ctl[kFallback] = 1;
     }
     const bool fixed_hit = static_collision(R, S);
     __syncthreads();
     const int n_end_workers = P.W > 1 ? 2 : 1;
     for (int e = w; e < 2; e += n_end_workers) {
-        if (lane < dof) {
+        if (lead && lane < dof) {
             const float v = e == 0 ? P.start[lane] : P.goal[lane];
             wp[lane] = v;
             wp[dof + lane] = v;
         }
         __syncthreads();
-        const bool ok = !fixed_hit && wave_check<TP, B, false>(R, S, wp, 1, 0, P.res, ws) == 1;
-        if (!ok && lane == 0) atomicOr(ctl + kEndpointBad, 1);
+        const bool ok = !fixed_hit && wave_check<TP, B, false, NW>(R, S, wp, 1, 0, P.res, ws) == 1;
+        if (!ok && tid == 0) atomicOr(ctl + kEndpointBad, 1);
         __syncthreads();
     }
     if (!group_barrier(P.bar, w, P.W)) return false;
     if (ctl[kEndpointBad]) {
-        if (w == 0 && lane == 0) ctl[kStatus] = kStInvalidEndpoint;
+        if (w == 0 && tid == 0) ctl[kStatus] = kStInvalidEndpoint;
         return true;
     }
     const unsigned long long t_start = wall_clock64();
@@ -358,17 +365,17 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     float v = 0.0f;
                     drawn = gmm_draw(gmm_s, dof, lo_j, hi_j, P.seed, P.query, (unsigned)round, (unsigned)w,
                                      4u * t + a, lane, &v);
-                    if (drawn && lane < dof) c_rand[lane] = v;
+                    if (drawn && lead && lane < dof) c_rand[lane] = v;
                 }
                 my_learned += drawn;
             }
-            if (!drawn && lane < dof)
+            if (!drawn && lead && lane < dof)
                 c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof, lane,
                                             pick(R.lo, lane), pick(R.hi, lane));
             __syncthreads();
             const int cand = wave_nearest(qs, bs, cap, ns, c_rand, dof);
             if (cand < 0) break;
-            if (lane < dof) c_nn[lane] = qs[(size_t)lane * cap + cand];
+            if (lead && lane < dof) c_nn[lane] = qs[(size_t)lane * cap + cand];
             __syncthreads();
             if (P.dds_radius > 0.0f && !(norm_diff_f32(c_nn, c_rand, dof) <= rs[cand])) continue;
             nn = cand;
@@ -378,7 +385,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             {
 #pragma clang fp contract(off)
                 const float L = norm_diff_f32(c_nn, c_rand, dof);
-                if (lane < dof) {
+                if (lead && lane < dof) {
                     if (L <= P.delta) {
                         c_new[lane] = c_rand[lane];
                     } else {
@@ -390,14 +397,14 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 }
             }
             __syncthreads();
-            const bool ext_ok = wave_check<TP, B, false>(R, S, wp, 1, 1, P.res, ws) == 1;
+            const bool ext_ok = wave_check<TP, B, false, NW>(R, S, wp, 1, 1, P.res, ws) == 1;
             my_edges += 1;
             if (!ext_ok) fail = nn;
             if (ext_ok) {
                 count = 1;
                 other = wave_nearest(qo, bo, cap, no, c_new, dof);
                 if (other >= 0) {
-                    if (lane < dof) c_nno[lane] = qo[(size_t)lane * cap + other];
+                    if (lead && lane < dof) c_nno[lane] = qo[(size_t)lane * cap + other];
                     __syncthreads();
                     int n_ext;
                     {
@@ -409,11 +416,11 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     }
                     if (n_ext > P.stage_cap) {
                         // cannot happen for nodes inside the joint limits
-                        if (lane == 0) atomicExch(P.bar + kAbort, 2);
+                        if (tid == 0) atomicExch(P.bar + kAbort, 2);
                         n_ext = P.stage_cap;
                     }
                     // waypoints t_0 = c_new, t_k = fmaf(k / n_ext, c_nno - c_new, c_new), t_n = c_nno
-                    for (int e = lane; e < (n_ext + 1) * dof; e += kWave) {
+                    for (int e = tid; e < (n_ext + 1) * dof; e += nth) {
                         const int k = e / dof, j = e - k * dof;
                         float v;
                         if (k == 0) v = c_new[j];
@@ -426,17 +433,17 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                         wp[e] = v;
                     }
                     __syncthreads();
-                    const int K = wave_check<TP, B, true>(R, S, wp, n_ext, 1, P.res, ws);
+                    const int K = wave_check<TP, B, true, NW>(R, S, wp, n_ext, 1, P.res, ws);
                     my_edges += min(K + 1, n_ext);
                     count = 1 + min(K, n_ext - 1);
                     conn = K == n_ext;
                 }
                 // stage c_new and the valid intermediate targets
                 float* st = P.stage + (size_t)w * P.stage_cap * dof;
-                for (int e = lane; e < count * dof; e += kWave) st[e] = (e < dof) ? c_new[e] : wp[e];
+                for (int e = tid; e < count * dof; e += nth) st[e] = (e < dof) ? c_new[e] : wp[e];
             }
         }
-        if (lane == 0) {
+        if (tid == 0) {
             P.st_count[w] = count;
             P.st_nn[w] = nn;
             P.st_other[w] = other;
@@ -458,7 +465,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             }
             const int base_i = ns + running + incl - cnt;
             const bool fits = base_i + cnt <= cap;
-            if (wi == w) sh_i[0] = base_i;
+            if (lead && wi == w) sh_i[0] = base_i;
             const int cand = wave_min_int((cn && fits) ? wi : 0x7fffffff);
             if (first == 0x7fffffff && cand != 0x7fffffff) {
                 first = cand;
@@ -475,20 +482,20 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         {
             const int c = max(0, min(count, cap - my_base));
             const float* st = P.stage + (size_t)w * P.stage_cap * dof;
-            for (int e = lane; e < c * dof; e += kWave) {
+            for (int e = tid; e < c * dof; e += nth) {
                 const int k = e / dof, j = e - k * dof;
                 qs[(size_t)j * cap + my_base + k] = st[e];
             }
-            for (int k = lane; k < c; k += kWave) {
+            for (int k = tid; k < c; k += nth) {
                 ps[my_base + k] = k == 0 ? nn : my_base + k - 1;
                 bs[my_base + k] = 0;
                 rs[my_base + k] = __builtin_inff();
             }
             // a failed extension shrinks its start node's domain (same value
             // from every worker, so the order of these writes does not matter)
-            if (lane == 0 && fail >= 0 && P.dds_radius > 0.0f) rs[fail] = P.dds_radius;
+            if (tid == 0 && fail >= 0 && P.dds_radius > 0.0f) rs[fail] = P.dds_radius;
         }
-        if (w == 0 && lane == 0) {
+        if (w == 0 && tid == 0) {
             const int new_size = min(cap, ns + running);
             ctl[s_is_a ? kSizeA : kSizeB] = new_size;
             if (P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks) ctl[kStop] = 1;
@@ -499,7 +506,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             const int xa = s_is_a ? first_last : first_other;
             const int xb = s_is_a ? first_other : first_last;
             if (w == 0) {
-                if (lane == 0) {
+                if (tid == 0) {
                     // one walk per tree: A from the connection node up to its root
                     // (stored reversed, flipped below), B from its node up to its root
                     int bad = 0, la = 0, lb = 0, x = xa;
@@ -534,14 +541,14 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 __threadfence_block();
                 const int la = sh_i[1], len = sh_i[2];
                 if (len <= P.path_cap) {
-                    for (int m = lane; m < la / 2; m += kWave) {
+                    for (int m = tid; m < la / 2; m += nth) {
                         const int u = P.path_idx[m], v = P.path_idx[la - 1 - m];
                         P.path_idx[m] = v;
                         P.path_idx[la - 1 - m] = u;
                     }
                     __syncthreads();
                     __threadfence_block();
-                    for (int e = lane; e < len * dof; e += kWave) {
+                    for (int e = tid; e < len * dof; e += nth) {
                         const int m = e / dof, j = e - m * dof;
                         const bool in_a = m < la;
                         const float* q = in_a ? P.qa : P.qb;
@@ -555,11 +562,11 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 // each segment's points in kValChunks chunks, one per worker
                 for (int item = w; item < (len - 1) * kValChunks; item += P.W) {
                     const int k = item / kValChunks, c = item - k * kValChunks;
-                    if (lane < 2 * dof) wp[lane] = P.path[(size_t)k * dof + lane];
+                    if (lead && lane < 2 * dof) wp[lane] = P.path[(size_t)k * dof + lane];
                     __syncthreads();
-                    const bool ok = wave_check<TP, B, false>(R, S, wp, 1, 0, P.res_v, ws, c, kValChunks) == 1;
+                    const bool ok = wave_check<TP, B, false, NW>(R, S, wp, 1, 0, P.res_v, ws, c, kValChunks) == 1;
                     if (c == 0) my_edges += 1;
-                    if (!ok && lane == 0) {
+                    if (!ok && tid == 0) {
                         ctl[kValBad] = 1;
                         if (k + 1 < la) P.ba[P.path_idx[k + 1]] = 1;
                         else if (k + 1 == la) { if (s_is_a) P.ba[xa] = 1; else P.bb[xb] = 1; }
@@ -571,27 +578,27 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             if (!group_barrier(P.bar, w, P.W)) break;
             if (!ctl[kValBad]) {
                 status = kStOk;
-                if (w == 0 && lane == 0) ctl[kConnWorker] = first;
+                if (w == 0 && tid == 0) ctl[kConnWorker] = first;
                 ++round;
                 break;
             }
-            if (w == 0 && lane == 0) ctl[kValFails] += 1;
+            if (w == 0 && tid == 0) ctl[kValFails] += 1;
         }
         if (ctl[kStop]) {
             ++round;
             break;
         }
     }
-    if (lane == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
-    if (lane == 0 && my_learned)
+    if (tid == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
+    if (tid == 0 && my_learned)
         atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kLearnedLo), (unsigned long long)my_learned);
     const bool aborted = __hip_atomic_load(P.bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     if (w == 0) {
         // hand the path to the query's own buffer (the group's is reused)
         const int len = ctl[kPathLen];
         if (!aborted && status == kStOk && P.out_path != P.path && len <= P.out_path_cap)
-            for (int e = lane; e < len * dof; e += kWave) P.out_path[e] = P.path[e];
-        if (lane == 0) {
+            for (int e = tid; e < len * dof; e += nth) P.out_path[e] = P.path[e];
+        if (tid == 0) {
             ctl[kRounds] = round;
             ctl[kStatus] = aborted ? kStInternal : status;
         }
@@ -612,21 +619,20 @@ __global__ void k_plan_init(int* bar, int n_groups, int bar_words, size_t bar_st
         reinterpret_cast<int*>(Pq)[t] = reinterpret_cast<const int*>(&one_query)[t];
 }
 
-// Persistent planner: n_groups groups of W one-wave workgroups; group g runs
-// queries g, g + n_groups, ... one after another.  All queries of a launch
-// share W.  A group that aborts leaves its remaining queries at "internal".
-template <int TP, int B>
-#ifndef PRRTC_PLAN_WAVES_PER_EU
-#define PRRTC_PLAN_WAVES_PER_EU 3
-#endif
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(PRRTC_PLAN_WAVES_PER_EU))) void k_plan(
+// Persistent planner: n_groups groups of W workgroups (NW waves each); group
+// g runs queries g, g + n_groups, ... one after another.  All queries of a
+// launch share W.  A group that aborts leaves its remaining queries at
+// "internal".
+// WPE: waves per SIMD the register allocation must allow.
+template <int TP, int B, int NW, int WPE>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE))) void k_plan(
     const PlanArgs* __restrict__ Pq, int n_queries, int n_groups) {
     extern __shared__ float4 lds4[];
     const int W = Pq[0].W;
     const int g = blockIdx.x / W;
     const int w = blockIdx.x - g * W;
     for (int k = g; k < n_queries; k += n_groups)
-        if (!plan_query<TP, B>(((CPlanArgs*)Pq)[k], w, lds4)) break;
+        if (!plan_query<TP, B, NW>(((CPlanArgs*)Pq)[k], w, lds4)) break;
 }
 
 }  // namespace prrtc
