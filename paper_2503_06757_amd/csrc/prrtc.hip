@@ -1065,7 +1065,14 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     if (stats) fill_stats(ctl, ms, stats);
     const int status = ctl[kStatus];
-    if (status == kStInternal) return fail(ctx, PRRTC_E_HIP, "planner aborted on the device");
+    if (status == kStInternal) {
+        int code = 0;
+        (void)hipMemcpy(&code, A.bar + kAbort, sizeof code, hipMemcpyDeviceToHost);
+        return fail(ctx, PRRTC_E_HIP, "planner aborted on the device (%s)",
+                    code == 1 ? "a group barrier waited more than 2 s"
+                    : code == 2 ? "connect steps beyond the staging capacity"
+                    : code == 3 ? "a parent chain longer than its tree" : "unknown cause");
+    }
     if (status == kStInvalidEndpoint) return fail(ctx, PRRTC_E_INVALID_ENDPOINT, "start or goal in collision");
     if (status == kStNoSolution) return fail(ctx, PRRTC_E_NO_SOLUTION, "no connection within the round/time budget");
     const int len = ctl[kPathLen];

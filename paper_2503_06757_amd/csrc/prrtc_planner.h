@@ -151,7 +151,7 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
 // Group barrier without a shared counter: every workgroup w > 0 publishes its
 // arrival by storing the next generation number into its own flag word
 // (flags = bar + kBarWords, one int per worker) and then waits for the
-// generation word to advance; workgroup 0 polls all flags with its whole wave
+// generation word to advance; the first wave of workgroup 0 polls all flags
 // and advances the generation once every flag shows it.  Release stores and
 // acquire loads at agent scope carry each workgroup's earlier writes through
 // workgroup 0 to everyone.  Flags and generation only grow, so nothing is
@@ -166,7 +166,9 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks) {
     unsigned* gen = reinterpret_cast<unsigned*>(bar + kBarGen);
     unsigned* flags = reinterpret_cast<unsigned*>(bar + kBarWords);
     int ok = 1;
-    if (w == 0) {
+    if (w == 0 && threadIdx.x < kWave) {
+        // only wave 0 of workgroup 0 polls and releases: a second wave that
+        // read the generation after the release would wait for the next one
         const int lane = threadIdx.x & (kWave - 1);
         const unsigned g = __shfl(lane == 0 ? __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0u,
                                   0, kWave);

@@ -200,3 +200,28 @@ def test_plan_time_budget(gpu, orc, r7):
     assert st in (0, P.PRRTC_E_NO_SOLUTION)
     if st == P.PRRTC_E_NO_SOLUTION:
         assert stats["rounds"] < 100000 and stats["gpu_ms"] < 2000
+
+
+@pytest.mark.parametrize("tile", [64, 16])
+def test_plan_r14_shelf_queries(gpu, orc, r14, tile):
+    """Stored dual-arm shelf queries under a short budget: every call ends in
+    a solution or E_NO_SOLUTION (never a device abort, e.g. a group barrier
+    that waited for a generation already released), and every solution is
+    oracle-valid at 4x.  The four-wave workers (tile 64) meet at the same
+    barriers as the one-wave workers (tile 16)."""
+    import os
+    P, ctx, _ = gpu
+    say("R14 shelf queries, tile", tile)
+    prims = W.scene_shelf(r14)
+    rid, sid = P.prrtc_load_robot(ctx, r14), P.prrtc_load_scene(ctx, prims)
+    Q = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "shelf_queries_r14.txt"), dtype=np.float32)
+    solved = 0
+    for k in range(20):
+        s, g = Q[k, :14], Q[k, 14:]
+        st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, seed=W.SEED_QUERY + k, max_rounds=4000,
+                                                                   time_budget_ms=60.0, tile=tile))
+        assert st in (0, P.PRRTC_E_NO_SOLUTION), (k, st)
+        if st == 0:
+            solved += 1
+            path_ok(orc, r14, prims, path, s, g)
+    say("  solved", solved, "of 20")
