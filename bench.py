@@ -271,7 +271,7 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
             "time_budget_ms": budget_ms}
 
 
-def bench_throughput(P, ctx, torch, pool, n_queries=2048, workers=(16, 32, 64, 128, 256), max_rounds=4000,
+def bench_throughput(P, ctx, torch, pool, n_queries=1024, workers=(16, 64, 256), max_rounds=4000,
                      budget_ms=100.0, log=None):
     """Queries/s of one prrtc_plan_batch launch over the served pool for each
     worker count (the planner's launch-shape tuning)."""
@@ -279,15 +279,15 @@ def bench_throughput(P, ctx, torch, pool, n_queries=2048, workers=(16, 32, 64, 1
     rows = []
     for wk in workers:
         prm = P.prrtc_plan_params_default()
-        prm.workers, prm.max_rounds, prm.time_budget_ms = wk, max_rounds, budget_ms
+        prm.workers, prm.max_rounds, prm.time_budget_ms, prm.tile = wk, max_rounds, budget_ms, 16
         qs = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
                7 + k, 0) for k in range(n_queries)]
         t0 = time.perf_counter()
         used, out = P.prrtc_plan_batch(ctx, qs, prm, groups=0, path_cap=128)
         dt = time.perf_counter() - t0
         ok = np.mean([o[0] == P.PRRTC_OK for o in out])
-        rows.append({"workers": wk, "groups": used, "queries_per_s": n_queries / dt, "success": float(ok),
-                     "time_budget_ms": budget_ms})
+        rows.append({"workers": wk, "tile": 16, "groups": used, "queries_per_s": n_queries / dt,
+                     "success": float(ok), "time_budget_ms": budget_ms})
         if log:
             log("  workers %d: %s" % (wk, rows[-1]))
     return rows
@@ -358,6 +358,51 @@ def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
             "plain": cmp["plain"], "learned": cmp["learned"]}
 
 
+def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=200.0):
+    """The learned proposal on the dual arm: training queries made with the
+    library's FK and checks, paths from the uniform planner (one batched
+    launch), a 14-DoF model trained on them, then uniform against learned
+    sampling on the stored shelf queries (same seeds, rounds and budget)."""
+    from paper_2503_06757_amd import proposal as PR
+    robot = W.robot_r14()
+    rid = P.prrtc_load_robot(ctx, robot)
+    sid = P.prrtc_load_scene(ctx, W.scene_shelf(robot))
+    vox = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    P.prrtc_voxelize(ctx, sid, vox.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    vox_row = vox.cpu().numpy()
+    t0 = time.perf_counter()
+    starts, goals = PR.shelf_queries(P, ctx, torch, rid, sid, robot, n_train, seed=0x57000000, max_batches=4000,
+                                     log=log)
+    ds = PR.shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row)
+    gen_s = time.perf_counter() - t0
+    log("  shelf training data: %d of %d queries solved, %d samples, %.1f s" % (ds.vox.shape[0], n_train,
+                                                                                 len(ds.scene_of), gen_s))
+    mid = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(14, 2), 14))
+    losses = PR.train(P, ctx, torch, mid, rid, ds, epochs, log=log)
+    Q = np.loadtxt(SHELF_QUERIES, dtype=np.float32)[:n_eval]
+    res = {}
+    for name, sampler in (("plain", 0), ("learned", 1)):
+        rows = []
+        for k, row in enumerate(Q):
+            prm = P.prrtc_plan_params_default()
+            prm.seed, prm.max_rounds, prm.time_budget_ms = W.SEED_QUERY + k, 4000, budget_ms
+            prm.sampler, prm.model_id, prm.mix = sampler, mid, 0.5
+            t1 = time.perf_counter()
+            st, _, stats = P.prrtc_plan(ctx, rid, sid, row[:14], row[14:], prm)
+            rows.append((st == P.PRRTC_OK, (time.perf_counter() - t1) * 1e3, stats["rounds"]))
+        a = np.array(rows, np.float64)
+        t = np.where(a[:, 0] > 0, a[:, 1], np.inf)
+        res[name] = {"queries": len(a), "success": float(a[:, 0].mean()), "p50_ms": float(np.percentile(t, 50)),
+                     "p50_solved_ms": float(np.median(a[a[:, 0] > 0, 1])) if a[:, 0].any() else None,
+                     "mean_rounds_solved": float(a[a[:, 0] > 0, 2].mean()) if a[:, 0].any() else None}
+        log("  shelf %s: %s" % (name, res[name]))
+    return {"workload": "learned_r14_shelf", "train_queries": n_train, "solved_train_queries": int(ds.vox.shape[0]),
+            "samples": int(len(ds.scene_of)), "epochs": epochs, "datagen_s": gen_s,
+            "loss_first_epoch": float(losses[0]) if len(losses) else None,
+            "loss_last_epoch": float(losses[-1]) if len(losses) else None,
+            "time_budget_ms": budget_ms, "plain": res["plain"], "learned": res["learned"]}
+
+
 def cpu_baseline(ce, budget_s=12.0):
     """The oracle (serial C, FP64, boolean mode with early exit) on one host
     core over a growing prefix of the same batch until the budget is spent."""
@@ -397,12 +442,15 @@ def main():
     ap.add_argument("--skip-plan", action="store_true", help="omit the planner ms-to-solution run")
     ap.add_argument("--skip-learned", action="store_true", help="omit the learned-proposal leg")
     ap.add_argument("--skip-shelf", action="store_true", help="omit the 14-DoF shelf leg")
-    ap.add_argument("--shelf-queries", type=int, default=500)
-    ap.add_argument("--learned-scenes", type=int, default=2000, help="training scenes (10000 for the full set)")
-    ap.add_argument("--learned-eval", type=int, default=200, help="held-out scenes")
+    ap.add_argument("--learned-shelf", action="store_true", help="add the 14-DoF learned-proposal leg")
+    ap.add_argument("--learned-shelf-train", type=int, default=1500)
+    ap.add_argument("--learned-shelf-eval", type=int, default=100)
+    ap.add_argument("--shelf-queries", type=int, default=200, help="stored shelf queries planned (500 in all)")
+    ap.add_argument("--learned-scenes", type=int, default=1000, help="training scenes (10000 for the full set)")
+    ap.add_argument("--learned-eval", type=int, default=100, help="held-out scenes")
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--skip-serve", action="store_true", help="omit the batched / served planner legs")
-    ap.add_argument("--serve-queries", type=int, default=10000)
+    ap.add_argument("--serve-queries", type=int, default=4000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -444,6 +492,12 @@ def main():
         log("learned proposal")
         learned = bench_learned(P, ctx, torch, args.learned_scenes, args.learned_eval, args.learned_epochs, log)
         log("  " + json.dumps(finite_or_null(learned)))
+    learned_shelf = None
+    if args.learned_shelf:
+        log("learned proposal, dual-arm shelf")
+        learned_shelf = bench_learned_shelf(P, ctx, torch, args.learned_shelf_train, args.learned_shelf_eval,
+                                            args.learned_epochs, log)
+        log("  " + json.dumps(finite_or_null(learned_shelf)))
     ms_per_step = ce["wall_s"] * 1e3 / args.steps
     value = N_EDGES / (ce["wall_s"] / args.steps)
     achieved = ce["alg_flop"] / (ce["kernel_ms"] * 1e-3) / 1e12
@@ -474,6 +528,7 @@ def main():
         "batched": batch,
         "served": serve,
         "learned": learned,
+        "learned_r14_shelf": learned_shelf,
     }
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(ce)

@@ -328,3 +328,160 @@ def main(argv=None):
 
 if __name__ == "__main__":
     main()
+
+
+# ---- the dual-arm shelf: queries from the library's own FK and checks, training, comparison -----
+def _valid_configs(P, ctx, torch, rid, sid, q):
+    """uint8 [n]: each configuration collision-free (a zero-length edge)."""
+    qd = torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda()
+    ok = torch.zeros(qd.shape[0], dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, qd.data_ptr(), qd.data_ptr(), qd.shape[0], 32.0, ok.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    return ok.cpu().numpy().astype(bool)
+
+
+def _valid_edges(P, ctx, torch, rid, sid, a, b):
+    ad = torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    bd = torch.from_numpy(np.ascontiguousarray(b, np.float32)).cuda()
+    ok = torch.zeros(ad.shape[0], dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, ad.data_ptr(), bd.data_ptr(), ad.shape[0], 32.0, ok.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    return ok.cpu().numpy().astype(bool)
+
+
+def _fk(P, ctx, torch, rid, q, n_spheres):
+    """Sphere centres [n][n_spheres][3] (device tensor) from the library's FK."""
+    qd = torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda()
+    xyz = torch.zeros((qd.shape[0], n_spheres, 3), dtype=torch.float32, device="cuda")
+    P.prrtc_fk_spheres(ctx, rid, qd.data_ptr(), qd.shape[0], xyz.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return xyz
+
+
+def _front(P, ctx, torch, rid, q, n_spheres):
+    """Every sphere in front of the shelf (x < 0.4 m)?"""
+    return (_fk(P, ctx, torch, rid, q, n_spheres)[..., 0].amax(1) < 0.4).cpu().numpy()
+
+
+def _arm_goals(P, ctx, torch, rid, sid, robot, arm, rng, want, max_batches, parked):
+    """Goals of one arm, with the other arm parked at collision-free start
+    configurations (rows of `parked`): the hand-bar centre in a shelf cell on
+    the arm's side and the configuration collision-free; kept if also
+    collision-free together with 16 random 0.05 rad moves of the arm (room
+    around the hand) and with a straight retreat of 0.5-2 rad that reaches
+    the front of the shelf collision-free.  Uniform sampling finds few such
+    poses (about 1 in 2000), so accepted and in-cell poses also seed random
+    walks (steps of 0.15 rad in the arm's joints)."""
+    from . import workloads as W
+    lo, hi = robot["q_lo"].astype(np.float64), robot["q_hi"].astype(np.float64)
+    dof = lo.shape[0]
+    n_sph = robot["sphere_xyzr"].shape[0]
+    j0, j1 = 7 * arm, 7 * arm + 7
+    hand = np.arange(n_sph // 2)[W.HAND_SPHERES] + (n_sph // 2) * arm
+    cells = W.shelf_cells()
+    inset = W.SHELF_WALL / 2 + W.SHELF_MARGIN
+    c_lo = np.array([c[0] + inset for c in cells])
+    c_hi = np.array([c[1] - inset for c in cells])
+    side = np.array([(c[1][1] <= 1e-9) if arm == 0 else (c[0][1] >= -1e-9) for c in cells])
+    hand_t = torch.from_numpy(hand).cuda()
+
+    def in_cell_valid(q):
+        h = _fk(P, ctx, torch, rid, q, n_sph).index_select(1, hand_t).mean(1).cpu().numpy()
+        ok = np.any(np.all((h[:, None, :] >= c_lo[None]) & (h[:, None, :] <= c_hi[None]), axis=2) & side[None], axis=1)
+        idx = np.nonzero(ok)[0]
+        if len(idx):
+            idx = idx[_valid_configs(P, ctx, torch, rid, sid, q[idx])]
+        return q[idx]
+
+    def roomy(g):
+        d = np.zeros((16, dof))
+        d[:, j0:j1] = rng.standard_normal((16, 7))
+        d *= 0.05 / np.linalg.norm(d, axis=1, keepdims=True)
+        moves = np.clip(g[None] + d, lo, hi).astype(np.float32)
+        if not _valid_edges(P, ctx, torch, rid, sid, np.repeat(g[None], 16, 0), moves).all():
+            return False
+        d = np.zeros((32, dof))
+        d[:, j0:j1] = rng.standard_normal((32, 7))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        back = np.clip(g[None] + rng.uniform(0.5, 2.0, (32, 1)) * d, lo, hi).astype(np.float32)
+        fr = _front(P, ctx, torch, rid, back, n_sph)
+        return bool(fr.any() and _valid_edges(P, ctx, torch, rid, sid, np.repeat(g[None], int(fr.sum()), 0),
+                                              back[fr]).any())
+
+    seeds, out = [], []
+    for _ in range(max_batches):
+        if len(out) >= want:
+            break
+        if len(seeds) < 8:
+            q = parked[rng.integers(0, len(parked), 16384)].astype(np.float32)
+            q[:, j0:j1] = rng.uniform(lo[j0:j1], hi[j0:j1], (16384, 7))
+        else:
+            base = np.array(seeds, np.float32)[rng.integers(0, len(seeds), 4096)]
+            q = base.copy()
+            q[:, j0:j1] = np.clip(base[:, j0:j1] + rng.normal(0.0, 0.15, (4096, 7)), lo[j0:j1], hi[j0:j1])
+        found = in_cell_valid(q)
+        seeds.extend(list(found[:256]))
+        for g in found[:64]:
+            if roomy(g):
+                out.append(g[j0:j1].copy())
+                if len(out) >= want:
+                    break
+    return np.array(out[:want], np.float32).reshape(-1, 7)
+
+
+def shelf_queries(P, ctx, torch, rid, sid, robot, n, seed, max_batches=200, log=None):
+    """Dual-arm shelf queries built with the library's FK and collision checks
+    (training data; the stored benchmark queries come from the oracle): each
+    arm's goal as in _arm_goals, the two combined and checked together;
+    start uniform, collision-free, every sphere in front of the shelf.  At
+    most max_batches sampling rounds per arm, so fewer than n queries may
+    come back."""
+    rng = np.random.default_rng(seed)
+    lo, hi = robot["q_lo"].astype(np.float64), robot["q_hi"].astype(np.float64)
+    dof = lo.shape[0]
+    n_sph = robot["sphere_xyzr"].shape[0]
+    starts = []
+    for _ in range(max_batches):
+        if len(starts) >= n:
+            break
+        q = rng.uniform(lo, hi, (8192, dof)).astype(np.float32)
+        cand = q[_front(P, ctx, torch, rid, q, n_sph)]
+        if len(cand):
+            cand = cand[_valid_configs(P, ctx, torch, rid, sid, cand)]
+        starts.extend(list(cand[:n - len(starts)]))
+    starts = np.array(starts, np.float32).reshape(-1, dof)
+    if not len(starts):
+        return starts, starts
+    ga = _arm_goals(P, ctx, torch, rid, sid, robot, 0, rng, n, max_batches, starts)
+    gb = _arm_goals(P, ctx, torch, rid, sid, robot, 1, rng, n, max_batches, starts)
+    m = min(len(ga), len(gb))
+    goals = np.concatenate([ga[:m], gb[:m]], axis=1).astype(np.float32)
+    if m:
+        goals = goals[_valid_configs(P, ctx, torch, rid, sid, goals)]
+    if log:
+        log("  shelf goals: arm 0 %d, arm 1 %d, together %d" % (len(ga), len(gb), len(goals)))
+    k = min(len(starts), len(goals))
+    return np.array(starts[:k], np.float32).reshape(-1, dof), goals[:k]
+
+
+def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, budget_ms=300.0, seed=0x57000000):
+    """Solve the queries with the uniform planner in one batched launch and
+    keep the paths' waypoints every 0.25 rad; one voxel row per query (the
+    scene is shared)."""
+    prm = P.prrtc_plan_params_default()
+    prm.workers, prm.tile, prm.max_rounds, prm.time_budget_ms = workers, 16, 8000, budget_ms
+    qs = [(rid, sid, s, g, seed + k, 0) for k, (s, g) in enumerate(zip(starts, goals))]
+    _, out = P.prrtc_plan_batch(ctx, qs, prm, path_cap=512)
+    ds = Dataset(starts.shape[1])
+    for (st, path, _), s, g in zip(out, starts, goals):
+        if st != P.PRRTC_OK:
+            continue
+        k = len(ds.vox)
+        ds.vox.append(vox_row)
+        ds.queries.append((s, g))
+        ds.paths.append(path)
+        for w in resample_path(path):
+            ds.scene_of.append(k)
+            ds.start.append(s)
+            ds.goal.append(g)
+            ds.waypoint.append(w)
+    return ds.finish()

@@ -301,3 +301,25 @@ def test_plan_learned_bad_arguments(gpu, r7):
             setattr(p, k, v)
         with pytest.raises(P.PrrtcError):
             P.prrtc_plan(ctx, rid, sid, s, s, p)
+
+
+def test_shelf_query_generator(gpu, orc, r14):
+    """Training queries made with the library's FK and checks satisfy what
+    they promise, as the oracle sees it."""
+    P, ctx, torch = gpu
+    say("GPU shelf query generator")
+    prims = W.scene_shelf(r14)
+    rid, sid = P.prrtc_load_robot(ctx, r14), P.prrtc_load_scene(ctx, prims)
+    starts, goals = PR.shelf_queries(P, ctx, torch, rid, sid, r14, 3, seed=0x57000123, max_batches=40)
+    assert len(goals) >= 1
+    rob = orc.OracleRobot(r14)
+    cells = W.shelf_cells()
+    for s, g in zip(starts, goals):
+        assert orc.config_clearance(rob, prims, s.astype(np.float64)) >= -orc.FLAG_BAND
+        assert np.all(orc.fk_spheres(rob, s)[:, 0] < 0.4 + 1e-5)
+        assert orc.config_clearance(rob, prims, g.astype(np.float64)) >= -orc.FLAG_BAND
+        xyz = orc.fk_spheres(rob, g)
+        for arm in (0, 1):
+            c = W.hand_cell(xyz[60 * arm:60 * (arm + 1)][W.HAND_SPHERES], margin=W.SHELF_MARGIN - 1e-4)
+            assert c >= 0
+            assert (cells[c][1][1] <= 1e-9) if arm == 0 else (cells[c][0][1] >= -1e-9)
