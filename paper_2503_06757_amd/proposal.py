@@ -392,20 +392,22 @@ def _arm_goals(P, ctx, torch, rid, sid, robot, arm, rng, want, max_batches, park
             idx = idx[_valid_configs(P, ctx, torch, rid, sid, q[idx])]
         return q[idx]
 
-    def roomy(g):
-        d = np.zeros((16, dof))
-        d[:, j0:j1] = rng.standard_normal((16, 7))
-        d *= 0.05 / np.linalg.norm(d, axis=1, keepdims=True)
-        moves = np.clip(g[None] + d, lo, hi).astype(np.float32)
-        if not _valid_edges(P, ctx, torch, rid, sid, np.repeat(g[None], 16, 0), moves).all():
-            return False
-        d = np.zeros((32, dof))
-        d[:, j0:j1] = rng.standard_normal((32, 7))
-        d /= np.linalg.norm(d, axis=1, keepdims=True)
-        back = np.clip(g[None] + rng.uniform(0.5, 2.0, (32, 1)) * d, lo, hi).astype(np.float32)
+    def roomy(gs):
+        """Which of the candidate goals gs [m][dof] have room and a retreat
+        (three batched library calls for all of them)."""
+        m = len(gs)
+        d = np.zeros((m, 16, dof))
+        d[:, :, j0:j1] = rng.standard_normal((m, 16, 7))
+        d *= 0.05 / np.linalg.norm(d, axis=2, keepdims=True)
+        moves = np.clip(gs[:, None] + d, lo, hi).astype(np.float32).reshape(-1, dof)
+        ok = _valid_edges(P, ctx, torch, rid, sid, np.repeat(gs, 16, 0), moves).reshape(m, 16).all(1)
+        d = np.zeros((m, 32, dof))
+        d[:, :, j0:j1] = rng.standard_normal((m, 32, 7))
+        d /= np.linalg.norm(d, axis=2, keepdims=True)
+        back = np.clip(gs[:, None] + rng.uniform(0.5, 2.0, (m, 32, 1)) * d, lo, hi).astype(np.float32).reshape(-1, dof)
         fr = _front(P, ctx, torch, rid, back, n_sph)
-        return bool(fr.any() and _valid_edges(P, ctx, torch, rid, sid, np.repeat(g[None], int(fr.sum()), 0),
-                                              back[fr]).any())
+        esc = fr & _valid_edges(P, ctx, torch, rid, sid, np.repeat(gs, 32, 0), back)
+        return ok & esc.reshape(m, 32).any(1)
 
     seeds, out = [], []
     for _ in range(max_batches):
@@ -420,11 +422,9 @@ def _arm_goals(P, ctx, torch, rid, sid, robot, arm, rng, want, max_batches, park
             q[:, j0:j1] = np.clip(base[:, j0:j1] + rng.normal(0.0, 0.15, (4096, 7)), lo[j0:j1], hi[j0:j1])
         found = in_cell_valid(q)
         seeds.extend(list(found[:256]))
-        for g in found[:64]:
-            if roomy(g):
-                out.append(g[j0:j1].copy())
-                if len(out) >= want:
-                    break
+        if len(found):
+            keep = found[:256][roomy(found[:256])]
+            out.extend(list(keep[:, j0:j1]))
     return np.array(out[:want], np.float32).reshape(-1, 7)
 
 
@@ -452,6 +452,8 @@ def shelf_queries(P, ctx, torch, rid, sid, robot, n, seed, max_batches=200, log=
     if not len(starts):
         return starts, starts
     ga = _arm_goals(P, ctx, torch, rid, sid, robot, 0, rng, n, max_batches, starts)
+    if log:
+        log("  shelf goals, arm 0: %d" % len(ga))
     gb = _arm_goals(P, ctx, torch, rid, sid, robot, 1, rng, n, max_batches, starts)
     m = min(len(ga), len(gb))
     goals = np.concatenate([ga[:m], gb[:m]], axis=1).astype(np.float32)
