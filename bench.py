@@ -139,7 +139,7 @@ def bench_plan(P, ctx, n_instances=100, n_seeds=50):
     robot = W.robot_r7()
     rid = P.prrtc_load_robot(ctx, robot)
     prm = P.prrtc_plan_params_default()
-    prm.max_rounds = 2000
+    prm.max_rounds, prm.time_budget_ms = 1 << 30, 1000.0
     times, rounds, costs, fails = [], [], [], 0
     jobs = [(k, k) for k in range(n_instances)] + [(0, 1000 + s) for s in range(n_seeds)]
     scene_ids, queries = {}, {}
@@ -176,7 +176,8 @@ def bench_plan(P, ctx, n_instances=100, n_seeds=50):
     return {"workload": "plan_r7_s12", "queries": len(jobs), "success": float(np.mean(np.isfinite(t))),
             "p50_ms": pct(50), "p95_ms": pct(95), "p99_ms": pct(99),
             "max_solved_ms": float(ok.max()) if ok.size else None, "mean_rounds": float(np.mean(rounds)) if rounds else None,
-            "mean_cost": float(np.mean(costs)) if costs else None, "workers": prm.workers}
+            "mean_cost": float(np.mean(costs)) if costs else None, "workers": prm.workers,
+            "time_budget_ms": prm.time_budget_ms}
 
 
 def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, budget_ms=100.0):
@@ -296,7 +297,21 @@ def bench_throughput(P, ctx, torch, pool, n_queries=1024, workers=(16, 64, 256),
 SHELF_QUERIES = os.path.join(ROOT, "tests", "golden", "shelf_queries_r14.txt")
 
 
-def bench_shelf(P, ctx, n_queries=500, max_rounds=4000, budget_ms=200.0, workers=256):
+SHELF_BUDGET_MS = 1000.0     # per query, fixed beforehand for both samplers
+SHELF_MAX_ROUNDS = 1 << 30   # the time budget ends a query, not a round count
+
+
+def pcts(t):
+    """p50 / p90 / p99 of per-query times with failures as +inf (a percentile
+    that a failure reaches is reported as null)."""
+    out = {}
+    for q in (50, 90, 99):
+        v = float(np.percentile(t, q)) if len(t) else float("inf")
+        out["p%d_ms" % q] = v if np.isfinite(v) else None
+    return out
+
+
+def bench_shelf(P, ctx, n_queries=500, max_rounds=SHELF_MAX_ROUNDS, budget_ms=SHELF_BUDGET_MS, workers=256):
     """ms-to-solution of the dual arm (14-DoF, 3600 inter-arm pairs) reaching
     into the 5x3 shelf with 24 random spheres: the stored generated queries
     (start in front of the shelf, each hand in a cell on its side)."""
@@ -316,8 +331,7 @@ def bench_shelf(P, ctx, n_queries=500, max_rounds=4000, budget_ms=200.0, workers
     a = np.array(rows, np.float64)
     ok = a[:, 0] > 0
     t = np.where(ok, a[:, 1], np.inf)
-    return {"workload": "plan_r14_shelf", "queries": len(a), "success": float(ok.mean()),
-            "p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)),
+    return {"workload": "plan_r14_shelf", "queries": len(a), "success": float(ok.mean()), **pcts(t),
             "mean_rounds": float(a[ok, 2].mean()) if ok.any() else None,
             "edge_checks_per_s": float(a[:, 3].sum() / (a[:, 4].sum() * 1e-3)),
             "max_rounds": max_rounds, "time_budget_ms": budget_ms, "workers": workers}
@@ -355,10 +369,12 @@ def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
             "train_tflops": flop / train_s / 1e12, "bf16_peak_tflops": 2500.0,
             "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
             "heldout_nll_init": nll0, "heldout_nll": nll, "eval_scenes": n_eval,
+            "free_queries": cmp["free_queries"], "solvable_queries": cmp["solvable_queries"],
+            "time_budget_ms": cmp["time_budget_ms"], "screen_ms": cmp["screen_ms"],
             "plain": cmp["plain"], "learned": cmp["learned"]}
 
 
-def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=200.0):
+def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=SHELF_BUDGET_MS):
     """The learned proposal on the dual arm: training queries made with the
     library's FK and checks, paths from the uniform planner (one batched
     launch), a 14-DoF model trained on them, then uniform against learned
@@ -385,15 +401,14 @@ def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=2
         rows = []
         for k, row in enumerate(Q):
             prm = P.prrtc_plan_params_default()
-            prm.seed, prm.max_rounds, prm.time_budget_ms = W.SEED_QUERY + k, 4000, budget_ms
+            prm.seed, prm.max_rounds, prm.time_budget_ms = W.SEED_QUERY + k, SHELF_MAX_ROUNDS, budget_ms
             prm.sampler, prm.model_id, prm.mix = sampler, mid, 0.5
             t1 = time.perf_counter()
             st, _, stats = P.prrtc_plan(ctx, rid, sid, row[:14], row[14:], prm)
             rows.append((st == P.PRRTC_OK, (time.perf_counter() - t1) * 1e3, stats["rounds"]))
         a = np.array(rows, np.float64)
         t = np.where(a[:, 0] > 0, a[:, 1], np.inf)
-        res[name] = {"queries": len(a), "success": float(a[:, 0].mean()), "p50_ms": float(np.percentile(t, 50)),
-                     "p50_solved_ms": float(np.median(a[a[:, 0] > 0, 1])) if a[:, 0].any() else None,
+        res[name] = {"queries": len(a), "success": float(a[:, 0].mean()), **pcts(t),
                      "mean_rounds_solved": float(a[a[:, 0] > 0, 2].mean()) if a[:, 0].any() else None}
         log("  shelf %s: %s" % (name, res[name]))
     return {"workload": "learned_r14_shelf", "train_queries": n_train, "solved_train_queries": int(ds.vox.shape[0]),
@@ -442,12 +457,12 @@ def main():
     ap.add_argument("--skip-plan", action="store_true", help="omit the planner ms-to-solution run")
     ap.add_argument("--skip-learned", action="store_true", help="omit the learned-proposal leg")
     ap.add_argument("--skip-shelf", action="store_true", help="omit the 14-DoF shelf leg")
-    ap.add_argument("--learned-shelf", action="store_true", help="add the 14-DoF learned-proposal leg")
+    ap.add_argument("--skip-learned-shelf", action="store_true", help="omit the 14-DoF learned-proposal leg")
     ap.add_argument("--learned-shelf-train", type=int, default=1500)
-    ap.add_argument("--learned-shelf-eval", type=int, default=100)
-    ap.add_argument("--shelf-queries", type=int, default=200, help="stored shelf queries planned (500 in all)")
+    ap.add_argument("--learned-shelf-eval", type=int, default=500)
+    ap.add_argument("--shelf-queries", type=int, default=500, help="stored shelf queries planned (500 in all)")
     ap.add_argument("--learned-scenes", type=int, default=1000, help="training scenes (10000 for the full set)")
-    ap.add_argument("--learned-eval", type=int, default=100, help="held-out scenes")
+    ap.add_argument("--learned-eval", type=int, default=300, help="held-out scenes")
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--skip-serve", action="store_true", help="omit the batched / served planner legs")
     ap.add_argument("--serve-queries", type=int, default=4000)
@@ -493,7 +508,7 @@ def main():
         learned = bench_learned(P, ctx, torch, args.learned_scenes, args.learned_eval, args.learned_epochs, log)
         log("  " + json.dumps(finite_or_null(learned)))
     learned_shelf = None
-    if args.learned_shelf:
+    if not args.skip_learned_shelf:
         log("learned proposal, dual-arm shelf")
         learned_shelf = bench_learned_shelf(P, ctx, torch, args.learned_shelf_train, args.learned_shelf_eval,
                                             args.learned_epochs, log)

@@ -249,34 +249,67 @@ def mean_nll(P, ctx, torch, mid: int, rid: int, ds: Dataset, lo, hi) -> float:
     return float(-(m[:, 0] + np.log(np.exp(a - m).sum(1))).mean())
 
 
+SCREEN_SEED = 0x0A000000    # added to a query's seed for its screening runs
+
+
 def compare(P, ctx, torch, mid: int, rid: int, robot: dict, n_scenes: int, base: int = SEED_EVAL,
-            mix: float = 0.5, max_rounds: int = 2000, budget_ms: float = 100.0, log=None) -> dict:
+            mix: float = 0.5, max_rounds: int = 1 << 30, budget_ms: float = 1000.0,
+            screen_ms: float = 1000.0, log=None) -> dict:
     """Uniform against learned sampling on held-out scenes, one query each,
     same seed, round limit and time budget: wall time of the prrtc_plan call
-    and success."""
-    res = {"plain": [], "learned": []}
+    and success.
+
+    Many generated queries have no solution at all (start and goal in
+    different free regions of a crowded scene).  A screening pass first plans
+    every query with both samplers under other seeds (one batched launch per
+    sampler, screen_ms each); queries that neither solves are dropped, so the
+    comparison runs on queries known to be solvable, chosen without favouring
+    either sampler."""
+    sids, queries = [], []
     for i in range(n_scenes):
         sid = P.prrtc_load_scene(ctx, scene(robot, i, base))
         q = free_query(P, ctx, torch, rid, sid, robot, base + i)
-        if q is not None:
-            for name, sampler in (("plain", 0), ("learned", 1)):
-                p = P.prrtc_plan_params_default()
-                p.seed, p.max_rounds, p.sampler, p.model_id, p.mix = base + i, max_rounds, sampler, mid, mix
-                p.time_budget_ms = budget_ms
-                t0 = time.perf_counter()
-                st, _, stats = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
-                ms = (time.perf_counter() - t0) * 1e3
-                res[name].append((st == P.PRRTC_OK, ms, stats["rounds"], stats["gpu_ms"]))
+        if q is None:
+            P.prrtc_unload_scene(ctx, sid)
+            continue
+        sids.append(sid)
+        queries.append((i, q))
+    solvable = np.zeros(len(queries), bool)
+    for sampler in (0, 1):
+        p = P.prrtc_plan_params_default()
+        p.workers, p.tile, p.max_rounds, p.time_budget_ms = 64, 16, max_rounds, screen_ms
+        p.sampler, p.model_id, p.mix = sampler, mid, mix
+        batch = [(rid, sid, q[0], q[1], SCREEN_SEED + base + i, i) for sid, (i, q) in zip(sids, queries)]
+        if batch:
+            _, res = P.prrtc_plan_batch(ctx, batch, p)
+            solvable |= np.array([r[0] == P.PRRTC_OK for r in res])
+    if log:
+        log("  screening: %d of %d free queries solvable" % (int(solvable.sum()), len(queries)))
+    res = {"plain": [], "learned": []}
+    for k, (sid, (i, q)) in enumerate(zip(sids, queries)):
+        if not solvable[k]:
+            continue
+        for name, sampler in (("plain", 0), ("learned", 1)):
+            p = P.prrtc_plan_params_default()
+            p.seed, p.max_rounds, p.sampler, p.model_id, p.mix = base + i, max_rounds, sampler, mid, mix
+            p.time_budget_ms = budget_ms
+            t0 = time.perf_counter()
+            st, _, stats = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
+            ms = (time.perf_counter() - t0) * 1e3
+            res[name].append((st == P.PRRTC_OK, ms, stats["rounds"], stats["gpu_ms"]))
+    for sid in sids:
         P.prrtc_unload_scene(ctx, sid)
-        if log and (i + 1) % 50 == 0:
-            log("  compared %d/%d scenes" % (i + 1, n_scenes))
-    out = {}
+    out = {"free_queries": len(queries), "solvable_queries": int(solvable.sum()), "time_budget_ms": budget_ms,
+           "screen_ms": screen_ms}
     for name, rows in res.items():
         a = np.array(rows, np.float64).reshape(-1, 4)
         ok = a[:, 0] > 0
-        out[name] = dict(queries=int(len(a)), success=float(ok.mean()) if len(a) else 0.0,
-                         p50_ms=float(np.median(a[ok, 1])) if ok.any() else None,
-                         p99_ms=float(np.percentile(a[ok, 1], 99)) if ok.any() else None,
+        t = np.where(ok, a[:, 1], np.inf)
+        pct = {}
+        for qq in (50, 90, 99):
+            v = float(np.percentile(t, qq)) if len(t) else float("inf")
+            pct["p%d_ms" % qq] = v if np.isfinite(v) else None
+        out[name] = dict(queries=int(len(a)), success=float(ok.mean()) if len(a) else 0.0, **pct,
                          p50_rounds=float(np.median(a[ok, 2])) if ok.any() else None,
                          p50_gpu_ms=float(np.median(a[ok, 3])) if ok.any() else None)
         if log:

@@ -267,6 +267,10 @@ def scene_shelf(robot: dict, n_random_spheres: int = 24, seed: int = SEED_SHELF_
 
     20 horizontal boards (4 levels x 5 columns), 18 vertical dividers
     (6 x 3 rows), one back panel and one pedestal.  The opening faces -x.
+    The random spheres (r ~ U[0.05, 0.15]) lie in the upper half of the scene
+    cube, clear of the shelf, of the arm bases and of the approach slab
+    between the bases and the shelf front (0 <= x <= 0.45 m): clutter around
+    and behind the robot, not a wall across every route into the cells.
     """
     ident = np.eye(3)
     t = SHELF_WALL / 2.0
@@ -297,6 +301,10 @@ def scene_shelf(robot: dict, n_random_spheres: int = 24, seed: int = SEED_SHELF_
     return prims
 
 
+APPROACH_LO = np.array([0.0, -SCENE_HALF, 0.0])            # region kept free of random spheres
+APPROACH_HI = np.array([SHELF_FRONT_X, SCENE_HALF, SHELF_Z0 + 0.9])
+
+
 def _random_spheres_outside_shelf(seed, robot, n):
     rng = np.random.default_rng(seed)
     fixed = _fixed_sphere_world(robot)
@@ -315,6 +323,10 @@ def _random_spheres_outside_shelf(seed, robot, n):
             continue
         # keep the shelf cells themselves clear so goals inside them stay reachable
         if np.all(c > shelf_lo - r) and np.all(c < shelf_hi + r):
+            continue
+        # and the approach to the opening: the slab between the arm bases and
+        # the shelf front, across the shelf's width and height
+        if np.all(c > APPROACH_LO - r) and np.all(c < APPROACH_HI + r):
             continue
         entries.append((PRIM_SPHERE, c, np.eye(3), (r, 0.0, 0.0)))
     return make_prims(entries)
