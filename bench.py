@@ -463,7 +463,7 @@ def main():
     ap.add_argument("--shelf-queries", type=int, default=500, help="stored shelf queries planned (500 in all)")
     ap.add_argument("--learned-scenes", type=int, default=1000, help="training scenes (10000 for the full set)")
     ap.add_argument("--learned-eval", type=int, default=300, help="held-out scenes")
-    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--learned-epochs", type=int, default=16)
     ap.add_argument("--skip-serve", action="store_true", help="omit the batched / served planner legs")
     ap.add_argument("--serve-queries", type=int, default=4000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -498,12 +498,12 @@ def shelf_queries(P, ctx, torch, rid, sid, robot, n, seed, max_batches=200, log=
     return np.array(starts[:k], np.float32).reshape(-1, dof), goals[:k]
 
 
-def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, budget_ms=300.0, seed=0x57000000):
+def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, budget_ms=1000.0, seed=0x57000000):
     """Solve the queries with the uniform planner in one batched launch and
     keep the paths' waypoints every 0.25 rad; one voxel row per query (the
     scene is shared)."""
     prm = P.prrtc_plan_params_default()
-    prm.workers, prm.tile, prm.max_rounds, prm.time_budget_ms = workers, 16, 8000, budget_ms
+    prm.workers, prm.tile, prm.max_rounds, prm.time_budget_ms = workers, 16, 1 << 30, budget_ms
     qs = [(rid, sid, s, g, seed + k, 0) for k, (s, g) in enumerate(zip(starts, goals))]
     _, out = P.prrtc_plan_batch(ctx, qs, prm, path_cap=512)
     ds = Dataset(starts.shape[1])
