@@ -1047,7 +1047,7 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     }
     const int bar_words = kBarWords + W;
     hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((std::max(bar_words, 256) + 255) / 256)), dim3(256), 0, sm, A.bar,
-                       1, bar_words, (size_t)0, A.ctl, 1, A, Pq);
+                       1, bar_words, (size_t)0, A.ctl, 1, A, Pq, (int*)nullptr);
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = 1, n_g = 1;
     void* kargs[] = {&Pq, &n_q, &n_g};
@@ -1154,7 +1154,8 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     // device memory: groups | query words | arguments | paths | proposal staging
     const int Cw = kComp * (1 + 2 * kMaxDof);
     const size_t o_ctl = (size_t)G * L.bytes;
-    const size_t o_args = align_up<int>(o_ctl + sizeof(int) * kCtlWords * (size_t)n_live);
+    const size_t o_next = align_up<int>(o_ctl + sizeof(int) * kCtlWords * (size_t)n_live);
+    const size_t o_args = align_up<int>(o_next + sizeof(int));
     const size_t o_path = align_up<int>(o_args + sizeof(PlanArgs) * (size_t)n_live);
     const size_t o_vox = align_up<int>(o_path + sizeof(float) * (size_t)path_cap * kMaxDof * n_live);
     const size_t o_qin = align_up<int>(o_vox + (p.sampler == 1 ? (size_t)kVoxCells * n_live : 0));
@@ -1198,7 +1199,9 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
         PlanArgs& A = args[i];
         query_args(ctx, A, p, r, ctx->scenes[q.scene_id], q.start, q.goal, q.seed, q.query,
                    stage_cap_for(r.args, p.delta));
-        group_args(A, m + (size_t)(i % G) * L.bytes, L, W, cap);
+        group_args(A, m, L, W, cap);   // group 0; the group that takes the query adds its offset
+        A.group_bytes = L.bytes;
+        A.next = reinterpret_cast<int*>(m + o_next);
         A.ctl = reinterpret_cast<int*>(m + o_ctl) + (size_t)kCtlWords * i;
         A.out_path = reinterpret_cast<float*>(m + o_path) + (size_t)path_cap * kMaxDof * i;
         A.out_path_cap = path_cap;
@@ -1210,7 +1213,8 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     const int bar_words = kBarWords + W;
     const int init_threads = std::max(bar_words * G, kCtlWords * n_live);
     hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((init_threads + 255) / 256)), dim3(256), 0, sm, args[0].bar, G,
-                       bar_words, L.bytes / sizeof(int), args[0].ctl, n_live, args[0], (PlanArgs*)nullptr);
+                       bar_words, L.bytes / sizeof(int), args[0].ctl, n_live, args[0], (PlanArgs*)nullptr,
+                       args[0].next);
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = n_live, n_g = G;
     void* kargs[] = {&Pq, &n_q, &n_g};

@@ -30,8 +30,8 @@ namespace prrtc {
 
 // Barrier words (int32) of one worker group in device memory, zeroed before
 // each launch: arrival counter, generation and the group's sticky abort word
-// on separate cache lines.
-enum Bar { kBarCount = 0, kBarGen = 32, kAbort = 64, kBarWords = 96 };
+// on separate cache lines; kNext holds the query the group takes next.
+enum Bar { kBarCount = 0, kBarGen = 32, kAbort = 64, kNext = 72, kBarWords = 96 };
 
 // Control and result words (int32) of one query, set up before each launch
 // (status = internal error, everything else 0).
@@ -64,7 +64,8 @@ constexpr int kValChunks = 4;
 constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInternal = -7;
 
 // One query of a launch.  Trees, staging, path and barrier words belong to
-// the worker group that runs the query; ctl and out_path to the query.
+// the worker group that runs the query (the pointers name group 0's memory;
+// group g adds g * group_bytes); ctl and out_path belong to the query.
 struct PlanArgs {
     const RobotArgs* R;       // device copies of the robot and scene tables
     const SceneArgs* S;
@@ -88,8 +89,10 @@ struct PlanArgs {
     float* path;              // [path_cap][dof]
     int* path_idx;            // [path_cap] tree node index; tree = (k < na ? A : B)
     int path_cap;
-    float* out_path;          // [out_path_cap][dof]: the query's path (may equal path)
+    float* out_path;          // [out_path_cap][dof]: the query's path
     int out_path_cap;
+    unsigned long long group_bytes;  // group g's memory = the pointers above + g * group_bytes
+    int* next;                // launch-wide count of queries handed out (several queries per group)
 };
 static_assert(sizeof(PlanArgs) % sizeof(int) == 0 && sizeof(PlanArgs) <= 256 * sizeof(int),
               "k_plan_init copies PlanArgs with one block of 256 threads");
@@ -159,7 +162,12 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
 #ifndef PRRTC_FLAG_BARRIER
 #define PRRTC_FLAG_BARRIER 1
 #endif
-__device__ inline bool group_barrier(int* bar, int w, int nblocks) {
+//
+// With `next`, the barrier also hands out work: once every worker has
+// arrived, workgroup 0 takes the next query index from the launch-wide
+// counter and stores it in bar[kNext] before the release, so every worker
+// reads the same index after the barrier.
+__device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = nullptr) {
 #if PRRTC_FLAG_BARRIER
     __shared__ int ok_s;
     __syncthreads();
@@ -189,7 +197,13 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks) {
             }
         }
         __atomic_thread_fence(__ATOMIC_ACQUIRE);   // the flags' release stores happen before what follows
-        if (ok && threadIdx.x == 0) __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (ok && threadIdx.x == 0) {
+            if (next)
+                __hip_atomic_store(bar + kNext,
+                                   __hip_atomic_fetch_add(next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     } else if (threadIdx.x == 0) {
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(flags + w, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -215,6 +229,9 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks) {
     return ok_s != 0;
 #else
     (void)w;
+    if (next && w == 0 && threadIdx.x == 0)   // before arriving: nobody reads it until the release
+        __hip_atomic_store(bar + kNext, __hip_atomic_fetch_add(next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return grid_barrier(bar, nblocks);
 #endif
 }
@@ -262,8 +279,49 @@ typedef __attribute__((address_space(4))) const PlanArgs CPlanArgs;
 // A worker is a workgroup of NW waves: wave 0 ("lead") does the worker's
 // scalar bookkeeping and writes its small LDS vectors; every wave computes the
 // same samples and nearest neighbours and shares the collision checks.
+// The group's own memory: the query's group-0 pointers moved by goff bytes.
+// Each pointer is formed where it is used (a scalar load and add), so the
+// seventeen of them do not all stay live in registers.
+template <class T>
+__device__ inline T* moved(T* p, unsigned long long goff) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + goff);
+}
+
+// The offset passes through an empty asm at every use, so the compiler does
+// not hoist all the moved pointers out of the round loop (they would crowd
+// out the scalar registers and spill).
+__device__ inline unsigned long long opaque(unsigned long long v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+struct GroupView {
+    CPlanArgs& P;
+    unsigned long long off_;
+    __device__ unsigned long long off() const { return opaque(off_); }
+    __device__ float* qa() const { return moved(P.qa, off()); }
+    __device__ int* pa() const { return moved(P.pa, off()); }
+    __device__ unsigned char* ba() const { return moved(P.ba, off()); }
+    __device__ float* ra() const { return moved(P.ra, off()); }
+    __device__ float* qb() const { return moved(P.qb, off()); }
+    __device__ int* pb() const { return moved(P.pb, off()); }
+    __device__ unsigned char* bb() const { return moved(P.bb, off()); }
+    __device__ float* rb() const { return moved(P.rb, off()); }
+    __device__ int* bar() const { return moved(P.bar, off()); }
+    __device__ float* stage() const { return moved(P.stage, off()); }
+    __device__ int* st_count() const { return moved(P.st_count, off()); }
+    __device__ int* st_nn() const { return moved(P.st_nn, off()); }
+    __device__ int* st_other() const { return moved(P.st_other, off()); }
+    __device__ int* st_conn() const { return moved(P.st_conn, off()); }
+    __device__ int* st_fail() const { return moved(P.st_fail, off()); }
+    __device__ float* path() const { return moved(P.path, off()); }
+    __device__ int* path_idx() const { return moved(P.path_idx, off()); }
+};
+
 template <int TP, int B, int NW>
-__device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, float4* lds4) {
+__device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, float4* lds4,
+                                                          unsigned long long goff) {
+    const GroupView G{P, goff};
     const RobotArgs& R = *P.R;   // device memory: uniform reads are scalar loads
     const SceneArgs& S = *P.S;
     const int tid = threadIdx.x, nth = NW * kWave;
@@ -297,16 +355,16 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
 
     // ---- prologue: roots, endpoint checks
     if (w == 0 && lead && lane < dof) {
-        P.qa[(size_t)lane * cap] = P.start[lane];
-        P.qb[(size_t)lane * cap] = P.goal[lane];
+        G.qa()[(size_t)lane * cap] = P.start[lane];
+        G.qb()[(size_t)lane * cap] = P.goal[lane];
     }
     if (w == 0 && tid == 0) {
-        P.pa[0] = -1;
-        P.pb[0] = -1;
-        P.ba[0] = 0;
-        P.bb[0] = 0;
-        P.ra[0] = __builtin_inff();
-        P.rb[0] = __builtin_inff();
+        G.pa()[0] = -1;
+        G.pb()[0] = -1;
+        G.ba()[0] = 0;
+        G.bb()[0] = 0;
+        G.ra()[0] = __builtin_inff();
+        G.rb()[0] = __builtin_inff();
         ctl[kSizeA] = 1;
         ctl[kSizeB] = 1;
     }
@@ -333,7 +391,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         if (!ok && tid == 0) atomicOr(ctl + kEndpointBad, 1);
         __syncthreads();
     }
-    if (!group_barrier(P.bar, w, P.W)) return false;
+    if (!group_barrier(G.bar(), w, P.W)) return false;
     if (ctl[kEndpointBad]) {
         if (w == 0 && tid == 0) ctl[kStatus] = kStInvalidEndpoint;
         return true;
@@ -345,12 +403,12 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         const int na = __hip_atomic_load(ctl + kSizeA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int nb = __hip_atomic_load(ctl + kSizeB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const bool s_is_a = na <= nb;
-        float* qs = s_is_a ? P.qa : P.qb;
-        int* ps = s_is_a ? P.pa : P.pb;
-        unsigned char* bs = s_is_a ? P.ba : P.bb;
-        float* rs = s_is_a ? P.ra : P.rb;
-        const float* qo = s_is_a ? P.qb : P.qa;
-        const unsigned char* bo = s_is_a ? P.bb : P.ba;
+        float* qs = s_is_a ? G.qa() : G.qb();
+        int* ps = s_is_a ? G.pa() : G.pb();
+        unsigned char* bs = s_is_a ? G.ba() : G.bb();
+        float* rs = s_is_a ? G.ra() : G.rb();
+        const float* qo = s_is_a ? G.qb() : G.qa();
+        const unsigned char* bo = s_is_a ? G.bb() : G.ba();
         const int ns = s_is_a ? na : nb, no = s_is_a ? nb : na;
         // ===== phase A: sample, nearest, extend, connect
         int count = 0, nn = -1, other = -1, conn = 0, fail = -1;
@@ -418,7 +476,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     }
                     if (n_ext > P.stage_cap) {
                         // cannot happen for nodes inside the joint limits
-                        if (tid == 0) atomicExch(P.bar + kAbort, 2);
+                        if (tid == 0) atomicExch(G.bar() + kAbort, 2);
                         n_ext = P.stage_cap;
                     }
                     // waypoints t_0 = c_new, t_k = fmaf(k / n_ext, c_nno - c_new, c_new), t_n = c_nno
@@ -441,24 +499,24 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     conn = K == n_ext;
                 }
                 // stage c_new and the valid intermediate targets
-                float* st = P.stage + (size_t)w * P.stage_cap * dof;
+                float* st = G.stage() + (size_t)w * P.stage_cap * dof;
                 for (int e = tid; e < count * dof; e += nth) st[e] = (e < dof) ? c_new[e] : wp[e];
             }
         }
         if (tid == 0) {
-            P.st_count[w] = count;
-            P.st_nn[w] = nn;
-            P.st_other[w] = other;
-            P.st_conn[w] = conn;
-            P.st_fail[w] = fail;
+            G.st_count()[w] = count;
+            G.st_nn()[w] = nn;
+            G.st_other()[w] = other;
+            G.st_conn()[w] = conn;
+            G.st_fail()[w] = fail;
         }
-        if (!group_barrier(P.bar, w, P.W)) break;
+        if (!group_barrier(G.bar(), w, P.W)) break;
         // ===== phase B: ordered commit
         int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1;
         for (int c0 = 0; c0 < P.W; c0 += kWave) {
             const int wi = c0 + lane;
-            const int cnt = wi < P.W ? P.st_count[wi] : 0;
-            const int cn = wi < P.W ? P.st_conn[wi] : 0;
+            const int cnt = wi < P.W ? G.st_count()[wi] : 0;
+            const int cn = wi < P.W ? G.st_conn()[wi] : 0;
             int incl = cnt;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
@@ -475,7 +533,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 const int fb = __shfl(base_i, src, kWave);
                 const int fc = __shfl(cnt, src, kWave);
                 first_last = fb + fc - 1;
-                first_other = P.st_other[cand];
+                first_other = G.st_other()[cand];
             }
             running += __shfl(incl, kWave - 1, kWave);
         }
@@ -483,7 +541,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         my_base = sh_i[0];
         {
             const int c = max(0, min(count, cap - my_base));
-            const float* st = P.stage + (size_t)w * P.stage_cap * dof;
+            const float* st = G.stage() + (size_t)w * P.stage_cap * dof;
             for (int e = tid; e < c * dof; e += nth) {
                 const int k = e / dof, j = e - k * dof;
                 qs[(size_t)j * cap + my_base + k] = st[e];
@@ -502,7 +560,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             ctl[s_is_a ? kSizeA : kSizeB] = new_size;
             if (P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks) ctl[kStop] = 1;
         }
-        if (!group_barrier(P.bar, w, P.W)) break;
+        if (!group_barrier(G.bar(), w, P.W)) break;
         // ===== phase C: path and re-check
         if (first != 0x7fffffff) {
             const int xa = s_is_a ? first_last : first_other;
@@ -512,28 +570,28 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     // one walk per tree: A from the connection node up to its root
                     // (stored reversed, flipped below), B from its node up to its root
                     int bad = 0, la = 0, lb = 0, x = xa;
-                    for (; x >= 0 && la < cap; x = P.pa[x]) {
-                        P.path_idx[la++] = x;
-                        bad |= P.ba[x];
+                    for (; x >= 0 && la < cap; x = G.pa()[x]) {
+                        G.path_idx()[la++] = x;
+                        bad |= G.ba()[x];
                     }
                     int y = xb;
-                    for (; y >= 0 && lb < cap; y = P.pb[y]) {
-                        P.path_idx[la + lb++] = y;
-                        bad |= P.bb[y];
+                    for (; y >= 0 && lb < cap; y = G.pb()[y]) {
+                        G.path_idx()[la + lb++] = y;
+                        bad |= G.bb()[y];
                     }
                     int len = la + lb;
                     if (x >= 0 || y >= 0) {           // a parent chain longer than the tree
                         bad = 1;
                         len = P.path_cap + 1;
-                        atomicExch(P.bar + kAbort, 3);
+                        atomicExch(G.bar() + kAbort, 3);
                     }
                     if (P.validate <= 0) bad = len > P.path_cap;  // no re-check: blocked nodes cannot exist
                     ctl[kNa] = la;
                     ctl[kPathLen] = len;
                     ctl[kValBad] = bad;
                     if (bad && len <= P.path_cap) {
-                        if (xa != 0) P.ba[xa] = 1;
-                        if (xb != 0) P.bb[xb] = 1;
+                        if (xa != 0) G.ba()[xa] = 1;
+                        if (xb != 0) G.bb()[xb] = 1;
                     }
                     __threadfence_block();
                     sh_i[1] = la;
@@ -544,40 +602,40 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 const int la = sh_i[1], len = sh_i[2];
                 if (len <= P.path_cap) {
                     for (int m = tid; m < la / 2; m += nth) {
-                        const int u = P.path_idx[m], v = P.path_idx[la - 1 - m];
-                        P.path_idx[m] = v;
-                        P.path_idx[la - 1 - m] = u;
+                        const int u = G.path_idx()[m], v = G.path_idx()[la - 1 - m];
+                        G.path_idx()[m] = v;
+                        G.path_idx()[la - 1 - m] = u;
                     }
                     __syncthreads();
                     __threadfence_block();
                     for (int e = tid; e < len * dof; e += nth) {
                         const int m = e / dof, j = e - m * dof;
                         const bool in_a = m < la;
-                        const float* q = in_a ? P.qa : P.qb;
-                        P.path[e] = q[(size_t)j * cap + P.path_idx[m]];
+                        const float* q = in_a ? G.qa() : G.qb();
+                        G.path()[e] = q[(size_t)j * cap + G.path_idx()[m]];
                     }
                 }
             }
-            if (!group_barrier(P.bar, w, P.W)) break;
+            if (!group_barrier(G.bar(), w, P.W)) break;
             const int la = ctl[kNa], len = ctl[kPathLen];
             if (P.validate > 0) {
                 // each segment's points in kValChunks chunks, one per worker
                 for (int item = w; item < (len - 1) * kValChunks; item += P.W) {
                     const int k = item / kValChunks, c = item - k * kValChunks;
-                    if (lead && lane < 2 * dof) wp[lane] = P.path[(size_t)k * dof + lane];
+                    if (lead && lane < 2 * dof) wp[lane] = G.path()[(size_t)k * dof + lane];
                     __syncthreads();
                     const bool ok = wave_check<TP, B, false, NW>(R, S, wp, 1, 0, P.res_v, ws, c, kValChunks) == 1;
                     if (c == 0) my_edges += 1;
                     if (!ok && tid == 0) {
                         ctl[kValBad] = 1;
-                        if (k + 1 < la) P.ba[P.path_idx[k + 1]] = 1;
-                        else if (k + 1 == la) { if (s_is_a) P.ba[xa] = 1; else P.bb[xb] = 1; }
-                        else P.bb[P.path_idx[k]] = 1;
+                        if (k + 1 < la) G.ba()[G.path_idx()[k + 1]] = 1;
+                        else if (k + 1 == la) { if (s_is_a) G.ba()[xa] = 1; else G.bb()[xb] = 1; }
+                        else G.bb()[G.path_idx()[k]] = 1;
                     }
                     __syncthreads();
                 }
             }
-            if (!group_barrier(P.bar, w, P.W)) break;
+            if (!group_barrier(G.bar(), w, P.W)) break;
             if (!ctl[kValBad]) {
                 status = kStOk;
                 if (w == 0 && tid == 0) ctl[kConnWorker] = first;
@@ -594,12 +652,12 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     if (tid == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
     if (tid == 0 && my_learned)
         atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kLearnedLo), (unsigned long long)my_learned);
-    const bool aborted = __hip_atomic_load(P.bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const bool aborted = __hip_atomic_load(G.bar() + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     if (w == 0) {
         // hand the path to the query's own buffer (the group's is reused)
         const int len = ctl[kPathLen];
-        if (!aborted && status == kStOk && P.out_path != P.path && len <= P.out_path_cap)
-            for (int e = tid; e < len * dof; e += nth) P.out_path[e] = P.path[e];
+        if (!aborted && status == kStOk && P.out_path != G.path() && len <= P.out_path_cap)
+            for (int e = tid; e < len * dof; e += nth) P.out_path[e] = G.path()[e];
         if (tid == 0) {
             ctl[kRounds] = round;
             ctl[kStatus] = aborted ? kStInternal : status;
@@ -613,18 +671,22 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
 // error, rest 0); with Pq, the single query's arguments (by value) are stored
 // there.
 __global__ void k_plan_init(int* bar, int n_groups, int bar_words, size_t bar_stride, int* ctl, int n_queries,
-                            PlanArgs one_query, PlanArgs* Pq) {
+                            PlanArgs one_query, PlanArgs* Pq, int* next) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_groups * bar_words) bar[(size_t)(t / bar_words) * bar_stride + t % bar_words] = 0;
+    if (next && t == 0) *next = 0;
     if (t < n_queries * kCtlWords) ctl[t] = (t % kCtlWords) == kStatus ? kStInternal : 0;
     if (Pq && t < (int)(sizeof(PlanArgs) / sizeof(int)))
         reinterpret_cast<int*>(Pq)[t] = reinterpret_cast<const int*>(&one_query)[t];
 }
 
-// Persistent planner: n_groups groups of W workgroups (NW waves each); group
-// g runs queries g, g + n_groups, ... one after another.  All queries of a
-// launch share W.  A group that aborts leaves its remaining queries at
-// "internal".
+// Persistent planner: n_groups groups of W workgroups (NW waves each).  With
+// no more queries than groups, group g runs query g.  Otherwise the groups
+// take queries one at a time from a launch-wide counter (handed out at a
+// group barrier), so a group whose queries end early takes more of them and
+// the launch is not held to the unluckiest static share.  All queries of a
+// launch share W.  A group that aborts stops taking queries; one it had
+// taken is left at "internal".
 // WPE: waves per SIMD the register allocation must allow.
 template <int TP, int B, int NW, int WPE>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE))) void k_plan(
@@ -633,8 +695,21 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
     const int W = Pq[0].W;
     const int g = blockIdx.x / W;
     const int w = blockIdx.x - g * W;
-    for (int k = g; k < n_queries; k += n_groups)
-        if (!plan_query<TP, B, NW>(((CPlanArgs*)Pq)[k], w, lds4)) break;
+    const unsigned long long goff = (unsigned long long)g * Pq[0].group_bytes;
+    const bool handed_out = n_queries > n_groups;
+    int k = g;
+    for (;;) {
+        if (handed_out) {
+            int* bar = moved(Pq[0].bar, goff);
+            if (!group_barrier(bar, w, W, Pq[0].next)) break;
+            // one value for the whole workgroup: keeps the query's arguments
+            // on scalar loads
+            k = __builtin_amdgcn_readfirstlane(__hip_atomic_load(bar + kNext, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT));
+        }
+        if (k >= n_queries) break;
+        if (!plan_query<TP, B, NW>(((CPlanArgs*)Pq)[k], w, lds4, goff) || !handed_out) break;
+    }
 }
 
 }  // namespace prrtc
