@@ -192,6 +192,59 @@ __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
     }
 }
 
+// The same recursion on four lanes (a quad) per configuration.  The rows of
+// a frame evolve independently given the joint's (cos q, sin q), so lane r of
+// the quad (r < 3) carries row r with exactly the arithmetic of fk_frames
+// (bit-identical frames), and the trigonometry is shared: for joints
+// j4..j4+3 of the chain, lane r takes sincos of joint j4 + r and each joint's
+// pair is broadcast from the lane that made it (DPP within the quad).  Stores
+// only slotted frames (3 * slot).  The whole quad must be active.
+#ifndef PRRTC_FK_QUAD
+#define PRRTC_FK_QUAD 1
+#endif
+// Broadcast lane u of each quad to the whole quad (DPP quad_perm).
+template <int U>
+__device__ inline float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), U * 0x55, 0xF, 0xF, false));
+}
+
+template <class QF>
+__device__ inline void fk_rows(const RobotArgs& R, QF qf, float4* out, int r) {
+    const int rr = r < 3 ? r : 2;   // lane 3 shadows row 2 and stores nothing
+    for (int c = 0; c < R.n_chains; ++c) {
+        const float* B = R.base[c] + 4 * rr;
+        float x = B[0], y = B[1], z = B[2], t = B[3];
+        int f = R.chain_f0[c];
+        auto store = [&](int fr) {
+            const int at = R.frame_slot[fr];
+            if (at >= 0 && r < 3) out[3 * at + r] = make_float4(x, y, z, t);
+        };
+        store(f);
+        const int q0 = R.chain_q0[c], cd = R.chain_dof[c];
+        for (int j4 = 0; j4 < cd; j4 += 4) {
+            float sv = 0.0f, cv = 1.0f;
+            if (j4 + r < cd) sincosf(qf(q0 + j4 + r), &sv, &cv);
+            auto joint = [&](int jj, float sq, float cq) {
+                const int j = q0 + jj;
+                const float ca = R.ca[j], sa = R.sa[j], a = R.a[j], d = R.d[j];
+                const float u = ca * y + sa * z;
+                const float m = ca * z - sa * y;
+                t += a * x + d * m;
+                const float n0 = cq * x + sq * u;
+                const float n1 = cq * u - sq * x;
+                x = n0;
+                y = n1;
+                z = m;
+                store(++f);
+            };
+            joint(j4, quad_bcast<0>(sv), quad_bcast<0>(cv));
+            if (j4 + 1 < cd) joint(j4 + 1, quad_bcast<1>(sv), quad_bcast<1>(cv));
+            if (j4 + 2 < cd) joint(j4 + 2, quad_bcast<2>(sv), quad_bcast<2>(cv));
+            if (j4 + 3 < cd) joint(j4 + 3, quad_bcast<3>(sv), quad_bcast<3>(cv));
+        }
+    }
+}
+
 __device__ inline float3 frame_apply(const float4* fr, float x, float y, float z) {
     const float4 a = fr[0], b = fr[1], c = fr[2];
     return make_float3(a.x * x + a.y * y + a.z * z + a.w, b.x * x + b.y * y + b.z * z + b.w,
@@ -429,10 +482,13 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
     const int S_move = R.n_move;
     for (int g0 = 0; g0 < total; g0 += TP) {
         const int np = min(TP, total - g0);
-        // ---- FK of the tile's configurations: slot wave * TP / NW + lane takes
-        // point g0 + slot
-        const int slot = wave * (TP / NW) + lane;
-        if (lane < TP / NW && slot < np) {
+        // ---- FK of the tile's configurations: slot wave * TP / NW + lane / LPC
+        // takes point g0 + slot, on LPC lanes (a quad when the wave's share of
+        // the tile leaves room for it)
+        constexpr int CPW = TP / NW;
+        constexpr int LPC = (PRRTC_FK_QUAD && 4 * CPW <= kWave) ? 4 : 1;
+        const int slot = wave * CPW + lane / LPC;
+        if (lane < CPW * LPC && slot < np) {
             const int g = g0 + slot;
             int k = 0;
             if (MULTI)
@@ -441,9 +497,12 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             const float t = (float)i / (float)ws.sub_n[k];
             const float* w0 = wp + k * dof;
             const float* w1 = w0 + dof;
-            ws.pk[slot] = k;
-            fk_frames<false>(R, [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); },
-                             ws.frames + slot * fstride);
+            if (lane % LPC == 0) ws.pk[slot] = k;
+            auto qf = [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); };
+            if (LPC == 4)
+                fk_rows(R, qf, ws.frames + slot * fstride, lane & 3);
+            else
+                fk_frames<false>(R, qf, ws.frames + slot * fstride);
         }
         __syncthreads();
         // ---- (point, sphere) items, point-major, against the obstacles
