@@ -177,6 +177,8 @@ struct SceneRec {
     SceneArgs* dev_args = nullptr;  // copy of args in device memory
     void* mem = nullptr;
     uint8_t* vox = nullptr;         // occupancy grid, made by the first learned plan
+    float* emb = nullptr;           // [kHidden] the grid's embedding under the model stamped emb_stamp
+    uint64_t emb_stamp = 0;
     int n = 0;
 };
 
@@ -220,6 +222,7 @@ struct ModelRec {
     PropLayout L{};
     float* mem = nullptr;      // params | grads | adam m | adam v, each L.off[pCount] floats
     long long adam_t = 0;
+    uint64_t stamp = 0;        // changes whenever the parameters change (context-wide counter)
     void* ws = nullptr;        // activation workspace
     size_t ws_bytes = 0;
     size_t n() const { return L.off[pCount]; }
@@ -262,6 +265,7 @@ struct prrtc_ctx {
     PlannerBuffers batch;              // batched launches
     std::vector<float> stage_host;     // host staging of batched proposal inputs
     std::vector<ModelRec> models;
+    uint64_t model_stamp = 0;         // last stamp given to a model's parameters
     EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
     unsigned counter_next = 0;
     int edge_grid = 0;                 // resident workgroups of k_check_edges (cached)
@@ -371,6 +375,7 @@ void prrtc_destroy(prrtc_ctx* ctx) {
         hipFree(s.mem);
         hipFree(s.dev_args);
         if (s.vox) hipFree(s.vox);
+        if (s.emb) hipFree(s.emb);
     }
     planner_free(ctx->plan);
     planner_free(ctx->batch);
@@ -678,6 +683,7 @@ prrtc_status prrtc_unload_scene(prrtc_ctx* ctx, int32_t scene_id) {
     PRRTC_HIP(ctx, hipFree(rec.mem));
     PRRTC_HIP(ctx, hipFree(rec.dev_args));
     if (rec.vox) PRRTC_HIP(ctx, hipFree(rec.vox));
+    if (rec.emb) PRRTC_HIP(ctx, hipFree(rec.emb));
     rec = SceneRec{};
     return PRRTC_OK;
 }
@@ -1510,7 +1516,7 @@ void prop_forward(hipStream_t sm, ModelRec& M, const PropWs& W, const RobotArgs*
         // a few queries: split embedding and one workgroup per row
         hipLaunchKernelGGL(k_embed_partial, dim3(kEmbedSlices), dim3(256), 0, sm, vox, S, M.p(pWv), W.part);
         hipLaunchKernelGGL(k_embed_reduce, dim3(S), dim3(256), 0, sm, W.part, M.p(pbv), W.E);
-        hipLaunchKernelGGL(k_mlp_rows, dim3(n), dim3(256), 0, sm, s, g, scene_of, W.E, lo, hi, L.dof, M.p(pW1),
+        hipLaunchKernelGGL(k_mlp_rows, dim3(n), dim3(kRowThreads), 0, sm, s, g, scene_of, W.E, lo, hi, L.dof, M.p(pW1),
                            M.p(pb1), M.p(pW2), M.p(pb2), M.p(pW3), M.p(pb3), M.p(pW4), M.p(pb4), gmm_out);
         return;
     }
@@ -1580,7 +1586,21 @@ prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, 
     const int zero = 0;
     memcpy(&host[2 * dof], &zero, sizeof zero);
     PRRTC_HIP(ctx, hipMemcpyAsync(qin, host, sizeof(float) * (2 * dof + 1), hipMemcpyHostToDevice, sm));
-    prop_forward(sm, M, W, r.dev_args, s.vox, 1, reinterpret_cast<const int*>(qin + 2 * dof), qin, qin + dof, nullptr, 1, gmm);
+    // the grid's embedding depends on the scene and the parameters only: kept
+    // per scene and recomputed when the model (or its parameters) change
+    if (!s.emb) PRRTC_HIP(ctx, hipMalloc(&s.emb, sizeof(float) * kHidden));
+    if (s.emb_stamp != M.stamp) {
+        hipLaunchKernelGGL(k_embed_partial, dim3(kEmbedSlices), dim3(256), 0, sm, s.vox, 1, M.p(pWv), W.part);
+        hipLaunchKernelGGL(k_embed_reduce, dim3(1), dim3(256), 0, sm, W.part, M.p(pbv), s.emb);
+        s.emb_stamp = M.stamp;
+    }
+    const char* rb = reinterpret_cast<const char*>(r.dev_args);
+    const float* lo = reinterpret_cast<const float*>(rb + offsetof(RobotArgs, lo));
+    const float* hi = reinterpret_cast<const float*>(rb + offsetof(RobotArgs, hi));
+    const PropLayout& L = M.L;
+    hipLaunchKernelGGL(k_mlp_rows, dim3(1), dim3(kRowThreads), 0, sm, qin, qin + dof,
+                       reinterpret_cast<const int*>(qin + 2 * dof), s.emb, lo, hi, L.dof, M.p(pW1), M.p(pb1),
+                       M.p(pW2), M.p(pb2), M.p(pW3), M.p(pb3), M.p(pW4), M.p(pb4), gmm);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
 }
@@ -1645,6 +1665,7 @@ prrtc_status prrtc_load_proposal(prrtc_ctx* ctx, const void* blob, size_t bytes,
         return fail(ctx, PRRTC_E_HIP, "proposal upload: %s", hipGetErrorString(e));
     }
     M.adam_t = h.has_adam ? h.adam_t : 0;
+    M.stamp = ++ctx->model_stamp;
     models_of(ctx).push_back(M);
     *model_id = (int32_t)models_of(ctx).size() - 1;
     return PRRTC_OK;
@@ -1768,6 +1789,7 @@ prrtc_status prrtc_train_proposal(prrtc_ctx* ctx, int32_t model_id, int32_t robo
     hipLaunchKernelGGL(k_adam, dim3(blocks(n, 256)), dim3(256), 0, sm, M->mem, M->mem + n, M->mem + 2 * n,
                        M->mem + 3 * n, n, lr, (float)b1, (float)b2, 1e-8f, c1, c2);
     PRRTC_HIP(ctx, hipGetLastError());
+    M->stamp = ++ctx->model_stamp;
     return PRRTC_OK;
 }
 

@@ -214,8 +214,9 @@ __global__ void k_gmm_head(const float* __restrict__ O, int n, int dof, const fl
 //   k_embed_reduce: E[s][col] = b_v[col] + the slices' partial sums, in
 //     slice order;
 //   k_mlp_rows: one workgroup per query row, activations in LDS, each layer
-//     a BF16-operand FP32-accumulate dot product per output column, GELU,
-//     and the mixture head (log sigma clamped).
+//     a BF16-operand FP32-accumulate dot product per output column (k split
+//     four ways, the quarters added in order), GELU, and the mixture head
+//     (log sigma clamped).
 // Same arithmetic as the GEMM path (BF16 operands, FP32 sums); only the
 // order of the sums differs.
 // ---------------------------------------------------------------------------
@@ -249,29 +250,57 @@ __global__ __launch_bounds__(256) void k_embed_reduce(const float* __restrict__ 
     E[(size_t)r * kHidden + col] = e + bv[col];
 }
 
-// out[col] = act(sum_k bf16(x[k]) bf16(W[k][col]) + b[col]) for col < N (threads stride N)
+// out[col] = act(sum_k bf16(x[k]) bf16(W[k][col]) + b[col]) for col < N <= kHidden.
+// kRowSplit groups of kHidden threads each sum a quarter of k (loads issued
+// eight at a time), and the quarters are added in order: a short dependent
+// chain per thread instead of one K-long chain of loads.
+constexpr int kRowSplit = 4;
+constexpr int kRowThreads = kRowSplit * kHidden;
+
 template <bool GELU>
 __device__ inline void row_layer(const float* __restrict__ x, int K, const float* __restrict__ W, int N,
-                                 const float* __restrict__ b, float* __restrict__ out) {
-    for (int col = threadIdx.x; col < N; col += blockDim.x) {
+                                 const float* __restrict__ b, float* __restrict__ out, float* red) {
+    const int c = threadIdx.x % kHidden, part = threadIdx.x / kHidden;
+    const int k0 = K * part / kRowSplit, k1 = K * (part + 1) / kRowSplit;
+    for (int c0 = 0; c0 < N; c0 += kHidden) {   // uniform: every thread takes each pass
+        const int col = c0 + c;
         float acc = 0.0f;
-        for (int k = 0; k < K; ++k) acc = fmaf(x[k], bf16_round(W[(size_t)k * N + col]), acc);
-        float v = acc + b[col];
-        if (GELU) v = 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
-        out[col] = v;
+        if (col < N) {
+            int k = k0;
+            for (; k + 8 <= k1; k += 8) {
+                float w[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) w[u] = bf16_round(W[(size_t)(k + u) * N + col]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = fmaf(x[k + u], w[u], acc);
+            }
+            for (; k < k1; ++k) acc = fmaf(x[k], bf16_round(W[(size_t)k * N + col]), acc);
+        }
+        red[part * kHidden + c] = acc;
+        __syncthreads();
+        if (part == 0 && col < N) {
+            float v = red[c];
+#pragma unroll
+            for (int q = 1; q < kRowSplit; ++q) v += red[q * kHidden + c];
+            v += b[col];
+            if (GELU) v = 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
+            out[col] = v;
+        }
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_rows(const float* __restrict__ s, const float* __restrict__ g,
-                                                  const int* __restrict__ scene_of, const float* __restrict__ E,
-                                                  const float* __restrict__ lo, const float* __restrict__ hi,
-                                                  int dof, const float* __restrict__ W1, const float* __restrict__ b1,
-                                                  const float* __restrict__ W2, const float* __restrict__ b2,
-                                                  const float* __restrict__ W3, const float* __restrict__ b3,
-                                                  const float* __restrict__ W4, const float* __restrict__ b4,
-                                                  float* __restrict__ gmm) {
+__global__ __launch_bounds__(kRowThreads) void k_mlp_rows(const float* __restrict__ s, const float* __restrict__ g,
+                                                          const int* __restrict__ scene_of, const float* __restrict__ E,
+                                                          const float* __restrict__ lo, const float* __restrict__ hi,
+                                                          int dof, const float* __restrict__ W1,
+                                                          const float* __restrict__ b1, const float* __restrict__ W2,
+                                                          const float* __restrict__ b2, const float* __restrict__ W3,
+                                                          const float* __restrict__ b3, const float* __restrict__ W4,
+                                                          const float* __restrict__ b4, float* __restrict__ gmm) {
     __shared__ float xa[2 * kMaxDof + kHidden];
     __shared__ float xb[kComp * (1 + 2 * kMaxDof) > kHidden ? kComp * (1 + 2 * kMaxDof) : kHidden];
+    __shared__ float red[kRowThreads];
     const int row = blockIdx.x, t = threadIdx.x;
     const int D0 = 2 * dof + kHidden, Cw = kComp * (1 + 2 * dof);
     for (int c = t; c < D0; c += blockDim.x) {
@@ -286,19 +315,19 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const float* __restrict__ s, c
         xa[c] = bf16_round(v);
     }
     __syncthreads();
-    row_layer<true>(xa, D0, W1, kHidden, b1, xb);
+    row_layer<true>(xa, D0, W1, kHidden, b1, xb, red);
     __syncthreads();
     for (int c = t; c < kHidden; c += blockDim.x) xa[c] = bf16_round(xb[c]);
     __syncthreads();
-    row_layer<true>(xa, kHidden, W2, kHidden, b2, xb);
+    row_layer<true>(xa, kHidden, W2, kHidden, b2, xb, red);
     __syncthreads();
     for (int c = t; c < kHidden; c += blockDim.x) xa[c] = bf16_round(xb[c]);
     __syncthreads();
-    row_layer<true>(xa, kHidden, W3, kHidden, b3, xb);
+    row_layer<true>(xa, kHidden, W3, kHidden, b3, xb, red);
     __syncthreads();
     for (int c = t; c < kHidden; c += blockDim.x) xa[c] = bf16_round(xb[c]);
     __syncthreads();
-    row_layer<false>(xa, kHidden, W4, Cw, b4, xb);
+    row_layer<false>(xa, kHidden, W4, Cw, b4, xb, red);
     __syncthreads();
     float* out = gmm + (size_t)row * Cw;
     for (int c = t; c < Cw; c += blockDim.x)

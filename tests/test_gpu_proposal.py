@@ -288,6 +288,46 @@ def test_plan_learned_valid_and_reproducible(gpu, orc, r7, mix):
         assert stats2["learned_samples"] == stats["learned_samples"]
 
 
+def test_plan_learned_embedding_follows_training(gpu, orc, r7):
+    """A single learned plan keeps the scene's grid embedding between calls;
+    after a training step the next plan must use the new parameters: it
+    equals the plan of a freshly loaded copy of the trained model."""
+    from conftest import free_query
+    P, ctx, torch = gpu
+    say("learned plan after training: cached grid embedding refreshed")
+    prims = W.scene_s12(r7, 1)
+    rid, sid = P.prrtc_load_robot(ctx, r7), P.prrtc_load_scene(ctx, prims)
+    s, g = free_query(orc, orc.OracleRobot(r7), prims, r7, W.SEED_QUERY + 1)
+    model = _learned_model(P, ctx, 7, 34)
+
+    def run(mid):
+        p = P.prrtc_plan_params_default()
+        p.seed, p.max_rounds, p.sampler, p.model_id, p.mix = 77, 1000, 1, mid, 1.0
+        return P.prrtc_plan(ctx, rid, sid, s, g, p)
+
+    st0, path0, stats0 = run(model)          # fills the embedding cache
+    assert st0 == 0, stats0
+    rng = np.random.default_rng(21)
+    vox_t = gpu_vox(gpu, [prims])
+    scene_of, start, qs, qg, q = _batch(rng, r7, 1, 64)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in
+           dict(scene_of=scene_of, start=start, s=qs, g=qg, q=q).items()}
+    loss = torch.zeros(1, device="cuda")
+    b = P.prrtc_train_batch(vox=vox_t.data_ptr(), n_scenes=1, scene_start=dev["start"].data_ptr(),
+                            scene_of=dev["scene_of"].data_ptr(), start=dev["s"].data_ptr(),
+                            goal=dev["g"].data_ptr(), waypoint=dev["q"].data_ptr(), n=len(qs))
+    for _ in range(20):
+        P.prrtc_train_proposal(ctx, model, rid, b, 5e-2, loss.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    st1, path1, stats1 = run(model)
+    fresh = P.prrtc_load_proposal(ctx, P.prrtc_save_proposal(ctx, model))
+    st2, path2, stats2 = run(fresh)
+    say("  rounds before / after training / fresh copy", stats0["rounds"], stats1["rounds"], stats2["rounds"])
+    assert st1 == st2 and np.array_equal(path1, path2)
+    for k in ("rounds", "nodes_a", "nodes_b", "learned_samples"):
+        assert stats1[k] == stats2[k], k
+
+
 def test_plan_learned_bad_arguments(gpu, r7):
     P, ctx, _ = gpu
     rid = P.prrtc_load_robot(ctx, r7)
