@@ -265,16 +265,30 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
                                int32_t *best_workers, int32_t *best_tile);
 
 /*
- * Serving: a thread owned by the context gathers submitted queries into
- * prrtc_plan_batch launches (up to `slots` queries per launch, groups sized
- * by memory_budget as in prrtc_plan_batch), so queries arriving over time
- * are planned as they come (continuous batching at launch granularity).
+ * Serving: a thread owned by the context plans submitted queries as they
+ * arrive.  With uniform sampling (params->sampler 0) it keeps one persistent
+ * launch running: queries are published into a ring of 16 x slots entries
+ * (32 to 4096) that the launch's worker groups take from while it runs (at
+ * most `slots` in flight), and each result returns as soon as its query
+ * ends.  The launch leaves after 50 ms without work and is started again by
+ * the next submission; a used-up ring drains the launch and the next one
+ * starts on the reset ring.  Group buffers are sized for the largest robot
+ * loaded when serving starts (robots cannot be loaded while serving).  With
+ * the learned sampler it gathers queries into prrtc_plan_batch launches of
+ * up to `slots` queries (continuous batching at launch granularity).  Groups
+ * are sized by memory_budget as in prrtc_plan_batch.  Results equal those
+ * of prrtc_plan / prrtc_plan_batch for the same query, seed and parameters.
  * While serving, the context accepts only prrtc_submit, prrtc_poll,
  * prrtc_serve_stop and prrtc_last_error (everything else: E_STATE).
  *
  * prrtc_serve_start: params as for prrtc_plan_batch; slots >= 1;
  *   max_pending >= slots bounds the queries admitted and not yet polled;
- *   path_cap >= 1 nodes kept per query.
+ *   path_cap >= 1 nodes kept per query.  E_STATE if no robot is loaded
+ *   (uniform sampling); E_CAPACITY if one worker group does not fit;
+ *   E_HIP if the ring buffers (pinned host and device memory) cannot be
+ *   allocated.  A query rejected by the host checks (unknown ids, endpoints
+ *   outside the limits) comes back through prrtc_poll with that status;
+ *   one whose worker group aborted comes back as E_HIP.
  * prrtc_submit: copies *query and returns a ticket; E_BUSY (admission
  *   refused) when max_pending queries are queued, running or unpolled.
  * prrtc_poll: E_BUSY while the ticket is queued or running; OK with *result
@@ -283,7 +297,7 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
  *   released; E_CAPACITY if path_cap < result->path_len (ticket kept);
  *   E_STATE for an unknown or released ticket.
  * prrtc_serve_stop: plans everything still queued, joins the thread, drops
- *   unpolled results; *launches (may be NULL) = batched launches made.
+ *   unpolled results; *launches (may be NULL) = launches made.
  */
 prrtc_status prrtc_serve_start(prrtc_ctx *ctx, const prrtc_plan_params *params, int32_t slots,
                                int32_t max_pending, int64_t memory_budget, int32_t path_cap);

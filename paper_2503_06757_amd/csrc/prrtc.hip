@@ -231,6 +231,11 @@ struct ModelRec {
 };
 
 
+// Device buffers of one worker group (reused by every query the group runs).
+struct GroupLayout {
+    size_t qa, pa, ba, ra, qb, pb, bb, rb, bar, stage, st, path, path_idx, bytes;
+};
+
 // Serving state of a context (see prrtc_serve_start).
 struct ServeDone {
     prrtc_query_result res;
@@ -251,6 +256,23 @@ struct Server {
     std::unordered_map<uint64_t, ServeDone> done;
     long long launches = 0;
     size_t in_flight() const { return queue.size() + running.size() + done.size(); }
+    // persistent mode (uniform sampling): one long launch takes queries as
+    // they are published into a ring (see k_serve)
+    bool persistent = false;
+    int ring = 0, path_stride = 0, groups = 0, W = 0;
+    size_t lds = 0;
+    const void* kernel = nullptr;
+    void* host_mem = nullptr;        // pinned: args ring | result words | paths | control words
+    PlanArgs* host_args = nullptr;
+    int* host_ctl = nullptr;
+    float* host_path = nullptr;
+    int* host_ctrl = nullptr;        // [0] published, [32] drain
+    void* dev_mem = nullptr;         // groups | args ring | words | paths | counter | ServeArgs
+    char* dev_groups = nullptr;
+    ServeArgs* dev_sa = nullptr;
+    ServeArgs sa{};
+    GroupLayout L{};
+    int tree_cap = 0;
 };
 
 struct prrtc_ctx {
@@ -798,12 +820,15 @@ namespace {
 struct PlanShape {
     int tile, items, waves;
     const void* kernel;
+    const void* serve;   // the persistent serving kernel of the same shape
 };
 
 const PlanShape* plan_shape(int tile) {
     static const PlanShape shapes[] = {
-        {64, 6, PRRTC_PLAN_WAVES, reinterpret_cast<const void*>(&k_plan<64, 6, PRRTC_PLAN_WAVES, 2>)},
-        {16, 3, 1, reinterpret_cast<const void*>(&k_plan<16, 3, 1, 3>)},
+        {64, 6, PRRTC_PLAN_WAVES, reinterpret_cast<const void*>(&k_plan<64, 6, PRRTC_PLAN_WAVES, 2>),
+         reinterpret_cast<const void*>(&k_serve<64, 6, PRRTC_PLAN_WAVES, 2>)},
+        {16, 3, 1, reinterpret_cast<const void*>(&k_plan<16, 3, 1, 3>),
+         reinterpret_cast<const void*>(&k_serve<16, 3, 1, 3>)},
     };
     if (tile == 0) return &shapes[0];
     for (const PlanShape& sh : shapes)
@@ -811,10 +836,6 @@ const PlanShape* plan_shape(int tile) {
     return nullptr;
 }
 
-// Device buffers of one worker group (reused by every query the group runs).
-struct GroupLayout {
-    size_t qa, pa, ba, ra, qb, pb, bb, rb, bar, stage, st, path, path_idx, bytes;
-};
 
 GroupLayout group_layout(int dof, int cap, int W, int stage_cap) {
     GroupLayout L{};
@@ -1360,6 +1381,269 @@ void serve_loop(prrtc_ctx* ctx) {
     }
 }
 
+// Persistent mode: one k_serve launch takes queries as they are published
+// into the ring; results come back through host memory as each query ends.
+// The launch leaves after kServeIdleMs without work (relaunched on the next
+// submission) or, once the ring is used up, after draining; the ring then
+// starts again at slot 0 with the next launch.
+constexpr double kServeIdleMs = 50.0;
+
+void serve_result(prrtc_ctx* ctx, Server& S, uint64_t ticket, int k, const prrtc_query& q, double ms) {
+    const int* c = S.host_ctl + (size_t)k * (kCtlWords + 1) + 1;
+    ServeDone d;
+    fill_stats(c, (float)ms, &d.res.stats);
+    d.res.status = status_of(c[kStatus]);
+    if (d.res.status == PRRTC_OK) {
+        d.res.path_len = c[kPathLen];
+        const int dof = ctx->robots[q.robot_id].dof;
+        if (d.res.path_len > S.path_cap || (size_t)d.res.path_len * dof > (size_t)S.path_stride) {
+            d.res.status = PRRTC_E_CAPACITY;
+        } else {
+            const float* src = S.host_path + (size_t)k * S.path_stride;
+            d.path.assign(src, src + (size_t)d.res.path_len * dof);
+        }
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.done[ticket] = std::move(d);
+    S.running.erase(ticket);
+}
+
+void serve_loop_persistent(prrtc_ctx* ctx) {
+    Server& S = *ctx->server;
+    (void)hipSetDevice(ctx->device);
+    volatile int* published = S.host_ctrl;
+    volatile int* drain = S.host_ctrl + 32;
+    std::vector<uint64_t> ticket_of(S.ring);
+    std::vector<prrtc_query> query_of(S.ring);
+    std::vector<char> pending(S.ring, 0);
+    std::vector<std::chrono::steady_clock::time_point> t_pub(S.ring);
+    bool launched = false;
+    int pub = 0, n_pending = 0;
+    const prrtc_plan_params& p = S.params;
+    const int bar_words = kBarWords + S.W;
+    auto fail_pending = [&](prrtc_status st) {
+        for (int k = 0; k < pub; ++k) {
+            if (!pending[k]) continue;
+            ServeDone d;
+            d.res.status = st;
+            std::lock_guard<std::mutex> lk(S.mu);
+            S.done[ticket_of[k]] = std::move(d);
+            S.running.erase(ticket_of[k]);
+            pending[k] = 0;
+        }
+        n_pending = 0;
+    };
+    for (;;) {
+        bool busy = false;
+        // 1. publish queued queries (host checks first; rejected ones answer at once)
+        int pub0 = pub;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            if (!launched && S.queue.empty() && n_pending == 0) {
+                if (S.stop) return;
+                S.cv.wait_for(lk, std::chrono::milliseconds(5));
+                if (S.queue.empty()) continue;
+            }
+            while (!S.queue.empty() && pub < S.ring && n_pending < S.slots && !(*drain && launched)) {
+                const uint64_t t = S.queue.front().first;
+                const prrtc_query q = S.queue.front().second;
+                S.queue.pop_front();
+                const RobotRec* r = nullptr;
+                const SceneRec* sc = nullptr;
+                prrtc_status st = lookup(ctx, q.robot_id, q.scene_id, &r, &sc);
+                if (st == PRRTC_OK) st = endpoints_ok(ctx, r->args, q.start, q.goal);
+                int stage_cap = 0;
+                if (st == PRRTC_OK) {
+                    stage_cap = stage_cap_for(r->args, p.delta);
+                    if (stage_cap < 0) st = PRRTC_E_ARG;
+                }
+                if (st != PRRTC_OK) {
+                    ServeDone d;
+                    d.res.status = st;
+                    S.done[t] = std::move(d);
+                    continue;
+                }
+                const int k = pub++;
+                PlanArgs& A = S.host_args[k];
+                A = PlanArgs{};
+                query_args(ctx, A, p, *r, *sc, q.start, q.goal, q.seed, q.query, stage_cap);
+                group_args(A, S.dev_groups, S.L, S.W, S.tree_cap);
+                A.group_bytes = S.L.bytes;
+                A.ctl = S.sa.dev_ctl + (size_t)k * kCtlWords;
+                A.out_path = S.sa.dev_path + (size_t)k * S.path_stride;
+                A.out_path_cap = S.path_stride / r->dof;
+                __atomic_store_n(S.host_ctl + (size_t)k * (kCtlWords + 1), 0, __ATOMIC_RELAXED);
+                ticket_of[k] = t;
+                query_of[k] = q;
+                pending[k] = 1;
+                t_pub[k] = std::chrono::steady_clock::now();
+                ++n_pending;
+                S.running[t] = 1;
+            }
+        }
+        if (pub != pub0) {
+            __atomic_store_n(published, pub, __ATOMIC_RELEASE);   // the arguments are written before
+            busy = true;
+        }
+        // 2. a launch when work is waiting and none is running
+        if (!launched && n_pending > 0) {
+            *drain = 0;
+            hipStream_t sm = ctx->stream;
+            hipLaunchKernelGGL(k_plan_init, dim3((unsigned)((bar_words * S.groups + 255) / 256)), dim3(256), 0, sm,
+                               reinterpret_cast<int*>(S.dev_groups + S.L.bar), S.groups, bar_words,
+                               S.L.bytes / sizeof(int), (int*)nullptr, 0, PlanArgs{}, (PlanArgs*)nullptr, S.sa.next);
+            void* kargs[] = {&S.dev_sa};
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipLaunchCooperativeKernel(S.kernel, dim3((unsigned)(S.groups * S.W)),
+                                               dim3(kWave * plan_shape(p.tile)->waves), kargs, (unsigned)S.lds, sm);
+            if (e != hipSuccess) {
+                fail_pending(PRRTC_E_HIP);
+                pub = 0;
+                continue;
+            }
+            launched = true;
+            std::lock_guard<std::mutex> lk(S.mu);
+            ++S.launches;
+        }
+        // 3. results of queries that have ended
+        for (int k = 0; k < pub && n_pending > 0; ++k) {
+            if (!pending[k]) continue;
+            if (__atomic_load_n(S.host_ctl + (size_t)k * (kCtlWords + 1), __ATOMIC_ACQUIRE) == 0) continue;
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_pub[k]).count();
+            serve_result(ctx, S, ticket_of[k], k, query_of[k], ms);
+            pending[k] = 0;
+            --n_pending;
+            busy = true;
+        }
+        // 4. the ring is used up, or the server stops: the launch drains
+        bool stopping;
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            stopping = S.stop;
+        }
+        if (launched && (pub == S.ring || stopping)) *drain = 1;
+        // 5. the launch has ended (idle, drained or aborted)
+        if (launched && hipStreamQuery(ctx->stream) != hipErrorNotReady) {
+            (void)hipStreamSynchronize(ctx->stream);
+            for (int k = 0; k < pub && n_pending > 0; ++k)   // results that landed at the end
+                if (pending[k] && __atomic_load_n(S.host_ctl + (size_t)k * (kCtlWords + 1), __ATOMIC_ACQUIRE)) {
+                    serve_result(ctx, S, ticket_of[k], k, query_of[k], 0.0);
+                    pending[k] = 0;
+                    --n_pending;
+                }
+            fail_pending(PRRTC_E_HIP);   // claimed by a group that aborted (as an aborted batch query)
+            launched = false;
+            pub = 0;
+            __atomic_store_n(published, 0, __ATOMIC_RELEASE);
+            busy = true;
+        }
+        if (!busy) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+#ifndef PRRTC_SERVE_PERSISTENT
+#define PRRTC_SERVE_PERSISTENT 1   // uniform-sampling servers run one persistent launch
+#endif
+constexpr int kServeRingMax = 4096;   // queries per persistent launch before it drains (16 x slots, at most)
+
+void serve_free_persistent(Server& S) {
+    if (S.dev_mem) (void)hipFree(S.dev_mem);
+    if (S.host_mem) (void)hipHostFree(S.host_mem);
+    S.dev_mem = nullptr;
+    S.host_mem = nullptr;
+}
+
+// Buffers and launch shape of the persistent mode.  Group buffers are sized
+// for the largest robot loaded now (robots cannot be loaded while serving).
+prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
+    const prrtc_plan_params& p = S.params;
+    const PlanShape& shape = *plan_shape(p.tile);
+    int dof_max = 0, stage_max = 1;
+    size_t lds = 0;
+    for (const RobotRec& r : ctx->robots) {
+        if (!r.dev_args) continue;
+        const int sc = stage_cap_for(r.args, p.delta);
+        if (sc < 0) return fail(ctx, PRRTC_E_ARG, "delta too small for a loaded robot's joint range");
+        dof_max = std::max(dof_max, r.dof);
+        stage_max = std::max(stage_max, sc);
+        lds = std::max(lds, plan_lds_bytes(r.args, sc, r.dof, shape.tile));
+    }
+    if (dof_max == 0) return fail(ctx, PRRTC_E_STATE, "load the robots before serving");
+    S.W = p.workers;
+    S.tree_cap = p.tree_capacity;
+    S.L = group_layout(dof_max, p.tree_capacity, S.W, stage_max);
+    S.lds = lds;
+    S.kernel = shape.serve;
+    S.ring = std::min(kServeRingMax, std::max(32, 16 * S.slots));
+    S.path_stride = S.path_cap * dof_max;
+    int per_cu = 0;
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.serve, kWave * shape.waves, lds));
+    int G = per_cu * ctx->n_cu / S.W;
+    if (G < 1) return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once", S.W);
+    const size_t R = (size_t)S.ring;
+    const size_t o_args = align_up<int>(0);
+    const size_t o_ctl = align_up<int>(o_args + sizeof(PlanArgs) * R);
+    const size_t o_path = align_up<int>(o_ctl + sizeof(int) * kCtlWords * R);
+    const size_t o_next = align_up<int>(o_path + sizeof(float) * S.path_stride * R);
+    const size_t o_sa = align_up<int>(o_next + 256);
+    const size_t ring_bytes = align_up<int>(o_sa + sizeof(ServeArgs));
+    if (S.budget > 0) {
+        const long long fit = (S.budget - (long long)ring_bytes) / (long long)S.L.bytes;
+        if (fit < 1) return fail(ctx, PRRTC_E_CAPACITY, "memory budget below one worker group");
+        G = (int)std::min<long long>(G, fit);
+    }
+    G = std::min(G, S.slots);
+    S.groups = G;
+    S.persistent = true;
+    const size_t groups_bytes = align_up<int>((size_t)G * S.L.bytes);
+    PRRTC_HIP(ctx, hipMalloc(&S.dev_mem, groups_bytes + ring_bytes));
+    char* d = static_cast<char*>(S.dev_mem);
+    S.dev_groups = d;
+    char* dr = d + groups_bytes;
+    const size_t h_args = 0;
+    const size_t h_ctl = align_up<int>(h_args + sizeof(PlanArgs) * R);
+    const size_t h_path = align_up<int>(h_ctl + sizeof(int) * (kCtlWords + 1) * R);
+    const size_t h_ctrl = align_up<int>(h_path + sizeof(float) * S.path_stride * R);
+    const size_t host_bytes = h_ctrl + 256;
+    hipError_t e = hipHostMalloc(&S.host_mem, host_bytes, hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        serve_free_persistent(S);
+        return fail(ctx, PRRTC_E_HIP, "serving ring: %s", hipGetErrorString(e));
+    }
+    char* h = static_cast<char*>(S.host_mem);
+    memset(h, 0, host_bytes);
+    S.host_args = reinterpret_cast<PlanArgs*>(h + h_args);
+    S.host_ctl = reinterpret_cast<int*>(h + h_ctl);
+    S.host_path = reinterpret_cast<float*>(h + h_path);
+    S.host_ctrl = reinterpret_cast<int*>(h + h_ctrl);
+    ServeArgs& A = S.sa;
+    A.host_args = S.host_args;
+    A.dev_args = reinterpret_cast<PlanArgs*>(dr + o_args);
+    A.dev_ctl = reinterpret_cast<int*>(dr + o_ctl);
+    A.dev_path = reinterpret_cast<float*>(dr + o_path);
+    A.host_ctl = S.host_ctl;
+    A.host_path = S.host_path;
+    A.published = S.host_ctrl;
+    A.drain = S.host_ctrl + 32;
+    A.next = reinterpret_cast<int*>(dr + o_next);
+    A.bar0 = reinterpret_cast<int*>(d + S.L.bar);
+    A.group_bytes = S.L.bytes;
+    A.idle_ticks = (long long)(kServeIdleMs * ctx->wall_khz);
+    A.cap = S.ring;
+    A.W = S.W;
+    A.path_stride = S.path_stride;
+    S.dev_sa = reinterpret_cast<ServeArgs*>(dr + o_sa);
+    e = hipMemcpy(S.dev_sa, &A, sizeof A, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        serve_free_persistent(S);
+        return fail(ctx, PRRTC_E_HIP, "serving arguments: %s", hipGetErrorString(e));
+    }
+    return PRRTC_OK;
+}
+
 void serve_shutdown(prrtc_ctx* ctx) {
     if (!ctx->server) return;
     {
@@ -1368,6 +1652,11 @@ void serve_shutdown(prrtc_ctx* ctx) {
     }
     ctx->server->cv.notify_all();
     if (ctx->server->th.joinable()) ctx->server->th.join();
+    Server& S = *ctx->server;
+    if (S.persistent) {
+        (void)hipStreamSynchronize(ctx->stream);   // the launch has drained before its buffers go
+        serve_free_persistent(S);
+    }
     ctx->server.reset();
     ctx->serving.store(false);
 }
@@ -1392,11 +1681,16 @@ prrtc_status prrtc_serve_start(prrtc_ctx* ctx, const prrtc_plan_params* params, 
     S->max_pending = max_pending;
     S->budget = memory_budget;
     S->path_cap = path_cap;
+    if (params->sampler == 0 && PRRTC_SERVE_PERSISTENT) {
+        st = serve_setup_persistent(ctx, *S);
+        if (st != PRRTC_OK) return st;
+    }
     ctx->server = std::move(S);
     ctx->serving.store(true);
     try {
-        ctx->server->th = std::thread(serve_loop, ctx);
+        ctx->server->th = std::thread(ctx->server->persistent ? serve_loop_persistent : serve_loop, ctx);
     } catch (...) {
+        serve_free_persistent(*ctx->server);
         ctx->server.reset();
         ctx->serving.store(false);
         return fail(ctx, PRRTC_E_STATE, "cannot start the serving thread");

@@ -545,13 +545,15 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             // One obstacle against the lane's B items.  Returns true when the
             // block (single sub-edge: the whole check) is decided.
             auto test = [&](auto&& hit) -> bool {
-                bool any = false;
+                // one vote per item slot, OR-ed as wave masks (the compares'
+                // own masks, no per-lane boolean to re-vote)
+                unsigned long long votes = 0;
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const bool h = hit(cx[b], cy[b], cz[b], cr[b]);
-                    any |= MULTI ? (h && ck[b] < kmin) : h;
+                    votes |= __ballot(MULTI ? (h && ck[b] < kmin) : h);
                 }
-                if (!__any(any)) return false;
+                if (!votes) return false;
                 if (!MULTI) return true;
                 int mk = 0x7fffffff;
 #pragma unroll

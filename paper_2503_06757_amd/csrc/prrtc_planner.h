@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "prrtc_device.h"
 #include "prrtc_proposal.h"
 
@@ -66,7 +68,7 @@ constexpr int kStOk = 0, kStNoSolution = -5, kStInvalidEndpoint = -4, kStInterna
 // One query of a launch.  Trees, staging, path and barrier words belong to
 // the worker group that runs the query (the pointers name group 0's memory;
 // group g adds g * group_bytes); ctl and out_path belong to the query.
-struct PlanArgs {
+struct alignas(64) PlanArgs {   // whole cache lines: a slot never shares one with its neighbour
     const RobotArgs* R;       // device copies of the robot and scene tables
     const SceneArgs* S;
     float start[kMaxDof], goal[kMaxDof];
@@ -167,7 +169,16 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
 // arrived, workgroup 0 takes the next query index from the launch-wide
 // counter and stores it in bar[kNext] before the release, so every worker
 // reads the same index after the barrier.
-__device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = nullptr) {
+//
+// With `act`, the first wave of workgroup 0 runs act() (all its lanes) once
+// every worker has arrived and before the release, so whatever act writes is
+// visible to every worker after the barrier.
+struct NoAct {
+    __device__ void operator()() const {}
+};
+
+template <class Act = NoAct>
+__device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = nullptr, const Act& act = Act()) {
 #if PRRTC_FLAG_BARRIER
     __shared__ int ok_s;
     __syncthreads();
@@ -197,6 +208,10 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
             }
         }
         __atomic_thread_fence(__ATOMIC_ACQUIRE);   // the flags' release stores happen before what follows
+        if (ok) {
+            act();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
         if (ok && threadIdx.x == 0) {
             if (next)
                 __hip_atomic_store(bar + kNext,
@@ -228,10 +243,12 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
     __syncthreads();
     return ok_s != 0;
 #else
-    (void)w;
     if (next && w == 0 && threadIdx.x == 0)   // before arriving: nobody reads it until the release
         __hip_atomic_store(bar + kNext, __hip_atomic_fetch_add(next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_barrier(bar, nblocks)) return false;
+    if (std::is_same<Act, NoAct>::value) return true;
+    if (w == 0 && threadIdx.x < kWave) act();   // everyone has arrived; a second barrier publishes it
     return grid_barrier(bar, nblocks);
 #endif
 }
@@ -709,6 +726,108 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
         }
         if (k >= n_queries) break;
         if (!plan_query<TP, B, NW>(((CPlanArgs*)Pq)[k], w, lds4, goff) || !handed_out) break;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Persistent serving launch: queries are published while the kernel runs.
+// The host writes query k's arguments into host memory (host_args[k]) and then
+// raises *published past k; a group claims the next published index at its
+// fetch barrier, copies the arguments into device memory (dev_args[k], read
+// through the constant address space like a batch launch's) and plans it.  At
+// its next fetch barrier the group copies the finished query's words and path
+// into host memory (host_ctl[k], host_path[k]) and raises host_ctl[k][0].  A
+// slot is written once per launch, so no cache holds an older copy of it.  The
+// kernel ends when *drain is set and nothing is left to claim, or after
+// idle_ticks of the wall clock with nothing to claim.
+// ----------------------------------------------------------------------------
+struct ServeArgs {
+    const PlanArgs* host_args;    // [cap] host memory
+    PlanArgs* dev_args;           // [cap]
+    int* dev_ctl;                 // [cap][kCtlWords]
+    float* dev_path;              // [cap][path_stride]
+    int* host_ctl;                // [cap][kCtlWords + 1]: done flag, then the query's words
+    float* host_path;             // [cap][path_stride]
+    const int* published;         // host memory: queries published so far this launch
+    const int* drain;             // host memory: 1 = leave once nothing is left to claim
+    int* next;                    // device: claim counter
+    int* bar0;                    // group 0's barrier words
+    unsigned long long group_bytes;
+    long long idle_ticks;
+    int cap, W, path_stride, pad;
+};
+
+typedef __attribute__((address_space(4))) const ServeArgs CServeArgs;
+
+template <int TP, int B, int NW, int WPE>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE))) void k_serve(
+    const ServeArgs* __restrict__ SAp) {
+    extern __shared__ float4 lds4[];
+    CServeArgs& SA = *(CServeArgs*)SAp;
+    const int W = SA.W;
+    const int g = blockIdx.x / W;
+    const int w = blockIdx.x - g * W;
+    const unsigned long long goff = (unsigned long long)g * SA.group_bytes;
+    int* bar = moved(SA.bar0, goff);
+    int prev = -1;
+    for (;;) {
+        // first wave of workgroup 0, everyone arrived: hand back the previous
+        // query, claim the next, stage its arguments and words
+        auto act = [&]() {
+            const int lane = threadIdx.x & (kWave - 1);
+            if (prev >= 0) {
+                const int* c = SA.dev_ctl + (size_t)prev * kCtlWords;
+                int* hc = SA.host_ctl + (size_t)prev * (kCtlWords + 1);
+                if (lane < kCtlWords) hc[1 + lane] = __hip_atomic_load(c + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int len = c[kPathLen];
+                const int dof = SA.dev_args[prev].R->dof;
+                if (c[kStatus] == kStOk && len * dof <= SA.path_stride) {
+                    const float* src = SA.dev_path + (size_t)prev * SA.path_stride;
+                    float* dst = SA.host_path + (size_t)prev * SA.path_stride;
+                    for (int e = lane; e < len * dof; e += kWave) dst[e] = src[e];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // system scope: the host reads these
+                if (lane == 0) __hip_atomic_store(hc, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            int k = -1;
+            if (lane == 0) {
+                const unsigned long long t0 = wall_clock64();
+                for (;;) {
+                    const int pub = __hip_atomic_load(SA.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    const int n = __hip_atomic_load(SA.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (n < pub && n < SA.cap) {
+                        int want = n;
+                        if (__hip_atomic_compare_exchange_strong(SA.next, &want, n + 1, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            k = n;
+                            break;
+                        }
+                        continue;
+                    }
+                    if (__hip_atomic_load(SA.drain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                    if ((long long)(wall_clock64() - t0) > SA.idle_ticks) break;
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            k = __shfl(k, 0, kWave);
+            if (k >= 0) {
+                // the host's copy of the arguments, then fresh query words
+                const int* src = reinterpret_cast<const int*>(SA.host_args + k);
+                int* dst = reinterpret_cast<int*>(SA.dev_args + k);
+                constexpr int kWords = (int)(sizeof(PlanArgs) / sizeof(int));
+                for (int e = lane; e < kWords; e += kWave)
+                    dst[e] = __hip_atomic_load(src + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                int* c = SA.dev_ctl + (size_t)k * kCtlWords;
+                if (lane < kCtlWords) c[lane] = lane == kStatus ? kStInternal : 0;
+            }
+            if (lane == 0) __hip_atomic_store(bar + kNext, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        if (!group_barrier(bar, w, W, nullptr, act)) break;
+        const int k = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(bar + kNext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (k < 0) break;
+        prev = k;
+        if (!plan_query<TP, B, NW>(((CPlanArgs*)SA.dev_args)[k], w, lds4, goff)) break;
     }
 }
 

@@ -165,6 +165,44 @@ def test_serving_submit_poll(gpu, mixed):
             assert np.array_equal(path, path1)
 
 
+def test_serving_ring_drains_and_relaunches(gpu, mixed):
+    """A uniform-sampling server plans in one persistent launch whose ring
+    holds 16 x slots queries (at least 32); more submissions than that make
+    the launch drain and a new one start on the reset ring.  Every result
+    still equals the single-launch plan, whichever launch ran it."""
+    import time
+    P, ctx, _ = gpu
+    say("serving: ring drain and relaunch")
+    prm = params(P, workers=32, max_rounds=300)
+    qs = [mixed[i % len(mixed)][:4] + (500 + i, i % 3) for i in range(3 * 32 + 7)]
+    P.prrtc_serve_start(ctx, prm, slots=2, max_pending=len(qs), memory_budget=0, path_cap=512)
+    try:
+        tickets = [P.prrtc_submit(ctx, *q) for q in qs]
+        assert all(t is not None for t in tickets)
+        got = {}
+        t0 = time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 120:
+            for t, q in zip(tickets, qs):
+                if t not in got:
+                    r = P.prrtc_poll(ctx, t, len(q[2]), 512)
+                    if r is not None:
+                        got[t] = r
+            time.sleep(0.001)
+        assert len(got) == len(tickets)
+    finally:
+        launches = P.prrtc_serve_stop(ctx)
+    say("  launches", launches)
+    assert launches >= 4
+    for t, q in list(zip(tickets, qs))[::5]:
+        st, path, stats = got[t]
+        st1, path1, stats1 = _single(P, ctx, q, params(P, workers=32, max_rounds=300))
+        assert st == st1
+        for key in KEYS:
+            assert stats[key] == stats1[key], key
+        if st == 0:
+            assert np.array_equal(path, path1)
+
+
 def test_tune_launch_and_tiles(gpu, mixed):
     """The tuner returns the fastest (workers, tile) pair; the FK tile changes
     only speed: every query plans identically with tile 16 and tile 64."""
