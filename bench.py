@@ -465,7 +465,7 @@ def main():
     ap.add_argument("--learned-eval", type=int, default=300, help="held-out scenes")
     ap.add_argument("--learned-epochs", type=int, default=16)
     ap.add_argument("--skip-serve", action="store_true", help="omit the batched / served planner legs")
-    ap.add_argument("--serve-queries", type=int, default=4000)
+    ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
