@@ -605,11 +605,20 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     PRRTC_NOT_SERVING(ctx);
     if (!scene_id || n < 0 || n > PRRTC_MAX_PRIMS || (n > 0 && !p))
         return fail(ctx, PRRTC_E_ARG, "bad scene arguments (n must be in 0..%d)", PRRTC_MAX_PRIMS);
-    std::vector<float4> sph, sph_b, box_b, cyl_b;
+    std::vector<float4> sph, sph_b, box_b, cyl_b, box_e, cyl_e;
     std::vector<float> box, cyl;
     const float margin = 1e-4f;
     auto bound = [&](const prrtc_prim& q, double rad) {
         return make_float4(q.c[0], q.c[1], q.c[2], (float)(rad * (1.0 + 1e-6)) + margin);
+    };
+    // A world-axis box is worth its extra test when it is much thinner than
+    // the bounding sphere along some axis (boards, rods): counted per type,
+    // and the boxes are used for a type when a quarter of it is so.
+    int box_thin = 0, cyl_thin = 0;
+    auto extent = [&](const double* e, double rad, int& thin) {
+        if (std::min(e[0], std::min(e[1], e[2])) < 0.5 * rad) ++thin;
+        return make_float4((float)(e[0] * (1.0 + 1e-6)) + margin, (float)(e[1] * (1.0 + 1e-6)) + margin,
+                           (float)(e[2] * (1.0 + 1e-6)) + margin, 0.0f);
     };
     for (int i = 0; i < n; ++i) {
         const prrtc_prim& q = p[i];
@@ -635,14 +644,29 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
                                        q.rot[2], q.rot[5], q.rot[8],
                                        q.dims[0], q.dims[1], q.dims[2]};
                 box.insert(box.end(), rec, rec + 16);
-                box_b.push_back(bound(q, std::sqrt((double)q.dims[0] * q.dims[0] + (double)q.dims[1] * q.dims[1] +
-                                                   (double)q.dims[2] * q.dims[2])));
+                const double rad = std::sqrt((double)q.dims[0] * q.dims[0] + (double)q.dims[1] * q.dims[1] +
+                                             (double)q.dims[2] * q.dims[2]);
+                box_b.push_back(bound(q, rad));
+                // world half-size along axis i: sum over k of |axis_k[i]| h_k
+                double e[3];
+                for (int i = 0; i < 3; ++i)
+                    e[i] = std::fabs((double)q.rot[3 * i]) * q.dims[0] + std::fabs((double)q.rot[3 * i + 1]) * q.dims[1] +
+                           std::fabs((double)q.rot[3 * i + 2]) * q.dims[2];
+                box_e.push_back(extent(e, rad, box_thin));
             } else {
                 if (!(q.dims[0] > 0.0f && q.dims[1] > 0.0f))
                     return fail(ctx, PRRTC_E_ARG, "primitive %d: cylinder radius/half-height <= 0", i);
                 const float rec[8] = {q.c[0], q.c[1], q.c[2], q.rot[2], q.rot[5], q.rot[8], q.dims[0], q.dims[1]};
                 cyl.insert(cyl.end(), rec, rec + 8);
-                cyl_b.push_back(bound(q, std::sqrt((double)q.dims[0] * q.dims[0] + (double)q.dims[1] * q.dims[1])));
+                const double rad = std::sqrt((double)q.dims[0] * q.dims[0] + (double)q.dims[1] * q.dims[1]);
+                cyl_b.push_back(bound(q, rad));
+                // along world axis i: |a_i| h + r sqrt(1 - a_i^2) (the end discs' reach)
+                double e[3];
+                for (int i = 0; i < 3; ++i) {
+                    const double a = q.rot[3 * i + 2];
+                    e[i] = std::fabs(a) * q.dims[1] + q.dims[0] * std::sqrt(std::max(0.0, 1.0 - a * a));
+                }
+                cyl_e.push_back(extent(e, rad, cyl_thin));
             }
         } else {
             return fail(ctx, PRRTC_E_ARG, "primitive %d: unknown type %d", i, q.type);
@@ -654,7 +678,9 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     const size_t o_sb = align_up<int>(o_cyl + sizeof(float) * cyl.size());
     const size_t o_bb = align_up<int>(o_sb + sizeof(float4) * sph_b.size());
     const size_t o_cb = align_up<int>(o_bb + sizeof(float4) * box_b.size());
-    const size_t bytes = std::max<size_t>(256, align_up<int>(o_cb + sizeof(float4) * cyl_b.size()));
+    const size_t o_be = align_up<int>(o_cb + sizeof(float4) * cyl_b.size());
+    const size_t o_ce = align_up<int>(o_be + sizeof(float4) * box_e.size());
+    const size_t bytes = std::max<size_t>(256, align_up<int>(o_ce + sizeof(float4) * cyl_e.size()));
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     SceneRec rec;
     PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
@@ -665,6 +691,8 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     if (!sph_b.empty()) memcpy(host.data() + o_sb, sph_b.data(), sizeof(float4) * sph_b.size());
     if (!box_b.empty()) memcpy(host.data() + o_bb, box_b.data(), sizeof(float4) * box_b.size());
     if (!cyl_b.empty()) memcpy(host.data() + o_cb, cyl_b.data(), sizeof(float4) * cyl_b.size());
+    if (!box_e.empty()) memcpy(host.data() + o_be, box_e.data(), sizeof(float4) * box_e.size());
+    if (!cyl_e.empty()) memcpy(host.data() + o_ce, cyl_e.data(), sizeof(float4) * cyl_e.size());
     hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(rec.mem);
@@ -680,6 +708,10 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     rec.args.sph_bnd = reinterpret_cast<const float4*>(base + o_sb);
     rec.args.box_bnd = reinterpret_cast<const float4*>(base + o_bb);
     rec.args.cyl_bnd = reinterpret_cast<const float4*>(base + o_cb);
+    rec.args.box_ext = 4 * box_thin >= (int)box_e.size() && box_thin > 0 ? reinterpret_cast<const float4*>(base + o_be)
+                                                                         : nullptr;
+    rec.args.cyl_ext = 4 * cyl_thin >= (int)cyl_e.size() && cyl_thin > 0 ? reinterpret_cast<const float4*>(base + o_ce)
+                                                                         : nullptr;
     rec.n = n;
     e = hipMalloc(&rec.dev_args, sizeof(SceneArgs));
     if (e == hipSuccess) e = hipMemcpy(rec.dev_args, &rec.args, sizeof(SceneArgs), hipMemcpyHostToDevice);

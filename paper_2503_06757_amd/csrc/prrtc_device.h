@@ -29,6 +29,9 @@ constexpr int kWave = 64;
 #ifndef PRRTC_ITEM_ORDER
 #define PRRTC_ITEM_ORDER 1  // 0: configuration-major items, 1: sphere-major
 #endif
+#ifndef PRRTC_EXT_CULL
+#define PRRTC_EXT_CULL 1    // cuboids and cylinders also culled by their world-axis box
+#endif
 #ifndef PRRTC_CULL
 #define PRRTC_CULL 1        // block bounding-box culling of obstacles
 #endif
@@ -66,6 +69,9 @@ struct RobotArgs {
 //        axis_k . p - axis_k . c, three FMAs each)
 //   cyl: 8 floats: c(3), unit axis(3), R, half-height
 //   *_bnd: bounding sphere of each primitive, (centre, radius + 1e-4 m)
+//   *_ext: half-sizes of the world-axis bounding box of each cuboid and
+//          cylinder around the same centre (+ 1e-4 m), w unused; null when
+//          these boxes would cull little beyond the bounding spheres
 struct SceneArgs {
     int n_sph, n_box, n_cyl;
     const float4* sph;
@@ -74,6 +80,8 @@ struct SceneArgs {
     const float4* sph_bnd;
     const float4* box_bnd;
     const float4* cyl_bnd;
+    const float4* box_ext;
+    const float4* cyl_ext;
 };
 
 // ----------------------------------------------------------------------------
@@ -583,11 +591,22 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             lx = wave_min_f(lx); ly = wave_min_f(ly); lz = wave_min_f(lz);
             hx = wave_max_f(hx); hy = wave_max_f(hy); hz = wave_max_f(hz);
             bool done = false;
-            auto sweep = [&](int n, const float4* bnd, float4 first, auto&& exact) {
+            // Cuboids and cylinders must also reach the block's box with
+            // their own world-axis box (far tighter than the bounding
+            // sphere for flat or long ones, such as shelf boards).
+            auto sweep = [&](int n, const float4* bnd, float4 first, const float4* ext, auto&& exact) {
                 for (int c0 = 0; c0 < n && !done; c0 += kWave) {
                     const int o = c0 + lane;
                     bool keep = false;
-                    if (o < n) keep = sphere_meets_box(c0 == 0 ? first : bnd[o], lx, ly, lz, hx, hy, hz);
+                    if (o < n) {
+                        const float4 b = c0 == 0 ? first : bnd[o];
+                        keep = sphere_meets_box(b, lx, ly, lz, hx, hy, hz);
+                        if (ext && keep) {
+                            const float4 e = ext[o];
+                            keep = b.x - e.x <= hx && b.x + e.x >= lx && b.y - e.y <= hy && b.y + e.y >= ly &&
+                                   b.z - e.z <= hz && b.z + e.z >= lz;
+                        }
+                    }
                     unsigned long long m = __ballot(keep);
                     while (m && !done) {
                         const int oi = c0 + (int)__builtin_ctzll(m);
@@ -596,15 +615,12 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     }
                 }
             };
-            sweep(S.n_sph, S.sph_bnd, ws.bnd_sph, [&](float x, float y, float z, float r, int oi) {
-                return hit_sphere(x, y, z, r, ld_sph(S, oi));
-            });
-            sweep(S.n_box, S.box_bnd, ws.bnd_box, [&](float x, float y, float z, float r, int oi) {
-                return hit_box(x, y, z, r, ld_box(S, oi));
-            });
-            sweep(S.n_cyl, S.cyl_bnd, ws.bnd_cyl, [&](float x, float y, float z, float r, int oi) {
-                return hit_cyl(x, y, z, r, ld_cyl(S, oi));
-            });
+            sweep(S.n_sph, S.sph_bnd, ws.bnd_sph, (const float4*)nullptr,
+                  [&](float x, float y, float z, float r, int oi) { return hit_sphere(x, y, z, r, ld_sph(S, oi)); });
+            sweep(S.n_box, S.box_bnd, ws.bnd_box, PRRTC_EXT_CULL ? S.box_ext : nullptr,
+                  [&](float x, float y, float z, float r, int oi) { return hit_box(x, y, z, r, ld_box(S, oi)); });
+            sweep(S.n_cyl, S.cyl_bnd, ws.bnd_cyl, PRRTC_EXT_CULL ? S.cyl_ext : nullptr,
+                  [&](float x, float y, float z, float r, int oi) { return hit_cyl(x, y, z, r, ld_cyl(S, oi)); });
 #else
             // obstacles in groups of U between ballots (a tail group re-tests
             // its last obstacle, which cannot change the verdict)
