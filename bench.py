@@ -85,6 +85,10 @@ def load_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
+EDGE_SCHEDULES = {0: "k_check_edges<16, 3, false>: 3 items per lane, spheres swept first",
+                  1: "k_check_edges<16, 2, true>: 2 items per lane, cuboids swept first"}
+
+
 def edge_counts(a, b, res):
     """Points per edge for the FLOP model (FP32, as the kernel decides it)."""
     d = (b - a).astype(np.float32)
@@ -110,8 +114,9 @@ def bench_check_edges(P, ctx, torch, steps, warmup):
                             stream.cuda_stream)
 
     for _ in range(warmup):
-        step()
+        step()          # the first call also times the two kernel schedules on this pair
     torch.cuda.synchronize()
+    schedule = P.prrtc_edge_schedule(ctx, rid, sid)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for e0, e1 in evs:
@@ -128,7 +133,7 @@ def bench_check_edges(P, ctx, torch, steps, warmup):
     # of every collision-free edge in full; colliding edges counted as zero.
     alg_flop = float(np.sum(n_pts[valid])) * fl_point
     dense_flop = float(np.sum(n_pts)) * fl_point
-    return dict(robot=robot, prims=prims, a=a, b=b, wall_s=t1 - t0, kernel_ms=kernel_ms,
+    return dict(robot=robot, prims=prims, a=a, b=b, wall_s=t1 - t0, kernel_ms=kernel_ms, schedule=schedule,
                 valid_frac=float(valid.mean()), alg_flop=alg_flop, dense_flop=dense_flop,
                 flop_per_point=fl_point, mean_points=float(n_pts.mean()))
 
@@ -537,6 +542,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": load_traffic("k_check_edges", "r7_s64_2p20"),
                      "kernel": "k_check_edges", "kernel_ms": ce["kernel_ms"],
+                     "schedule": EDGE_SCHEDULES.get(ce["schedule"], "none"),
                      "flop_per_launch": ce["alg_flop"], "flop_per_point": ce["flop_per_point"]},
         "ms_to_solution": plan,
         "ms_to_solution_r14_shelf": shelf,

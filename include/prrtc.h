@@ -126,10 +126,22 @@ prrtc_status prrtc_unload_scene(prrtc_ctx *ctx, int32_t scene_id);
  *         synchronised.  n_edges = 0 is a no-op.  Launches on one context
  *         draw from a ring of 256 work counters, so at most 256 launches of
  *         one context may be in flight at once.
+ *
+ * Two kernel schedules give the same verdicts at different speeds (items
+ * per lane, order of the obstacle types).  The first batch of at least 8192
+ * edges on a (robot, scene) pair times both on its first 65536 edges and
+ * keeps the faster for that pair; that one call waits for the stream.
  */
 prrtc_status prrtc_check_edges(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id,
                                const float *a, const float *b, int64_t n_edges, float res,
                                uint8_t *valid, void *stream);
+
+/* The check_edges schedule of a (robot, scene) pair: set = 0 or 1 pins that
+ * schedule, -1 forgets the choice (the next large batch times both again),
+ * -2 changes nothing.  *schedule (may be NULL) = the schedule in force
+ * after the call, -1 while none is chosen.  E_ARG for another set value. */
+prrtc_status prrtc_edge_schedule(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, int32_t set,
+                                 int32_t *schedule);
 
 /*
  * Test hook: world-frame sphere centres of every configuration (FK only).

@@ -443,12 +443,15 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
 // With n_chunks > 1 (one sub-edge only) the points i_first..n are split into
 // n_chunks equal runs and only run `chunk` is checked.
 //
+// BOX_FIRST: cuboids are swept before spheres (the first hit ends the
+// check, so the order only changes the time; check_edges picks it by timing).
+//
 // NW > 1: the NW waves of a workgroup check together.  Every wave runs the
 // same tile loop; the tile's FK is split into TP / NW configurations per
 // wave, its item blocks are dealt to the waves in turn, and at the end of
 // the tile the waves' results meet in LDS (ws.shared[0]: least colliding
 // sub-edge; ws.shared[1]: a wave found a hit, single sub-edge).
-template <int TP, int B, bool MULTI, int NW = 1>
+template <int TP, int B, bool MULTI, int NW = 1, bool BOX_FIRST = false>
 __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
                           int i_first, float res, const WaveWs& ws, int chunk = 0, int n_chunks = 1) {
     static_assert(TP >= 1 && TP <= kWave, "one configuration per lane in the FK tile");
@@ -615,12 +618,26 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     }
                 }
             };
-            sweep(S.n_sph, S.sph_bnd, ws.bnd_sph, (const float4*)nullptr,
-                  [&](float x, float y, float z, float r, int oi) { return hit_sphere(x, y, z, r, ld_sph(S, oi)); });
-            sweep(S.n_box, S.box_bnd, ws.bnd_box, PRRTC_EXT_CULL ? S.box_ext : nullptr,
-                  [&](float x, float y, float z, float r, int oi) { return hit_box(x, y, z, r, ld_box(S, oi)); });
-            sweep(S.n_cyl, S.cyl_bnd, ws.bnd_cyl, PRRTC_EXT_CULL ? S.cyl_ext : nullptr,
-                  [&](float x, float y, float z, float r, int oi) { return hit_cyl(x, y, z, r, ld_cyl(S, oi)); });
+            auto sweep_sph = [&]() {
+                sweep(S.n_sph, S.sph_bnd, ws.bnd_sph, (const float4*)nullptr,
+                      [&](float x, float y, float z, float r, int oi) { return hit_sphere(x, y, z, r, ld_sph(S, oi)); });
+            };
+            auto sweep_box = [&]() {
+                sweep(S.n_box, S.box_bnd, ws.bnd_box, PRRTC_EXT_CULL ? S.box_ext : nullptr,
+                      [&](float x, float y, float z, float r, int oi) { return hit_box(x, y, z, r, ld_box(S, oi)); });
+            };
+            auto sweep_cyl = [&]() {
+                sweep(S.n_cyl, S.cyl_bnd, ws.bnd_cyl, PRRTC_EXT_CULL ? S.cyl_ext : nullptr,
+                      [&](float x, float y, float z, float r, int oi) { return hit_cyl(x, y, z, r, ld_cyl(S, oi)); });
+            };
+            if (BOX_FIRST) {
+                sweep_box();
+                sweep_sph();
+            } else {
+                sweep_sph();
+                sweep_box();
+            }
+            sweep_cyl();
 #else
             // obstacles in groups of U between ballots (a tail group re-tests
             // its last obstacle, which cannot change the verdict)

@@ -139,6 +139,8 @@ def _load():
     L.prrtc_unload_scene.restype = I32
     L.prrtc_check_edges.argtypes = [P, I32, I32, VP, VP, I64, F, VP, VP]
     L.prrtc_check_edges.restype = I32
+    L.prrtc_edge_schedule.argtypes = [P, I32, I32, I32, C.POINTER(I32)]
+    L.prrtc_edge_schedule.restype = I32
     L.prrtc_fk_spheres.argtypes = [P, I32, VP, I64, VP, VP]
     L.prrtc_fk_spheres.restype = I32
     L.prrtc_load_proposal.argtypes = [P, VP, C.c_size_t, C.POINTER(I32)]
@@ -181,7 +183,7 @@ lib = _load()
 
 # the symbols include/prrtc.h declares (checked by the CPU test-suite)
 EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
-            "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_fk_spheres",
+            "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_edge_schedule", "prrtc_fk_spheres",
             "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_launch",
             "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
             "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_sample", "prrtc_train_proposal")
@@ -264,6 +266,14 @@ def prrtc_check_edges(ctx: int, robot_id: int, scene_id: int, a_dev: int, b_dev:
                       res: float, valid_dev: int, stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_check_edges(ctx, robot_id, scene_id, a_dev, b_dev, int(n_edges),
                                              float(res), valid_dev, stream))
+
+
+def prrtc_edge_schedule(ctx: int, robot_id: int, scene_id: int, set: int = -2) -> int:
+    """Pin (0/1), forget (-1) or only read (-2) the check_edges schedule of a
+    (robot, scene) pair; returns the schedule in force (-1: none chosen)."""
+    out = C.c_int32(0)
+    _check(ctx, lib.prrtc_edge_schedule(ctx, int(robot_id), int(scene_id), int(set), C.byref(out)))
+    return out.value
 
 
 def prrtc_fk_spheres(ctx: int, robot_id: int, q_dev: int, n: int, xyz_dev: int,

@@ -72,6 +72,32 @@ def test_check_edges_parity_s12_s64(gpu, orc, r7):
         say("  valid frac %.4f flagged %d" % (v.mean(), f.sum()))
 
 
+def test_check_edges_schedules_agree(gpu, orc, r7, r14):
+    """Both check_edges schedules (items per lane, obstacle-type order) give
+    the oracle's verdicts on the same batch; the timed choice on the first
+    large batch picks one of them and changes no verdict."""
+    P, ctx, _ = gpu
+    for robot, prims, name in ((r7, W.scene_s64(r7), "R7 S64"), (r14, W.scene_shelf(r14), "R14 shelf")):
+        rid, sid = P.prrtc_load_robot(ctx, robot), P.prrtc_load_scene(ctx, prims)
+        a, b = W.random_edges(robot, 12011, seed=4321)
+        say("check_edges schedules", name, a.shape)
+        assert P.prrtc_edge_schedule(ctx, rid, sid) == -1          # nothing chosen yet
+        outs = []
+        for k in (0, 1):
+            assert P.prrtc_edge_schedule(ctx, rid, sid, k) == k
+            outs.append(gpu_check(gpu, rid, sid, a, b))
+        assert np.array_equal(outs[0], outs[1])
+        assert_parity(orc, robot, prims, a, b, outs[0])
+        assert P.prrtc_edge_schedule(ctx, rid, sid, -1) == -1
+        got = gpu_check(gpu, rid, sid, a, b)                      # >= 8192 edges: times both
+        chosen = P.prrtc_edge_schedule(ctx, rid, sid)
+        say("  timed choice", chosen)
+        assert chosen in (0, 1)
+        assert np.array_equal(got, outs[0])
+        with pytest.raises(P.PrrtcError):
+            P.prrtc_edge_schedule(ctx, rid, sid, 2)
+
+
 def test_check_edges_parity_r14_shelf(gpu, orc, r14):
     P, ctx, _ = gpu
     rid = P.prrtc_load_robot(ctx, r14)
