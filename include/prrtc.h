@@ -129,8 +129,9 @@ prrtc_status prrtc_unload_scene(prrtc_ctx *ctx, int32_t scene_id);
  *
  * Two kernel schedules give the same verdicts at different speeds (items
  * per lane, order of the obstacle types).  The first batch of at least 8192
- * edges on a (robot, scene) pair times both on its first 65536 edges and
- * keeps the faster for that pair; that one call waits for the stream.
+ * edges on a (robot, scene) pair times both on its first 2^20 edges (all of
+ * a smaller batch) and keeps the faster for that pair; that one call waits
+ * for the stream.
  */
 prrtc_status prrtc_check_edges(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id,
                                const float *a, const float *b, int64_t n_edges, float res,

@@ -766,8 +766,9 @@ const void* edge_kernel(int schedule) {
                                reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true>)};
     return k[schedule];
 }
-constexpr long long kEdgeTuneMin = 8192;    // batches at least this large pick the schedule
-constexpr long long kEdgeTuneEdges = 65536; // edges timed per schedule
+constexpr long long kEdgeTuneMin = 8192;      // batches at least this large pick the schedule
+constexpr long long kEdgeTuneEdges = 1 << 20;  // edges timed per schedule (at most): small prefixes
+                                               // mostly time the launch's tail, not the schedule
 
 size_t sphere_lds_bytes(const RobotArgs& R) {
     return sizeof(float4) * R.n_move + sizeof(int) * ((R.n_move + 3) & ~3);
@@ -836,15 +837,15 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
     auto it = sr.edge_schedule.find(robot_id);
     int schedule = it == sr.edge_schedule.end() ? 0 : it->second;
     if (it == sr.edge_schedule.end() && n_edges >= kEdgeTuneMin) {
-        // time both schedules on a prefix of this batch (its verdicts are
-        // written again by the full launch below); synchronises this once
+        // time both schedules on (a prefix of) this batch; its verdicts are
+        // written again by the launch below.  Synchronises this once.
         const long long m = std::min<long long>(n_edges, kEdgeTuneEdges);
         float best = 0.0f;
         for (int k = 0; k < 2; ++k) {
-            st = launch(k, m);   // warm-up
+            st = launch(k, kEdgeTuneMin);   // warm-up
             if (st != PRRTC_OK) return st;
             PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
-            for (int rep = 0; rep < 2 && st == PRRTC_OK; ++rep) st = launch(k, m);
+            st = launch(k, m);
             if (st != PRRTC_OK) return st;
             PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
             PRRTC_HIP(ctx, hipEventSynchronize(ctx->ev1));
