@@ -1515,6 +1515,8 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
     std::vector<uint64_t> ticket_of(S.ring);
     std::vector<prrtc_query> query_of(S.ring);
     std::vector<char> pending(S.ring, 0);
+    std::vector<int> live;   // published slots whose result has not come back
+    live.reserve(S.slots);
     std::vector<std::chrono::steady_clock::time_point> t_pub(S.ring);
     bool launched = false;
     int pub = 0, n_pending = 0;
@@ -1531,6 +1533,7 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
             pending[k] = 0;
         }
         n_pending = 0;
+        live.clear();
     };
     for (;;) {
         bool busy = false;
@@ -1575,6 +1578,7 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
                 ticket_of[k] = t;
                 query_of[k] = q;
                 pending[k] = 1;
+                live.push_back(k);
                 t_pub[k] = std::chrono::steady_clock::now();
                 ++n_pending;
                 S.running[t] = 1;
@@ -1605,15 +1609,20 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
             std::lock_guard<std::mutex> lk(S.mu);
             ++S.launches;
         }
-        // 3. results of queries that have ended
-        for (int k = 0; k < pub && n_pending > 0; ++k) {
-            if (!pending[k]) continue;
-            if (__atomic_load_n(S.host_ctl + (size_t)k * (kCtlWords + 1), __ATOMIC_ACQUIRE) == 0) continue;
+        // 3. results of queries that have ended (only the live slots are scanned)
+        for (size_t i = 0; i < live.size();) {
+            const int k = live[i];
+            if (__atomic_load_n(S.host_ctl + (size_t)k * (kCtlWords + 1), __ATOMIC_ACQUIRE) == 0) {
+                ++i;
+                continue;
+            }
             const double ms =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_pub[k]).count();
             serve_result(ctx, S, ticket_of[k], k, query_of[k], ms);
             pending[k] = 0;
             --n_pending;
+            live[i] = live.back();
+            live.pop_back();
             busy = true;
         }
         // 4. the ring is used up, or the server stops: the launch drains
@@ -1626,7 +1635,7 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
         // 5. the launch has ended (idle, drained or aborted)
         if (launched && hipStreamQuery(ctx->stream) != hipErrorNotReady) {
             (void)hipStreamSynchronize(ctx->stream);
-            for (int k = 0; k < pub && n_pending > 0; ++k)   // results that landed at the end
+            for (int k : live)   // results that landed at the end
                 if (pending[k] && __atomic_load_n(S.host_ctl + (size_t)k * (kCtlWords + 1), __ATOMIC_ACQUIRE)) {
                     serve_result(ctx, S, ticket_of[k], k, query_of[k], 0.0);
                     pending[k] = 0;
@@ -1645,7 +1654,7 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
 #ifndef PRRTC_SERVE_PERSISTENT
 #define PRRTC_SERVE_PERSISTENT 1   // uniform-sampling servers run one persistent launch
 #endif
-constexpr int kServeRingMax = 4096;   // queries per persistent launch before it drains (16 x slots, at most)
+constexpr int kServeRingMax = 16384;  // queries per persistent launch before it drains (64 x slots, at most)
 
 void serve_free_persistent(Server& S) {
     if (S.dev_mem) (void)hipFree(S.dev_mem);
@@ -1675,7 +1684,7 @@ prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
     S.L = group_layout(dof_max, p.tree_capacity, S.W, stage_max);
     S.lds = lds;
     S.kernel = shape.serve;
-    S.ring = std::min(kServeRingMax, std::max(32, 16 * S.slots));
+    S.ring = std::min(kServeRingMax, std::max(32, 64 * S.slots));
     S.path_stride = S.path_cap * dof_max;
     int per_cu = 0;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));

@@ -167,15 +167,15 @@ def test_serving_submit_poll(gpu, mixed):
 
 def test_serving_ring_drains_and_relaunches(gpu, mixed):
     """A uniform-sampling server plans in one persistent launch whose ring
-    holds 16 x slots queries (at least 32); more submissions than that make
+    holds 64 x slots queries (at least 32); more submissions than that make
     the launch drain and a new one start on the reset ring.  Every result
     still equals the single-launch plan, whichever launch ran it."""
     import time
     P, ctx, _ = gpu
     say("serving: ring drain and relaunch")
     prm = params(P, workers=32, max_rounds=300)
-    qs = [mixed[i % len(mixed)][:4] + (500 + i, i % 3) for i in range(3 * 32 + 7)]
-    P.prrtc_serve_start(ctx, prm, slots=2, max_pending=len(qs), memory_budget=0, path_cap=512)
+    qs = [mixed[i % len(mixed)][:4] + (500 + i, i % 3) for i in range(3 * 64 + 7)]
+    P.prrtc_serve_start(ctx, prm, slots=1, max_pending=len(qs), memory_budget=0, path_cap=512)
     try:
         tickets = [P.prrtc_submit(ctx, *q) for q in qs]
         assert all(t is not None for t in tickets)
@@ -199,6 +199,45 @@ def test_serving_ring_drains_and_relaunches(gpu, mixed):
         assert st == st1
         for key in KEYS:
             assert stats[key] == stats1[key], key
+        if st == 0:
+            assert np.array_equal(path, path1)
+
+
+def test_serving_learned_equals_single(gpu, mixed):
+    """A learned-sampler server gathers queries into batched launches (the
+    mixture of every query is computed before its launch); each result equals
+    the single learned plan of the same query."""
+    import time
+    P, ctx, _ = gpu
+    say("serving with the learned sampler")
+    mid = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(7, 78), 7))
+    qs = [q for q in mixed if q[2].shape[0] == 7][:8]
+    prm = params(P, workers=64, max_rounds=500, sampler=1, model_id=mid, mix=0.7)
+    P.prrtc_serve_start(ctx, prm, slots=3, max_pending=len(qs), memory_budget=0, path_cap=512)
+    try:
+        tickets = [P.prrtc_submit(ctx, *q) for q in qs]
+        got = {}
+        t0 = time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 60:
+            for t, q in zip(tickets, qs):
+                if t not in got:
+                    r = P.prrtc_poll(ctx, t, len(q[2]), 512)
+                    if r is not None:
+                        got[t] = r
+            time.sleep(0.001)
+        assert len(got) == len(tickets)
+    finally:
+        launches = P.prrtc_serve_stop(ctx)
+    say("  launches", launches)
+    assert launches >= 3    # at most 3 queries per launch
+    for t, q in zip(tickets, qs):
+        st, path, stats = got[t]
+        st1, path1, stats1 = _single(P, ctx, q, params(P, workers=64, max_rounds=500, sampler=1, model_id=mid,
+                                                         mix=0.7))
+        assert st == st1
+        for key in KEYS:
+            assert stats[key] == stats1[key], key
+        assert stats["learned_samples"] > 0
         if st == 0:
             assert np.array_equal(path, path1)
 
