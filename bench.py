@@ -379,7 +379,7 @@ def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
             "plain": cmp["plain"], "learned": cmp["learned"]}
 
 
-def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=SHELF_BUDGET_MS):
+def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=SHELF_BUDGET_MS, tail=1.0):
     """The learned proposal on the dual arm: training queries made with the
     library's FK and checks, paths from the uniform planner (one batched
     launch), a 14-DoF model trained on them, then uniform against learned
@@ -394,7 +394,7 @@ def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=S
     t0 = time.perf_counter()
     starts, goals = PR.shelf_queries(P, ctx, torch, rid, sid, robot, n_train, seed=0x57000000, max_batches=4000,
                                      log=log)
-    ds = PR.shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row)
+    ds = PR.shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, tail=tail)
     gen_s = time.perf_counter() - t0
     log("  shelf training data: %d of %d queries solved, %d samples, %.1f s" % (ds.vox.shape[0], n_train,
                                                                                  len(ds.scene_of), gen_s))
@@ -420,7 +420,7 @@ def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=S
             "samples": int(len(ds.scene_of)), "epochs": epochs, "datagen_s": gen_s,
             "loss_first_epoch": float(losses[0]) if len(losses) else None,
             "loss_last_epoch": float(losses[-1]) if len(losses) else None,
-            "time_budget_ms": budget_ms, "plain": res["plain"], "learned": res["learned"]}
+            "time_budget_ms": budget_ms, "path_tail": tail, "plain": res["plain"], "learned": res["learned"]}
 
 
 def cpu_baseline(ce, budget_s=12.0):
@@ -465,6 +465,8 @@ def main():
     ap.add_argument("--skip-learned-shelf", action="store_true", help="omit the 14-DoF learned-proposal leg")
     ap.add_argument("--learned-shelf-train", type=int, default=1500)
     ap.add_argument("--learned-shelf-eval", type=int, default=500)
+    ap.add_argument("--learned-shelf-tail", type=float, default=1.0,
+                    help="train the shelf proposal on the last fraction of each path only")
     ap.add_argument("--shelf-queries", type=int, default=500, help="stored shelf queries planned (500 in all)")
     ap.add_argument("--learned-scenes", type=int, default=1000, help="training scenes (10000 for the full set)")
     ap.add_argument("--learned-eval", type=int, default=300, help="held-out scenes")
@@ -516,7 +518,7 @@ def main():
     if not args.skip_learned_shelf:
         log("learned proposal, dual-arm shelf")
         learned_shelf = bench_learned_shelf(P, ctx, torch, args.learned_shelf_train, args.learned_shelf_eval,
-                                            args.learned_epochs, log)
+                                            args.learned_epochs, log, tail=args.learned_shelf_tail)
         log("  " + json.dumps(finite_or_null(learned_shelf)))
     ms_per_step = ce["wall_s"] * 1e3 / args.steps
     value = N_EDGES / (ce["wall_s"] / args.steps)

@@ -63,15 +63,18 @@ def unpack(blob: bytes):
     return dof, adam_t, groups
 
 
-def resample_path(path: np.ndarray, step: float = 0.25) -> np.ndarray:
+def resample_path(path: np.ndarray, step: float = 0.25, tail: float = 1.0) -> np.ndarray:
     """Waypoints every `step` rad of arclength along a path, endpoints excluded
-    (training targets)."""
+    (training targets); with tail < 1 only those in the last `tail` fraction
+    of the arclength (the approach to the goal)."""
     p = np.asarray(path, np.float64)
     seg = np.linalg.norm(np.diff(p, axis=0), axis=1)
     cum = np.concatenate([[0.0], np.cumsum(seg)])
     total = cum[-1]
     out = []
     t = step
+    while t < (1.0 - tail) * total:
+        t += step
     while t < total - 1e-9:
         i = min(int(np.searchsorted(cum, t, side="right")) - 1, len(seg) - 1)
         f = (t - cum[i]) / seg[i] if seg[i] > 0 else 0.0
@@ -498,7 +501,8 @@ def shelf_queries(P, ctx, torch, rid, sid, robot, n, seed, max_batches=200, log=
     return np.array(starts[:k], np.float32).reshape(-1, dof), goals[:k]
 
 
-def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, budget_ms=1000.0, seed=0x57000000):
+def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, budget_ms=1000.0, seed=0x57000000,
+                  tail=1.0):
     """Solve the queries with the uniform planner in one batched launch and
     keep the paths' waypoints every 0.25 rad; one voxel row per query (the
     scene is shared)."""
@@ -514,7 +518,7 @@ def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, b
         ds.vox.append(vox_row)
         ds.queries.append((s, g))
         ds.paths.append(path)
-        for w in resample_path(path):
+        for w in resample_path(path, tail=tail):
             ds.scene_of.append(k)
             ds.start.append(s)
             ds.goal.append(g)
