@@ -145,7 +145,8 @@ prrtc_status prrtc_edge_schedule(prrtc_ctx *ctx, int32_t robot_id, int32_t scene
                                  int32_t *schedule);
 
 /*
- * Test hook: world-frame sphere centres of every configuration (FK only).
+ * FK (Sec. III-A): world-frame sphere centres of every configuration, from
+ * the same four-lanes-per-configuration FK the collision checks use.
  * q: device float32 [n][dof]; xyz: device float32 [n][n_spheres][3], in the
  * robot descriptor's sphere order.  Asynchronous on `stream`.
  */

@@ -140,20 +140,29 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
     }
 }
 
-// FK test hook: one lane per configuration, frames staged in LDS.
+// FK entry point: the collision kernels' four-lanes-per-configuration FK
+// (16 configurations per wave, every frame staged in LDS), then one lane per
+// (configuration, sphere).
+constexpr int kFkPerBlock = kWave / 4;
+
 __global__ __launch_bounds__(kWave) void k_fk_spheres(RobotArgs R, const float* __restrict__ q,
                                                       long long n, float* __restrict__ xyz) {
     extern __shared__ float4 lds4[];
-    const long long cfg = (long long)blockIdx.x * kWave + threadIdx.x;
-    if (cfg >= n) return;
-    float4* fr = lds4 + threadIdx.x * 3 * R.n_frames;
-    const float* qc = q + cfg * R.dof;
-    fk_frames<true>(R, [&](int j) { return qc[j]; }, fr);
+    const int lane = threadIdx.x;
+    const long long c0 = (long long)blockIdx.x * kFkPerBlock;
+    const int slot = lane >> 2;
+    if (c0 + slot < n) {   // whole quads
+        const float* qc = q + (c0 + slot) * R.dof;
+        fk_rows<true>(R, [&](int j) { return qc[j]; }, lds4 + slot * 3 * R.n_frames, lane & 3);
+    }
+    __syncthreads();
     const int ns = R.n_move + R.n_static;
-    for (int s = 0; s < ns; ++s) {
+    const int m = (int)min((long long)kFkPerBlock, n - c0);
+    for (int it = lane; it < m * ns; it += kWave) {
+        const int p = it / ns, s = it - p * ns;
         const float4 loc = R.sph[s];
-        const float3 c = frame_apply(fr + 3 * R.sph_frame[s], loc.x, loc.y, loc.z);
-        float* o = xyz + (cfg * ns + R.desc_index[s]) * 3;
+        const float3 c = frame_apply(lds4 + p * 3 * R.n_frames + 3 * R.sph_frame[s], loc.x, loc.y, loc.z);
+        float* o = xyz + ((c0 + p) * ns + R.desc_index[s]) * 3;
         o[0] = c.x;
         o[1] = c.y;
         o[2] = c.z;
@@ -894,8 +903,9 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
     if (!q || !xyz) return fail(ctx, PRRTC_E_ARG, "null buffer");
     hipStream_t sm = static_cast<hipStream_t>(stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    const long long blocks = (n + kWave - 1) / kWave;
-    const size_t lds = sizeof(float4) * kWave * 3 * r->args.n_frames;
+    const long long blocks = (n + kFkPerBlock - 1) / kFkPerBlock;
+    if (blocks > 0x7fffffffLL) return fail(ctx, PRRTC_E_ARG, "n too large for one launch");
+    const size_t lds = sizeof(float4) * kFkPerBlock * 3 * r->args.n_frames;
     hipLaunchKernelGGL(k_fk_spheres, dim3((unsigned)blocks), dim3(kWave), lds, sm, r->args, q, (long long)n, xyz);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;

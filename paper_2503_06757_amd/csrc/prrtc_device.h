@@ -205,8 +205,9 @@ __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
 // the quad (r < 3) carries row r with exactly the arithmetic of fk_frames
 // (bit-identical frames), and the trigonometry is shared: for joints
 // j4..j4+3 of the chain, lane r takes sincos of joint j4 + r and each joint's
-// pair is broadcast from the lane that made it (DPP within the quad).  Stores
-// only slotted frames (3 * slot).  The whole quad must be active.
+// pair is broadcast from the lane that made it (DPP within the quad).  ALL =
+// true stores every frame at 3 * f; otherwise only slotted frames, at
+// 3 * slot.  The whole quad must be active.
 #ifndef PRRTC_FK_QUAD
 #define PRRTC_FK_QUAD 1
 #endif
@@ -216,7 +217,7 @@ __device__ inline float quad_bcast(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), U * 0x55, 0xF, 0xF, false));
 }
 
-template <class QF>
+template <bool ALL, class QF>
 __device__ inline void fk_rows(const RobotArgs& R, QF qf, float4* out, int r) {
     const int rr = r < 3 ? r : 2;   // lane 3 shadows row 2 and stores nothing
     for (int c = 0; c < R.n_chains; ++c) {
@@ -224,7 +225,7 @@ __device__ inline void fk_rows(const RobotArgs& R, QF qf, float4* out, int r) {
         float x = B[0], y = B[1], z = B[2], t = B[3];
         int f = R.chain_f0[c];
         auto store = [&](int fr) {
-            const int at = R.frame_slot[fr];
+            const int at = ALL ? fr : R.frame_slot[fr];
             if (at >= 0 && r < 3) out[3 * at + r] = make_float4(x, y, z, t);
         };
         store(f);
@@ -511,7 +512,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             if (lane % LPC == 0) ws.pk[slot] = k;
             auto qf = [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); };
             if (LPC == 4)
-                fk_rows(R, qf, ws.frames + slot * fstride, lane & 3);
+                fk_rows<false>(R, qf, ws.frames + slot * fstride, lane & 3);
             else
                 fk_frames<false>(R, qf, ws.frames + slot * fstride);
         }
