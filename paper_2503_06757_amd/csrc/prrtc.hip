@@ -1651,6 +1651,20 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
                     pending[k] = 0;
                     --n_pending;
                 }
+            // published after the groups had left (idle) or after an abort,
+            // never claimed: queued again, in order, for the next launch
+            int claimed = pub;
+            if (hipMemcpy(&claimed, S.sa.next, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) claimed = pub;
+            {
+                std::lock_guard<std::mutex> lk(S.mu);
+                for (int k = pub - 1; k >= std::max(claimed, 0); --k) {
+                    if (!pending[k]) continue;
+                    S.queue.emplace_front(ticket_of[k], query_of[k]);
+                    S.running.erase(ticket_of[k]);
+                    pending[k] = 0;
+                    --n_pending;
+                }
+            }
             fail_pending(PRRTC_E_HIP);   // claimed by a group that aborted (as an aborted batch query)
             launched = false;
             pub = 0;

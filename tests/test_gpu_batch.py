@@ -203,6 +203,46 @@ def test_serving_ring_drains_and_relaunches(gpu, mixed):
             assert np.array_equal(path, path1)
 
 
+def test_serving_relaunch_after_idle(gpu, mixed):
+    """The persistent serving launch leaves after 50 ms without work; a later
+    submission starts a new one and is answered like the first."""
+    import time
+    P, ctx, _ = gpu
+    say("serving: idle exit and relaunch")
+    prm = params(P, workers=32, max_rounds=300)
+
+    def run(qs):
+        tickets = [P.prrtc_submit(ctx, *q) for q in qs]
+        got = {}
+        t0 = time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 60:
+            for t, q in zip(tickets, qs):
+                if t not in got:
+                    r = P.prrtc_poll(ctx, t, len(q[2]), 512)
+                    if r is not None:
+                        got[t] = r
+            time.sleep(0.001)
+        assert len(got) == len(tickets)
+        return [got[t] for t in tickets]
+
+    P.prrtc_serve_start(ctx, prm, slots=4, max_pending=16, memory_budget=0, path_cap=512)
+    try:
+        first = run(mixed[:3])
+        time.sleep(0.3)                     # longer than the idle limit: the launch has left
+        second = run(mixed[3:6])
+    finally:
+        launches = P.prrtc_serve_stop(ctx)
+    say("  launches", launches)
+    assert launches >= 2
+    for (st, path, stats), q in zip(first + second, mixed[:6]):
+        st1, path1, stats1 = _single(P, ctx, q, params(P, workers=32, max_rounds=300))
+        assert st == st1
+        for key in KEYS:
+            assert stats[key] == stats1[key], key
+        if st == 0:
+            assert np.array_equal(path, path1)
+
+
 def test_serving_learned_equals_single(gpu, mixed):
     """A learned-sampler server gathers queries into batched launches (the
     mixture of every query is computed before its launch); each result equals
