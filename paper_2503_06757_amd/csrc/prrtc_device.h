@@ -29,9 +29,6 @@ constexpr int kWave = 64;
 #ifndef PRRTC_ITEM_ORDER
 #define PRRTC_ITEM_ORDER 1  // 0: configuration-major items, 1: sphere-major
 #endif
-#ifndef PRRTC_CYL_SECOND
-#define PRRTC_CYL_SECOND 0  // cuboid-first schedule: cylinders before spheres
-#endif
 #ifndef PRRTC_EXT_CULL
 #define PRRTC_EXT_CULL 1    // cuboids and cylinders also culled by their world-axis box
 #endif
@@ -636,18 +633,12 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             };
             if (BOX_FIRST) {
                 sweep_box();
-#if PRRTC_CYL_SECOND
-                sweep_cyl();
                 sweep_sph();
-#else
-                sweep_sph();
-                sweep_cyl();
-#endif
             } else {
                 sweep_sph();
                 sweep_box();
-                sweep_cyl();
             }
+            sweep_cyl();
 #else
             // obstacles in groups of U between ballots (a tail group re-tests
             // its last obstacle, which cannot change the verdict)
