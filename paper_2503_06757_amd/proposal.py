@@ -362,9 +362,6 @@ def main(argv=None):
     P.prrtc_destroy(ctx)
 
 
-if __name__ == "__main__":
-    main()
-
 
 # ---- the dual-arm shelf: queries from the library's own FK and checks, training, comparison -----
 def _valid_configs(P, ctx, torch, rid, sid, q):
@@ -524,3 +521,7 @@ def shelf_dataset(P, ctx, torch, rid, sid, starts, goals, vox_row, workers=64, b
             ds.goal.append(g)
             ds.waypoint.append(w)
     return ds.finish()
+
+
+if __name__ == "__main__":
+    main()
