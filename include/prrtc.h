@@ -282,9 +282,10 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
  * Serving: a thread owned by the context plans submitted queries as they
  * arrive.  With uniform sampling (params->sampler 0) it keeps one persistent
  * launch running: queries are published into a ring of 64 x slots entries
- * (32 to 16384) that the launch's worker groups take from while it runs (at
- * most `slots` in flight), and each result returns as soon as its query
- * ends.  The launch leaves after 50 ms without work and is started again by
+ * (32 to 16384, and within about 256 MiB of pinned host memory for the
+ * entries' arguments and paths) that the launch's worker groups take from
+ * while it runs (at most `slots` in flight), and each result returns as
+ * soon as its query ends.  The launch leaves after 50 ms without work and is started again by
  * the next submission; a used-up ring drains the launch and the next one
  * starts on the reset ring.  Group buffers are sized for the largest robot
  * loaded when serving starts (robots cannot be loaded while serving).  With

@@ -1708,8 +1708,12 @@ prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
     S.L = group_layout(dof_max, p.tree_capacity, S.W, stage_max);
     S.lds = lds;
     S.kernel = shape.serve;
-    S.ring = std::min(kServeRingMax, std::max(32, 64 * S.slots));
     S.path_stride = S.path_cap * dof_max;
+    // ring entries: 64 x slots, at most kServeRingMax and about 256 MiB of
+    // pinned host memory (arguments, words and path of each entry)
+    const size_t entry = sizeof(PlanArgs) + sizeof(int) * (kCtlWords + 1) + sizeof(float) * S.path_stride;
+    const int by_memory = (int)std::max<size_t>(32, (size_t(256) << 20) / entry);
+    S.ring = std::min({kServeRingMax, std::max(32, 64 * S.slots), by_memory});
     int per_cu = 0;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.serve, kWave * shape.waves, lds));
