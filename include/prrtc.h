@@ -215,7 +215,9 @@ void prrtc_plan_params_default(prrtc_plan_params *p);
  * Synchronous.  Returns OK with *path_len nodes written (path[0] == start,
  * path[len-1] == goal bit for bit; every segment no longer than delta);
  * E_CAPACITY if path_cap is too small (then *path_len = nodes needed and
- * nothing is written: call again with a larger buffer);
+ * nothing is written: call again with a larger buffer), or, before any work,
+ * if params->workers workgroups of the chosen tile cannot all be resident on
+ * the device at once (*path_len = 0);
  * E_INVALID_ENDPOINT, E_NO_SOLUTION as documented above.  stats may be NULL.
  */
 prrtc_status prrtc_plan(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, const float *start,

@@ -1172,6 +1172,13 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
     const PlanShape& shape = *plan_shape(p.tile);
     const size_t lds = plan_lds_bytes(r->args, stage_cap, dof, shape.tile);
+    {   // the cooperative launch needs every worker resident at once
+        int per_cu = 0;
+        PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.kernel, kWave * shape.waves, lds));
+        if ((long long)per_cu * ctx->n_cu < W)
+            return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once (%d with tile %d)", W,
+                        per_cu * ctx->n_cu, shape.tile);
+    }
     hipStream_t sm = ctx->stream;
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
     if (p.sampler == 1) {

@@ -183,6 +183,10 @@ def test_plan_status_codes(gpu, orc, r7):
                dict(max_rounds=-1), dict(dds_tries=0), dict(dds_radius=-1.0)):
         with pytest.raises(P.PrrtcError):
             P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
+    # more workers than can be resident at once: refused before any launch
+    st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, workers=4096, tile=64))
+    assert st == P.PRRTC_E_CAPACITY and path is None and stats["path_len"] == 0
+    assert "workers do not fit" in P.prrtc_last_error(ctx)
     # a tiny tree fills up; the planner stops cleanly
     st, _, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, tree_capacity=2, workers=8, max_rounds=20))
     assert st in (0, P.PRRTC_E_NO_SOLUTION) and stats["nodes_a"] <= 2 and stats["nodes_b"] <= 2
