@@ -174,7 +174,8 @@ def bench_plan(P, ctx, n_instances=100, n_seeds=50):
 
     def pct(q):
         # failures count as infinitely slow; a percentile they reach is reported as null
-        v = float(np.percentile(t, q))
+        with np.errstate(invalid="ignore"):   # interpolating between two failures
+            v = float(np.percentile(t, q))
         return v if np.isfinite(v) else None
 
     ok = t[np.isfinite(t)]
@@ -311,7 +312,8 @@ def pcts(t):
     that a failure reaches is reported as null)."""
     out = {}
     for q in (50, 90, 99):
-        v = float(np.percentile(t, q)) if len(t) else float("inf")
+        with np.errstate(invalid="ignore"):   # interpolating between two failures
+            v = float(np.percentile(t, q)) if len(t) else float("inf")
         out["p%d_ms" % q] = v if np.isfinite(v) else None
     return out
 
