@@ -310,7 +310,8 @@ def compare(P, ctx, torch, mid: int, rid: int, robot: dict, n_scenes: int, base:
         t = np.where(ok, a[:, 1], np.inf)
         pct = {}
         for qq in (50, 90, 99):
-            v = float(np.percentile(t, qq)) if len(t) else float("inf")
+            with np.errstate(invalid="ignore"):   # interpolating between two failures
+                v = float(np.percentile(t, qq)) if len(t) else float("inf")
             pct["p%d_ms" % qq] = v if np.isfinite(v) else None
         out[name] = dict(queries=int(len(a)), success=float(ok.mean()) if len(a) else 0.0, **pct,
                          p50_rounds=float(np.median(a[ok, 2])) if ok.any() else None,
