@@ -219,9 +219,10 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
                 budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None):
     """The served workload through the library's serving thread: queries
     arrive as a Poisson stream (exponential gaps) and are submitted at their
-    arrival time (refused submissions are retried: admission); the thread
-    batches whatever is queued into one launch at a time.  Latency =
-    completion seen by polling - arrival, on the host clock."""
+    arrival time (refused submissions are retried: admission); with uniform
+    sampling the thread keeps one persistent launch that takes each query as
+    it is published.  Latency = completion seen by polling - arrival, on the
+    host clock."""
     pool, tried = pool
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_queries))
