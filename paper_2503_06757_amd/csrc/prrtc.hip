@@ -300,6 +300,7 @@ struct prrtc_ctx {
     uint64_t model_stamp = 0;         // last stamp given to a model's parameters
     EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
     unsigned counter_next = 0;
+    std::unordered_map<uint64_t, int> plan_per_cu;   // resident planner workgroups per CU by (tile, LDS bytes)
     int edge_grid[2] = {0, 0};         // resident workgroups of each k_check_edges schedule (cached)
     size_t edge_grid_lds[2] = {0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1172,9 +1173,10 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
     const PlanShape& shape = *plan_shape(p.tile);
     const size_t lds = plan_lds_bytes(r->args, stage_cap, dof, shape.tile);
-    {   // the cooperative launch needs every worker resident at once
-        int per_cu = 0;
-        PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.kernel, kWave * shape.waves, lds));
+    {   // the cooperative launch needs every worker resident at once (cached per shape and LDS size)
+        int& per_cu = ctx->plan_per_cu[((uint64_t)shape.tile << 40) | (uint64_t)lds];
+        if (per_cu == 0)
+            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.kernel, kWave * shape.waves, lds));
         if ((long long)per_cu * ctx->n_cu < W)
             return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once (%d with tile %d)", W,
                         per_cu * ctx->n_cu, shape.tile);
