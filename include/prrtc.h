@@ -296,7 +296,9 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
  * are sized by memory_budget as in prrtc_plan_batch.  Results equal those
  * of prrtc_plan / prrtc_plan_batch for the same query, seed and parameters.
  * While serving, the context accepts only prrtc_submit, prrtc_poll,
- * prrtc_serve_stop and prrtc_last_error (everything else: E_STATE).
+ * prrtc_serve_stop and prrtc_last_error (everything else: E_STATE).  The
+ * serving thread never writes the message prrtc_last_error returns: served
+ * queries report their outcome through their result status only.
  *
  * prrtc_serve_start: params as for prrtc_plan_batch; slots >= 1;
  *   max_pending >= slots bounds the queries admitted and not yet polled;

@@ -307,6 +307,7 @@ struct prrtc_ctx {
     float* pinned = nullptr;           // kPinnedFloats of pinned host staging
     std::unique_ptr<struct Server> server;
     std::atomic<bool> serving{false};  // while set, only submit/poll/serve_stop are accepted
+    std::atomic<std::thread::id> serve_tid{};   // the serving thread: it never writes err
 };
 
 constexpr int kPinnedFloats = 1024;
@@ -315,8 +316,13 @@ constexpr int kCounterSlots = 256;
 
 namespace {
 
+// The message of the caller's last failure.  The serving thread records
+// none: its queries' outcomes come back as statuses, and the user's thread
+// may read the message meanwhile.
+bool records_errors(const prrtc_ctx* ctx) { return ctx && std::this_thread::get_id() != ctx->serve_tid.load(); }
+
 prrtc_status fail(prrtc_ctx* ctx, prrtc_status st, const char* fmt, ...) {
-    if (ctx) {
+    if (records_errors(ctx)) {
         char buf[512];
         va_list ap;
         va_start(ap, fmt);
@@ -1236,7 +1242,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
                                     const prrtc_plan_params* prm, int32_t groups, int64_t memory_budget,
                                     float* paths, int32_t path_cap, prrtc_query_result* results,
                                     int32_t* groups_used) {
-    ctx->err.clear();
+    if (records_errors(ctx)) ctx->err.clear();
     if (groups_used) *groups_used = 0;
     if (n < 0 || !prm || (n > 0 && (!queries || !results)) || path_cap < 0 || (path_cap > 0 && !paths) ||
         groups < 0 || memory_budget < 0)
@@ -1273,7 +1279,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
         stage_max = std::max(stage_max, sc);
         lds = std::max(lds, plan_lds_bytes(r->args, sc, r->dof, plan_shape(p.tile)->tile));
     }
-    ctx->err.clear();
+    if (records_errors(ctx)) ctx->err.clear();
     const int n_live = (int)live.size();
     if (n_live == 0) return PRRTC_OK;
     const GroupLayout L = group_layout(dof_max, cap, W, stage_max);
@@ -1455,6 +1461,7 @@ namespace {
 
 void serve_loop(prrtc_ctx* ctx) {
     Server& S = *ctx->server;
+    ctx->serve_tid.store(std::this_thread::get_id());
     (void)hipSetDevice(ctx->device);
     std::vector<prrtc_query> qs;
     std::vector<uint64_t> tickets;
@@ -1528,6 +1535,7 @@ void serve_result(prrtc_ctx* ctx, Server& S, uint64_t ticket, int k, const prrtc
 
 void serve_loop_persistent(prrtc_ctx* ctx) {
     Server& S = *ctx->server;
+    ctx->serve_tid.store(std::this_thread::get_id());
     (void)hipSetDevice(ctx->device);
     volatile int* published = S.host_ctrl;
     volatile int* drain = S.host_ctrl + 32;
@@ -1803,6 +1811,7 @@ void serve_shutdown(prrtc_ctx* ctx) {
         serve_free_persistent(S);
     }
     ctx->server.reset();
+    ctx->serve_tid.store(std::thread::id());
     ctx->serving.store(false);
 }
 
