@@ -61,6 +61,17 @@ class PlanParams(C.Structure):
     ]
 
 
+class TreeDump(C.Structure):
+    _fields_ = [
+        ("nodes_a", C.c_void_p),
+        ("nodes_b", C.c_void_p),
+        ("parent_a", C.c_void_p),
+        ("parent_b", C.c_void_p),
+        ("blocked_a", C.c_void_p),
+        ("blocked_b", C.c_void_p),
+    ]
+
+
 class PlanStats(C.Structure):
     _fields_ = [
         ("rounds", C.c_int32),
@@ -107,6 +118,8 @@ def lib():
                                             P, P, C.c_int32, P]
         L.orc_plan.argtypes = [P, P, C.c_int32, P, P, P, P, C.c_int32, P, P, C.c_int32]
         L.orc_plan.restype = C.c_int32
+        L.orc_plan_dump.argtypes = [P, P, C.c_int32, P, P, P, P, C.c_int32, P, P, C.c_int32, P]
+        L.orc_plan_dump.restype = C.c_int32
         L.orc_path_clearance.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_float, P]
         L.orc_path_clearance.restype = C.c_double
         _lib = L
@@ -264,6 +277,39 @@ def plan(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=256, del
                             _ptr(path), cap, C.byref(ln), C.byref(st), int(n_threads))
     stats = {f: getattr(st, f) for f, _ in PlanStats._fields_}
     return status, (path[: ln.value].copy() if status == 0 else None), stats
+
+
+def plan_trees(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=256, delta=0.5,
+               res=32.0, max_rounds=200, tree_capacity=4096, validate_factor=4, dds_radius=0.0,
+               dds_tries=1, n_threads=1):
+    """As plan(), also returning the final trees: (status, path, stats, trees) with
+    trees = {"a": (nodes (n, dof), parent (n,), blocked (n,)), "b": (...)}."""
+    p = _prims(prims)
+    s = np.ascontiguousarray(start, np.float32)
+    g = np.ascontiguousarray(goal, np.float32)
+    pp = PlanParams(seed=seed, query=query, workers=workers, delta=delta, res=res,
+                    max_rounds=max_rounds, tree_capacity=tree_capacity,
+                    validate_factor=validate_factor, dds_radius=dds_radius, dds_tries=dds_tries)
+    st = PlanStats()
+    cap = 4096
+    path = np.zeros((cap, rob.dof), np.float32)
+    ln = C.c_int32(0)
+    na = np.zeros((tree_capacity, rob.dof), np.float32)
+    nb = np.zeros_like(na)
+    pa = np.zeros(tree_capacity, np.int32)
+    pb = np.zeros_like(pa)
+    ba = np.zeros(tree_capacity, np.uint8)
+    bb = np.zeros_like(ba)
+    dump = TreeDump(na.ctypes.data, nb.ctypes.data, pa.ctypes.data, pb.ctypes.data,
+                    ba.ctypes.data, bb.ctypes.data)
+    status = lib().orc_plan_dump(rob.ref, _ptr(p), p.shape[0], _ptr(s), _ptr(g), C.byref(pp),
+                                 _ptr(path), cap, C.byref(ln), C.byref(st), int(n_threads),
+                                 C.byref(dump))
+    stats = {f: getattr(st, f) for f, _ in PlanStats._fields_}
+    ka, kb = stats["nodes_a"], stats["nodes_b"]
+    trees = {"a": (na[:ka].copy(), pa[:ka].copy(), ba[:ka].copy()),
+             "b": (nb[:kb].copy(), pb[:kb].copy(), bb[:kb].copy())}
+    return status, (path[: ln.value].copy() if status == 0 else None), stats, trees
 
 
 def path_clearance(rob: OracleRobot, prims, path, res: float):

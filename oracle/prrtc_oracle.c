@@ -508,9 +508,25 @@ static int32_t walk_to_root(const orc_tree *T, int32_t node, int32_t *out, int32
     return n; /* node first, root last */
 }
 
+static void tree_dump(const orc_tree *T, int dof, float *nodes, int32_t *parent, uint8_t *blocked) {
+    for (int32_t i = 0; i < T->size; i++) {
+        if (nodes) tree_get(T, dof, i, nodes + (size_t)i * dof);
+        if (parent) parent[i] = T->parent[i];
+        if (blocked) blocked[i] = T->blocked[i];
+    }
+}
+
 int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, const float *start,
                  const float *goal, const orc_plan_params *p, float *path, int32_t path_cap,
                  int32_t *path_len, orc_plan_stats *st_out, int32_t n_threads) {
+    return orc_plan_dump(R, prims, n_prims, start, goal, p, path, path_cap, path_len, st_out,
+                         n_threads, NULL);
+}
+
+int32_t orc_plan_dump(const orc_robot *R, const orc_prim *prims, int32_t n_prims, const float *start,
+                      const float *goal, const orc_plan_params *p, float *path, int32_t path_cap,
+                      int32_t *path_len, orc_plan_stats *st_out, int32_t n_threads,
+                      orc_tree_dump *dump) {
     const int dof = orc_dof(R);
     orc_plan_stats st;
     memset(&st, 0, sizeof st);
@@ -667,6 +683,10 @@ int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, con
     st.nodes_a = A.size;
     st.nodes_b = B.size;
     if (st_out) *st_out = st;
+    if (dump) {
+        tree_dump(&A, dof, dump->nodes_a, dump->parent_a, dump->blocked_a);
+        tree_dump(&B, dof, dump->nodes_b, dump->parent_b, dump->blocked_b);
+    }
     free(stages);
     free(stage_mem);
     free(walk_a);

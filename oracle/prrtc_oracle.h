@@ -123,6 +123,21 @@ int32_t orc_plan(const orc_robot *R, const orc_prim *prims, int32_t n_prims, con
                  const float *goal, const orc_plan_params *p, float *path, int32_t path_cap,
                  int32_t *path_len, orc_plan_stats *st, int32_t n_threads);
 
+/* Final state of both trees, for tests of the round structure: node k of a
+ * tree is nodes[k * dof .. k * dof + dof - 1], its parent parent[k] (-1 for
+ * the root); every array holds tree_capacity entries.  Sizes are the stats'
+ * nodes_a / nodes_b.  Any pointer may be NULL. */
+typedef struct {
+    float *nodes_a, *nodes_b;
+    int32_t *parent_a, *parent_b;
+    uint8_t *blocked_a, *blocked_b;
+} orc_tree_dump;
+
+/* orc_plan, also writing the final trees into *dump (when not NULL). */
+int32_t orc_plan_dump(const orc_robot *R, const orc_prim *prims, int32_t n_prims, const float *start,
+                      const float *goal, const orc_plan_params *p, float *path, int32_t path_cap,
+                      int32_t *path_len, orc_plan_stats *st, int32_t n_threads, orc_tree_dump *dump);
+
 /* Re-check a path's segments (points i = 0..n at resolution res).  Returns
  * the minimum clearance over all segments; *n_flag counts segments within
  * the flag band. */
