@@ -361,6 +361,23 @@ prrtc_status prrtc_proposal_forward(prrtc_ctx *ctx, int32_t model_id, int32_t ro
                                     int32_t n_scenes, const int32_t *scene_of, const float *start,
                                     const float *goal, int32_t n, float *gmm, void *stream);
 
+/*
+ * prrtc_proposal_forward for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, kernels and results, but the activations live
+ * in a fixed device array of about 3.3 MiB that each GPU the library runs on
+ * holds until the process ends.  No allocation, no synchronisation.
+ * Limits: n <= 256 samples and n_scenes <= 256 scenes, else E_ARG (before
+ * any work).  Every call on one device shares that array: calls that overlap
+ * on one GPU (other streams, other contexts or threads) race and must be
+ * serialised by the caller.  Nothing in the array needs clearing between
+ * calls.
+ */
+prrtc_status prrtc_proposal_forward_noalloc(prrtc_ctx *ctx, int32_t model_id, int32_t robot_id,
+                                            const uint8_t *vox, int32_t n_scenes, const int32_t *scene_of,
+                                            const float *start, const float *goal, int32_t n, float *gmm,
+                                            void *stream);
+
 /* One training step on a batch whose samples are grouped by scene: samples
  * scene_start[s] .. scene_start[s+1]-1 belong to scene s (scene_of repeats
  * that mapping per sample).  All pointers are device memory; waypoint is the

@@ -305,6 +305,7 @@ struct prrtc_ctx {
     size_t edge_grid_lds[2] = {0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float* pinned = nullptr;           // kPinnedFloats of pinned host staging
+    float* scratch = nullptr;          // this device's address of the static scratch array
     std::unique_ptr<struct Server> server;
     std::atomic<bool> serving{false};  // while set, only submit/poll/serve_stop are accepted
     std::atomic<std::thread::id> serve_tid{};   // the serving thread: it never writes err
@@ -372,6 +373,7 @@ size_t align_up(size_t x) {
 
 namespace {
 void serve_shutdown(prrtc_ctx* ctx);   // stops and joins a context's serving thread
+hipError_t scratch_address(int device, float** out);   // the static scratch array on a device
 }  // namespace
 
 extern "C" {
@@ -396,6 +398,7 @@ prrtc_status prrtc_create(prrtc_ctx** out, int device) {
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev0));
     PRRTC_HIP(ctx.get(), hipEventCreate(&ctx->ev1));
     PRRTC_HIP(ctx.get(), hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), sizeof(float) * kPinnedFloats));
+    PRRTC_HIP(ctx.get(), scratch_address(device, &ctx->scratch));   // with `device` current
     *out = ctx.release();
     return PRRTC_OK;
 }
@@ -1910,7 +1913,61 @@ struct PropWs {
     float *E, *dE, *X0, *dX0, *Z1, *H1, *Z2, *H2, *Z3, *H3, *O, *dO, *dZ, *dH, *qh, *nll, *part;
 };
 
+// Activations of prrtc_proposal_forward_noalloc, for callers that cannot
+// allocate: a fixed device array sized for kNoAllocRows samples over
+// kNoAllocScenes scenes at the largest DoF.  Each device keeps its own copy
+// for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (scratch_address).
+constexpr int kNoAllocRows = 256, kNoAllocScenes = 256;
+constexpr size_t kNoAllocFloats =
+    (size_t)kNoAllocScenes * kHidden +                               // E
+    (size_t)kNoAllocRows * (2 * kMaxDof + kHidden) +                 // X0
+    (size_t)6 * kNoAllocRows * kHidden +                             // Z1 H1 Z2 H2 Z3 H3
+    (size_t)kNoAllocRows * kComp * (1 + 2 * kMaxDof) +               // O
+    (size_t)kEmbedSlices * kSmallRows * kHidden;                     // partial embeddings
+static_assert(kNoAllocScenes * kHidden % 64 == 0 && kNoAllocRows % 64 == 0 && kSmallRows * kHidden % 64 == 0,
+              "every scratch region starts on a 256-byte boundary");
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
 namespace {
+
+// Device address of `scratch` on `device`, which must be the current device.
+// Looked up once per device and kept.
+hipError_t scratch_address(int device, float** out) {
+    static std::mutex mu;
+    static std::unordered_map<int, float*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(device, static_cast<float*>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+// The forward pass's buffers carved out of the scratch array (training-only
+// buffers stay null: the forward kernels never touch them without a target).
+// Nothing in them needs clearing: every kernel writes each value it later reads.
+PropWs noalloc_workspace(float* base, int n, int S, int dof) {
+    PropWs W{};
+    float* p = base;
+    W.E = p;
+    p += (size_t)S * kHidden;
+    W.X0 = p;
+    p += (size_t)n * (2 * dof + kHidden);
+    float** hid[6] = {&W.Z1, &W.H1, &W.Z2, &W.H2, &W.Z3, &W.H3};
+    for (float** h : hid) {
+        *h = p;
+        p += (size_t)n * kHidden;
+    }
+    W.O = p;
+    p += (size_t)n * kComp * (1 + 2 * dof);
+    W.part = p;
+    return W;
+}
 
 std::vector<ModelRec>& models_of(prrtc_ctx* ctx) { return ctx->models; }
 
@@ -2185,6 +2242,30 @@ prrtc_status prrtc_proposal_forward(prrtc_ctx* ctx, int32_t model_id, int32_t ro
     st = prop_workspace(ctx, *M, n, n_scenes, W);
     if (st != PRRTC_OK) return st;
     prop_forward(sm, *M, W, ctx->robots[robot_id].dev_args, vox, n_scenes, scene_of, start, goal, nullptr, n, gmm);
+    PRRTC_HIP(ctx, hipGetLastError());
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_proposal_forward_noalloc(prrtc_ctx* ctx, int32_t model_id, int32_t robot_id, const uint8_t* vox,
+                                            int32_t n_scenes, const int32_t* scene_of, const float* start,
+                                            const float* goal, int32_t n, float* gmm, void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
+    ModelRec* M;
+    const RobotArgs* R;
+    prrtc_status st = prop_common(ctx, model_id, robot_id, &M, &R);
+    if (st != PRRTC_OK) return st;
+    if (n < 0 || n_scenes < 1) return fail(ctx, PRRTC_E_ARG, "bad sizes");
+    if (n > kNoAllocRows || n_scenes > kNoAllocScenes)
+        return fail(ctx, PRRTC_E_ARG, "%d samples over %d scenes exceed the static scratch (at most %d samples, %d scenes)",
+                    n, n_scenes, kNoAllocRows, kNoAllocScenes);
+    if (n == 0) return PRRTC_OK;
+    if (!vox || !scene_of || !start || !goal || !gmm) return fail(ctx, PRRTC_E_ARG, "null buffer");
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    const PropWs W = noalloc_workspace(ctx->scratch, n, n_scenes, M->L.dof);
+    prop_forward(static_cast<hipStream_t>(stream), *M, W, ctx->robots[robot_id].dev_args, vox, n_scenes, scene_of,
+                 start, goal, nullptr, n, gmm);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
 }

@@ -151,6 +151,8 @@ def _load():
     L.prrtc_voxelize.restype = I32
     L.prrtc_proposal_forward.argtypes = [P, I32, I32, VP, I32, VP, VP, VP, I32, VP, VP]
     L.prrtc_proposal_forward.restype = I32
+    L.prrtc_proposal_forward_noalloc.argtypes = [P, I32, I32, VP, I32, VP, VP, VP, I32, VP, VP]
+    L.prrtc_proposal_forward_noalloc.restype = I32
     L.prrtc_train_proposal.argtypes = [P, I32, I32, C.POINTER(prrtc_train_batch), F, VP, VP]
     L.prrtc_train_proposal.restype = I32
     L.prrtc_proposal_sample.argtypes = [P, I32, VP, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, I32, VP, VP,
@@ -186,7 +188,8 @@ EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_rob
             "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_edge_schedule", "prrtc_fk_spheres",
             "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_launch",
             "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
-            "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_sample", "prrtc_train_proposal")
+            "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_forward_noalloc", "prrtc_proposal_sample",
+            "prrtc_train_proposal")
 
 
 # ---- C-named wrappers ------------------------------------------------------------
@@ -435,6 +438,13 @@ def prrtc_proposal_forward(ctx: int, model_id: int, robot_id: int, vox_dev: int,
                            stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_proposal_forward(ctx, model_id, robot_id, vox_dev, n_scenes, scene_of_dev,
                                                   start_dev, goal_dev, n, gmm_dev, stream))
+
+
+def prrtc_proposal_forward_noalloc(ctx: int, model_id: int, robot_id: int, vox_dev: int, n_scenes: int,
+                                   scene_of_dev: int, start_dev: int, goal_dev: int, n: int, gmm_dev: int,
+                                   stream: int | None = None) -> int:
+    return _check(ctx, lib.prrtc_proposal_forward_noalloc(ctx, model_id, robot_id, vox_dev, n_scenes, scene_of_dev,
+                                                          start_dev, goal_dev, n, gmm_dev, stream))
 
 
 def prrtc_train_proposal(ctx: int, model_id: int, robot_id: int, batch: prrtc_train_batch, lr: float,
