@@ -98,6 +98,8 @@ def lib():
         L.orc_n_frames.argtypes = [P]
         L.orc_fk_frames.argtypes = [P, P, P]
         L.orc_fk_spheres.argtypes = [P, P, P]
+        L.orc_fk_spheres_batch.argtypes = [P, P, C.c_int64, P, C.c_int32]
+        L.orc_fk_spheres_batch.restype = None
         L.orc_clearance.argtypes = [P, C.c_double, P]
         L.orc_clearance.restype = C.c_double
         L.orc_config_clearance.argtypes = [P, P, C.c_int32, P]
@@ -180,6 +182,14 @@ def fk_spheres(rob: OracleRobot, q) -> np.ndarray:
     q = np.ascontiguousarray(q, np.float32)
     out = np.zeros((rob.struct.n_spheres, 3))
     lib().orc_fk_spheres(rob.ref, _ptr(q), _ptr(out))
+    return out
+
+
+def fk_spheres_batch(rob: OracleRobot, q, n_threads: int = 0) -> np.ndarray:
+    """fk_spheres of every row of q [n][dof] -> [n][n_spheres][3] (FP64)."""
+    q = np.ascontiguousarray(q, np.float32)
+    out = np.zeros((q.shape[0], rob.struct.n_spheres, 3))
+    lib().orc_fk_spheres_batch(rob.ref, _ptr(q), q.shape[0], _ptr(out), int(n_threads))
     return out
 
 

@@ -133,6 +133,13 @@ void orc_fk_spheres(const orc_robot *R, const float *q, double *xyz) {
     spheres_world(R, qd, xyz);
 }
 
+void orc_fk_spheres_batch(const orc_robot *R, const float *q, int64_t n, double *xyz, int32_t n_threads) {
+    const int dof = orc_dof(R);
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+    for (int64_t i = 0; i < n; i++) orc_fk_spheres(R, q + i * dof, xyz + i * 3 * R->n_spheres);
+}
+
 /* ---------------------------------------------------------------------------
  * Signed clearance of a sphere to a primitive (Sec. III-A: sphere tests
  * against primitive obstacles).  Negative = penetration, i.e. collision.

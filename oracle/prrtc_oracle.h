@@ -84,6 +84,9 @@ int orc_n_frames(const orc_robot *R);
 void orc_fk_frames(const orc_robot *R, const double *q, double *frames);
 /* Sphere centres in world coordinates for configuration q (float32 input). */
 void orc_fk_spheres(const orc_robot *R, const float *q, double *xyz);
+/* orc_fk_spheres for n configurations q[n][dof] -> xyz[n][n_spheres][3],
+ * OpenMP over configurations (n_threads <= 0: all). */
+void orc_fk_spheres_batch(const orc_robot *R, const float *q, int64_t n, double *xyz, int32_t n_threads);
 
 /* Signed clearance of a sphere (centre c, radius r) to one primitive. */
 double orc_clearance(const double c[3], double r, const orc_prim *p);

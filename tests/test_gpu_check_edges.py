@@ -40,23 +40,28 @@ def assert_parity(orc, robot, prims, a, b, got, res=32.0, threads=0):
 
 @pytest.mark.parametrize("robot_name", ["r7", "r14"])
 def test_fk_spheres_parity(gpu, orc, robot_name, request):
+    """Worst case over 10^6 random configurations (a little outside the
+    joint limits too) of the FP32 sphere centres against the FP64 oracle."""
     P, ctx, torch = gpu
     robot = request.getfixturevalue(robot_name)
     say("fk parity", robot_name)
     rid = P.prrtc_load_robot(ctx, robot)
     rng = np.random.default_rng(1)
     dof = W.robot_dof(robot)
-    q = rng.uniform(-3.2, 3.2, (3000, dof)).astype(np.float32)   # also a little outside limits
-    tq = torch.from_numpy(q).cuda()
     ns = robot["sphere_xyzr"].shape[0]
-    out = torch.zeros((3000, ns, 3), dtype=torch.float32, device="cuda")
-    P.prrtc_fk_spheres(ctx, rid, tq.data_ptr(), 3000, out.data_ptr(),
-                       torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
-    got = out.cpu().numpy().astype(np.float64)
     rob = orc.OracleRobot(robot)
-    err = max(np.max(np.abs(got[i] - orc.fk_spheres(rob, q[i]))) for i in range(0, 3000, 7))
-    say("  max |fk err| =", err)
+    n_total, chunk = 1 << 20, 1 << 16
+    out = torch.zeros((chunk, ns, 3), dtype=torch.float32, device="cuda")
+    err = 0.0
+    for c0 in range(0, n_total, chunk):
+        q = rng.uniform(-3.2, 3.2, (chunk, dof)).astype(np.float32)
+        tq = torch.from_numpy(q).cuda()
+        P.prrtc_fk_spheres(ctx, rid, tq.data_ptr(), chunk, out.data_ptr(),
+                           torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        err = max(err, float(np.max(np.abs(got - orc.fk_spheres_batch(rob, q)))))
+    say("  max |fk err| over %d configurations = %.3g m" % (n_total, err))
     assert err <= FK_TOL
 
 
@@ -114,6 +119,29 @@ def test_check_edges_parity_r14_shelf(gpu, orc, r14):
     v0, f0 = assert_parity(orc, r14, np.zeros(0, W.PRIM_DTYPE), a, b, got0)
     say("  self-only valid frac %.4f" % v0.mean())
     assert 0.0 < v0.mean() < 1.0
+
+
+def test_check_edges_near_contact(gpu, orc, r7, r14):
+    """Edges built to end 1e-6 .. 1e-3 m from contact, on either side, against
+    each primitive type, the shelf's thin boards and the inter-arm pairs.
+    Unflagged edges (|clearance| > 1e-5 m) must match the oracle; flagged
+    ones are counted, with how many still agree."""
+    import near_contact as NC
+    P, ctx, _ = gpu
+    say("near-contact edges")
+    for name, robot, prims in NC.graze_scenes(W, r7, r14):
+        rid, sid = P.prrtc_load_robot(ctx, robot), P.prrtc_load_scene(ctx, prims)
+        cf = NC.graze_configs(orc, robot, prims, 12, seed=0x4E43)
+        a, b = NC.graze_edges(cf)
+        got = gpu_check(gpu, rid, sid, a, b)
+        rob = orc.OracleRobot(robot)
+        v, f, m = orc.check_edges(rob, prims, a, b, 32.0, early_exit=False, want_m=True)
+        mism = (got != v) & (f == 0)
+        near = (f == 0) & (np.abs(m) < 1e-4)
+        say("  %s: %d edges, %d within 1e-5..1e-4 m (unflagged, all equal: %s), %d flagged, %d of them agree"
+            % (name, len(v), near.sum(), not mism.any(), f.sum(), np.sum((got == v) & (f == 1))))
+        assert near.sum() >= 8 * 12 and f.sum() >= 4 * 12
+        assert not mism.any(), (name, np.nonzero(mism)[0][:10], m[mism][:10])
 
 
 def test_check_edges_edge_cases(gpu, orc, r7):

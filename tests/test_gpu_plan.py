@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from conftest import free_query
+from conftest import free_query, path_ok, replay_equal
 from paper_2503_06757_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -29,34 +29,6 @@ def params(P, **kw):
     for k, v in kw.items():
         setattr(p, k, v)
     return p
-
-
-def path_ok(orc, robot, prims, path, s, g, delta=0.5, res=32.0):
-    rob = orc.OracleRobot(robot)
-    assert np.array_equal(path[0], s) and np.array_equal(path[-1], g)
-    seg = np.linalg.norm(np.diff(path.astype(np.float64), axis=0), axis=1)
-    assert np.all(seg <= delta * (1 + 1e-6))
-    m, _ = orc.path_clearance(rob, prims, path, 4 * res)
-    assert m >= -orc.FLAG_BAND, m
-
-
-def replay_equal(orc, robot, prims, s, g, gst, gpath, gstats, **kw):
-    rob = orc.OracleRobot(robot)
-    ost, opath, ostats = orc.plan(rob, prims, s, g, n_threads=16, **kw)
-    say("   oracle:", ost, ostats, " gpu:", gst, {k: gstats[k] for k in
-                                                 ("rounds", "nodes_a", "nodes_b", "edges_checked",
-                                                  "validation_failures", "connect_worker")})
-    if ostats["flagged_edges"] == 0:
-        assert gst == ost
-        assert gstats["rounds"] == ostats["rounds"]
-        assert gstats["nodes_a"] == ostats["nodes_a"] and gstats["nodes_b"] == ostats["nodes_b"]
-        assert gstats["edges_checked"] == ostats["edges_checked"]
-        assert gstats["validation_failures"] == ostats["validation_failures"]
-        if gst == 0:
-            assert gstats["connect_worker"] == ostats["connect_worker"]
-            assert np.array_equal(gpath, opath)
-        return True
-    return False
 
 
 @pytest.mark.parametrize("instance", range(6))
@@ -229,3 +201,28 @@ def test_plan_r14_shelf_queries(gpu, orc, r14, tile):
             solved += 1
             path_ok(orc, r14, prims, path, s, g)
     say("  solved", solved, "of 20")
+
+
+def test_plan_r14_shelf_replay(gpu, orc, r14):
+    """Stored dual-arm shelf queries, bounded by 40 rounds (no time budget,
+    so the run is a pure function of the seed): the GPU's status, rounds,
+    trees, edge count and path equal the oracle's replay whenever the replay
+    met no edge within the flag band."""
+    import os
+    P, ctx, _ = gpu
+    say("R14 shelf replay")
+    prims = W.scene_shelf(r14)
+    rid, sid = P.prrtc_load_robot(ctx, r14), P.prrtc_load_scene(ctx, prims)
+    Q = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "shelf_queries_r14.txt"), dtype=np.float32)
+    replayed = solved = 0
+    for k in range(8):
+        s, g = Q[k, :14], Q[k, 14:]
+        kw = dict(seed=W.SEED_QUERY + k, max_rounds=40)
+        st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
+        assert st in (0, P.PRRTC_E_NO_SOLUTION), (k, st)
+        if st == 0:
+            solved += 1
+            path_ok(orc, r14, prims, path, s, g)
+        replayed += replay_equal(orc, r14, prims, s, g, st, path, stats, **kw)
+    say("  %d of 8 replayed, %d solved within 40 rounds" % (replayed, solved))
+    assert replayed >= 4

@@ -142,6 +142,64 @@ def test_gradient_parity_and_roundtrip(gpu, prop, r7):
     assert np.array_equal(a, c)
 
 
+def test_adam_step_parity(gpu, prop, r7):
+    """One GPU training step from a non-trivial Adam state (t = 7, random
+    moments) against the oracle's Adam.  The GPU gradient is recovered from
+    the new first moment, g = (m1 - beta1 m0) / (1 - beta1), and must match the
+    oracle's gradient; the oracle's Adam step on that gradient must then give
+    the GPU's second moment and parameters.  Bounds: the kernel holds beta1,
+    beta2 in FP32 (1 - beta2 is 1.3e-5 off 0.001 relative), and p1 is rounded
+    to FP32."""
+    P, ctx, torch = gpu
+    say("Adam step parity")
+    rng = np.random.default_rng(15)
+    dof, t0, lr, b1, b2 = 7, 7, 1e-3, 0.9, 0.999
+    params = PR.init_params(dof, 14)
+    for k in ("bv", "b1", "b2", "b3", "b4"):
+        params[k] = (rng.standard_normal(params[k].shape) * 0.05).astype(np.float32)
+    rid = P.prrtc_load_robot(ctx, r7)
+    scenes = [W.scene_s12(r7, i) for i in range(3)]
+    vox_t = gpu_vox(gpu, scenes)
+    vox = vox_t.cpu().numpy().astype(np.float64)
+    scene_of, start, s, g, q = _batch(rng, r7, 3, 20)
+    gm, cache = prop.forward(params, vox, scene_of, s, g, r7["q_lo"], r7["q_hi"])
+    qh = prop.scale(q, r7["q_lo"], r7["q_hi"])
+    G = prop.backward(params, cache, gm, qh)
+    # moments on the scale of each tensor's gradient
+    m0, v0 = {}, {}
+    for k in PR.PARAM_ORDER:
+        sc = float(np.std(G[k])) + 1e-6
+        m0[k] = (rng.standard_normal(G[k].shape) * 0.5 * sc).astype(np.float32)
+        v0[k] = (rng.uniform(0.5, 2.0, G[k].shape) * sc * sc).astype(np.float32)
+    mid = P.prrtc_load_proposal(ctx, PR.pack(params, dof, m0, v0, adam_t=t0))
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in
+           dict(scene_of=scene_of, start=start, s=s, g=g, q=q).items()}
+    loss = torch.zeros(1, device="cuda")
+    b = P.prrtc_train_batch(vox=vox_t.data_ptr(), n_scenes=3, scene_start=dev["start"].data_ptr(),
+                            scene_of=dev["scene_of"].data_ptr(), start=dev["s"].data_ptr(),
+                            goal=dev["g"].data_ptr(), waypoint=dev["q"].data_ptr(), n=len(s))
+    P.prrtc_train_proposal(ctx, mid, rid, b, lr, loss.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    _, adam_t, (p1, m1, v1) = PR.unpack(P.prrtc_save_proposal(ctx, mid))
+    assert adam_t == t0 + 1
+    f64 = lambda d: {k: np.asarray(x, np.float64) for k, x in d.items()}
+    g_gpu = {k: (m1[k].astype(np.float64) - b1 * m0[k].astype(np.float64)) / (1.0 - b1) for k in PR.PARAM_ORDER}
+    p_ref, m_ref, v_ref = prop.adam(f64(params), g_gpu, f64(m0), f64(v0), t0 + 1, lr=lr, b1=b1, b2=b2)
+    for k in PR.PARAM_ORDER:
+        rel = np.linalg.norm(g_gpu[k] - G[k]) / max(np.linalg.norm(G[k]), 1e-30)
+        assert rel <= 2e-2, (k, rel)
+        assert np.allclose(m1[k], m_ref[k], rtol=1e-6, atol=1e-12 + 1e-6 * np.abs(m0[k]).max()), k
+        dv = np.abs(v1[k] - v_ref[k])
+        assert np.all(dv <= 3e-5 * (1.0 - b2) * g_gpu[k] ** 2 + 1e-6 * v_ref[k] + 1e-30), (k, dv.max())
+        step = np.abs(p_ref[k] - params[k].astype(np.float64))
+        dp = np.abs(p1[k].astype(np.float64) - p_ref[k])
+        bound = 2.0 ** -23 * np.abs(params[k]) + 3e-5 * step + 1e-12
+        say("  %s: |step| mean %.2e, max |dp|/bound %.3f" % (k, step.mean(), (dp / bound).max()))
+        assert np.all(dp <= bound), k
+        # a visible step: bias correction and the learning rate matter at this size
+        assert step.mean() > 1e-5, k
+
+
 def test_training_reduces_loss(gpu, r7):
     """Waypoints drawn around a per-scene mean: 300 Adam steps must cut the
     mean NLL substantially (the model can read the scene from the grid)."""

@@ -193,3 +193,24 @@ def test_sample_config_range_determinism_uniformity(orc, r7):
         cnt = np.bincount(np.minimum((u[:, j] * 16).astype(int), 15), minlength=16)
         exp = len(u) / 16
         assert np.sum((cnt - exp) ** 2 / exp) < 37.7
+
+
+def test_near_contact_construction(orc, wl, r7, r14):
+    """The near-contact edge sets land where they are meant to: every built
+    configuration's oracle clearance is within 1 um of its target (1e-6 ..
+    1e-3 m either side of contact), a zero-length edge's clearance is that
+    configuration's, and exactly the edges within 1e-5 m are flagged."""
+    import near_contact as NC
+    for name, robot, prims in NC.graze_scenes(wl, r7, r14):
+        cf = NC.graze_configs(orc, robot, prims, 2, seed=11)
+        assert len(cf) == 2 * len(NC.TARGETS), name
+        for q, c, m, _, _ in cf:
+            assert abs(m - c) <= 1e-6, (name, c, m)
+        a, b = NC.graze_edges(cf)
+        rob = orc.OracleRobot(robot)
+        v, f, me = orc.check_edges(rob, prims, a, b, 32.0, early_exit=False, want_m=True)
+        assert np.array_equal(me[0::2], [m for _, _, m, _, _ in cf]), name
+        assert np.array_equal(f.astype(bool), np.abs(me) <= orc.FLAG_BAND), name
+        assert np.array_equal(v.astype(bool), me >= 0), name
+        # both sides of the band are populated
+        assert np.sum((me > orc.FLAG_BAND) & (me < 1e-4)) >= 4 and np.sum((me < -orc.FLAG_BAND) & (me > -1e-4)) >= 4

@@ -230,3 +230,12 @@ def test_config_clearance_is_min_over_tests(orc, r14):
         d = np.linalg.norm(xyz[pairs[:, 0]] - xyz[pairs[:, 1]], axis=1) - rad[pairs[:, 0]] - rad[pairs[:, 1]]
         m = min(m, d.min())
         assert orc.config_clearance(rob, prims, q.astype(np.float64)) == pytest.approx(m, abs=1e-15)
+
+
+def test_fk_batch_equals_single(orc, r14):
+    """The batched FK loop returns each configuration's single-call FK."""
+    rob = orc.OracleRobot(r14)
+    q = np.random.default_rng(8).uniform(-3, 3, (257, 14)).astype(np.float32)
+    out = orc.fk_spheres_batch(rob, q, n_threads=4)
+    for i in (0, 1, 100, 256):
+        assert np.array_equal(out[i], orc.fk_spheres(rob, q[i]))
