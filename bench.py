@@ -30,19 +30,38 @@ N_EDGES = 1 << 20
 RES = 32.0
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 
-# Algorithmic FP32 work per checked configuration (FMA = 2, add/sub/mul = 1,
-# compare/min/max/abs = 0, sqrt = 1):
+# Algorithmic FP32 work per checked configuration, the dense per-point model
+# (FMA = 2, add/sub/mul = 1, compare/min/max = 0): every robot sphere against
+# every obstacle (sphere 10, cuboid 28, cylinder 27) and every self pair (10),
+# plus FK: 67 per joint frame composition, 18 per sphere transform, 2 per
+# joint of interpolation (sin/cos not counted).  7-DoF arm (60 spheres) among
+# 32 spheres, 21 cuboids and 11 cylinders: 73,863 FLOP per configuration.
+MODEL_SPHERE, MODEL_CUBOID, MODEL_CYLINDER, MODEL_PAIR = 10, 28, 27, 10
+MODEL_JOINT, MODEL_SPHERE_XFORM, MODEL_INTERP = 67, 18, 2
+
+
+def point_flops_model(robot, prims):
+    t = np.bincount(prims["type"], minlength=3)
+    n_sph = robot["sphere_xyzr"].shape[0]
+    dof = sum(robot["chain_dof"])
+    per_sphere = MODEL_SPHERE * t[0] + MODEL_CUBOID * t[1] + MODEL_CYLINDER * t[2]
+    return int(n_sph * per_sphere + MODEL_PAIR * len(robot["self_pairs"]) +
+               dof * (MODEL_JOINT + MODEL_INTERP) + n_sph * MODEL_SPHERE_XFORM)
+
+
+# A reduced count of the same work, as this kernel organises it: base-frame
+# spheres never move, so they are tested once per launch, not per
+# configuration; cuboid 27 and cylinder 26 (box-frame coordinates from three
+# FMAs each), frame update 48.
 FLOP_SPHERE, FLOP_CUBOID, FLOP_CYLINDER = 10, 27, 26
-FLOP_JOINT = 48          # one modified-DH frame update (sin/cos not counted)
-FLOP_SPHERE_XFORM = 18   # rotate + translate a sphere centre
-FLOP_INTERP = 2          # per joint: one FMA
+FLOP_JOINT = 48
+FLOP_SPHERE_XFORM = 18
+FLOP_INTERP = 2
 
 
 def point_flops(robot, prims):
-    """FLOPs to decide one configuration: FK of the moving spheres and every
-    moving-sphere x obstacle test.  Base-frame spheres never move, so they
-    are tested once per launch, not per configuration."""
-    n_frames = sum(d + 1 for d in robot["chain_dof"])
+    """Reduced count per configuration: FK of the moving spheres and every
+    moving-sphere x obstacle test."""
     bases = set()
     f = 0
     for d in robot["chain_dof"]:
@@ -52,7 +71,6 @@ def point_flops(robot, prims):
     t = np.bincount(prims["type"], minlength=3)
     per_sphere = FLOP_SPHERE * t[0] + FLOP_CUBOID * t[1] + FLOP_CYLINDER * t[2]
     dof = sum(robot["chain_dof"])
-    del n_frames
     return dof * (FLOP_JOINT + FLOP_INTERP) + moving * (FLOP_SPHERE_XFORM + per_sphere)
 
 
@@ -128,14 +146,34 @@ def bench_check_edges(P, ctx, torch, steps, warmup):
     kernel_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
     valid = tv.cpu().numpy().astype(bool)
     n_pts = edge_counts(a, b, RES) + 1
+    fl_model = point_flops_model(robot, prims)
     fl_point = int(point_flops(robot, prims))
     # Lower bound of the work any correct checker must do: every configuration
     # of every collision-free edge in full; colliding edges counted as zero.
-    alg_flop = float(np.sum(n_pts[valid])) * fl_point
-    dense_flop = float(np.sum(n_pts)) * fl_point
+    free_points = float(np.sum(n_pts[valid]))
+    # The collision-free edges alone as their own launch (inputs resident):
+    # every configuration of every edge must be checked, so early exit cannot help.
+    fa, fb = ta[torch.from_numpy(valid).cuda()].contiguous(), tb[torch.from_numpy(valid).cuda()].contiguous()
+    nf = int(fa.shape[0])
+    tvf = torch.empty(max(nf, 1), dtype=torch.uint8, device="cuda")
+
+    def step_free():
+        P.prrtc_check_edges(ctx, rid, sid, fa.data_ptr(), fb.data_ptr(), nf, RES, tvf.data_ptr(), stream.cuda_stream)
+
+    for _ in range(warmup):
+        step_free()
+    evf = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evf:
+        e0.record(stream)
+        step_free()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    free_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evf]))
+    free_ok = bool(tvf[:nf].all().item())
     return dict(robot=robot, prims=prims, a=a, b=b, wall_s=t1 - t0, kernel_ms=kernel_ms, schedule=schedule,
-                valid_frac=float(valid.mean()), alg_flop=alg_flop, dense_flop=dense_flop,
-                flop_per_point=fl_point, mean_points=float(n_pts.mean()))
+                valid=valid, valid_frac=float(valid.mean()), free_points=free_points,
+                flop_per_point_model=fl_model, flop_per_point=fl_point, mean_points=float(n_pts.mean()),
+                free_edges=nf, free_ms=free_ms, free_all_valid=free_ok)
 
 
 def bench_plan(P, ctx, n_instances=100, n_seeds=50):
@@ -216,20 +254,26 @@ def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, budget_
 
 
 def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None, slots=256, max_pending=1024,
-                budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None):
+                budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None, models=None, tile=16):
     """The served workload through the library's serving thread: queries
     arrive as a Poisson stream (exponential gaps) and are submitted at their
-    arrival time (refused submissions are retried: admission); with uniform
-    sampling the thread keeps one persistent launch that takes each query as
-    it is published.  Latency = completion seen by polling - arrival, on the
-    host clock."""
+    arrival time (refused submissions are retried: admission); the thread
+    keeps one persistent launch that takes each query as it is published.
+    models: None (uniform sampling) or (7-DoF model, 14-DoF model): learned
+    sampling, each query with its robot's model (the group computes the
+    mixture in the launch).  Latency = completion seen by polling - arrival,
+    on the host clock."""
     pool, tried = pool
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_queries))
     picks = rng.integers(0, len(pool), n_queries)
     prm = P.prrtc_plan_params_default()
     prm.max_rounds, prm.time_budget_ms = max_rounds, budget_ms
+    if models is not None:
+        prm.sampler, prm.model_id, prm.mix = 1, models[0], 0.5
     tune = None
+    if workers is not None:
+        prm.tile = tile
     if workers is None:
         # launch shape from the autotuner on a sample of the pool
         sample = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
@@ -253,7 +297,7 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
             now = time.perf_counter() - t0
             while nxt < n_queries and arrivals[nxt] <= now:
                 rid, sid, s, g, kind = pool[picks[nxt]]
-                t = P.prrtc_submit(ctx, rid, sid, s, g, seed + nxt, 0)
+                t = P.prrtc_submit(ctx, rid, sid, s, g, seed + nxt, 0, -1 if models is None else models[kind])
                 if t is None:
                     refused += 1
                     break
@@ -271,7 +315,8 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
     lat = (done - arrivals) * 1e3
     ok = status == P.PRRTC_OK
     span = float(np.nanmax(done))
-    return {"workload": "serve_mixed_r7_r14", "queries": n_queries, "rate_per_s": rate, "workers": workers,
+    return {"workload": "serve_mixed_r7_r14", "sampler": "uniform" if models is None else "learned",
+            "queries": n_queries, "rate_per_s": rate, "workers": workers, "tile": int(prm.tile),
             "slots": slots, "max_pending": max_pending, "memory_budget_bytes": budget, "success": float(ok.mean()),
             "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
             "queries_per_s": n_queries / span, "launches": launches, "mean_batch": n_queries / max(launches, 1),
@@ -371,7 +416,8 @@ def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
     flop = 3 * epochs * (n_samples * fwd_sample + ds.vox.shape[0] * fwd_scene)
     nll = PR.mean_nll(P, ctx, torch, mid, rid, ev, robot["q_lo"], robot["q_hi"])
     cmp = PR.compare(P, ctx, torch, mid, rid, robot, n_eval, log=log)
-    return {"workload": "learned_r7_mixed_scenes", "train_scenes": n_train, "solved_scenes": int(ds.vox.shape[0]),
+    return {"_model": mid, "workload": "learned_r7_mixed_scenes", "train_scenes": n_train,
+            "solved_scenes": int(ds.vox.shape[0]),
             "samples": n_samples, "epochs": epochs, "datagen_s": gen_s, "train_s": train_s,
             "train_samples_per_s": epochs * n_samples / train_s,
             "train_tflops": flop / train_s / 1e12, "bf16_peak_tflops": 2500.0,
@@ -419,28 +465,50 @@ def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=S
         res[name] = {"queries": len(a), "success": float(a[:, 0].mean()), **pcts(t),
                      "mean_rounds_solved": float(a[a[:, 0] > 0, 2].mean()) if a[:, 0].any() else None}
         log("  shelf %s: %s" % (name, res[name]))
-    return {"workload": "learned_r14_shelf", "train_queries": n_train, "solved_train_queries": int(ds.vox.shape[0]),
+    return {"_model": mid, "workload": "learned_r14_shelf", "train_queries": n_train,
+            "solved_train_queries": int(ds.vox.shape[0]),
             "samples": int(len(ds.scene_of)), "epochs": epochs, "datagen_s": gen_s,
             "loss_first_epoch": float(losses[0]) if len(losses) else None,
             "loss_last_epoch": float(losses[-1]) if len(losses) else None,
             "time_budget_ms": budget_ms, "path_tail": tail, "plain": res["plain"], "learned": res["learned"]}
 
 
-def cpu_baseline(ce, budget_s=12.0):
-    """The oracle (serial C, FP64, boolean mode with early exit) on one host
-    core over a growing prefix of the same batch until the budget is spent."""
+def host_cpu():
+    """Model name and logical CPU counts of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(ce, max_threads=16):
+    """The oracle (C, FP64, boolean mode: each edge stops at its first
+    colliding point) on the host: OpenMP over the full 2^20-edge batch on the
+    cores this process may use (at most 16), and one core on the first 65,536
+    edges.  Also returns the oracle's verdicts of the full batch."""
     import oracle
     rob = oracle.OracleRobot(ce["robot"])
-    n, t = 0, 0.0
-    chunk = 4096
+    model, nproc, avail = host_cpu()
+    threads = max(1, min(max_threads, avail))
     t0 = time.perf_counter()
-    while t < budget_s and n < N_EDGES:
-        oracle.check_edges(rob, ce["prims"], ce["a"][n:n + chunk], ce["b"][n:n + chunk], RES,
-                           early_exit=True, n_threads=1)
-        n += chunk
-        t = time.perf_counter() - t0
-    return {"value": n / t, "unit": "edge checks/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} edges of the 2^20-edge batch, early-exit boolean mode, 1 thread, {t:.1f} s"}
+    v, f, _ = oracle.check_edges(rob, ce["prims"], ce["a"], ce["b"], RES, early_exit=True, n_threads=threads)
+    t_all = time.perf_counter() - t0
+    n1 = 65536
+    t0 = time.perf_counter()
+    oracle.check_edges(rob, ce["prims"], ce["a"][:n1], ce["b"][:n1], RES, early_exit=True, n_threads=1)
+    t_one = time.perf_counter() - t0
+    out = {"value": N_EDGES / t_all, "unit": "edge checks/s", "cores": threads, "kind": "oracle",
+           "sample": f"the full 2^20-edge batch, early-exit boolean mode, OpenMP on {threads} threads, {t_all:.1f} s",
+           "single_core": {"value": n1 / t_one, "unit": "edge checks/s", "cores": 1,
+                           "sample": f"first {n1} edges of the batch, 1 thread, {t_one:.1f} s"},
+           "cpu_model": model, "nproc": nproc, "cpus_available": avail}
+    return out, v.astype(bool), f.astype(bool)
 
 
 def finite_or_null(x):
@@ -503,7 +571,7 @@ def main():
         log("14-DoF shelf")
         shelf = bench_shelf(P, ctx, args.shelf_queries)
         log("  " + json.dumps(finite_or_null(shelf)))
-    serve = batch = None
+    serve = batch = pool = None
     if not args.skip_serve:
         log("batched planner: launch shapes")
         pool = query_pool(P, ctx, torch)
@@ -516,16 +584,31 @@ def main():
     if not args.skip_learned:
         log("learned proposal")
         learned = bench_learned(P, ctx, torch, args.learned_scenes, args.learned_eval, args.learned_epochs, log)
-        log("  " + json.dumps(finite_or_null(learned)))
+        log("  " + json.dumps(finite_or_null({k: v for k, v in learned.items() if k != "_model"})))
     learned_shelf = None
     if not args.skip_learned_shelf:
         log("learned proposal, dual-arm shelf")
         learned_shelf = bench_learned_shelf(P, ctx, torch, args.learned_shelf_train, args.learned_shelf_eval,
                                             args.learned_epochs, log, tail=args.learned_shelf_tail)
-        log("  " + json.dumps(finite_or_null(learned_shelf)))
+        log("  " + json.dumps(finite_or_null({k: v for k, v in learned_shelf.items() if k != "_model"})))
+    served_learned = None
+    if serve is not None and learned is not None and learned_shelf is not None:
+        # the same pool, arrivals and launch shape with learned sampling: the
+        # 7-DoF model of the generated scenes, the dual arm's shelf model
+        log("served planner, learned sampling")
+        served_learned = bench_serve(P, ctx, torch, pool, n_queries=args.serve_queries, log=log,
+                                     models=(learned["_model"], learned_shelf["_model"]),
+                                     workers=serve["workers"], tile=serve["tile"])
+        log("  " + json.dumps(finite_or_null(served_learned)))
+    for leg in (learned, learned_shelf):
+        if leg is not None:
+            leg.pop("_model", None)
     ms_per_step = ce["wall_s"] * 1e3 / args.steps
     value = N_EDGES / (ce["wall_s"] / args.steps)
-    achieved = ce["alg_flop"] / (ce["kernel_ms"] * 1e-3) / 1e12
+    alg_flop = ce["free_points"] * ce["flop_per_point_model"]
+    achieved = alg_flop / (ce["kernel_ms"] * 1e-3) / 1e12
+    reduced = ce["free_points"] * ce["flop_per_point"] / (ce["kernel_ms"] * 1e-3) / 1e12
+    free_tflops = ce["free_points"] * ce["flop_per_point_model"] / (ce["free_ms"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": value,
@@ -548,16 +631,26 @@ def main():
                      "traffic": load_traffic("k_check_edges", "r7_s64_2p20"),
                      "kernel": "k_check_edges", "kernel_ms": ce["kernel_ms"],
                      "schedule": EDGE_SCHEDULES.get(ce["schedule"], "none"),
-                     "flop_per_launch": ce["alg_flop"], "flop_per_point": ce["flop_per_point"]},
+                     "flop_per_launch": alg_flop, "flop_per_point": ce["flop_per_point_model"],
+                     "points_counted": ce["free_points"],
+                     "reduced_model": {"flop_per_point": ce["flop_per_point"], "achieved": reduced,
+                                       "frac": reduced / PEAK_FP32_TFLOPS},
+                     "collision_free_launch": {"edges": ce["free_edges"], "kernel_ms": ce["free_ms"],
+                                               "achieved": free_tflops, "frac": free_tflops / PEAK_FP32_TFLOPS,
+                                               "all_valid": ce["free_all_valid"]}},
         "ms_to_solution": plan,
         "ms_to_solution_r14_shelf": shelf,
         "batched": batch,
         "served": serve,
+        "served_learned": served_learned,
         "learned": learned,
         "learned_r14_shelf": learned_shelf,
     }
     if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(ce)
+        cb, ov, of = cpu_baseline(ce)
+        cb["gpu_verdicts_equal_unflagged"] = bool(np.array_equal(ov[~of], ce["valid"][~of]))
+        cb["flagged"] = int(of.sum())
+        out["cpu_baseline"] = cb
     P.prrtc_destroy(ctx)
     print(json.dumps(finite_or_null(out)), flush=True)
 

@@ -80,6 +80,15 @@ typedef struct {
     const float *sphere_xyzr;                  /* host [n_spheres][4] centre in frame, radius > 0 */
     int32_t n_self_pairs;                      /* 0..16384 */
     const int32_t *self_pairs;                 /* host [n_self_pairs][2] sphere indices, i != j */
+    /* Two-stage checks (Sec. III-A: a low-resolution pass over coarse spheres
+     * flags the links that may collide; only their fine spheres are checked).
+     * n_coarse = 0 (all three NULL): one stage.  Else sphere k lies inside
+     * coarse sphere sphere_coarse[k], on the same frame (|p_k - c| + r_k <=
+     * R, checked: E_ARG).  Verdicts do not change, only the work. */
+    int32_t n_coarse;                          /* 0..256 */
+    const int32_t *coarse_frame;               /* host [n_coarse] global frame id */
+    const float *coarse_xyzr;                  /* host [n_coarse][4] centre in frame, radius */
+    const int32_t *sphere_coarse;              /* host [n_spheres] coarse sphere of each sphere */
 } prrtc_robot_desc;
 
 /* Validate and copy a robot to the device.  E_ARG on non-finite values,
@@ -108,6 +117,37 @@ prrtc_status prrtc_load_scene(prrtc_ctx *ctx, const prrtc_prim *prims, int32_t n
 /* Release a scene's device memory (waits for all work on the device first).
  * Its id stays retired: later calls naming it return E_STATE. */
 prrtc_status prrtc_unload_scene(prrtc_ctx *ctx, int32_t scene_id);
+
+/*
+ * ESDF grid (Sec. III-A: with maps built from camera data, the planner checks
+ * the robot's spheres against a Euclidean signed distance field instead of
+ * primitives).  Node (i, j, k) sits at origin + voxel (i, j, k) and holds the
+ * signed distance values[(k dims[1] + j) dims[0] + i] (metres, negative
+ * inside obstacles).  A sphere (centre c, radius r) collides iff E(c) < r, E
+ * the trilinear interpolation of the node values at c, with c's grid
+ * coordinates clamped to the grid's box (outside the box the field continues
+ * as its value at the box's nearest point).  FP32 throughout.
+ */
+typedef struct {
+    float origin[3];
+    float voxel;             /* node spacing, > 0 */
+    int32_t dims[3];         /* nodes along x, y, z: each 2..1024, at most 2^27 in all */
+    const float *values;     /* host [dims[2]][dims[1]][dims[0]], no NaN */
+} prrtc_esdf_desc;
+
+/* Attach a copy of an ESDF grid to a scene (replacing any it had; desc NULL
+ * detaches it).  The scene's primitives, if any, still count: a sphere
+ * collides if it meets either.  Waits for the device; the scene's timed
+ * check_edges schedules are timed again.  E_ARG on bad geometry or NaN. */
+prrtc_status prrtc_scene_set_esdf(prrtc_ctx *ctx, int32_t scene_id, const prrtc_esdf_desc *desc);
+
+/* Build a grid from a scene's primitives (standing in for a map from camera
+ * data): values (device float32 [dims[2]][dims[1]][dims[0]]) = the signed
+ * distance of each node to the union of the primitives (the least of their
+ * signed distances; +inf for a scene without primitives), FP32.  Async on
+ * stream.  An attached grid is not part of the union. */
+prrtc_status prrtc_esdf_from_scene(prrtc_ctx *ctx, int32_t scene_id, const float origin[3], float voxel,
+                                   const int32_t dims[3], float *values, void *stream);
 
 /*
  * check_edges (Alg. 2 / Sec. III-A).  For edge e with endpoints a_e, b_e:
@@ -183,7 +223,13 @@ typedef struct {
                                 sampling radius to this; 0 (default) turns it off */
     int32_t dds_tries;       /* samples a worker draws per round until one lies
                                 within its nearest node's radius (1..64, default 1) */
-    int32_t sampler;         /* 0: uniform (default); 1: learned proposal, see below */
+    int32_t sampler;         /* 0: uniform Philox draws (default); 1: learned proposal,
+                                see below; 2: Halton points (the sampler of the paper's
+                                experiments, Sec. IV-A): point i = (low word of seed) +
+                                65536 query + (round W + worker) dds_tries + try + 1
+                                (mod 2^32), joint j the radical inverse of i in the j-th
+                                prime base (2, 3, 5, ..., 53) as the exact rational
+                                rounded to FP64 then FP32, q_j = fmaf(u, hi_j - lo_j, lo_j) */
     int32_t model_id;        /* proposal model for sampler 1; its dof must match */
     float mix;               /* sampler 1: probability that a draw comes from the
                                 mixture (0..1, default 0.5); 0 gives the uniform plan */
@@ -232,7 +278,10 @@ prrtc_status prrtc_plan(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, cons
  * each exactly as prrtc_plan would with the same parameters, seed and query
  * word (identical trees, path and statistics).  Queries may mix robots and
  * scenes; all share *params (its seed and query fields are ignored).  With
- * sampler 1 every query must use the same robot.
+ * sampler 1 each query uses its own model_id (or params->model_id) and the
+ * group that runs it computes its mixture from the scene's occupancy-grid
+ * embedding, with the arithmetic of prrtc_plan's, so learned queries also
+ * plan exactly as prrtc_plan would.
  *
  * groups: G, or 0 for as many as are resident at once (capped at n).  More
  *   than fit on the device at once is E_CAPACITY.
@@ -253,7 +302,8 @@ typedef struct {
     float start[PRRTC_MAX_DOF], goal[PRRTC_MAX_DOF];
     uint64_t seed;
     uint32_t query;
-    int32_t pad;
+    int32_t model_id;        /* sampler 1: this query's proposal model (its dof must
+                                match the robot's); -1 = params->model_id */
 } prrtc_query;
 
 typedef struct {
@@ -287,8 +337,9 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
  * (32 to 16384, and within about 256 MiB of pinned host memory for the
  * entries' arguments and paths) that the launch's worker groups take from
  * while it runs (at most `slots` in flight), and each result returns as
- * soon as its query ends.  The launch leaves after 50 ms without work and is started again by
- * the next submission; a used-up ring drains the launch and the next one
+ * soon as its query ends.  The launch closes once no query has been claimed for 50 ms
+ * (every group leaves at its next claim) and is started again by the next
+ * submission; a used-up ring drains the launch and the next one
  * starts on the reset ring.  Group buffers are sized for the largest robot
  * loaded when serving starts (robots cannot be loaded while serving).  With
  * the learned sampler it gathers queries into prrtc_plan_batch launches of

@@ -58,6 +58,16 @@ class PlanParams(C.Structure):
         ("validate_factor", C.c_int32),
         ("dds_radius", C.c_float),
         ("dds_tries", C.c_int32),
+        ("sampler", C.c_int32),
+    ]
+
+
+class Esdf(C.Structure):
+    _fields_ = [
+        ("origin", C.c_float * 3),
+        ("voxel", C.c_float),
+        ("dims", C.c_int32 * 3),
+        ("values", C.c_void_p),
     ]
 
 
@@ -100,6 +110,17 @@ def lib():
         L.orc_fk_spheres.argtypes = [P, P, P]
         L.orc_fk_spheres_batch.argtypes = [P, P, C.c_int64, P, C.c_int32]
         L.orc_fk_spheres_batch.restype = None
+        L.orc_esdf_attach.argtypes = [P]
+        L.orc_esdf_attach.restype = None
+        L.orc_esdf_value.argtypes = [P, P]
+        L.orc_esdf_value.restype = C.c_double
+        L.orc_esdf_from_prims.argtypes = [P, C.c_int32, P, C.c_float, P, P, C.c_int32]
+        L.orc_esdf_from_prims.restype = None
+        L.orc_radical_inverse.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_radical_inverse.restype = C.c_float
+        L.orc_halton_config.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint32, P, P, C.c_int32, P]
+        L.orc_halton_config.restype = None
         L.orc_clearance.argtypes = [P, C.c_double, P]
         L.orc_clearance.restype = C.c_double
         L.orc_config_clearance.argtypes = [P, P, C.c_int32, P]
@@ -269,16 +290,73 @@ def sample_config(seed: int, query: int, rnd: int, worker: int, lo, hi) -> np.nd
     return out
 
 
+class EsdfGrid:
+    """An ESDF grid for the oracle: node values [nz][ny][nx] (x fastest) at
+    origin + voxel (i, j, k).  attach() makes every clearance of the oracle
+    take it into account (one grid at a time; detach() ends it)."""
+
+    def __init__(self, origin, voxel, values):
+        self.values = np.ascontiguousarray(values, np.float32)
+        nz, ny, nx = self.values.shape
+        self.struct = Esdf((C.c_float * 3)(*[float(x) for x in origin]), float(voxel),
+                           (C.c_int32 * 3)(nx, ny, nz), self.values.ctypes.data)
+
+    def value(self, p) -> float:
+        p = np.ascontiguousarray(p, np.float64)
+        return lib().orc_esdf_value(C.byref(self.struct), _ptr(p))
+
+    def attach(self):
+        lib().orc_esdf_attach(C.byref(self.struct))
+        return self
+
+    def detach(self):
+        lib().orc_esdf_attach(None)
+
+    def __enter__(self):
+        return self.attach()
+
+    def __exit__(self, *exc):
+        self.detach()
+
+
+def esdf_of_scene(prims, origin, voxel, dims, n_threads: int = 0) -> np.ndarray:
+    """Node values of the signed distance to the union of the primitives
+    (the least signed clearance at radius 0), FP64 rounded to FP32,
+    [nz][ny][nx] for dims = (nx, ny, nz)."""
+    p = _prims(prims)
+    nx, ny, nz = (int(d) for d in dims)
+    out = np.zeros((nz, ny, nx), np.float32)
+    o = np.ascontiguousarray(origin, np.float32)
+    d = np.array([nx, ny, nz], np.int32)
+    lib().orc_esdf_from_prims(_ptr(p), p.shape[0], _ptr(o), float(voxel), _ptr(d), _ptr(out), int(n_threads))
+    return out
+
+
+def radical_inverse(i: int, base: int) -> float:
+    return float(lib().orc_radical_inverse(int(i) & 0xFFFFFFFF, int(base)))
+
+
+def halton_config(seed: int, query: int, rnd: int, worker: int, workers: int, tries: int, attempt: int,
+                  lo, hi) -> np.ndarray:
+    lo = np.ascontiguousarray(lo, np.float32)
+    hi = np.ascontiguousarray(hi, np.float32)
+    out = np.zeros(lo.shape[0], np.float32)
+    lib().orc_halton_config(int(seed), int(query), int(rnd), int(worker), int(workers), int(tries), int(attempt),
+                            _ptr(lo), _ptr(hi), lo.shape[0], _ptr(out))
+    return out
+
+
 def plan(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=256, delta=0.5, res=32.0,
          max_rounds=200, tree_capacity=1 << 16, validate_factor=4, dds_radius=0.0, dds_tries=1,
-         n_threads=0):
+         n_threads=0, sampler=0):
     """Round replay of the planner.  Returns (status, path (K, dof) or None, stats dict)."""
     p = _prims(prims)
     s = np.ascontiguousarray(start, np.float32)
     g = np.ascontiguousarray(goal, np.float32)
     pp = PlanParams(seed=seed, query=query, workers=workers, delta=delta, res=res,
                     max_rounds=max_rounds, tree_capacity=tree_capacity,
-                    validate_factor=validate_factor, dds_radius=dds_radius, dds_tries=dds_tries)
+                    validate_factor=validate_factor, dds_radius=dds_radius, dds_tries=dds_tries,
+                    sampler=sampler)
     st = PlanStats()
     cap = 4096
     path = np.zeros((cap, rob.dof), np.float32)
@@ -291,7 +369,7 @@ def plan(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=256, del
 
 def plan_trees(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=256, delta=0.5,
                res=32.0, max_rounds=200, tree_capacity=4096, validate_factor=4, dds_radius=0.0,
-               dds_tries=1, n_threads=1):
+               dds_tries=1, n_threads=1, sampler=0):
     """As plan(), also returning the final trees: (status, path, stats, trees) with
     trees = {"a": (nodes (n, dof), parent (n,), blocked (n,)), "b": (...)}."""
     p = _prims(prims)
@@ -299,7 +377,8 @@ def plan_trees(rob: OracleRobot, prims, start, goal, seed=1, query=0, workers=25
     g = np.ascontiguousarray(goal, np.float32)
     pp = PlanParams(seed=seed, query=query, workers=workers, delta=delta, res=res,
                     max_rounds=max_rounds, tree_capacity=tree_capacity,
-                    validate_factor=validate_factor, dds_radius=dds_radius, dds_tries=dds_tries)
+                    validate_factor=validate_factor, dds_radius=dds_radius, dds_tries=dds_tries,
+                    sampler=sampler)
     st = PlanStats()
     cap = 4096
     path = np.zeros((cap, rob.dof), np.float32)

@@ -189,6 +189,56 @@ double orc_clearance(const double c[3], double r, const orc_prim *p) {
     return sqrt(dz * dz + dr * dr) - r;
 }
 
+/* ---------------------------------------------------------------------------
+ * ESDF grid: trilinear interpolation of the node values (clamped coordinates).
+ * ------------------------------------------------------------------------- */
+static const orc_esdf *g_esdf = NULL;
+
+void orc_esdf_attach(const orc_esdf *g) { g_esdf = g; }
+
+double orc_esdf_value(const orc_esdf *g, const double p[3]) {
+    int32_t i0[3];
+    double t[3];
+    for (int a = 0; a < 3; a++) {
+        const int32_t n = g->dims[a];
+        double x = (p[a] - (double)g->origin[a]) / (double)g->voxel;
+        if (x < 0.0) x = 0.0;
+        if (x > (double)(n - 1)) x = (double)(n - 1);
+        int32_t i = (int32_t)floor(x);
+        if (i > n - 2) i = n - 2;
+        i0[a] = i;
+        t[a] = x - (double)i;
+    }
+    double e = 0.0;
+    for (int dz = 0; dz < 2; dz++)
+        for (int dy = 0; dy < 2; dy++)
+            for (int dx = 0; dx < 2; dx++) {
+                const double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
+                const size_t at = ((size_t)(i0[2] + dz) * g->dims[1] + (size_t)(i0[1] + dy)) * g->dims[0] +
+                                  (size_t)(i0[0] + dx);
+                e += w * (double)g->values[at];
+            }
+    return e;
+}
+
+void orc_esdf_from_prims(const orc_prim *prims, int32_t n, const float origin[3], float voxel,
+                         const int32_t dims[3], float *values, int32_t n_threads) {
+    const int64_t total = (int64_t)dims[0] * dims[1] * dims[2];
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+    for (int64_t at = 0; at < total; at++) {
+        const int64_t i = at % dims[0], j = (at / dims[0]) % dims[1], k = at / ((int64_t)dims[0] * dims[1]);
+        const double p[3] = {(double)origin[0] + (double)voxel * (double)i, (double)origin[1] + (double)voxel * (double)j,
+                             (double)origin[2] + (double)voxel * (double)k};
+        double m = INFINITY;
+        for (int32_t o = 0; o < n; o++) {
+            const double s = orc_clearance(p, 0.0, prims + o);
+            if (s < m) m = s;
+        }
+        values[at] = (float)m;
+    }
+}
+
 /* min clearance at one configuration; stops early once below stop_below. */
 static double point_clearance(const orc_robot *R, const orc_prim *prims, int32_t n_prims,
                               const double *q, double stop_below) {
@@ -202,6 +252,10 @@ static double point_clearance(const orc_robot *R, const orc_prim *prims, int32_t
             const double s = orc_clearance(buf + 3 * k, r, prims + o);
             if (s < m) m = s;
             if (m < stop_below) break;
+        }
+        if (g_esdf) {
+            const double s = orc_esdf_value(g_esdf, buf + 3 * k) - r;
+            if (s < m) m = s;
         }
     }
     for (int pidx = 0; pidx < R->n_self_pairs && m >= stop_below; pidx++) {
@@ -374,6 +428,24 @@ void orc_sample_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t w
     orc_sample_config_try(seed, query, round, worker, 0, lo, hi, dof, out);
 }
 
+/* Halton points (the sampler of the paper's experiments, Sec. IV-A). */
+float orc_radical_inverse(uint32_t i, uint32_t b) {
+    uint64_t v = 0, bm = 1; /* v / b^m with the digits reversed */
+    for (uint32_t x = i; x > 0; x /= b) {
+        v = v * b + x % b;
+        bm *= b;
+    }
+    return (float)((double)v / (double)bm);
+}
+
+static const uint32_t kPrimes[ORC_MAX_DOF] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
+
+void orc_halton_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker, uint32_t workers,
+                       uint32_t tries, uint32_t attempt, const float *lo, const float *hi, int32_t dof, float *out) {
+    const uint32_t i = (uint32_t)seed + 65536u * query + (round * workers + worker) * tries + attempt + 1u;
+    for (int j = 0; j < dof; j++) out[j] = fmaf(orc_radical_inverse(i, kPrimes[j]), hi[j] - lo[j], lo[j]);
+}
+
 /* ---------------------------------------------------------------------------
  * Planner (Alg. 1) in deterministic rounds.
  *
@@ -456,7 +528,11 @@ static void worker_round(const orc_robot *R, const orc_prim *prims, int32_t n_pr
     st->nn = -1;
     const int tries = p->dds_tries > 0 ? p->dds_tries : 1;
     for (int t = 0; t < tries; t++) {
-        orc_sample_config_try(p->seed, p->query, round, w, (uint32_t)t, R->q_lo, R->q_hi, dof, c_rand);
+        if (p->sampler == 2)
+            orc_halton_config(p->seed, p->query, round, w, (uint32_t)p->workers, (uint32_t)tries, (uint32_t)t,
+                              R->q_lo, R->q_hi, dof, c_rand);
+        else
+            orc_sample_config_try(p->seed, p->query, round, w, (uint32_t)t, R->q_lo, R->q_hi, dof, c_rand);
         const int32_t nn = orc_nearest(Ts->q, Ts->cap, ns, Ts->blocked, c_rand, dof);
         if (nn < 0) return;
         tree_get(Ts, dof, nn, c_nn);

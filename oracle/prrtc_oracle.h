@@ -66,6 +66,7 @@ typedef struct {
     int32_t validate_factor;
     float dds_radius;  /* dynamic-domain radius after a failed extension; 0 = off */
     int32_t dds_tries; /* samples drawn per worker and round before giving up */
+    int32_t sampler;   /* 0: Philox uniform draws; 2: Halton points (orc_halton_config) */
 } orc_plan_params;
 
 typedef struct {
@@ -77,6 +78,31 @@ typedef struct {
     int32_t connect_worker;
 } orc_plan_stats;
 
+/* ESDF grid (Sec. III-A: with camera-built maps the planner checks spheres
+ * against a Euclidean signed distance field instead of primitives).  Node
+ * (i, j, k) sits at origin + voxel (i, j, k); values[(k dims[1] + j) dims[0] +
+ * i] is the signed distance there.  A sphere (c, r) collides iff E(c) < r,
+ * E the trilinear interpolation of the node values, with c's grid
+ * coordinates clamped to the grid's box (outside, the field continues as its
+ * value at the nearest point of the box). */
+typedef struct {
+    float origin[3];
+    float voxel;
+    int32_t dims[3]; /* each >= 2 */
+    const float *values;
+} orc_esdf;
+
+/* The ESDF that every clearance below also takes into account (NULL: none).
+ * Test infrastructure: one grid at a time, set while no check runs. */
+void orc_esdf_attach(const orc_esdf *g);
+/* E(p): trilinear interpolation in FP64 of the FP32 node values. */
+double orc_esdf_value(const orc_esdf *g, const double p[3]);
+/* Node values of the signed distance to the union of n primitives (the least
+ * signed clearance at radius 0; +inf for none) at origin + voxel (i, j, k),
+ * in FP64 rounded to FP32; OpenMP over nodes. */
+void orc_esdf_from_prims(const orc_prim *prims, int32_t n, const float origin[3], float voxel,
+                         const int32_t dims[3], float *values, int32_t n_threads);
+
 int orc_dof(const orc_robot *R);
 int orc_n_frames(const orc_robot *R);
 
@@ -84,6 +110,16 @@ int orc_n_frames(const orc_robot *R);
 void orc_fk_frames(const orc_robot *R, const double *q, double *frames);
 /* Sphere centres in world coordinates for configuration q (float32 input). */
 void orc_fk_spheres(const orc_robot *R, const float *q, double *xyz);
+/* Radical inverse of index i in base b (van der Corput): with i's base-b
+ * digits d_0 (least significant) .. d_{m-1}, the value sum_k d_k b^-(k+1) =
+ * v / b^m as an exact rational, rounded to FP64 and then to FP32. */
+float orc_radical_inverse(uint32_t i, uint32_t b);
+/* Halton RANDOM_CONFIG (Sec. IV-A samples configurations from Halton
+ * sequences): point i = (low word of seed) + 65536 query + (round W + worker)
+ * tries + attempt + 1 (mod 2^32); joint j takes the radical inverse of i in
+ * the j-th prime base (2, 3, 5, ..., 53) and q_j = fmaf(u_j, hi_j - lo_j, lo_j). */
+void orc_halton_config(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker, uint32_t workers,
+                       uint32_t tries, uint32_t attempt, const float *lo, const float *hi, int32_t dof, float *out);
 /* orc_fk_spheres for n configurations q[n][dof] -> xyz[n][n_spheres][3],
  * OpenMP over configurations (n_threads <= 0: all). */
 void orc_fk_spheres_batch(const orc_robot *R, const float *q, int64_t n, double *xyz, int32_t n_threads);

@@ -53,7 +53,7 @@ struct EdgeCounter {
     unsigned int pad[15];
 };
 
-template <int TP, int B, bool BOX_FIRST>
+template <int TP, int B, bool BOX_FIRST, bool TWO>
 __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
                                                        const float* __restrict__ A,
                                                        const float* __restrict__ Bv,
@@ -73,6 +73,7 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
     ws.pk = reinterpret_cast<int*>(wp + 2 * kMaxDof);
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + 2;
+    two_stage_ws(R, TP, ws.sub_off + 2, ws);
     ws.shared = nullptr;   // single-wave checks share nothing
     stage_spheres(R, sph, slot3);
     load_bounds(S, ws);
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
                 rb = Bv[nx * dof + lane];
             }
             __syncthreads();
-            const int ok = fixed_hit ? 0 : (wave_check<TP, B, false, 1, BOX_FIRST>(R, S, wp, 1, 0, res, ws) == 1);
+            const int ok = fixed_hit ? 0 : (wave_check<TP, B, false, 1, BOX_FIRST, TWO>(R, S, wp, 1, 0, res, ws) == 1);
             if (lane == 0) valid[e] = (uint8_t)ok;
             __syncthreads();
         }
@@ -169,6 +170,21 @@ __global__ __launch_bounds__(kWave) void k_fk_spheres(RobotArgs R, const float* 
     }
 }
 
+// ESDF grid of a scene's primitives: each node's signed distance to their
+// union (the least signed distance; +inf with none), one thread per node.
+__global__ void k_esdf_build(SceneArgs S, float ox, float oy, float oz, float h, int nx, int ny, int nz,
+                             float* __restrict__ out) {
+    const long long at = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (at >= (long long)nx * ny * nz) return;
+    const int i = (int)(at % nx), j = (int)((at / nx) % ny), k = (int)(at / ((long long)nx * ny));
+    const float x = fmaf(h, (float)i, ox), y = fmaf(h, (float)j, oy), z = fmaf(h, (float)k, oz);
+    float m = __builtin_inff();
+    for (int o = 0; o < S.n_sph; ++o) m = fminf(m, sd_sphere(x, y, z, ld_sph(S, o)));
+    for (int o = 0; o < S.n_box; ++o) m = fminf(m, sd_box(x, y, z, ld_box(S, o)));
+    for (int o = 0; o < S.n_cyl; ++o) m = fminf(m, sd_cyl(x, y, z, ld_cyl(S, o)));
+    out[at] = m;
+}
+
 // ----------------------------------------------------------------------------
 // Host side
 // ----------------------------------------------------------------------------
@@ -190,6 +206,7 @@ struct SceneRec {
     uint64_t emb_stamp = 0;
     std::unordered_map<int, int> edge_schedule;   // robot id -> timed check_edges schedule
     int n = 0;
+    void* esdf_mem = nullptr;       // node values of an attached ESDF grid
 };
 
 }  // namespace
@@ -241,6 +258,14 @@ struct ModelRec {
 };
 
 
+// Offsets of a learned launch's tables from one base (see learned_tables).
+struct LearnedLayout {
+    size_t mdev = 0, emb = 0, vox = 0, part = 0, end = 0;
+    int n_scenes = 0, n_models = 0;
+    // query (scene row si, model row mi): its embedding
+    size_t emb_at(int si, int mi) const { return emb + sizeof(float) * kHidden * ((size_t)mi * n_scenes + si); }
+};
+
 // Device buffers of one worker group (reused by every query the group runs).
 struct GroupLayout {
     size_t qa, pa, ba, ra, qb, pb, bb, rb, bar, stage, st, path, path_idx, bytes;
@@ -283,6 +308,12 @@ struct Server {
     ServeArgs sa{};
     GroupLayout L{};
     int tree_cap = 0;
+    // learned sampling: every loaded (scene, model) pair's grid embedding, made
+    // when serving starts (nothing can be loaded while serving)
+    LearnedLayout LL{};
+    std::vector<int> scene_row;      // scene id -> row of the tables (-1: not loaded)
+    float* dev_gmm = nullptr;        // [ring][kComp (1 + 2 kMaxDof)] the queries' mixtures
+    char* ring_base = nullptr;       // device: what the ring's and tables' offsets count from
 };
 
 struct prrtc_ctx {
@@ -301,8 +332,8 @@ struct prrtc_ctx {
     EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
     unsigned counter_next = 0;
     std::unordered_map<uint64_t, int> plan_per_cu;   // resident planner workgroups per CU by (tile, LDS bytes)
-    int edge_grid[2] = {0, 0};         // resident workgroups of each k_check_edges schedule (cached)
-    size_t edge_grid_lds[2] = {0, 0};
+    int edge_grid[4] = {0, 0, 0, 0};   // resident workgroups of each k_check_edges kernel (cached)
+    size_t edge_grid_lds[4] = {0, 0, 0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float* pinned = nullptr;           // kPinnedFloats of pinned host staging
     float* scratch = nullptr;          // this device's address of the static scratch array
@@ -418,6 +449,7 @@ void prrtc_destroy(prrtc_ctx* ctx) {
         hipFree(s.dev_args);
         if (s.vox) hipFree(s.vox);
         if (s.emb) hipFree(s.emb);
+        if (s.esdf_mem) hipFree(s.esdf_mem);
     }
     planner_free(ctx->plan);
     planner_free(ctx->batch);
@@ -468,6 +500,27 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
         if (!finite_all(d->sphere_xyzr + 4 * k, 4) || !(d->sphere_xyzr[4 * k + 3] > 0.0f))
             return fail(ctx, PRRTC_E_ARG, "sphere %d: not finite or radius <= 0", k);
     }
+    // coarse spheres (two-stage checks): each fine sphere names one on its
+    // own frame that encloses it
+    const int nc = d->n_coarse;
+    if (nc < 0 || nc > PRRTC_MAX_SPHERES || (nc > 0 && (!d->coarse_frame || !d->coarse_xyzr || !d->sphere_coarse)))
+        return fail(ctx, PRRTC_E_ARG, "n_coarse must be in 0..%d with its tables", PRRTC_MAX_SPHERES);
+    for (int c = 0; c < nc; ++c)
+        if (d->coarse_frame[c] < 0 || d->coarse_frame[c] >= n_frames || !finite_all(d->coarse_xyzr + 4 * c, 4) ||
+            !(d->coarse_xyzr[4 * c + 3] > 0.0f))
+            return fail(ctx, PRRTC_E_ARG, "coarse sphere %d: bad frame, not finite or radius <= 0", c);
+    for (int k = 0; nc > 0 && k < ns; ++k) {
+        const int c = d->sphere_coarse[k];
+        if (c < 0 || c >= nc || d->coarse_frame[c] != d->sphere_frame[k])
+            return fail(ctx, PRRTC_E_ARG, "sphere %d: coarse sphere out of range or on another frame", k);
+        const float* f = d->sphere_xyzr + 4 * k;
+        const float* g = d->coarse_xyzr + 4 * c;
+        const double dist = std::sqrt(((double)f[0] - g[0]) * ((double)f[0] - g[0]) +
+                                      ((double)f[1] - g[1]) * ((double)f[1] - g[1]) +
+                                      ((double)f[2] - g[2]) * ((double)f[2] - g[2]));
+        if (dist + (double)f[3] > (double)g[3] * (1.0 + 1e-6) + 1e-7)
+            return fail(ctx, PRRTC_E_ARG, "sphere %d is not inside its coarse sphere %d", k, c);
+    }
     const int np = d->n_self_pairs;
     if (np < 0 || np > PRRTC_MAX_SELF_PAIRS || (np > 0 && !d->self_pairs))
         return fail(ctx, PRRTC_E_ARG, "n_self_pairs must be in 0..%d", PRRTC_MAX_SELF_PAIRS);
@@ -485,8 +538,11 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     std::vector<int> order;
     for (int k = 0; k < ns; ++k)
         if (!is_fixed(k)) order.push_back(k);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return d->sphere_frame[x] > d->sphere_frame[y]; });
+    // (with coarse spheres: the fine spheres of one coarse sphere side by side)
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (d->sphere_frame[x] != d->sphere_frame[y]) return d->sphere_frame[x] > d->sphere_frame[y];
+        return nc > 0 && d->sphere_coarse[x] < d->sphere_coarse[y];
+    });
     const int n_move = (int)order.size();
     for (int k = 0; k < ns; ++k)
         if (is_fixed(k)) order.push_back(k);
@@ -542,6 +598,21 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
             pairs.clear();  // covered group against group
         }
     }
+    // coarse spheres on moving frames, in the order of their fine runs
+    std::vector<float4> csph;
+    std::vector<int> cslot3, cfirst;
+    if (nc > 0) {
+        for (int k = 0; k < n_move; ++k) {
+            const int c = d->sphere_coarse[order[k]];
+            if (k == 0 || c != d->sphere_coarse[order[k - 1]]) {
+                const float* g = d->coarse_xyzr + 4 * c;
+                csph.push_back(make_float4(g[0], g[1], g[2], g[3] + kCoarseMargin));
+                cslot3.push_back(3 * frame_slot[d->coarse_frame[c]]);
+                cfirst.push_back(k);
+            }
+        }
+        cfirst.push_back(n_move);
+    }
     const size_t o_sph = 0;
     const size_t o_frame = align_up<int>(o_sph + sizeof(float4) * ns);
     const size_t o_slot = align_up<int>(o_frame + sizeof(int) * ns);
@@ -550,7 +621,10 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     const size_t o_spairs = align_up<int>(o_pairs + sizeof(int2) * pairs.size());
     const size_t o_bipa = align_up<int>(o_spairs + sizeof(int2) * spairs.size());
     const size_t o_bipb = align_up<int>(o_bipa + sizeof(int) * bip_a.size());
-    const size_t bytes = align_up<int>(o_bipb + sizeof(int) * bip_b.size());
+    const size_t o_csph = align_up<int>(o_bipb + sizeof(int) * bip_b.size());
+    const size_t o_cslot = align_up<int>(o_csph + sizeof(float4) * csph.size());
+    const size_t o_cfirst = align_up<int>(o_cslot + sizeof(int) * cslot3.size());
+    const size_t bytes = align_up<int>(o_cfirst + sizeof(int) * cfirst.size());
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     RobotRec rec;
     PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
@@ -564,6 +638,9 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     if (!spairs.empty()) memcpy(host.data() + o_spairs, spairs.data(), sizeof(int2) * spairs.size());
     if (!bip_a.empty()) memcpy(host.data() + o_bipa, bip_a.data(), sizeof(int) * bip_a.size());
     if (!bip_b.empty()) memcpy(host.data() + o_bipb, bip_b.data(), sizeof(int) * bip_b.size());
+    if (!csph.empty()) memcpy(host.data() + o_csph, csph.data(), sizeof(float4) * csph.size());
+    if (!cslot3.empty()) memcpy(host.data() + o_cslot, cslot3.data(), sizeof(int) * cslot3.size());
+    if (!cfirst.empty()) memcpy(host.data() + o_cfirst, cfirst.data(), sizeof(int) * cfirst.size());
     hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(rec.mem);
@@ -605,6 +682,10 @@ prrtc_status prrtc_load_robot(prrtc_ctx* ctx, const prrtc_robot_desc* d, int32_t
     A.n_bip_b = (int)bip_b.size();
     A.bip_a = reinterpret_cast<const int*>(base + o_bipa);
     A.bip_b = reinterpret_cast<const int*>(base + o_bipb);
+    A.n_cmove = (int)csph.size();
+    A.csph = reinterpret_cast<const float4*>(base + o_csph);
+    A.cslot3 = reinterpret_cast<const int*>(base + o_cslot);
+    A.cfirst = reinterpret_cast<const int*>(base + o_cfirst);
     rec.dof = dof;
     rec.n_spheres = ns;
     e = hipMalloc(&rec.dev_args, sizeof(RobotArgs));
@@ -758,7 +839,112 @@ prrtc_status prrtc_unload_scene(prrtc_ctx* ctx, int32_t scene_id) {
     PRRTC_HIP(ctx, hipFree(rec.dev_args));
     if (rec.vox) PRRTC_HIP(ctx, hipFree(rec.vox));
     if (rec.emb) PRRTC_HIP(ctx, hipFree(rec.emb));
+    if (rec.esdf_mem) PRRTC_HIP(ctx, hipFree(rec.esdf_mem));
     rec = SceneRec{};
+    return PRRTC_OK;
+}
+
+namespace {
+bool esdf_geometry_ok(prrtc_ctx* ctx, const float origin[3], float voxel, const int32_t dims[3]) {
+    if (!finite_all(origin, 3) || !(voxel > 0.0f) || !std::isfinite(voxel)) {
+        fail(ctx, PRRTC_E_ARG, "ESDF origin must be finite and voxel > 0");
+        return false;
+    }
+    long long total = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] < 2 || dims[a] > 1024) {
+            fail(ctx, PRRTC_E_ARG, "ESDF dims must be in 2..1024");
+            return false;
+        }
+        total *= dims[a];
+    }
+    if (total > (1LL << 27)) {
+        fail(ctx, PRRTC_E_ARG, "ESDF of %lld nodes exceeds 2^27", total);
+        return false;
+    }
+    return true;
+}
+}  // namespace
+
+prrtc_status prrtc_scene_set_esdf(prrtc_ctx* ctx, int32_t scene_id, const prrtc_esdf_desc* d) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
+    if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
+        return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
+    SceneRec& rec = ctx->scenes[scene_id];
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    void* mem = nullptr;
+    SceneArgs args = rec.args;
+    if (d) {
+        if (!esdf_geometry_ok(ctx, d->origin, d->voxel, d->dims)) return PRRTC_E_ARG;
+        if (!d->values) return fail(ctx, PRRTC_E_ARG, "null ESDF values");
+        const size_t n = (size_t)d->dims[0] * d->dims[1] * d->dims[2];
+        for (size_t k = 0; k < n; ++k)
+            if (std::isnan(d->values[k])) return fail(ctx, PRRTC_E_ARG, "ESDF value %zu is NaN", k);
+        PRRTC_HIP(ctx, hipMalloc(&mem, sizeof(float) * n));
+        hipError_t e = hipMemcpy(mem, d->values, sizeof(float) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return fail(ctx, PRRTC_E_HIP, "ESDF upload: %s", hipGetErrorString(e));
+        }
+        args.esdf = static_cast<const float*>(mem);
+        for (int a = 0; a < 3; ++a) {
+            args.esdf_o[a] = d->origin[a];
+            args.esdf_n[a] = d->dims[a];
+        }
+        args.esdf_ih = 1.0f / d->voxel;
+        // Lipschitz bound of the interpolated field: per axis the largest
+        // difference of neighbouring nodes over the spacing
+        double lip2 = 0.0;
+        const int nx = d->dims[0], ny = d->dims[1], nz = d->dims[2];
+        for (int a = 0; a < 3; ++a) {
+            const size_t step = a == 0 ? 1 : (a == 1 ? (size_t)nx : (size_t)nx * ny);
+            double m = 0.0;
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        if ((a == 0 && i == nx - 1) || (a == 1 && j == ny - 1) || (a == 2 && k == nz - 1)) continue;
+                        const size_t at = ((size_t)k * ny + j) * nx + i;
+                        const double diff = std::fabs((double)d->values[at + step] - (double)d->values[at]);
+                        if (!(diff <= m)) m = diff;   // also takes an infinite difference
+                    }
+            const double l = m / (double)d->voxel;
+            lip2 += l * l;
+        }
+        args.esdf_gate = (float)std::max(1.0, std::sqrt(lip2) * (1.0 + 1e-6));
+    } else {
+        args.esdf = nullptr;
+    }
+    // the device copy of the tables changes: wait for work that may read it
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(rec.dev_args, &args, sizeof(SceneArgs), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (mem) (void)hipFree(mem);
+        return fail(ctx, PRRTC_E_HIP, "scene tables: %s", hipGetErrorString(e));
+    }
+    if (rec.esdf_mem) (void)hipFree(rec.esdf_mem);
+    rec.esdf_mem = mem;
+    rec.args = args;
+    rec.edge_schedule.clear();   // the check_edges schedules are timed again
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_esdf_from_scene(prrtc_ctx* ctx, int32_t scene_id, const float origin[3], float voxel,
+                                   const int32_t dims[3], float* values, void* stream) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    PRRTC_NOT_SERVING(ctx);
+    if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].mem)
+        return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
+    if (!origin || !dims || !values) return fail(ctx, PRRTC_E_ARG, "null argument");
+    if (!esdf_geometry_ok(ctx, origin, voxel, dims)) return PRRTC_E_ARG;
+    PRRTC_HIP(ctx, hipSetDevice(ctx->device));
+    const long long n = (long long)dims[0] * dims[1] * dims[2];
+    hipLaunchKernelGGL(k_esdf_build, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       ctx->scenes[scene_id].args, origin[0], origin[1], origin[2], voxel, dims[0], dims[1], dims[2],
+                       values);
+    PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
 }
 
@@ -780,10 +966,14 @@ constexpr int kEdgeItems = PRRTC_EDGE_ITEMS;
 // (measured: 2 items with cuboids first is 10% faster on the 7-DoF arm among
 // 64 mixed obstacles, 3 items with spheres first 8% faster on the dual arm
 // in the shelf), so the first large batch on a (robot, scene) pair times both.
-const void* edge_kernel(int schedule) {
-    static const void* k[2] = {reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false>),
-                               reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true>)};
-    return k[schedule];
+// two: the robot has coarse spheres (the two-stage instantiations).
+const void* edge_kernel(int schedule, bool two) {
+    static const void* k[2][2] = {
+        {reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false, false>),
+         reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true, false>)},
+        {reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false, true>),
+         reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true, true>)}};
+    return k[two ? 1 : 0][schedule];
 }
 constexpr long long kEdgeTuneMin = 8192;      // batches at least this large pick the schedule
 constexpr long long kEdgeTuneEdges = 1 << 20;  // edges timed per schedule (at most): small prefixes
@@ -795,7 +985,7 @@ size_t sphere_lds_bytes(const RobotArgs& R) {
 
 size_t check_lds_bytes(const RobotArgs& R, int tp) {
     return sphere_lds_bytes(R) + sizeof(float4) * tp * 3 * R.n_slots + sizeof(float) * 2 * kMaxDof +
-           sizeof(int) * (tp + 4);
+           sizeof(int) * (tp + 4) + two_stage_lds_bytes(R, tp);
 }
 
 prrtc_status lookup(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const RobotRec** r,
@@ -832,15 +1022,17 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
     hipStream_t sm = static_cast<hipStream_t>(stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     const size_t lds = check_lds_bytes(r->args, kEdgeTile);
+    const bool two = r->args.n_cmove > 0;
     auto launch = [&](int schedule, long long n) -> prrtc_status {
-        if (ctx->edge_grid[schedule] == 0 || ctx->edge_grid_lds[schedule] != lds) {
+        const int kk = schedule + (two ? 2 : 0);
+        if (ctx->edge_grid[kk] == 0 || ctx->edge_grid_lds[kk] != lds) {
             int per_cu = 0;
-            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_kernel(schedule), kWave, lds));
-            ctx->edge_grid[schedule] = std::max(1, per_cu) * ctx->n_cu;
-            ctx->edge_grid_lds[schedule] = lds;
+            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_kernel(schedule, two), kWave, lds));
+            ctx->edge_grid[kk] = std::max(1, per_cu) * ctx->n_cu;
+            ctx->edge_grid_lds[kk] = lds;
         }
         // at least one workgroup per XCD range (empty ranges exit at once)
-        const long long grid = std::max<long long>(std::min<long long>(n, ctx->edge_grid[schedule]), kXcds);
+        const long long grid = std::max<long long>(std::min<long long>(n, ctx->edge_grid[kk]), kXcds);
         EdgeCounter* ctr = ctx->counters + (ctx->counter_next++ % kCounterSlots);
         RobotArgs ra = r->args;
         SceneArgs sa = s->args;
@@ -849,7 +1041,7 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
         float fres = res;
         uint8_t* pv = valid;
         void* kargs[] = {&ra, &sa, &pa, &pb, &n, &fres, &pv, &ctr};
-        PRRTC_HIP(ctx, hipLaunchKernel(edge_kernel(schedule), dim3((unsigned)grid), dim3(kWave), kargs, lds, sm));
+        PRRTC_HIP(ctx, hipLaunchKernel(edge_kernel(schedule, two), dim3((unsigned)grid), dim3(kWave), kargs, lds, sm));
         return PRRTC_OK;
     };
     SceneRec& sr = ctx->scenes[scene_id];
@@ -936,18 +1128,25 @@ namespace {
 #ifndef PRRTC_PLAN_WAVES
 #define PRRTC_PLAN_WAVES 4
 #endif
+// kernel[1] / serve[1]: with the two-stage pass (robots with coarse spheres).
 struct PlanShape {
     int tile, items, waves;
-    const void* kernel;
-    const void* serve;   // the persistent serving kernel of the same shape
+    const void* kernel[2];
+    const void* serve[2];   // the persistent serving kernels of the same shape
 };
 
 const PlanShape* plan_shape(int tile) {
     static const PlanShape shapes[] = {
-        {64, 6, PRRTC_PLAN_WAVES, reinterpret_cast<const void*>(&k_plan<64, 6, PRRTC_PLAN_WAVES, 2>),
-         reinterpret_cast<const void*>(&k_serve<64, 6, PRRTC_PLAN_WAVES, 2>)},
-        {16, 3, 1, reinterpret_cast<const void*>(&k_plan<16, 3, 1, 3>),
-         reinterpret_cast<const void*>(&k_serve<16, 3, 1, 3>)},
+        {64, 6, PRRTC_PLAN_WAVES,
+         {reinterpret_cast<const void*>(&k_plan<64, 6, PRRTC_PLAN_WAVES, 2, false>),
+          reinterpret_cast<const void*>(&k_plan<64, 6, PRRTC_PLAN_WAVES, 2, true>)},
+         {reinterpret_cast<const void*>(&k_serve<64, 6, PRRTC_PLAN_WAVES, 2, false>),
+          reinterpret_cast<const void*>(&k_serve<64, 6, PRRTC_PLAN_WAVES, 2, true>)}},
+        {16, 3, 1,
+         {reinterpret_cast<const void*>(&k_plan<16, 3, 1, 3, false>),
+          reinterpret_cast<const void*>(&k_plan<16, 3, 1, 3, true>)},
+         {reinterpret_cast<const void*>(&k_serve<16, 3, 1, 3, false>),
+          reinterpret_cast<const void*>(&k_serve<16, 3, 1, 3, true>)}},
     };
     if (tile == 0) return &shapes[0];
     for (const PlanShape& sh : shapes)
@@ -1009,9 +1208,13 @@ int stage_cap_for(const RobotArgs& RA, float delta) {
     return sc > 4096 ? -1 : sc;
 }
 
+// Spheres, then the FK tile, query vectors and sub-edge tables; the tile's
+// region also holds the input of a learned query's mixture before the rounds.
 size_t plan_lds_bytes(const RobotArgs& RA, int stage_cap, int dof, int tile) {
-    return sphere_lds_bytes(RA) + sizeof(float4) * tile * 3 * RA.n_slots +
-           sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) + sizeof(int) * (tile + 2 * (stage_cap + 2));
+    const size_t body = sizeof(float4) * tile * 3 * RA.n_slots +
+                        sizeof(float) * (4 * kMaxDof + (size_t)(stage_cap + 1) * dof) +
+                        sizeof(int) * (tile + 2 * (stage_cap + 2)) + two_stage_lds_bytes(RA, tile);
+    return sphere_lds_bytes(RA) + std::max(body, sizeof(float) * kMlpInFloats);
 }
 
 prrtc_status check_plan_params(prrtc_ctx* ctx, const prrtc_plan_params& p) {
@@ -1026,7 +1229,7 @@ prrtc_status check_plan_params(prrtc_ctx* ctx, const prrtc_plan_params& p) {
     if (!(p.dds_radius >= 0.0f) || !std::isfinite(p.dds_radius))
         return fail(ctx, PRRTC_E_ARG, "dds_radius must be finite and >= 0");
     if (p.dds_tries < 1 || p.dds_tries > 64) return fail(ctx, PRRTC_E_ARG, "dds_tries must be in 1..64");
-    if (p.sampler != 0 && p.sampler != 1) return fail(ctx, PRRTC_E_ARG, "sampler must be 0 or 1");
+    if (p.sampler < 0 || p.sampler > 2) return fail(ctx, PRRTC_E_ARG, "sampler must be 0, 1 or 2");
     if (!plan_shape(p.tile)) return fail(ctx, PRRTC_E_ARG, "tile must be 0, 16 or 64");
     if (p.sampler == 1) {
         if (!(p.mix >= 0.0f && p.mix <= 1.0f)) return fail(ctx, PRRTC_E_ARG, "mix must be in [0, 1]");
@@ -1058,7 +1261,10 @@ void query_args(prrtc_ctx* ctx, PlanArgs& A, const prrtc_plan_params& p, const R
     A.validate = p.validate_factor;
     A.dds_radius = p.dds_radius;
     A.dds_tries = p.dds_tries;
+    A.halton = p.sampler == 2;
     A.gmm = nullptr;
+    A.model = nullptr;
+    A.emb = nullptr;
     A.mix = p.mix;
     A.budget_ticks = p.time_budget_ms > 0.0f ? (long long)((double)p.time_budget_ms * ctx->wall_khz) : 0;
 }
@@ -1101,12 +1307,18 @@ prrtc_status status_of(int device_status) {
 prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, SceneRec& s, const float* start,
                            const float* goal, float* qin, float* gmm, hipStream_t sm);
 
-// Mixtures for a batch: grids of the distinct scenes into vox, one forward
-// pass over all queries.  qin: [n][2 dof_max + 1] device staging.
-prrtc_status batch_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, const std::vector<int>& scene_ids,
-                            const std::vector<int>& scene_row, const std::vector<const float*>& starts,
-                            const std::vector<const float*>& goals, uint8_t* vox, float* qin, float* gmm,
-                            hipStream_t sm);
+// Device tables of a learned batched or served launch, where each worker
+// group computes its query's mixture itself (mixture_in_block): the models'
+// parameter pointers and the grid embedding of every (scene, model) pair of
+// the given scenes and models, at offsets from one base.
+LearnedLayout learned_layout(size_t base, int n_scenes, int n_models);
+// Enqueue the tables on sm (the caller synchronises before the host vectors
+// go out of scope): occupancy grids, then k_embed_partial / k_embed_reduce
+// over up to kSmallRows scenes at a time -- the kernels and order of a single
+// plan's cached embedding, so the mixtures equal a single plan's.
+prrtc_status learned_tables(prrtc_ctx* ctx, hipStream_t sm, char* m, const LearnedLayout& L,
+                            const std::vector<int>& scenes, const std::vector<int>& models,
+                            std::vector<ModelDev>& host_mdev);
 
 }  // namespace
 
@@ -1182,10 +1394,12 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
     const PlanShape& shape = *plan_shape(p.tile);
     const size_t lds = plan_lds_bytes(r->args, stage_cap, dof, shape.tile);
-    {   // the cooperative launch needs every worker resident at once (cached per shape and LDS size)
-        int& per_cu = ctx->plan_per_cu[((uint64_t)shape.tile << 40) | (uint64_t)lds];
+    const int two = r->args.n_cmove > 0 ? 1 : 0;
+    {   // the cooperative launch needs every worker resident at once (cached per kernel and LDS size)
+        int& per_cu = ctx->plan_per_cu[((uint64_t)shape.tile << 40) | ((uint64_t)two << 39) | (uint64_t)lds];
         if (per_cu == 0)
-            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.kernel, kWave * shape.waves, lds));
+            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.kernel[two], kWave * shape.waves,
+                                                                        lds));
         if ((long long)per_cu * ctx->n_cu < W)
             return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once (%d with tile %d)", W,
                         per_cu * ctx->n_cu, shape.tile);
@@ -1205,8 +1419,8 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = 1, n_g = 1;
     void* kargs[] = {&Pq, &n_q, &n_g};
-    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(shape.kernel, dim3(W), dim3(kWave * shape.waves), kargs, (unsigned)lds,
-                                              sm));
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(shape.kernel[two], dim3(W), dim3(kWave * shape.waves), kargs,
+                                              (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
     // the words and the first nodes of the path in one copy to pinned memory
     const int prefix = std::min(std::min(path_cap, 2 * cap), (kPinnedFloats - kCtlWords) / dof);
@@ -1241,6 +1455,26 @@ prrtc_status prrtc_plan(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, cons
     return PRRTC_OK;
 }
 
+namespace {
+
+// The proposal model of a learned query (its own, else the parameters'),
+// checked against its robot; -1 with *status set when it cannot be used.
+int query_model(prrtc_ctx* ctx, const prrtc_query& q, const prrtc_plan_params& p, const RobotRec& r,
+                int32_t* status) {
+    const int m = q.model_id >= 0 ? q.model_id : p.model_id;
+    if (m < 0 || m >= (int)ctx->models.size()) {
+        *status = fail(ctx, PRRTC_E_STATE, "unknown model id %d", m);
+        return -1;
+    }
+    if (ctx->models[m].L.dof != r.dof) {
+        *status = fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", ctx->models[m].L.dof, r.dof);
+        return -1;
+    }
+    return m;
+}
+
+}  // namespace
+
 static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n,
                                     const prrtc_plan_params* prm, int32_t groups, int64_t memory_budget,
                                     float* paths, int32_t path_cap, prrtc_query_result* results,
@@ -1257,6 +1491,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     const int W = p.workers, cap = p.tree_capacity;
     // host-side checks per query; rejected queries are not launched
     std::vector<int> live;
+    std::vector<int> model_of(n, -1);
     int dof_max = 1, stage_max = 1;
     size_t lds = 0;
     for (int k = 0; k < n; ++k) {
@@ -1266,11 +1501,9 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
         const SceneRec* s = nullptr;
         res.status = lookup(ctx, queries[k].robot_id, queries[k].scene_id, &r, &s);
         if (res.status == PRRTC_OK) res.status = endpoints_ok(ctx, r->args, queries[k].start, queries[k].goal);
-        if (res.status == PRRTC_OK && p.sampler == 1 && ctx->models[p.model_id].L.dof != r->dof)
-            res.status = fail(ctx, PRRTC_E_ARG, "model dof %d != robot dof %d", ctx->models[p.model_id].L.dof,
-                              r->dof);
-        if (p.sampler == 1 && queries[k].robot_id != queries[0].robot_id)
-            return fail(ctx, PRRTC_E_ARG, "a learned batch must use one robot");
+        if (res.status == PRRTC_OK && p.sampler == 1) {
+            model_of[k] = query_model(ctx, queries[k], p, *r, &res.status);
+        }
         int sc = 0;
         if (res.status == PRRTC_OK) {
             sc = stage_cap_for(r->args, p.delta);
@@ -1286,11 +1519,15 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     const int n_live = (int)live.size();
     if (n_live == 0) return PRRTC_OK;
     const GroupLayout L = group_layout(dof_max, cap, W, stage_max);
+    // the two-stage kernel when any launched query's robot has coarse spheres
+    int two = 0;
+    for (int k : live) two |= ctx->robots[queries[k].robot_id].args.n_cmove > 0 ? 1 : 0;
+    const void* kernel = plan_shape(p.tile)->kernel[two];
     // co-residency bound of the cooperative launch, then the memory budget
     int per_cu = 0;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                       &per_cu, plan_shape(p.tile)->kernel, kWave * plan_shape(p.tile)->waves, lds));
+    PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave * plan_shape(p.tile)->waves,
+                                                                lds));
     const int g_resident = per_cu * ctx->n_cu / W;
     if (g_resident < 1) return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once", W);
     int G = groups > 0 ? groups : std::min(n_live, g_resident);
@@ -1305,15 +1542,30 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
         G = (int)std::min<long long>(G, fit);
     }
     if (groups_used) *groups_used = G;
-    // device memory: groups | query words | arguments | paths | proposal staging
+    // learned queries: the distinct scenes and models, whose embeddings the
+    // groups start from
+    std::vector<int> scenes_used, models_used, scene_row(n_live, -1), model_row(n_live, -1);
+    if (p.sampler == 1) {
+        auto row_of = [](std::vector<int>& v, int x) {
+            for (size_t t = 0; t < v.size(); ++t)
+                if (v[t] == x) return (int)t;
+            v.push_back(x);
+            return (int)v.size() - 1;
+        };
+        for (int i = 0; i < n_live; ++i) {
+            scene_row[i] = row_of(scenes_used, queries[live[i]].scene_id);
+            model_row[i] = row_of(models_used, model_of[live[i]]);
+        }
+    }
+    // device memory: groups | query words | arguments | paths | learned tables | mixtures
     const int Cw = kComp * (1 + 2 * kMaxDof);
     const size_t o_ctl = (size_t)G * L.bytes;
     const size_t o_next = align_up<int>(o_ctl + sizeof(int) * kCtlWords * (size_t)n_live);
     const size_t o_args = align_up<int>(o_next + sizeof(int));
     const size_t o_path = align_up<int>(o_args + sizeof(PlanArgs) * (size_t)n_live);
-    const size_t o_vox = align_up<int>(o_path + sizeof(float) * (size_t)path_cap * kMaxDof * n_live);
-    const size_t o_qin = align_up<int>(o_vox + (p.sampler == 1 ? (size_t)kVoxCells * n_live : 0));
-    const size_t o_gmm = align_up<int>(o_qin + (p.sampler == 1 ? sizeof(float) * (2 * kMaxDof + 1) * n_live : 0));
+    const size_t o_learn = align_up<int>(o_path + sizeof(float) * (size_t)path_cap * kMaxDof * n_live);
+    const LearnedLayout LL = learned_layout(o_learn, (int)scenes_used.size(), (int)models_used.size());
+    const size_t o_gmm = align_up<int>(LL.end);
     const size_t bytes = align_up<int>(o_gmm + (p.sampler == 1 ? sizeof(float) * Cw * (size_t)n_live : 0));
     if (ctx->batch.bytes < bytes) {
         planner_free(ctx->batch);
@@ -1324,26 +1576,9 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     hipStream_t sm = ctx->stream;
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
     float* gmm = reinterpret_cast<float*>(m + o_gmm);
+    std::vector<ModelDev> host_mdev;
     if (p.sampler == 1) {
-        // one forward pass over all launched queries (they share the model, hence the robot's dof)
-        std::vector<int> scene_ids, scene_row;
-        std::vector<const float*> starts, goals;
-        for (int i = 0; i < n_live; ++i) {
-            const prrtc_query& q = queries[live[i]];
-            int row = -1;
-            for (size_t t = 0; t < scene_ids.size(); ++t)
-                if (scene_ids[t] == q.scene_id) row = (int)t;
-            if (row < 0) {
-                row = (int)scene_ids.size();
-                scene_ids.push_back(q.scene_id);
-            }
-            scene_row.push_back(row);
-            starts.push_back(q.start);
-            goals.push_back(q.goal);
-        }
-        st = batch_proposal(ctx, p.model_id, ctx->robots[queries[live[0]].robot_id], scene_ids, scene_row, starts,
-                            goals, reinterpret_cast<uint8_t*>(m + o_vox), reinterpret_cast<float*>(m + o_qin), gmm,
-                            sm);
+        st = learned_tables(ctx, sm, m, LL, scenes_used, models_used, host_mdev);
         if (st != PRRTC_OK) return st;
     }
     std::vector<PlanArgs> args(n_live);
@@ -1359,7 +1594,11 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
         A.ctl = reinterpret_cast<int*>(m + o_ctl) + (size_t)kCtlWords * i;
         A.out_path = reinterpret_cast<float*>(m + o_path) + (size_t)path_cap * kMaxDof * i;
         A.out_path_cap = path_cap;
-        if (p.sampler == 1) A.gmm = gmm + (size_t)ctx->models[p.model_id].L.Cw * i;
+        if (p.sampler == 1) {
+            A.gmm = gmm + (size_t)Cw * i;
+            A.model = reinterpret_cast<const ModelDev*>(m + LL.mdev) + model_row[i];
+            A.emb = reinterpret_cast<const float*>(m + LL.emb_at(scene_row[i], model_row[i]));
+        }
     }
     PlanArgs* Pq = reinterpret_cast<PlanArgs*>(m + o_args);
     PRRTC_HIP(ctx, hipMemcpyAsync(Pq, args.data(), sizeof(PlanArgs) * n_live, hipMemcpyHostToDevice, sm));
@@ -1372,7 +1611,7 @@ static prrtc_status plan_batch_impl(prrtc_ctx* ctx, const prrtc_query* queries, 
     PRRTC_HIP(ctx, hipGetLastError());
     int n_q = n_live, n_g = G;
     void* kargs[] = {&Pq, &n_q, &n_g};
-    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(plan_shape(p.tile)->kernel, dim3((unsigned)(G * W)),
+    PRRTC_HIP(ctx, hipLaunchCooperativeKernel(kernel, dim3((unsigned)(G * W)),
                                               dim3(kWave * plan_shape(p.tile)->waves), kargs, (unsigned)lds, sm));
     PRRTC_HIP(ctx, hipEventRecord(ctx->ev1, sm));
     std::vector<int> ctl((size_t)kCtlWords * n_live);
@@ -1511,9 +1750,9 @@ void serve_loop(prrtc_ctx* ctx) {
 
 // Persistent mode: one k_serve launch takes queries as they are published
 // into the ring; results come back through host memory as each query ends.
-// The launch leaves after kServeIdleMs without work (relaunched on the next
-// submission) or, once the ring is used up, after draining; the ring then
-// starts again at slot 0 with the next launch.
+// The launch closes once no group has claimed a query for kServeIdleMs
+// (relaunched on the next submission) or, once the ring is used up, drains;
+// the ring then starts again at slot 0 with the next launch.
 constexpr double kServeIdleMs = 50.0;
 
 void serve_result(prrtc_ctx* ctx, Server& S, uint64_t ticket, int k, const prrtc_query& q, double ms) {
@@ -1589,6 +1828,12 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
                     stage_cap = stage_cap_for(r->args, p.delta);
                     if (stage_cap < 0) st = PRRTC_E_ARG;
                 }
+                int model = -1;
+                if (st == PRRTC_OK && p.sampler == 1) {
+                    int32_t mst = PRRTC_OK;
+                    model = query_model(ctx, q, p, *r, &mst);
+                    st = (prrtc_status)mst;
+                }
                 if (st != PRRTC_OK) {
                     ServeDone d;
                     d.res.status = st;
@@ -1604,6 +1849,12 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
                 A.ctl = S.sa.dev_ctl + (size_t)k * kCtlWords;
                 A.out_path = S.sa.dev_path + (size_t)k * S.path_stride;
                 A.out_path_cap = S.path_stride / r->dof;
+                if (p.sampler == 1) {
+                    // the group computes the mixture (every model is a table row, by id)
+                    A.gmm = S.dev_gmm + (size_t)k * kComp * (1 + 2 * kMaxDof);
+                    A.model = reinterpret_cast<const ModelDev*>(S.ring_base + S.LL.mdev) + model;
+                    A.emb = reinterpret_cast<const float*>(S.ring_base + S.LL.emb_at(S.scene_row[q.scene_id], model));
+                }
                 __atomic_store_n(S.host_ctl + (size_t)k * (kCtlWords + 1), 0, __ATOMIC_RELAXED);
                 ticket_of[k] = t;
                 query_of[k] = q;
@@ -1712,12 +1963,13 @@ void serve_free_persistent(Server& S) {
 prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
     const prrtc_plan_params& p = S.params;
     const PlanShape& shape = *plan_shape(p.tile);
-    int dof_max = 0, stage_max = 1;
+    int dof_max = 0, stage_max = 1, two = 0;
     size_t lds = 0;
     for (const RobotRec& r : ctx->robots) {
         if (!r.dev_args) continue;
         const int sc = stage_cap_for(r.args, p.delta);
         if (sc < 0) return fail(ctx, PRRTC_E_ARG, "delta too small for a loaded robot's joint range");
+        two |= r.args.n_cmove > 0 ? 1 : 0;
         dof_max = std::max(dof_max, r.dof);
         stage_max = std::max(stage_max, sc);
         lds = std::max(lds, plan_lds_bytes(r.args, sc, r.dof, shape.tile));
@@ -1727,7 +1979,7 @@ prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
     S.tree_cap = p.tree_capacity;
     S.L = group_layout(dof_max, p.tree_capacity, S.W, stage_max);
     S.lds = lds;
-    S.kernel = shape.serve;
+    S.kernel = shape.serve[two];
     S.path_stride = S.path_cap * dof_max;
     // ring entries: 64 x slots, at most kServeRingMax and about 256 MiB of
     // pinned host memory (arguments, words and path of each entry)
@@ -1736,7 +1988,7 @@ prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
     S.ring = std::min({kServeRingMax, std::max(32, 64 * S.slots), by_memory});
     int per_cu = 0;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shape.serve, kWave * shape.waves, lds));
+    PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S.kernel, kWave * shape.waves, lds));
     int G = per_cu * ctx->n_cu / S.W;
     if (G < 1) return fail(ctx, PRRTC_E_CAPACITY, "%d workers do not fit on the device at once", S.W);
     const size_t R = (size_t)S.ring;
@@ -1745,7 +1997,20 @@ prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
     const size_t o_path = align_up<int>(o_ctl + sizeof(int) * kCtlWords * R);
     const size_t o_next = align_up<int>(o_path + sizeof(float) * S.path_stride * R);
     const size_t o_sa = align_up<int>(o_next + 256);
-    const size_t ring_bytes = align_up<int>(o_sa + sizeof(ServeArgs));
+    std::vector<int> scenes_used, models_used;
+    if (p.sampler == 1) {
+        S.scene_row.assign(ctx->scenes.size(), -1);
+        for (size_t i = 0; i < ctx->scenes.size(); ++i)
+            if (ctx->scenes[i].mem) {
+                S.scene_row[i] = (int)scenes_used.size();
+                scenes_used.push_back((int)i);
+            }
+        for (size_t i = 0; i < ctx->models.size(); ++i) models_used.push_back((int)i);
+    }
+    S.LL = learned_layout(align_up<int>(o_sa + sizeof(ServeArgs)), (int)scenes_used.size(), (int)models_used.size());
+    const size_t o_gmm = align_up<int>(S.LL.end);
+    const size_t ring_bytes =
+        align_up<int>(o_gmm + (p.sampler == 1 ? sizeof(float) * kComp * (1 + 2 * kMaxDof) * R : 0));
     if (S.budget > 0) {
         const long long fit = (S.budget - (long long)ring_bytes) / (long long)S.L.bytes;
         if (fit < 1) return fail(ctx, PRRTC_E_CAPACITY, "memory budget below one worker group");
@@ -1797,6 +2062,19 @@ prrtc_status serve_setup_persistent(prrtc_ctx* ctx, Server& S) {
         serve_free_persistent(S);
         return fail(ctx, PRRTC_E_HIP, "serving arguments: %s", hipGetErrorString(e));
     }
+    S.ring_base = dr;
+    if (p.sampler == 1) {
+        // the LearnedLayout offsets count from the ring's base
+        S.dev_gmm = reinterpret_cast<float*>(dr + o_gmm);
+        std::vector<ModelDev> host_mdev;
+        prrtc_status st = learned_tables(ctx, ctx->stream, dr, S.LL, scenes_used, models_used, host_mdev);
+        if (st == PRRTC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess)
+            st = fail(ctx, PRRTC_E_HIP, "serving: grid embeddings failed");
+        if (st != PRRTC_OK) {
+            serve_free_persistent(S);
+            return st;
+        }
+    }
     return PRRTC_OK;
 }
 
@@ -1838,7 +2116,7 @@ prrtc_status prrtc_serve_start(prrtc_ctx* ctx, const prrtc_plan_params* params, 
     S->max_pending = max_pending;
     S->budget = memory_budget;
     S->path_cap = path_cap;
-    if (params->sampler == 0 && PRRTC_SERVE_PERSISTENT) {
+    if (PRRTC_SERVE_PERSISTENT) {
         st = serve_setup_persistent(ctx, *S);
         if (st != PRRTC_OK) return st;
     }
@@ -2110,31 +2388,49 @@ prrtc_status plan_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, 
     return PRRTC_OK;
 }
 
-prrtc_status batch_proposal(prrtc_ctx* ctx, int32_t model_id, const RobotRec& r, const std::vector<int>& scene_ids,
-                            const std::vector<int>& scene_row, const std::vector<const float*>& starts,
-                            const std::vector<const float*>& goals, uint8_t* vox, float* qin, float* gmm,
-                            hipStream_t sm) {
-    ModelRec& M = ctx->models[model_id];
-    const int dof = r.dof;
-    const int n = (int)starts.size(), S = (int)scene_ids.size();
-    for (int t = 0; t < S; ++t)
-        hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, sm, ctx->scenes[scene_ids[t]].args,
-                           vox + (size_t)t * kVoxCells);
-    PropWs W;
-    prrtc_status st = prop_workspace(ctx, M, n, S, W);
-    if (st != PRRTC_OK) return st;
-    // [n][dof] starts | [n][dof] goals | [n] scene rows; the host staging
-    // stays untouched until the batch has synchronised
-    std::vector<float>& h = ctx->stage_host;
-    h.assign((size_t)2 * n * dof + n, 0.0f);
-    for (int i = 0; i < n; ++i) {
-        memcpy(&h[(size_t)i * dof], starts[i], sizeof(float) * dof);
-        memcpy(&h[(size_t)(n + i) * dof], goals[i], sizeof(float) * dof);
-        memcpy(&h[(size_t)2 * n * dof + i], &scene_row[i], sizeof(int));
+LearnedLayout learned_layout(size_t base, int n_scenes, int n_models) {
+    LearnedLayout L;
+    L.n_scenes = n_scenes;
+    L.n_models = n_models;
+    if (n_scenes == 0 || n_models == 0) {
+        L.mdev = L.emb = L.vox = L.part = L.end = base;
+        return L;
     }
-    PRRTC_HIP(ctx, hipMemcpyAsync(qin, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, sm));
-    prop_forward(sm, M, W, r.dev_args, vox, S, reinterpret_cast<const int*>(qin + (size_t)2 * n * dof), qin,
-                 qin + (size_t)n * dof, nullptr, n, gmm);
+    L.mdev = align_up<int>(base);
+    L.emb = align_up<int>(L.mdev + sizeof(ModelDev) * (size_t)n_models);
+    L.vox = align_up<int>(L.emb + sizeof(float) * kHidden * (size_t)n_scenes * n_models);
+    L.part = align_up<int>(L.vox + (size_t)kVoxCells * n_scenes);
+    L.end = align_up<int>(L.part + sizeof(float) * (size_t)kEmbedSlices * kSmallRows * kHidden);
+    return L;
+}
+
+prrtc_status learned_tables(prrtc_ctx* ctx, hipStream_t sm, char* m, const LearnedLayout& L,
+                            const std::vector<int>& scenes, const std::vector<int>& models,
+                            std::vector<ModelDev>& host_mdev) {
+    if (scenes.empty() || models.empty()) return PRRTC_OK;
+    host_mdev.resize(models.size());
+    for (size_t i = 0; i < models.size(); ++i) {
+        ModelRec& M = ctx->models[models[i]];
+        host_mdev[i] = ModelDev{M.p(pW1), M.p(pb1), M.p(pW2), M.p(pb2), M.p(pW3), M.p(pb3), M.p(pW4), M.p(pb4),
+                                M.L.dof, 0};
+    }
+    PRRTC_HIP(ctx, hipMemcpyAsync(m + L.mdev, host_mdev.data(), sizeof(ModelDev) * host_mdev.size(),
+                                  hipMemcpyHostToDevice, sm));
+    uint8_t* vox = reinterpret_cast<uint8_t*>(m + L.vox);
+    for (size_t si = 0; si < scenes.size(); ++si)
+        hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, sm, ctx->scenes[scenes[si]].args,
+                           vox + si * kVoxCells);
+    float* part = reinterpret_cast<float*>(m + L.part);
+    for (size_t mi = 0; mi < models.size(); ++mi) {
+        ModelRec& M = ctx->models[models[mi]];
+        for (int s0 = 0; s0 < L.n_scenes; s0 += kSmallRows) {
+            const int S = std::min(kSmallRows, L.n_scenes - s0);
+            hipLaunchKernelGGL(k_embed_partial, dim3(kEmbedSlices), dim3(256), 0, sm, vox + (size_t)s0 * kVoxCells, S,
+                               M.p(pWv), part);
+            hipLaunchKernelGGL(k_embed_reduce, dim3(S), dim3(256), 0, sm, part, M.p(pbv),
+                               reinterpret_cast<float*>(m + L.emb_at(s0, (int)mi)));
+        }
+    }
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
 }

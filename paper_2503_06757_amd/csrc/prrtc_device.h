@@ -60,7 +60,19 @@ struct RobotArgs {
     int n_bip_a, n_bip_b;
     const int* bip_a;         // re-ordered sphere indices of group A
     const int* bip_b;
+    // Two-stage checks (Sec. III-A: a low-resolution sphere pass flags the
+    // links that may collide, and only their fine spheres are checked): coarse
+    // spheres on moving frames, coarse sphere c enclosing the moving fine
+    // spheres cfirst[c] .. cfirst[c + 1] - 1.  n_cmove = 0: one stage.
+    int n_cmove;
+    const float4* csph;       // [n_cmove] local centre, radius + kCoarseMargin
+    const int* cslot3;        // [n_cmove] 3 * frame slot
+    const int* cfirst;        // [n_cmove + 1]
 };
+
+// Margin added to coarse radii: a fine sphere that the FP32 tests find
+// colliding always lies in a coarse sphere that they find colliding too.
+constexpr float kCoarseMargin = 1e-4f;
 
 // Scene tables, one array per primitive type.
 //   sph: (cx, cy, cz, R)
@@ -72,6 +84,8 @@ struct RobotArgs {
 //   *_ext: half-sizes of the world-axis bounding box of each cuboid and
 //          cylinder around the same centre (+ 1e-4 m), w unused; null when
 //          these boxes would cull little beyond the bounding spheres
+//   esdf:  node values [nz][ny][nx] (x fastest) of an attached signed
+//          distance grid, node (i, j, k) at esdf_o + voxel (i, j, k), or null
 struct SceneArgs {
     int n_sph, n_box, n_cyl;
     const float4* sph;
@@ -82,6 +96,10 @@ struct SceneArgs {
     const float4* cyl_bnd;
     const float4* box_ext;
     const float4* cyl_ext;
+    const float* esdf;
+    float esdf_o[3], esdf_ih;   // origin, 1 / voxel
+    int esdf_n[3];              // nodes per axis, each >= 2
+    float esdf_gate;            // max(1, Lipschitz bound of the interpolated field)
 };
 
 // ----------------------------------------------------------------------------
@@ -154,6 +172,50 @@ __device__ inline float sample_joint(uint64_t seed, uint32_t query, uint32_t rou
     return fmaf(u, span, lo);
 }
 
+// Halton RANDOM_CONFIG (Sec. IV-A: the paper's experiments sample from Halton
+// sequences).  Point i = (low word of seed) + 65536 query + (round W + worker)
+// tries + attempt + 1 (mod 2^32); joint j takes the radical inverse of i in
+// the j-th prime base: with i's base-b digits d_0 (least significant) ..
+// d_{m-1}, sum_k d_k b^-(k+1) = v / b^m exactly (v the reversed digits), which
+// is rounded to FP64 by one division and then to FP32; q_j = fmaf(u, hi_j -
+// lo_j, lo_j).  v < b^m <= 53^6 < 2^53, so both are exact doubles.
+__device__ inline float radical_inverse(uint32_t i, uint32_t b) {
+    uint64_t v = 0, bm = 1;
+    for (uint32_t x = i; x > 0; x /= b) {
+        v = v * b + x % b;
+        bm *= b;
+    }
+    return (float)((double)v / (double)bm);
+}
+
+__device__ inline uint32_t halton_prime(int j) {
+    constexpr uint32_t primes[kMaxDof] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
+    uint32_t p = 2;
+#pragma unroll
+    for (int k = 0; k < kMaxDof; ++k) p = k == j ? primes[k] : p;
+    return p;
+}
+
+__device__ inline float halton_joint(uint64_t seed, uint32_t query, uint32_t round, uint32_t worker,
+                                     uint32_t workers, uint32_t tries, uint32_t attempt, int j, float lo, float hi) {
+    const uint32_t i = (uint32_t)seed + 65536u * query + (round * workers + worker) * tries + attempt + 1u;
+    return fmaf(radical_inverse(i, halton_prime(j)), hi - lo, lo);
+}
+
+// sin and cos of a joint angle for FK: the accurate library routine, or
+// (PRRTC_FK_NATIVE_TRIG) the hardware's transcendental unit.
+#ifndef PRRTC_FK_NATIVE_TRIG
+#define PRRTC_FK_NATIVE_TRIG 0
+#endif
+__device__ inline void joint_sincos(float q, float* s, float* c) {
+#if PRRTC_FK_NATIVE_TRIG
+    *s = __sinf(q);
+    *c = __cosf(q);
+#else
+    sincosf(q, s, c);
+#endif
+}
+
 // ----------------------------------------------------------------------------
 // Forward kinematics of one configuration (one lane).  Frame j+1 = frame j *
 // Rx(alpha_j) Tx(a_j) Rz(q_j) Tz(d_j); a frame is three float4 rows [R | t].
@@ -183,7 +245,7 @@ __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
         for (int jj = 0; jj < R.chain_dof[c]; ++jj) {
             const int j = q0 + jj;
             float sq, cq;
-            sincosf(qf(j), &sq, &cq);
+            joint_sincos(qf(j), &sq, &cq);
             const float ca = R.ca[j], sa = R.sa[j], a = R.a[j], d = R.d[j];
             const float u0 = ca * r01 + sa * r02, u1 = ca * r11 + sa * r12, u2 = ca * r21 + sa * r22;
             const float m0 = ca * r02 - sa * r01, m1 = ca * r12 - sa * r11, m2 = ca * r22 - sa * r21;
@@ -232,7 +294,7 @@ __device__ inline void fk_rows(const RobotArgs& R, QF qf, float4* out, int r) {
         const int q0 = R.chain_q0[c], cd = R.chain_dof[c];
         for (int j4 = 0; j4 < cd; j4 += 4) {
             float sv = 0.0f, cv = 1.0f;
-            if (j4 + r < cd) sincosf(qf(q0 + j4 + r), &sv, &cv);
+            if (j4 + r < cd) joint_sincos(qf(q0 + j4 + r), &sv, &cv);
             auto joint = [&](int jj, float sq, float cq) {
                 const int j = q0 + jj;
                 const float ca = R.ca[j], sa = R.sa[j], a = R.a[j], d = R.d[j];
@@ -298,6 +360,25 @@ __device__ inline bool hit_box(float cx, float cy, float cz, float r, const Box&
     return e0 * e0 + e1 * e1 + e2 * e2 < r * r;
 }
 
+__device__ inline float sd_box(float x, float y, float z, const Box& o) {
+    const float l0 = fmaf(o.b.x, x, fmaf(o.b.y, y, fmaf(o.b.z, z, o.a.x)));
+    const float l1 = fmaf(o.b.w, x, fmaf(o.c.x, y, fmaf(o.c.y, z, o.a.y)));
+    const float l2 = fmaf(o.c.z, x, fmaf(o.c.w, y, fmaf(o.d.x, z, o.a.z)));
+    const float q0 = fabsf(l0) - o.d.y, q1 = fabsf(l1) - o.d.z, q2 = fabsf(l2) - o.d.w;
+    const float e0 = fmaxf(q0, 0.0f), e1 = fmaxf(q1, 0.0f), e2 = fmaxf(q2, 0.0f);
+    return sqrtf(e0 * e0 + e1 * e1 + e2 * e2) + fminf(fmaxf(q0, fmaxf(q1, q2)), 0.0f);
+}
+
+__device__ inline float sd_cyl(float x, float y, float z, const Cyl& o) {
+    const float vx = x - o.a.x, vy = y - o.a.y, vz = z - o.a.z;
+    const float h = o.a.w * vx + o.b.x * vy + o.b.y * vz;
+    const float wx = vx - h * o.a.w, wy = vy - h * o.b.x, wz = vz - h * o.b.y;
+    const float dr = sqrtf(wx * wx + wy * wy + wz * wz) - o.b.z;
+    const float dz = fabsf(h) - o.b.w;
+    const float er = fmaxf(dr, 0.0f), ez = fmaxf(dz, 0.0f);
+    return sqrtf(er * er + ez * ez) + fminf(fmaxf(dr, dz), 0.0f);
+}
+
 __device__ inline bool hit_cyl(float cx, float cy, float cz, float r, const Cyl& o) {
     // o.a = (c, u.x), o.b = (u.yz, R, H)
     const float vx = cx - o.a.x, vy = cy - o.a.y, vz = cz - o.a.z;
@@ -307,6 +388,43 @@ __device__ inline bool hit_cyl(float cx, float cy, float cz, float r, const Cyl&
     const float dr = fmaxf(rho - o.b.z, 0.0f);
     const float dz = fmaxf(fabsf(z) - o.b.w, 0.0f);
     return dr * dr + dz * dz < r * r;
+}
+
+// ESDF grid (Sec. III-A: with camera-built maps the spheres are checked
+// against a Euclidean signed distance field): trilinear interpolation of the
+// node values, grid coordinates clamped to the grid's box (outside, the
+// field continues as its value at the nearest point of the box).  A sphere
+// collides iff the value at its centre is below its radius.
+__device__ inline float esdf_value(const SceneArgs& S, float x, float y, float z) {
+    const float p[3] = {x, y, z};
+    int i[3];
+    float t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float g = fminf(fmaxf((p[a] - S.esdf_o[a]) * S.esdf_ih, 0.0f), (float)(S.esdf_n[a] - 1));
+        i[a] = min((int)g, S.esdf_n[a] - 2);
+        t[a] = g - (float)i[a];
+    }
+    const size_t sy = (size_t)S.esdf_n[0], sz = sy * (size_t)S.esdf_n[1];
+    const float* v = S.esdf + (size_t)i[2] * sz + (size_t)i[1] * sy + (size_t)i[0];
+    const float c00 = fmaf(t[0], v[1] - v[0], v[0]);
+    const float c10 = fmaf(t[0], v[sy + 1] - v[sy], v[sy]);
+    const float c01 = fmaf(t[0], v[sz + 1] - v[sz], v[sz]);
+    const float c11 = fmaf(t[0], v[sz + sy + 1] - v[sz + sy], v[sz + sy]);
+    const float c0 = fmaf(t[1], c10 - c00, c00);
+    const float c1 = fmaf(t[1], c11 - c01, c01);
+    return fmaf(t[2], c1 - c0, c0);
+}
+
+__device__ inline bool hit_esdf(float cx, float cy, float cz, float r, const SceneArgs& S) {
+    return esdf_value(S, cx, cy, cz) < r;
+}
+
+// Signed distances (negative inside) of a point to the primitives, for
+// building a grid from a scene.
+__device__ inline float sd_sphere(float x, float y, float z, float4 o) {
+    const float dx = x - o.x, dy = y - o.y, dz = z - o.z;
+    return sqrtf(dx * dx + dy * dy + dz * dz) - o.w;
 }
 
 __device__ inline bool hit_pair(float4 a, float4 b) {
@@ -392,6 +510,7 @@ __device__ inline bool static_collision(const RobotArgs& R, const SceneArgs& S) 
         for (int o = 0; o < S.n_sph; ++o) hit |= hit_sphere(c.x, c.y, c.z, c.w, ld_sph(S, o));
         for (int o = 0; o < S.n_box; ++o) hit |= hit_box(c.x, c.y, c.z, c.w, ld_box(S, o));
         for (int o = 0; o < S.n_cyl; ++o) hit |= hit_cyl(c.x, c.y, c.z, c.w, ld_cyl(S, o));
+        if (S.esdf) hit |= hit_esdf(c.x, c.y, c.z, c.w, S);
     }
     for (int k = lane; k < R.n_static_pairs; k += kWave) {
         const int2 pr = R.static_pairs[k];
@@ -422,7 +541,27 @@ struct WaveWs {
     int* sub_off;
     int* shared;         // two ints: running minimum and stop flag (multi-wave checks only)
     float4 bnd_sph, bnd_box, bnd_cyl;  // per lane: bounds of obstacle `lane` of each type
+    // two-stage checks: flags of the tile's (coarse sphere, configuration)
+    // items [n_cmove][TP], the fine items they let through [TP n_move] as
+    // (sphere << 8 | configuration), and that list's length
+    unsigned char* cflag;
+    int* list;
+    int* list_n;
 };
+
+// LDS of the two-stage tables for a tile of tp configurations (none for a
+// one-stage robot): flags, item list, list length.
+__host__ __device__ inline size_t two_stage_lds_bytes(const RobotArgs& R, int tp) {
+    if (R.n_cmove == 0) return 0;
+    return sizeof(int) * (1 + (size_t)R.n_move * tp) + (((size_t)R.n_cmove * tp + 3) & ~(size_t)3);
+}
+
+// Carve the two-stage tables out of LDS at `at` (ints).
+__device__ inline void two_stage_ws(const RobotArgs& R, int tp, int* at, WaveWs& ws) {
+    ws.list_n = at;
+    ws.list = at + 1;
+    ws.cflag = reinterpret_cast<unsigned char*>(ws.list + (size_t)R.n_move * tp);
+}
 
 // Load each lane's first-chunk obstacle bounds (kept in registers).
 __device__ inline void load_bounds(const SceneArgs& S, WaveWs& ws) {
@@ -447,12 +586,15 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
 // BOX_FIRST: cuboids are swept before spheres (the first hit ends the
 // check, so the order only changes the time; check_edges picks it by timing).
 //
+// TWO: the kernel includes the two-stage pass for robots with coarse spheres
+// (without it, a robot's coarse spheres are ignored: one stage).
+//
 // NW > 1: the NW waves of a workgroup check together.  Every wave runs the
 // same tile loop; the tile's FK is split into TP / NW configurations per
 // wave, its item blocks are dealt to the waves in turn, and at the end of
 // the tile the waves' results meet in LDS (ws.shared[0]: least colliding
 // sub-edge; ws.shared[1]: a wave found a hit, single sub-edge).
-template <int TP, int B, bool MULTI, int NW = 1, bool BOX_FIRST = false>
+template <int TP, int B, bool MULTI, int NW = 1, bool BOX_FIRST = false, bool TWO = false>
 __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
                           int i_first, float res, const WaveWs& ws, int chunk = 0, int n_chunks = 1) {
     static_assert(TP >= 1 && TP <= kWave, "one configuration per lane in the FK tile");
@@ -462,9 +604,23 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
     volatile int* shared = ws.shared;
     const int dof = R.dof;
     const int fstride = 3 * R.n_slots;
-    // point counts and prefix offsets, in chunks of 64 sub-edges
+    // point counts and prefix offsets, in chunks of 64 sub-edges (one
+    // sub-edge: every lane computes the same count from the same LDS words)
     int total = 0;
-    for (int k0 = 0; k0 < n_sub; k0 += kWave) {
+    if (!MULTI) {
+        const int n = edge_count_f32(wp, wp + dof, dof, res);
+        int cnt = n - i_first + 1, lo = 0;
+        if (n_chunks > 1) {
+            lo = cnt * chunk / n_chunks;
+            cnt = cnt * (chunk + 1) / n_chunks - lo;
+        }
+        if (wave == 0 && lane == 0) {
+            ws.sub_n[0] = n;
+            ws.sub_off[0] = -lo;
+        }
+        total = cnt;
+    }
+    for (int k0 = 0; MULTI && k0 < n_sub; k0 += kWave) {
         const int k = k0 + lane;
         int cnt = 0, lo = 0;
         if (k < n_sub) {
@@ -517,8 +673,89 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 fk_frames<false>(R, qf, ws.frames + slot * fstride);
         }
         __syncthreads();
-        // ---- (point, sphere) items, point-major, against the obstacles
-        const int nitems = np * S_move;
+        // ---- two-stage checks, stage 1: every (coarse sphere, configuration)
+        // item against the obstacles, no early exit; a flagged item lets its
+        // fine spheres through to the (point, sphere) pass below
+        const bool two = TWO && R.n_cmove > 0;   // TWO: compiled with the two-stage pass
+        int nitems = np * S_move;
+        if (two) {
+            const int n1 = np * R.n_cmove;
+            for (int base = wave * kWave * B; base < n1; base += NW * kWave * B) {
+                float cx[B], cy[B], cz[B], cr[B];
+                bool hit[B];
+                float lx = 3.0e38f, ly = 3.0e38f, lz = 3.0e38f, hx = -3.0e38f, hy = -3.0e38f, hz = -3.0e38f;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int it = min(base + lane + kWave * b, n1 - 1);
+                    const int c = it / np, p = it - c * np;
+                    const float4 loc = R.csph[c];
+                    const float3 w = frame_apply(ws.frames + p * fstride + R.cslot3[c], loc.x, loc.y, loc.z);
+                    cx[b] = w.x; cy[b] = w.y; cz[b] = w.z; cr[b] = loc.w;
+                    hit[b] = false;
+                    lx = fminf(lx, w.x - loc.w); hx = fmaxf(hx, w.x + loc.w);
+                    ly = fminf(ly, w.y - loc.w); hy = fmaxf(hy, w.y + loc.w);
+                    lz = fminf(lz, w.z - loc.w); hz = fmaxf(hz, w.z + loc.w);
+                }
+                lx = wave_min_f(lx); ly = wave_min_f(ly); lz = wave_min_f(lz);
+                hx = wave_max_f(hx); hy = wave_max_f(hy); hz = wave_max_f(hz);
+                auto gate = [&](int n, const float4* bnd, auto&& exact) {
+                    for (int c0 = 0; c0 < n; c0 += kWave) {
+                        const int o = c0 + lane;
+                        const bool keep = o < n && sphere_meets_box(bnd[o], lx, ly, lz, hx, hy, hz);
+                        unsigned long long m = __ballot(keep);
+                        while (m) {
+                            const int oi = c0 + (int)__builtin_ctzll(m);
+                            m &= m - 1;
+#pragma unroll
+                            for (int b = 0; b < B; ++b) hit[b] |= exact(cx[b], cy[b], cz[b], cr[b], oi);
+                        }
+                    }
+                };
+                gate(S.n_sph, S.sph_bnd, [&](float x, float y, float z, float r, int oi) { return hit_sphere(x, y, z, r, ld_sph(S, oi)); });
+                gate(S.n_box, S.box_bnd, [&](float x, float y, float z, float r, int oi) { return hit_box(x, y, z, r, ld_box(S, oi)); });
+                gate(S.n_cyl, S.cyl_bnd, [&](float x, float y, float z, float r, int oi) { return hit_cyl(x, y, z, r, ld_cyl(S, oi)); });
+                // the interpolated field changes by at most esdf_gate per metre
+                // (>= 1), so a fine sphere that meets it lies in a coarse
+                // sphere whose radius, scaled by esdf_gate, meets it
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    if (S.esdf) hit[b] |= hit_esdf(cx[b], cy[b], cz[b], S.esdf_gate * cr[b] + kCoarseMargin, S);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int it = base + lane + kWave * b;
+                    if (it < n1) ws.cflag[it] = hit[b] ? 1 : 0;
+                }
+            }
+            __syncthreads();
+            // the fine items of the flagged coarse items, coarse-major
+            if (wave == 0) {
+                int total2 = 0;
+                for (int b0 = 0; b0 < n1; b0 += kWave) {
+                    const int it = b0 + lane;
+                    int cnt = 0, f0 = 0, p = 0;
+                    if (it < n1 && ws.cflag[it]) {
+                        const int c = it / np;
+                        p = it - c * np;
+                        f0 = R.cfirst[c];
+                        cnt = R.cfirst[c + 1] - f0;
+                    }
+                    int incl = cnt;
+#pragma unroll
+                    for (int off = 1; off < kWave; off <<= 1) {
+                        const int v = __shfl_up(incl, off, kWave);
+                        if (lane >= off) incl += v;
+                    }
+                    const int at = total2 + incl - cnt;
+                    for (int k = 0; k < cnt; ++k) ws.list[at + k] = ((f0 + k) << 8) | p;
+                    total2 += __shfl(incl, kWave - 1, kWave);
+                }
+                if (lane == 0) *ws.list_n = total2;
+            }
+            __syncthreads();
+            nitems = *ws.list_n;
+        }
+        // ---- (point, sphere) items, against the obstacles
+
         // it / np as a multiply and shift: with m = ceil(2^20 / np), (it m) >> 20
         // equals floor(it / np) for it < np * 256 and np <= 64 (the rounding
         // excess it (m - 2^20 / np) / 2^20 stays below 1/64 <= 1/np), and
@@ -534,15 +771,20 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 const int it = min(base + lane + kWave * b, nitems - 1);
 #if PRRTC_ITEM_ORDER == 1
 #if PRRTC_FASTDIV
-                const int s = (int)(((unsigned)it * div_m) >> 20);   // sphere-major
+                int s = (int)(((unsigned)it * div_m) >> 20);   // sphere-major
 #else
-                const int s = it / np;
+                int s = it / np;
 #endif
-                const int p = it - s * np;
+                int p = it - s * np;
 #else
-                const int p = it / S_move;      // point-major
-                const int s = it - p * S_move;
+                int p = it / S_move;      // point-major
+                int s = it - p * S_move;
 #endif
+                if (two) {
+                    const int e = ws.list[it];
+                    s = e >> 8;
+                    p = e & 255;
+                }
                 const float4 loc = ws.sph[s];
                 const float3 c = frame_apply(ws.frames + p * fstride + ws.slot3[s], loc.x, loc.y, loc.z);
                 cx[b] = c.x; cy[b] = c.y; cz[b] = c.z; cr[b] = loc.w;
@@ -639,6 +881,8 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 sweep_box();
             }
             sweep_cyl();
+            // an attached ESDF grid: every item, one interpolated lookup each
+            if (S.esdf && !done) done = test([&](float x, float y, float z, float r) { return hit_esdf(x, y, z, r, S); });
 #else
             // obstacles in groups of U between ballots (a tail group re-tests
             // its last obstacle, which cannot change the verdict)
@@ -666,6 +910,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     return h;
                 });
             }
+            if (S.esdf && !done) done = test([&](float x, float y, float z, float r) { return hit_esdf(x, y, z, r, S); });
             for (int o = 0; o < S.n_cyl && !done; o += U) {
                 Cyl ob[U];
 #pragma unroll

@@ -79,7 +79,10 @@ struct alignas(64) PlanArgs {   // whole cache lines: a slot never shares one wi
     int max_rounds, cap, stage_cap, validate;
     float dds_radius;         // dynamic-domain radius after a failed extension (0: off)
     int dds_tries;            // samples per worker and round
+    int halton;               // 1: RANDOM_CONFIG from Halton points instead of Philox draws
     const float* gmm;         // learned mixture [K (1 + 2 dof)] or null (uniform sampling)
+    const ModelDev* model;    // non-null: the group computes the mixture into gmm itself
+    const float* emb;         //   from this grid embedding [kHidden] of the scene
     float mix;                // probability of drawing from the mixture
     long long budget_ticks;   // <= 0: none
     float* qa; int* pa; unsigned char* ba; float* ra;
@@ -335,7 +338,7 @@ struct GroupView {
     __device__ int* path_idx() const { return moved(P.path_idx, off()); }
 };
 
-template <int TP, int B, int NW>
+template <int TP, int B, int NW, bool TWO>
 __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, float4* lds4,
                                                           unsigned long long goff) {
     const GroupView G{P, goff};
@@ -362,6 +365,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     ws.pk = reinterpret_cast<int*>(wp + (P.stage_cap + 1) * dof);
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + P.stage_cap + 2;
+    two_stage_ws(R, TP, ws.sub_off + P.stage_cap + 2, ws);
     __shared__ int sh_i[8];
     __shared__ int sh_check[2];
     ws.shared = sh_check;
@@ -387,13 +391,6 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     }
     stage_spheres(R, sph, slot3);
     load_bounds(S, ws);
-    bool use_gmm = false;
-    if (P.gmm) {
-        for (int t = tid; t < kComp * (1 + 2 * dof); t += nth) gmm_s[t] = P.gmm[t];
-        __syncthreads();
-        use_gmm = gmm_finite(gmm_s, dof);
-        if (!use_gmm && w == 0 && tid == 0) ctl[kFallback] = 1;
-    }
     const bool fixed_hit = static_collision(R, S);
     __syncthreads();
     const int n_end_workers = P.W > 1 ? 2 : 1;
@@ -404,14 +401,34 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             wp[dof + lane] = v;
         }
         __syncthreads();
-        const bool ok = !fixed_hit && wave_check<TP, B, false, NW>(R, S, wp, 1, 0, P.res, ws) == 1;
+        const bool ok = !fixed_hit && wave_check<TP, B, false, NW, false, TWO>(R, S, wp, 1, 0, P.res, ws) == 1;
         if (!ok && tid == 0) atomicOr(ctl + kEndpointBad, 1);
         __syncthreads();
+    }
+    // a learned query of a batched or served launch: one worker (not one of
+    // the two endpoint checkers when there are more) computes the mixture
+    // while the others check the endpoints; the LDS tile is free until the
+    // barrier, and gmm_s serves as the layer output
+    if (P.model && w == (P.W > 2 ? 2 : 0)) {
+        __syncthreads();
+        auto ends = [&](int c) { return c < dof ? P.start[c] : P.goal[c - dof]; };
+        mixture_in_block(*P.model, P.emb, ends, R.lo, R.hi, reinterpret_cast<float*>(ws.frames), gmm_s,
+                         const_cast<float*>(P.gmm));
     }
     if (!group_barrier(G.bar(), w, P.W)) return false;
     if (ctl[kEndpointBad]) {
         if (w == 0 && tid == 0) ctl[kStatus] = kStInvalidEndpoint;
         return true;
+    }
+    bool use_gmm = false;
+    if (P.gmm) {
+        // atomic loads: vector loads from the coherent level (another
+        // workgroup may have written the mixture in this launch)
+        for (int t = tid; t < kComp * (1 + 2 * dof); t += nth)
+            gmm_s[t] = __hip_atomic_load(P.gmm + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        use_gmm = gmm_finite(gmm_s, dof);
+        if (!use_gmm && w == 0 && tid == 0) ctl[kFallback] = 1;
     }
     const unsigned long long t_start = wall_clock64();
     int status = kStNoSolution;
@@ -447,8 +464,11 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 my_learned += drawn;
             }
             if (!drawn && lead && lane < dof)
-                c_rand[lane] = sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof, lane,
-                                            pick(R.lo, lane), pick(R.hi, lane));
+                c_rand[lane] = P.halton ? halton_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)P.W,
+                                                       (unsigned)P.dds_tries, (unsigned)t, lane, pick(R.lo, lane),
+                                                       pick(R.hi, lane))
+                                        : sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof,
+                                                       lane, pick(R.lo, lane), pick(R.hi, lane));
             __syncthreads();
             const int cand = wave_nearest(qs, bs, cap, ns, c_rand, dof);
             if (cand < 0) break;
@@ -474,7 +494,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 }
             }
             __syncthreads();
-            const bool ext_ok = wave_check<TP, B, false, NW>(R, S, wp, 1, 1, P.res, ws) == 1;
+            const bool ext_ok = wave_check<TP, B, false, NW, false, TWO>(R, S, wp, 1, 1, P.res, ws) == 1;
             my_edges += 1;
             if (!ext_ok) fail = nn;
             if (ext_ok) {
@@ -510,7 +530,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                         wp[e] = v;
                     }
                     __syncthreads();
-                    const int K = wave_check<TP, B, true, NW>(R, S, wp, n_ext, 1, P.res, ws);
+                    const int K = wave_check<TP, B, true, NW, false, TWO>(R, S, wp, n_ext, 1, P.res, ws);
                     my_edges += min(K + 1, n_ext);
                     count = 1 + min(K, n_ext - 1);
                     conn = K == n_ext;
@@ -641,7 +661,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     const int k = item / kValChunks, c = item - k * kValChunks;
                     if (lead && lane < 2 * dof) wp[lane] = G.path()[(size_t)k * dof + lane];
                     __syncthreads();
-                    const bool ok = wave_check<TP, B, false, NW>(R, S, wp, 1, 0, P.res_v, ws, c, kValChunks) == 1;
+                    const bool ok = wave_check<TP, B, false, NW, false, TWO>(R, S, wp, 1, 0, P.res_v, ws, c, kValChunks) == 1;
                     if (c == 0) my_edges += 1;
                     if (!ok && tid == 0) {
                         ctl[kValBad] = 1;
@@ -683,15 +703,22 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     return !aborted;
 }
 
+// Launch-wide words after the hand-out counter (next[0]), in the 128 bytes
+// k_plan_init clears: the wall-clock tick of the last claim (serving) and the
+// serving launch's closing flag.
+constexpr int kNextLastClaim = 16;   // unsigned long long at next + 16
+constexpr int kNextClosing = 24;
+constexpr int kNextWords = 32;
+
 // Prepare a launch: zero the barrier words (bar_words each) of n_groups groups
-// (bar_stride ints apart) and set every query's words to (status = internal
-// error, rest 0); with Pq, the single query's arguments (by value) are stored
-// there.
+// (bar_stride ints apart), the kNextWords launch-wide words at next, and set
+// every query's words to (status = internal error, rest 0); with Pq, the
+// single query's arguments (by value) are stored there.
 __global__ void k_plan_init(int* bar, int n_groups, int bar_words, size_t bar_stride, int* ctl, int n_queries,
                             PlanArgs one_query, PlanArgs* Pq, int* next) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_groups * bar_words) bar[(size_t)(t / bar_words) * bar_stride + t % bar_words] = 0;
-    if (next && t == 0) *next = 0;
+    if (next && t < kNextWords) next[t] = 0;
     if (t < n_queries * kCtlWords) ctl[t] = (t % kCtlWords) == kStatus ? kStInternal : 0;
     if (Pq && t < (int)(sizeof(PlanArgs) / sizeof(int)))
         reinterpret_cast<int*>(Pq)[t] = reinterpret_cast<const int*>(&one_query)[t];
@@ -705,7 +732,7 @@ __global__ void k_plan_init(int* bar, int n_groups, int bar_words, size_t bar_st
 // launch share W.  A group that aborts stops taking queries; one it had
 // taken is left at "internal".
 // WPE: waves per SIMD the register allocation must allow.
-template <int TP, int B, int NW, int WPE>
+template <int TP, int B, int NW, int WPE, bool TWO>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE))) void k_plan(
     const PlanArgs* __restrict__ Pq, int n_queries, int n_groups) {
     extern __shared__ float4 lds4[];
@@ -725,7 +752,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
                                                                  __HIP_MEMORY_SCOPE_AGENT));
         }
         if (k >= n_queries) break;
-        if (!plan_query<TP, B, NW>(((CPlanArgs*)Pq)[k], w, lds4, goff) || !handed_out) break;
+        if (!plan_query<TP, B, NW, TWO>(((CPlanArgs*)Pq)[k], w, lds4, goff) || !handed_out) break;
     }
 }
 
@@ -738,8 +765,11 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
 // its next fetch barrier the group copies the finished query's words and path
 // into host memory (host_ctl[k], host_path[k]) and raises host_ctl[k][0].  A
 // slot is written once per launch, so no cache holds an older copy of it.  The
-// kernel ends when *drain is set and nothing is left to claim, or after
-// idle_ticks of the wall clock with nothing to claim.
+// kernel ends when *drain is set and nothing is left to claim, or once the
+// launch has been idle: a group that waits idle_ticks of the wall clock after
+// the launch's last claim (by any group) closes the launch, and every group
+// leaves at its next claim, so the launch never keeps a few groups for a
+// later burst.
 // ----------------------------------------------------------------------------
 struct ServeArgs {
     const PlanArgs* host_args;    // [cap] host memory
@@ -750,7 +780,7 @@ struct ServeArgs {
     float* host_path;             // [cap][path_stride]
     const int* published;         // host memory: queries published so far this launch
     const int* drain;             // host memory: 1 = leave once nothing is left to claim
-    int* next;                    // device: claim counter
+    int* next;                    // device: claim counter, then the launch-wide words (kNextLastClaim, kNextClosing)
     int* bar0;                    // group 0's barrier words
     unsigned long long group_bytes;
     long long idle_ticks;
@@ -759,7 +789,7 @@ struct ServeArgs {
 
 typedef __attribute__((address_space(4))) const ServeArgs CServeArgs;
 
-template <int TP, int B, int NW, int WPE>
+template <int TP, int B, int NW, int WPE, bool TWO>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE))) void k_serve(
     const ServeArgs* __restrict__ SAp) {
     extern __shared__ float4 lds4[];
@@ -791,21 +821,30 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
             }
             int k = -1;
             if (lane == 0) {
+                int* closing = SA.next + kNextClosing;
+                unsigned long long* last = reinterpret_cast<unsigned long long*>(SA.next + kNextLastClaim);
                 const unsigned long long t0 = wall_clock64();
                 for (;;) {
+                    if (__hip_atomic_load(closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                     const int pub = __hip_atomic_load(SA.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
                     const int n = __hip_atomic_load(SA.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (n < pub && n < SA.cap) {
                         int want = n;
                         if (__hip_atomic_compare_exchange_strong(SA.next, &want, n + 1, __ATOMIC_RELAXED,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            __hip_atomic_store(last, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             k = n;
                             break;
                         }
                         continue;
                     }
                     if (__hip_atomic_load(SA.drain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-                    if ((long long)(wall_clock64() - t0) > SA.idle_ticks) break;
+                    // idle since this wait began and since the launch's last claim
+                    const unsigned long long lc = __hip_atomic_load(last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((long long)(wall_clock64() - (lc > t0 ? lc : t0)) > SA.idle_ticks) {
+                        __hip_atomic_store(closing, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
@@ -827,7 +866,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
             __hip_atomic_load(bar + kNext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (k < 0) break;
         prev = k;
-        if (!plan_query<TP, B, NW>(((CPlanArgs*)SA.dev_args)[k], w, lds4, goff)) break;
+        if (!plan_query<TP, B, NW, TWO>(((CPlanArgs*)SA.dev_args)[k], w, lds4, goff)) break;
     }
 }
 

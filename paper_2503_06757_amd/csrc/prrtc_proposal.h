@@ -334,6 +334,92 @@ __global__ __launch_bounds__(kRowThreads) void k_mlp_rows(const float* __restric
         out[c] = c < kComp * (1 + dof) ? xb[c] : fminf(fmaxf(xb[c], kLogSigLo), kLogSigHi);
 }
 
+// ---------------------------------------------------------------------------
+// The mixture of one query computed by one planner workgroup inside a
+// persistent launch (batched and served learned queries), from the scene's
+// grid embedding.  Same operands, rounding and order of every sum as
+// k_mlp_rows: each output column is kRowSplit sequential FMA chains over the
+// quarters of k, added in order, then the bias; so the mixture equals the one
+// a single plan computes with k_mlp_rows.
+// ---------------------------------------------------------------------------
+struct ModelDev {
+    const float *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
+    int dof, pad;
+};
+
+constexpr int kMlpInFloats = 2 * kMaxDof + kHidden;                 // LDS: layer input
+constexpr int kMlpOutFloats = kComp * (1 + 2 * kMaxDof) > kHidden ? kComp * (1 + 2 * kMaxDof) : kHidden;
+
+template <bool GELU>
+__device__ inline void block_layer(const float* x, int K, const float* __restrict__ W, int N,
+                                   const float* __restrict__ b, float* out) {
+    for (int col = threadIdx.x; col < N; col += blockDim.x) {
+        int k0[kRowSplit], k1[kRowSplit];
+        float acc[kRowSplit];
+#pragma unroll
+        for (int p = 0; p < kRowSplit; ++p) {
+            k0[p] = K * p / kRowSplit;
+            k1[p] = K * (p + 1) / kRowSplit;
+            acc[p] = 0.0f;
+        }
+        // the chains side by side; each stays in order of k
+        const int steps = k1[kRowSplit - 1] - k0[kRowSplit - 1];   // the longest quarter
+        for (int i = 0; i < steps; ++i) {
+#pragma unroll
+            for (int p = 0; p < kRowSplit; ++p) {
+                const int k = k0[p] + i;
+                if (k < k1[p]) acc[p] = fmaf(x[k], bf16_round(W[(size_t)k * N + col]), acc[p]);
+            }
+        }
+        float v = acc[0];
+#pragma unroll
+        for (int p = 1; p < kRowSplit; ++p) v += acc[p];
+        v += b[col];
+        if (GELU) v = 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
+        out[col] = v;
+    }
+}
+
+// x: LDS [kMlpInFloats], y: LDS [kMlpOutFloats]; ends(c): the query's start
+// (c < dof) then goal (c - dof); lo, hi: the robot's limits; emb: the scene's
+// embedding [kHidden]; out: the mixture [kComp (1 + 2 dof)] in global memory.
+// Every thread of the workgroup must call it.
+template <class Ends>
+__device__ inline void mixture_in_block(const ModelDev& M, const float* __restrict__ emb, Ends ends,
+                                        const float* lo, const float* hi, float* x, float* y,
+                                        float* __restrict__ out) {
+    const int dof = M.dof;
+    const int D0 = 2 * dof + kHidden, Cw = kComp * (1 + 2 * dof);
+    for (int c = threadIdx.x; c < D0; c += blockDim.x) {
+        float v;
+        if (c < 2 * dof) {
+            const int j = c % dof;
+            const float q = ends(c);
+            v = 2.0f * (q - lo[j]) / (hi[j] - lo[j]) - 1.0f;
+        } else {
+            v = emb[c - 2 * dof];
+        }
+        x[c] = bf16_round(v);
+    }
+    __syncthreads();
+    block_layer<true>(x, D0, M.W1, kHidden, M.b1, y);
+    __syncthreads();
+    for (int c = threadIdx.x; c < kHidden; c += blockDim.x) x[c] = bf16_round(y[c]);
+    __syncthreads();
+    block_layer<true>(x, kHidden, M.W2, kHidden, M.b2, y);
+    __syncthreads();
+    for (int c = threadIdx.x; c < kHidden; c += blockDim.x) x[c] = bf16_round(y[c]);
+    __syncthreads();
+    block_layer<true>(x, kHidden, M.W3, kHidden, M.b3, y);
+    __syncthreads();
+    for (int c = threadIdx.x; c < kHidden; c += blockDim.x) x[c] = bf16_round(y[c]);
+    __syncthreads();
+    block_layer<false>(x, kHidden, M.W4, Cw, M.b4, y);
+    __syncthreads();
+    for (int c = threadIdx.x; c < Cw; c += blockDim.x)
+        out[c] = c < kComp * (1 + dof) ? y[c] : fminf(fmaxf(y[c], kLogSigLo), kLogSigHi);
+}
+
 // dZ = dH * GELU'(Z)
 __global__ void k_gelu_bwd(const float* __restrict__ dH, const float* __restrict__ Z, float* __restrict__ dZ,
                            int n) {

@@ -131,40 +131,44 @@ class Dataset:
 
 
 def generate(P, ctx, torch, rid: int, robot: dict, n_scenes: int, base: int = SEED_TRAIN, max_rounds: int = 1000,
-             budget_ms: float = 50.0, log=None) -> Dataset:
+             budget_ms: float = 50.0, log=None, chunk: int = 1024, workers: int = 64) -> Dataset:
     """Solve one query per scene with the uniform planner and keep the path's
-    waypoints every 0.25 rad (endpoints excluded).  Scenes without a free
-    query or a solution within the round and time budget contribute no
+    waypoints every 0.25 rad (endpoints excluded).  Scenes are taken `chunk`
+    at a time: each scene's first free query, then one batched launch plans
+    them all (seed base + i, `workers` workers per query).  Scenes without a
+    free query or a solution within the round and time budget contribute no
     samples."""
     dof = int(np.asarray(robot["q_lo"]).shape[0])
     ds = Dataset(dof)
-    vox = torch.zeros(VOX ** 3, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    for i in range(n_scenes):
-        prims = scene(robot, i, base)
-        sid = P.prrtc_load_scene(ctx, prims)
-        q = free_query(P, ctx, torch, rid, sid, robot, base + i)
-        path = None
-        if q is not None:
-            p = P.prrtc_plan_params_default()
-            p.seed, p.max_rounds, p.time_budget_ms = base + i, max_rounds, budget_ms
-            st, path, _ = P.prrtc_plan(ctx, rid, sid, q[0], q[1], p)
-            if st != P.PRRTC_OK:
-                path = None
-        if path is not None:
-            P.prrtc_voxelize(ctx, sid, vox.data_ptr(), stream)
-            k = len(ds.vox)
-            ds.vox.append(vox.cpu().numpy().copy())
-            ds.queries.append(q)
+    vox = torch.zeros((chunk, VOX ** 3), dtype=torch.uint8, device="cuda")
+    p = P.prrtc_plan_params_default()
+    p.workers, p.tile, p.max_rounds, p.time_budget_ms = workers, 16, max_rounds, budget_ms
+    for c0 in range(0, n_scenes, chunk):
+        idx = list(range(c0, min(n_scenes, c0 + chunk)))
+        sids = [P.prrtc_load_scene(ctx, scene(robot, i, base)) for i in idx]
+        qs = [free_query(P, ctx, torch, rid, sid, robot, base + i) for i, sid in zip(idx, sids)]
+        live = [k for k, q in enumerate(qs) if q is not None]
+        batch = [(rid, sids[k], qs[k][0], qs[k][1], base + idx[k], 0) for k in live]
+        res = P.prrtc_plan_batch(ctx, batch, p, path_cap=512)[1] if batch else []
+        solved = [(k, r[1]) for k, r in zip(live, res) if r[0] == P.PRRTC_OK]
+        for j, (k, _) in enumerate(solved):
+            P.prrtc_voxelize(ctx, sids[k], vox[j].data_ptr(), stream)
+        grids = vox[:len(solved)].cpu().numpy()
+        for j, (k, path) in enumerate(solved):
+            n_vox = len(ds.vox)
+            ds.vox.append(grids[j].copy())
+            ds.queries.append(qs[k])
             ds.paths.append(path)
             for w in resample_path(path):
-                ds.scene_of.append(k)
-                ds.start.append(q[0])
-                ds.goal.append(q[1])
+                ds.scene_of.append(n_vox)
+                ds.start.append(qs[k][0])
+                ds.goal.append(qs[k][1])
                 ds.waypoint.append(w)
-        P.prrtc_unload_scene(ctx, sid)
-        if log and (i + 1) % 100 == 0:
-            log("  %d/%d scenes, %d solved, %d samples" % (i + 1, n_scenes, len(ds.vox), len(ds.scene_of)))
+        for sid in sids:
+            P.prrtc_unload_scene(ctx, sid)
+        if log:
+            log("  %d/%d scenes, %d solved, %d samples" % (idx[-1] + 1, n_scenes, len(ds.vox), len(ds.scene_of)))
     return ds.finish()
 
 

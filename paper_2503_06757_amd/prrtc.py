@@ -42,6 +42,10 @@ class prrtc_robot_desc(C.Structure):
         ("sphere_xyzr", C.POINTER(C.c_float)),
         ("n_self_pairs", C.c_int32),
         ("self_pairs", C.POINTER(C.c_int32)),
+        ("n_coarse", C.c_int32),
+        ("coarse_frame", C.POINTER(C.c_int32)),
+        ("coarse_xyzr", C.POINTER(C.c_float)),
+        ("sphere_coarse", C.POINTER(C.c_int32)),
     ]
 
 
@@ -88,7 +92,7 @@ class prrtc_query(C.Structure):
         ("goal", C.c_float * 16),
         ("seed", C.c_uint64),
         ("query", C.c_uint32),
-        ("pad", C.c_int32),
+        ("model_id", C.c_int32),
     ]
 
 
@@ -97,6 +101,15 @@ class prrtc_query_result(C.Structure):
         ("status", C.c_int32),
         ("path_len", C.c_int32),
         ("stats", prrtc_plan_stats),
+    ]
+
+
+class prrtc_esdf_desc(C.Structure):
+    _fields_ = [
+        ("origin", C.c_float * 3),
+        ("voxel", C.c_float),
+        ("dims", C.c_int32 * 3),
+        ("values", C.c_void_p),
     ]
 
 
@@ -137,6 +150,10 @@ def _load():
     L.prrtc_load_scene.restype = I32
     L.prrtc_unload_scene.argtypes = [P, I32]
     L.prrtc_unload_scene.restype = I32
+    L.prrtc_scene_set_esdf.argtypes = [P, I32, C.POINTER(prrtc_esdf_desc)]
+    L.prrtc_scene_set_esdf.restype = I32
+    L.prrtc_esdf_from_scene.argtypes = [P, I32, VP, F, VP, VP, VP]
+    L.prrtc_esdf_from_scene.restype = I32
     L.prrtc_check_edges.argtypes = [P, I32, I32, VP, VP, I64, F, VP, VP]
     L.prrtc_check_edges.restype = I32
     L.prrtc_edge_schedule.argtypes = [P, I32, I32, I32, C.POINTER(I32)]
@@ -185,7 +202,8 @@ lib = _load()
 
 # the symbols include/prrtc.h declares (checked by the CPU test-suite)
 EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_robot",
-            "prrtc_load_scene", "prrtc_unload_scene", "prrtc_check_edges", "prrtc_edge_schedule", "prrtc_fk_spheres",
+            "prrtc_load_scene", "prrtc_unload_scene", "prrtc_scene_set_esdf", "prrtc_esdf_from_scene",
+            "prrtc_check_edges", "prrtc_edge_schedule", "prrtc_fk_spheres",
             "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_launch",
             "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
             "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_forward_noalloc", "prrtc_proposal_sample",
@@ -241,6 +259,14 @@ def robot_desc(robot: dict):
     d.sphere_xyzr = keep["xyzr"].ctypes.data_as(fp)
     d.n_self_pairs = keep["pairs"].shape[0]
     d.self_pairs = keep["pairs"].ctypes.data_as(ip)
+    if "coarse_xyzr" in robot:     # two-stage checks
+        keep["cframe"] = np.ascontiguousarray(robot["coarse_frame"], np.int32)
+        keep["cxyzr"] = np.ascontiguousarray(robot["coarse_xyzr"], np.float32)
+        keep["owner"] = np.ascontiguousarray(robot["sphere_coarse"], np.int32)
+        d.n_coarse = keep["cxyzr"].shape[0]
+        d.coarse_frame = keep["cframe"].ctypes.data_as(ip)
+        d.coarse_xyzr = keep["cxyzr"].ctypes.data_as(fp)
+        d.sphere_coarse = keep["owner"].ctypes.data_as(ip)
     return d, keep
 
 
@@ -263,6 +289,27 @@ def prrtc_load_scene(ctx: int, prims: np.ndarray) -> int:
 
 def prrtc_unload_scene(ctx: int, scene_id: int) -> None:
     _check(ctx, lib.prrtc_unload_scene(ctx, int(scene_id)))
+
+
+def prrtc_scene_set_esdf(ctx: int, scene_id: int, origin=None, voxel: float = 0.0, values=None) -> None:
+    """Attach an ESDF grid: values float32 [nz][ny][nx] (x fastest) at
+    origin + voxel (i, j, k); origin None detaches the scene's grid."""
+    if origin is None:
+        _check(ctx, lib.prrtc_scene_set_esdf(ctx, int(scene_id), None))
+        return
+    v = np.ascontiguousarray(values, np.float32)
+    nz, ny, nx = v.shape
+    d = prrtc_esdf_desc((C.c_float * 3)(*[float(x) for x in origin]), float(voxel), (C.c_int32 * 3)(nx, ny, nz),
+                        v.ctypes.data)
+    _check(ctx, lib.prrtc_scene_set_esdf(ctx, int(scene_id), C.byref(d)))
+
+
+def prrtc_esdf_from_scene(ctx: int, scene_id: int, origin, voxel: float, dims, values_dev: int,
+                          stream: int | None = None) -> None:
+    o = np.ascontiguousarray(origin, np.float32)
+    d = np.ascontiguousarray(dims, np.int32)
+    _check(ctx, lib.prrtc_esdf_from_scene(ctx, int(scene_id), o.ctypes.data, float(voxel), d.ctypes.data,
+                                          values_dev, stream))
 
 
 def prrtc_check_edges(ctx: int, robot_id: int, scene_id: int, a_dev: int, b_dev: int, n_edges: int,
@@ -313,8 +360,8 @@ _RESULT_DT = np.dtype(prrtc_query_result)
 
 
 def prrtc_plan_batch(ctx: int, queries, params, groups: int = 0, memory_budget: int = 0, path_cap: int = 256):
-    """queries: list of (robot_id, scene_id, start, goal, seed, query).  Returns
-    (groups used, [(status, path or None, stats dict)])."""
+    """queries: list of (robot_id, scene_id, start, goal, seed, query[, model_id]).
+    Returns (groups used, [(status, path or None, stats dict)])."""
     n = len(queries)
     arr = _query_array(queries)
     paths = np.zeros((max(n, 1), path_cap, 16), np.float32)
@@ -346,6 +393,7 @@ def _query_array(queries):
         arr["scene_id"][:n] = [q[1] for q in queries]
         arr["seed"][:n] = [q[4] for q in queries]
         arr["query"][:n] = [q[5] for q in queries]
+        arr["model_id"][:n] = [q[6] if len(q) > 6 else -1 for q in queries]
         for k, q in enumerate(queries):
             d = len(q[2])
             arr["start"][k, :d] = q[2]
@@ -374,10 +422,12 @@ def prrtc_serve_start(ctx: int, params, slots: int = 256, max_pending: int = 102
                                       int(path_cap)))
 
 
-def prrtc_submit(ctx: int, robot_id: int, scene_id: int, start, goal, seed: int, query: int = 0):
+def prrtc_submit(ctx: int, robot_id: int, scene_id: int, start, goal, seed: int, query: int = 0,
+                 model_id: int = -1):
     """Ticket, or None when admission is refused (E_BUSY)."""
     q = prrtc_query()
     q.robot_id, q.scene_id, q.seed, q.query = int(robot_id), int(scene_id), int(seed), int(query)
+    q.model_id = int(model_id)
     for j, v in enumerate(np.asarray(start, np.float32)):
         q.start[j] = float(v)
     for j, v in enumerate(np.asarray(goal, np.float32)):

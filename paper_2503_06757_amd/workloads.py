@@ -143,6 +143,42 @@ def robot_r14_arm(arm: int, seed: int = SEED_R7_SPHERES) -> dict:
     return r7
 
 
+def with_coarse_spheres(robot: dict, group: int = 8) -> dict:
+    """The robot with a second, coarse sphere set for two-stage collision
+    checking (Sec. III-A checks low-resolution spheres first and re-checks
+    only the links they flag with the fine ones; the paper gets both sets from
+    `foam`, here they are synthetic): on each frame, runs of up to `group`
+    consecutive fine spheres share one coarse sphere centred on the run's
+    bounding box, its radius reaching the farthest fine sphere's far side.
+    Adds coarse_xyzr (n_c, 4), coarse_frame (n_c,) and sphere_coarse (fine ->
+    coarse index)."""
+    frames = np.asarray(robot["sphere_frame"])
+    xyzr = np.asarray(robot["sphere_xyzr"], np.float64)
+    coarse, cframe = [], []
+    owner = np.zeros(len(frames), np.int32)
+    for f in np.unique(frames):
+        idx = np.nonzero(frames == f)[0]
+        for k0 in range(0, len(idx), group):
+            run = idx[k0:k0 + group]
+            c = 0.5 * (xyzr[run, :3].min(axis=0) + xyzr[run, :3].max(axis=0))
+            r = np.max(np.linalg.norm(xyzr[run, :3] - c, axis=1) + xyzr[run, 3])
+            owner[run] = len(coarse)
+            coarse.append(np.concatenate([c, [r]]))
+            cframe.append(int(f))
+    out = dict(robot)
+    out["coarse_xyzr"] = np.array(coarse, np.float32)
+    # float32 centres: widen the radius so every fine sphere stays inside
+    cx = out["coarse_xyzr"]
+    for k in range(len(frames)):
+        d = np.linalg.norm(xyzr[k, :3] - cx[owner[k], :3].astype(np.float64)) + xyzr[k, 3]
+        if d > cx[owner[k], 3]:
+            cx[owner[k], 3] = np.nextafter(np.float32(d), np.float32(np.inf))
+    out["coarse_frame"] = np.array(cframe, np.int32)
+    out["sphere_coarse"] = owner
+    out["name"] = robot["name"] + "-2stage"
+    return out
+
+
 def robot_dof(robot: dict) -> int:
     return int(sum(robot["chain_dof"]))
 

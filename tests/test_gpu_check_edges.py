@@ -217,3 +217,81 @@ def test_check_edges_full_size_configuration(gpu, orc, r7):
     got = gpu_check(gpu, rid, sid, a, b)
     v, f = assert_parity(orc, r7, prims, a, b, got, threads=16)
     say("  valid frac %.4f flagged %d" % (v.mean(), f.sum()))
+
+
+ESDF_O, ESDF_H, ESDF_N = (-1.3, -1.3, -1.3), 2.6 / 63, (64, 64, 64)
+
+
+def test_esdf_builder_parity(gpu, orc, r7, r14):
+    """The library's grid of a scene's primitives against the oracle's node
+    values (FP32 against FP64 signed distances)."""
+    P, ctx, torch = gpu
+    for name, prims in (("S12", W.scene_s12(r7, 0)), ("S64", W.scene_s64(r7)), ("shelf", W.scene_shelf(r14))):
+        sid = P.prrtc_load_scene(ctx, prims)
+        out = torch.empty(ESDF_N[::-1], dtype=torch.float32, device="cuda")
+        P.prrtc_esdf_from_scene(ctx, sid, ESDF_O, ESDF_H, ESDF_N, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        want = orc.esdf_of_scene(prims, ESDF_O, ESDF_H, ESDF_N)
+        err = np.abs(out.cpu().numpy().astype(np.float64) - want)
+        say("ESDF builder %s: max |err| %.3g m" % (name, err.max()))
+        assert err.max() <= 2e-6
+
+
+@pytest.mark.parametrize("with_prims", [False, True])
+def test_check_edges_esdf_parity(gpu, orc, r7, with_prims):
+    """Edges against an ESDF grid (the oracle's grid of the 64-obstacle scene,
+    uploaded to the GPU): verdicts equal the oracle's trilinear clearances
+    except within the flag band.  With the 12-obstacle scene's primitives
+    in the same scene, both count."""
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    grid = orc.EsdfGrid(ESDF_O, ESDF_H, orc.esdf_of_scene(W.scene_s64(r7), ESDF_O, ESDF_H, ESDF_N))
+    prims = W.scene_s12(r7, 2) if with_prims else np.zeros(0, W.PRIM_DTYPE)
+    sid = P.prrtc_load_scene(ctx, prims)
+    P.prrtc_scene_set_esdf(ctx, sid, ESDF_O, ESDF_H, grid.values)
+    a, b = W.random_edges(r7, 20011, seed=99)
+    got = gpu_check(gpu, rid, sid, a, b)
+    with grid:
+        v, f = assert_parity(orc, r7, prims, a, b, got)
+    say("ESDF parity (prims %s): valid frac %.4f flagged %d" % (with_prims, v.mean(), f.sum()))
+    assert 0.01 < v.mean() < 0.99
+    # detached, only the primitives remain
+    P.prrtc_scene_set_esdf(ctx, sid, None)
+    got0 = gpu_check(gpu, rid, sid, a, b)
+    assert_parity(orc, r7, prims, a, b, got0)
+
+
+def test_check_edges_esdf_near_contact(gpu, orc, r7):
+    """Edges ending 1e-6 .. 1e-3 m from the ESDF's zero level: unflagged
+    verdicts match the oracle's."""
+    import near_contact as NC
+    P, ctx, _ = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    grid = orc.EsdfGrid(ESDF_O, ESDF_H, orc.esdf_of_scene(W.scene_s64(r7), ESDF_O, ESDF_H, ESDF_N))
+    empty = np.zeros(0, W.PRIM_DTYPE)
+    sid = P.prrtc_load_scene(ctx, empty)
+    P.prrtc_scene_set_esdf(ctx, sid, ESDF_O, ESDF_H, grid.values)
+    with grid:
+        cf = NC.graze_configs(orc, r7, empty, 12, seed=0x4E44)
+        a, b = NC.graze_edges(cf)
+        got = gpu_check(gpu, rid, sid, a, b)
+        v, f, m = orc.check_edges(orc.OracleRobot(r7), empty, a, b, 32.0, early_exit=False, want_m=True)
+    mism = (got != v) & (f == 0)
+    near = (f == 0) & (np.abs(m) < 1e-4)
+    say("ESDF near contact: %d edges, %d within 1e-5..1e-4 m, %d flagged (%d agree)"
+        % (len(v), near.sum(), f.sum(), np.sum((got == v) & (f == 1))))
+    assert near.sum() >= 8 * 12 and not mism.any()
+
+
+def test_esdf_argument_errors(gpu, r7):
+    P, ctx, _ = gpu
+    sid = P.prrtc_load_scene(ctx, np.zeros(0, W.PRIM_DTYPE))
+    for origin, voxel, vals in (((0, 0, 0), 0.0, np.zeros((2, 2, 2))), ((0, 0, 0), 0.1, np.zeros((1, 2, 2))),
+                                ((0, 0, float("nan")), 0.1, np.zeros((2, 2, 2))),
+                                ((0, 0, 0), 0.1, np.full((2, 2, 2), np.nan))):
+        with pytest.raises(P.PrrtcError) as e:
+            P.prrtc_scene_set_esdf(ctx, sid, origin, voxel, vals)
+        assert e.value.status == P.PRRTC_E_ARG
+    with pytest.raises(P.PrrtcError) as e:
+        P.prrtc_scene_set_esdf(ctx, 10_000, (0, 0, 0), 0.1, np.zeros((2, 2, 2)))
+    assert e.value.status == P.PRRTC_E_STATE

@@ -226,3 +226,56 @@ def test_plan_r14_shelf_replay(gpu, orc, r14):
         replayed += replay_equal(orc, r14, prims, s, g, st, path, stats, **kw)
     say("  %d of 8 replayed, %d solved within 40 rounds" % (replayed, solved))
     assert replayed >= 4
+
+
+@pytest.mark.parametrize("case", ["s12-0", "s12-3", "r14-1", "s64-0", "s64-3", "s64-dds"])
+def test_plan_halton_replay(gpu, orc, r7, r14, case):
+    """Halton samples (sampler 2): the GPU plan equals the oracle's replay,
+    also over many rounds (64-obstacle scene, 40 rounds, solved or not) and
+    with dynamic-domain redraws (several tries per worker and round)."""
+    P, ctx, _ = gpu
+    kind, k = case.split("-")
+    robot = r14 if kind == "r14" else r7
+    rob = orc.OracleRobot(robot)
+    kw = dict(seed=0x1234, max_rounds=300, sampler=2, workers=128)
+    if kind == "s12":
+        prims = W.scene_s12(robot, int(k))
+        s, g = free_query(orc, rob, prims, robot, W.SEED_QUERY + int(k))
+    elif kind == "r14":
+        prims = W.scene_mixed(0x53140000 + int(k), robot, 12)
+        s, g = free_query(orc, rob, prims, robot, W.SEED_QUERY + 100 + int(k), n=3000)
+    else:
+        prims = W.scene_s64(robot)
+        kk = 0 if k == "dds" else int(k)
+        s, g = free_query(orc, rob, prims, robot, W.SEED_QUERY + 300 + kk, n=2000)
+        kw = dict(seed=0x1234 + kk, max_rounds=40, sampler=2, workers=64, dds_tries=2)
+        if k == "dds":
+            kw.update(dds_radius=0.2, dds_tries=3)
+    rid, sid = P.prrtc_load_robot(ctx, robot), P.prrtc_load_scene(ctx, prims)
+    say("Halton plan", case)
+    st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
+    assert st in (0, P.PRRTC_E_NO_SOLUTION), (st, stats)
+    if st == 0:
+        path_ok(orc, robot, prims, path, s, g)
+    assert replay_equal(orc, robot, prims, s, g, st, path, stats, **kw)
+
+
+@pytest.mark.parametrize("instance", [0, 4])
+def test_plan_esdf_replay(gpu, orc, r7, instance):
+    """Planning against an ESDF grid (the oracle's grid of a 12-obstacle
+    scene, no primitives): the GPU plan equals the oracle's replay."""
+    P, ctx, _ = gpu
+    o, h, n = (-1.3, -1.3, -1.3), 2.6 / 63, (64, 64, 64)
+    prims = W.scene_s12(r7, instance)
+    grid = orc.EsdfGrid(o, h, orc.esdf_of_scene(prims, o, h, n))
+    empty = np.zeros(0, W.PRIM_DTYPE)
+    rid, sid = P.prrtc_load_robot(ctx, r7), P.prrtc_load_scene(ctx, empty)
+    P.prrtc_scene_set_esdf(ctx, sid, o, h, grid.values)
+    say("ESDF plan", instance)
+    kw = dict(seed=31 + instance, max_rounds=300)
+    with grid:
+        s, g = free_query(orc, orc.OracleRobot(r7), empty, r7, W.SEED_QUERY + instance)
+        st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, **kw))
+        assert st == 0, (st, stats)
+        path_ok(orc, r7, empty, path, s, g)
+        assert replay_equal(orc, r7, empty, s, g, st, path, stats, **kw)

@@ -90,13 +90,14 @@ def test_forward_parity(gpu, prop, r7, per_scene):
     got = _forward_gpu(gpu, mid, rid, vox_t, scene_of, s, g)
     (logits, mu, logsig), cache = prop.forward(params, vox, scene_of, s, g, r7["q_lo"], r7["q_hi"])
     ref = np.concatenate([logits, mu.reshape(len(s), -1), logsig.reshape(len(s), -1)], axis=1)
-    # bound: the head's |w x| sum at BF16, 4 x 2^-8 (both sides round the same operands;
-    # differences come from accumulation order and rare rounding flips upstream)
+    # bound 2^-7 sum|w x| over the head's BF16 operands: both sides round the same
+    # operands, so outputs differ only where an upstream FP32-vs-FP64 difference
+    # flips the BF16 rounding of a head input, by one BF16 ulp <= 2^-7 |x| each
     mag = np.abs(prop.bf16(cache["h3"])) @ np.abs(prop.bf16(params["W4"])) + np.abs(params["b4"])
     mag = np.concatenate([mag[:, :8], mag[:, 8:8 + 8 * dof], mag[:, 8 + 8 * dof:]], axis=1)
     err = np.abs(got - ref)
-    say("  max err %.3g, max err/bound %.3g" % (err.max(), (err / (4 * 2 ** -8 * mag + 1e-12)).max()))
-    assert np.all(err <= 4 * 2 ** -8 * mag + 1e-7)
+    say("  max err %.3g, max err/bound %.3g" % (err.max(), (err / (2 * 2 ** -8 * mag + 1e-12)).max()))
+    assert np.all(err <= 2 * 2 ** -8 * mag + 1e-7)
 
 
 def test_gradient_parity_and_roundtrip(gpu, prop, r7):
@@ -392,7 +393,7 @@ def test_plan_learned_bad_arguments(gpu, r7):
     sid = P.prrtc_load_scene(ctx, W.scene_s12(r7, 0))
     m14 = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(14, 1), 14))
     s = np.zeros(7, np.float32)
-    for kw in (dict(sampler=2), dict(sampler=1, model_id=99), dict(sampler=1, model_id=m14),
+    for kw in (dict(sampler=3), dict(sampler=1, model_id=99), dict(sampler=1, model_id=m14),
                dict(sampler=1, model_id=0, mix=1.5)):
         p = P.prrtc_plan_params_default()
         for k, v in kw.items():
