@@ -28,6 +28,7 @@ from paper_2503_06757_amd import workloads as W  # noqa: E402
 METRIC = "p50 ms-to-solution + edge checks/s (7/14-DoF), learned vs plain sampler"
 N_EDGES = 1 << 20
 RES = 32.0
+SEED_VARIANT_EDGES = 0x45000001   # edges of the collision-model variants
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 
 # Algorithmic FP32 work per checked configuration, the dense per-point model
@@ -174,6 +175,106 @@ def bench_check_edges(P, ctx, torch, steps, warmup):
                 valid=valid, valid_frac=float(valid.mean()), free_points=free_points,
                 flop_per_point_model=fl_model, flop_per_point=fl_point, mean_points=float(n_pts.mean()),
                 free_edges=nf, free_ms=free_ms, free_all_valid=free_ok)
+
+
+def time_edges(P, ctx, torch, rid, sid, a, b, reps=10, warmup=2):
+    """Mean kernel time (HIP events on the launch stream) of prrtc_check_edges
+    over a resident batch, and its verdicts."""
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    n = a.shape[0]
+    tv = torch.empty(n, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), n, RES, tv.data_ptr(), stream.cuda_stream)
+
+    for _ in range(warmup):
+        step()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])), tv.cpu().numpy().astype(bool)
+
+
+def bench_collision_variants(P, ctx, torch):
+    """check_edges throughput of the other collision models on their own
+    batches: two-stage checks (coarse spheres gating fine ones, Sec. III-A)
+    against one stage on the 7-DoF arm among 64 obstacles and the dual arm in
+    the shelf, and the 7-DoF arm against an ESDF grid of the 64 obstacles
+    (64^3 nodes over [-1.3, 1.3]^3, built by the library) instead of the
+    primitives.  Verdicts of the two-stage robot must equal the one-stage
+    robot's."""
+    out = {}
+    r7, r14 = W.robot_r7(), W.robot_r14()
+    for name, robot, prims, n in (("r7_s64", r7, W.scene_s64(r7), N_EDGES),
+                                  ("r14_shelf", r14, W.scene_shelf(r14), N_EDGES // 4)):
+        sid = P.prrtc_load_scene(ctx, prims)
+        a, b = W.random_edges(robot, n, seed=SEED_VARIANT_EDGES)
+        rows = {}
+        verdicts = {}
+        for kind, rb in (("one_stage", robot), ("two_stage", W.with_coarse_spheres(robot))):
+            rid = P.prrtc_load_robot(ctx, rb)
+            ms, v = time_edges(P, ctx, torch, rid, sid, a, b)
+            verdicts[kind] = v
+            rows[kind] = {"edges": n, "kernel_ms": ms, "edge_checks_per_s": n / (ms * 1e-3),
+                          "schedule": P.prrtc_edge_schedule(ctx, rid, sid), "valid_fraction": float(v.mean())}
+        rows["verdicts_equal"] = bool(np.array_equal(verdicts["one_stage"], verdicts["two_stage"]))
+        rows["speedup"] = rows["one_stage"]["kernel_ms"] / rows["two_stage"]["kernel_ms"]
+        out[name] = rows
+    o, h, dims = (-1.3, -1.3, -1.3), 2.6 / 63, (64, 64, 64)
+    src = P.prrtc_load_scene(ctx, W.scene_s64(r7))
+    grid = torch.empty((64, 64, 64), dtype=torch.float32, device="cuda")
+    P.prrtc_esdf_from_scene(ctx, src, o, h, dims, grid.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    sid = P.prrtc_load_scene(ctx, np.zeros(0, W.PRIM_DTYPE))
+    P.prrtc_scene_set_esdf(ctx, sid, o, h, grid.cpu().numpy())
+    a, b = W.random_edges(r7, N_EDGES, seed=SEED_VARIANT_EDGES)
+    rid = P.prrtc_load_robot(ctx, r7)
+    ms, v = time_edges(P, ctx, torch, rid, sid, a, b)
+    out["r7_esdf_s64"] = {"edges": N_EDGES, "kernel_ms": ms, "edge_checks_per_s": N_EDGES / (ms * 1e-3),
+                          "valid_fraction": float(v.mean()), "grid": "64^3 nodes, voxel %.4f m" % h}
+    return out
+
+
+def bench_graph_launches(P, ctx, torch, n_edges=4096, launches=200):
+    """Small check_edges batches back to back: launched one call at a time,
+    and the same calls captured once in a HIP graph and replayed (what a
+    caller gains from graphs where batches are small and launches dominate)."""
+    r7 = W.robot_r7()
+    rid, sid = P.prrtc_load_robot(ctx, r7), P.prrtc_load_scene(ctx, W.scene_s64(r7))
+    P.prrtc_edge_schedule(ctx, rid, sid, 1)
+    a, b = W.random_edges(r7, n_edges, seed=SEED_VARIANT_EDGES + 1)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    tv = torch.empty(n_edges, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+
+    def calls():
+        for _ in range(launches):
+            P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), n_edges, RES, tv.data_ptr(), s.cuda_stream)
+
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        calls()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        calls()
+    torch.cuda.synchronize()
+    eager = time.perf_counter() - t0
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        calls()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    graph = time.perf_counter() - t0
+    return {"edges_per_launch": n_edges, "launches": launches, "eager_us_per_launch": eager / launches * 1e6,
+            "graph_us_per_launch": graph / launches * 1e6}
 
 
 def bench_plan(P, ctx, n_instances=100, n_seeds=50):
@@ -390,6 +491,49 @@ def bench_shelf(P, ctx, n_queries=500, max_rounds=SHELF_MAX_ROUNDS, budget_ms=SH
             "max_rounds": max_rounds, "time_budget_ms": budget_ms, "workers": workers}
 
 
+def bench_sampling(P, ctx, n_shelf=100, n_r7=100, budget_ms=SHELF_BUDGET_MS, dds=(1.0, 4)):
+    """Sampling variants on the same queries, seeds and budgets: uniform
+    Philox draws, dynamic-domain sampling (Sec. III: a node whose extension
+    failed only accepts samples within dds_radius; redrawn up to dds_tries
+    times) and Halton points (the sampler of the paper's experiments,
+    Sec. IV-A), on the dual-arm shelf and the 7-DoF arm among 12 obstacles."""
+    variants = {"uniform": dict(), "dynamic_domain": dict(dds_radius=dds[0], dds_tries=dds[1]),
+                "halton": dict(sampler=2)}
+    Q = np.loadtxt(SHELF_QUERIES, dtype=np.float32)[:n_shelf]
+    r14, r7 = W.robot_r14(), W.robot_r7()
+    rid14, rid7 = P.prrtc_load_robot(ctx, r14), P.prrtc_load_robot(ctx, r7)
+    sid_shelf = P.prrtc_load_scene(ctx, W.scene_shelf(r14))
+    r7_jobs = []
+    for inst in range(n_r7):
+        sid = P.prrtc_load_scene(ctx, W.scene_s12(r7, inst))
+        for s, g in W.query_candidates(r7, W.SEED_QUERY + inst, 200):
+            prm = P.prrtc_plan_params_default()
+            prm.max_rounds = 0
+            if P.prrtc_plan(ctx, rid7, sid, s, g, prm)[0] != P.PRRTC_E_INVALID_ENDPOINT:
+                r7_jobs.append((sid, s, g, inst))
+                break
+    out = {"dds_radius": dds[0], "dds_tries": dds[1], "time_budget_ms": budget_ms}
+    for name, kw in variants.items():
+        legs = {}
+        for leg, rid, jobs in (("r14_shelf", rid14, [(sid_shelf, row[:14], row[14:], k) for k, row in enumerate(Q)]),
+                               ("r7_s12", rid7, r7_jobs)):
+            rows = []
+            for sid, s, g, k in jobs:
+                prm = P.prrtc_plan_params_default()
+                prm.seed, prm.max_rounds, prm.time_budget_ms = W.SEED_QUERY + k, SHELF_MAX_ROUNDS, budget_ms
+                for key, v in kw.items():
+                    setattr(prm, key, v)
+                t0 = time.perf_counter()
+                st, _, stats = P.prrtc_plan(ctx, rid, sid, s, g, prm)
+                rows.append((st == P.PRRTC_OK, (time.perf_counter() - t0) * 1e3, stats["rounds"]))
+            a = np.array(rows, np.float64)
+            t = np.where(a[:, 0] > 0, a[:, 1], np.inf)
+            legs[leg] = {"queries": len(a), "success": float(a[:, 0].mean()), **pcts(t),
+                         "mean_rounds_solved": float(a[a[:, 0] > 0, 2].mean()) if a[:, 0].any() else None}
+        out[name] = legs
+    return out
+
+
 def bench_learned(P, ctx, torch, n_train, n_eval, epochs, log):
     """The learned proposal end to end on the 7-DoF arm: data from the
     uniform planner on generated scenes, training (throughput against the
@@ -450,27 +594,44 @@ def bench_learned_shelf(P, ctx, torch, n_train, n_eval, epochs, log, budget_ms=S
     mid = P.prrtc_load_proposal(ctx, PR.pack(PR.init_params(14, 2), 14))
     losses = PR.train(P, ctx, torch, mid, rid, ds, epochs, log=log)
     Q = np.loadtxt(SHELF_QUERIES, dtype=np.float32)[:n_eval]
-    res = {}
+    res, runs = {}, {}
+
+    def plan_one(k, sampler, seed):
+        row = Q[k]
+        prm = P.prrtc_plan_params_default()
+        prm.seed, prm.max_rounds, prm.time_budget_ms = seed, SHELF_MAX_ROUNDS, budget_ms
+        prm.sampler, prm.model_id, prm.mix = sampler, mid, 0.5
+        t1 = time.perf_counter()
+        st, _, stats = P.prrtc_plan(ctx, rid, sid, row[:14], row[14:], prm)
+        return st == P.PRRTC_OK, (time.perf_counter() - t1) * 1e3, stats["rounds"]
+
     for name, sampler in (("plain", 0), ("learned", 1)):
-        rows = []
-        for k, row in enumerate(Q):
-            prm = P.prrtc_plan_params_default()
-            prm.seed, prm.max_rounds, prm.time_budget_ms = W.SEED_QUERY + k, SHELF_MAX_ROUNDS, budget_ms
-            prm.sampler, prm.model_id, prm.mix = sampler, mid, 0.5
-            t1 = time.perf_counter()
-            st, _, stats = P.prrtc_plan(ctx, rid, sid, row[:14], row[14:], prm)
-            rows.append((st == P.PRRTC_OK, (time.perf_counter() - t1) * 1e3, stats["rounds"]))
-        a = np.array(rows, np.float64)
+        a = np.array([plan_one(k, sampler, W.SEED_QUERY + k) for k in range(len(Q))], np.float64)
+        runs[name] = a
         t = np.where(a[:, 0] > 0, a[:, 1], np.inf)
         res[name] = {"queries": len(a), "success": float(a[:, 0].mean()), **pcts(t),
                      "mean_rounds_solved": float(a[a[:, 0] > 0, 2].mean()) if a[:, 0].any() else None}
         log("  shelf %s: %s" % (name, res[name]))
+    # where the two differ: the queries only one sampler failed, and whether
+    # the failures repeat under four other seeds (a systematic miss) or not
+    fails = {}
+    for name, sampler in (("plain", 0), ("learned", 1)):
+        other = "learned" if name == "plain" else "plain"
+        idx = [k for k in range(len(Q)) if not runs[name][k, 0]]
+        fails[name] = {"failed": idx,
+                       "failed_only_here": [k for k in idx if runs[other][k, 0]],
+                       "other_sampler_ms_on_those": [round(float(runs[other][k, 1]), 2) for k in idx if runs[other][k, 0]],
+                       "solved_with_other_seeds": [int(sum(plan_one(k, sampler, W.SEED_QUERY + k + 7919 * r)[0]
+                                                           for r in range(1, 5))) for k in idx]}
+        log("  shelf %s failures: %s" % (name, fails[name]))
+    res["failures"] = fails
     return {"_model": mid, "workload": "learned_r14_shelf", "train_queries": n_train,
             "solved_train_queries": int(ds.vox.shape[0]),
             "samples": int(len(ds.scene_of)), "epochs": epochs, "datagen_s": gen_s,
             "loss_first_epoch": float(losses[0]) if len(losses) else None,
             "loss_last_epoch": float(losses[-1]) if len(losses) else None,
-            "time_budget_ms": budget_ms, "path_tail": tail, "plain": res["plain"], "learned": res["learned"]}
+            "time_budget_ms": budget_ms, "path_tail": tail, "plain": res["plain"], "learned": res["learned"],
+            "failures": res["failures"]}
 
 
 def host_cpu():
@@ -539,10 +700,14 @@ def main():
     ap.add_argument("--learned-shelf-tail", type=float, default=1.0,
                     help="train the shelf proposal on the last fraction of each path only")
     ap.add_argument("--shelf-queries", type=int, default=500, help="stored shelf queries planned (500 in all)")
-    ap.add_argument("--learned-scenes", type=int, default=1000, help="training scenes (10000 for the full set)")
-    ap.add_argument("--learned-eval", type=int, default=300, help="held-out scenes")
+    ap.add_argument("--learned-scenes", type=int, default=10000, help="training scenes")
+    ap.add_argument("--learned-eval", type=int, default=500, help="held-out scenes")
     ap.add_argument("--learned-epochs", type=int, default=16)
     ap.add_argument("--skip-serve", action="store_true", help="omit the batched / served planner legs")
+    ap.add_argument("--skip-variants", action="store_true",
+                    help="omit the two-stage and ESDF check_edges variants")
+    ap.add_argument("--skip-sampling", action="store_true",
+                    help="omit the sampling variants (uniform, dynamic domain, Halton)")
     ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this size (counter calibration)")
@@ -562,6 +727,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     plan = None if args.skip_plan else bench_plan(P, ctx)
+    variants = None if args.skip_variants else bench_collision_variants(P, ctx, torch)
+    graphs = None if args.skip_variants else bench_graph_launches(P, ctx, torch)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -571,6 +738,11 @@ def main():
         log("14-DoF shelf")
         shelf = bench_shelf(P, ctx, args.shelf_queries)
         log("  " + json.dumps(finite_or_null(shelf)))
+    sampling = None
+    if not args.skip_sampling:
+        log("sampling variants")
+        sampling = bench_sampling(P, ctx)
+        log("  " + json.dumps(finite_or_null(sampling)))
     serve = batch = pool = None
     if not args.skip_serve:
         log("batched planner: launch shapes")
@@ -638,8 +810,11 @@ def main():
                      "collision_free_launch": {"edges": ce["free_edges"], "kernel_ms": ce["free_ms"],
                                                "achieved": free_tflops, "frac": free_tflops / PEAK_FP32_TFLOPS,
                                                "all_valid": ce["free_all_valid"]}},
+        "collision_variants": variants,
+        "graph_launches": graphs,
         "ms_to_solution": plan,
         "ms_to_solution_r14_shelf": shelf,
+        "sampling_variants": sampling,
         "batched": batch,
         "served": serve,
         "served_learned": served_learned,

@@ -51,7 +51,8 @@ typedef struct prrtc_ctx prrtc_ctx;
 #define PRRTC_MAX_SELF_PAIRS 16384
 
 /* Create a context on HIP device `device` (plan runs on the context's own
- * non-blocking stream; the asynchronous calls take the caller's stream). */
+ * non-blocking stream; the asynchronous calls take the caller's stream, or
+ * that stream when they are given NULL). */
 prrtc_status prrtc_create(prrtc_ctx **out, int device);
 /* Free every table and buffer of the context.  destroy(NULL) is a no-op. */
 void prrtc_destroy(prrtc_ctx *ctx);
@@ -161,9 +162,11 @@ prrtc_status prrtc_esdf_from_scene(prrtc_ctx *ctx, int32_t scene_id, const float
  * a, b:   device float32 [n_edges][dof], row-major, finite.
  * valid:  device uint8 [n_edges], written.
  * res:    points per radian (> 0).
- * stream: hipStream_t to enqueue on (NULL = the HIP default stream).  The
- *         call is asynchronous; buffers must stay alive until the stream is
- *         synchronised.  n_edges = 0 is a no-op.  Launches on one context
+ * stream: hipStream_t to enqueue on (NULL = the context's own stream, a
+ *         non-blocking stream that prrtc_plan also uses; hipDeviceSynchronize
+ *         waits for it; the null stream itself is named hipStreamLegacy).
+ *         The call is asynchronous; buffers must stay alive
+ *         until the stream is synchronised.  n_edges = 0 is a no-op.  Launches on one context
  *         draw from a ring of 256 work counters, so at most 256 launches of
  *         one context may be in flight at once.
  *
@@ -178,8 +181,9 @@ prrtc_status prrtc_check_edges(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_i
                                uint8_t *valid, void *stream);
 
 /* The check_edges schedule of a (robot, scene) pair: set = 0 or 1 pins that
- * schedule, -1 forgets the choice (the next large batch times both again),
- * -2 changes nothing.  *schedule (may be NULL) = the schedule in force
+ * schedule, -1 forgets the choice and its tuning record (the next large
+ * batch times both again), -2 changes nothing (a stored tuning record for the
+ * pair's key is taken up).  *schedule (may be NULL) = the schedule in force
  * after the call, -1 while none is chosen.  E_ARG for another set value. */
 prrtc_status prrtc_edge_schedule(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, int32_t set,
                                  int32_t *schedule);
@@ -331,19 +335,42 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
                                int32_t *best_workers, int32_t *best_tile);
 
 /*
+ * Tuning records (kept across processes).  The library records what it
+ * timed: each check_edges schedule it chose, keyed by the device
+ * architecture and the robot's and scene's shape (DoF, moving spheres,
+ * coarse spheres or not, self pairs, and primitive counts by type, counts in
+ * power-of-two buckets, ESDF or not), and each prrtc_tune_launch result,
+ * keyed by the device, the queries' DoF set, the largest obstacle count's
+ * bucket and the candidate lists.  A (robot, scene) pair whose key has a
+ * record takes its schedule without timing.
+ *
+ * prrtc_tuned_launch: the stored result of prrtc_tune_launch for these
+ *   queries and candidates (E_STATE if none).
+ * prrtc_tuning_save: write every record to a text file (one "key | value"
+ *   line each).  prrtc_tuning_load: add a file's records (later ones win).
+ *   E_ARG if the file cannot be written / read or a line is malformed.
+ */
+prrtc_status prrtc_tuned_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32_t n, const int32_t *workers,
+                                int32_t n_workers, const int32_t *tiles, int32_t n_tiles, int32_t *best_workers,
+                                int32_t *best_tile);
+prrtc_status prrtc_tuning_save(prrtc_ctx *ctx, const char *path);
+prrtc_status prrtc_tuning_load(prrtc_ctx *ctx, const char *path);
+
+/*
  * Serving: a thread owned by the context plans submitted queries as they
- * arrive.  With uniform sampling (params->sampler 0) it keeps one persistent
- * launch running: queries are published into a ring of 64 x slots entries
- * (32 to 16384, and within about 256 MiB of pinned host memory for the
- * entries' arguments and paths) that the launch's worker groups take from
- * while it runs (at most `slots` in flight), and each result returns as
- * soon as its query ends.  The launch closes once no query has been claimed for 50 ms
- * (every group leaves at its next claim) and is started again by the next
- * submission; a used-up ring drains the launch and the next one
- * starts on the reset ring.  Group buffers are sized for the largest robot
- * loaded when serving starts (robots cannot be loaded while serving).  With
- * the learned sampler it gathers queries into prrtc_plan_batch launches of
- * up to `slots` queries (continuous batching at launch granularity).  Groups
+ * arrive.  It keeps one persistent launch running: queries are published
+ * into a ring of 64 x slots entries (32 to 16384, and within about 256 MiB
+ * of pinned host memory for the entries' arguments and paths) that the
+ * launch's worker groups take from while it runs (at most `slots` in
+ * flight), and each result returns as soon as its query ends.  The launch
+ * closes once no query has been claimed for 50 ms (every group leaves at its
+ * next claim) and is started again by the next submission; a used-up ring
+ * drains the launch and the next one starts on the reset ring.  Group
+ * buffers are sized for the largest robot loaded when serving starts
+ * (robots cannot be loaded while serving).  With the learned sampler
+ * (params->sampler 1) each group computes its query's mixture inside the
+ * launch from tables of every (scene, model) pair loaded when serving
+ * starts.  Groups
  * are sized by memory_budget as in prrtc_plan_batch.  Results equal those
  * of prrtc_plan / prrtc_plan_batch for the same query, seed and parameters.
  * While serving, the context accepts only prrtc_submit, prrtc_poll,
@@ -353,8 +380,7 @@ prrtc_status prrtc_tune_launch(prrtc_ctx *ctx, const prrtc_query *queries, int32
  *
  * prrtc_serve_start: params as for prrtc_plan_batch; slots >= 1;
  *   max_pending >= slots bounds the queries admitted and not yet polled;
- *   path_cap >= 1 nodes kept per query.  E_STATE if no robot is loaded
- *   (uniform sampling); E_CAPACITY if one worker group does not fit;
+ *   path_cap >= 1 nodes kept per query.  E_STATE if no robot is loaded; E_CAPACITY if one worker group does not fit;
  *   E_HIP if the ring buffers (pinned host and device memory) cannot be
  *   allocated.  A query rejected by the host checks (unknown ids, endpoints
  *   outside the limits) comes back through prrtc_poll with that status;

@@ -14,20 +14,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "prrtc_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB may name another build of the same source (e.g. with sanitizers)
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 FLAG_BAND = 1e-5
 MAX_DOF = 16
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (FP contraction off, OpenMP on)."""
-    if force or not os.path.exists(_LIB):
+def build(force: bool = True, out: str | None = None, extra=()) -> str:
+    """Compile liboracle.so with gcc (FP contraction off, OpenMP on); `out`
+    and `extra` flags build another copy (e.g. with sanitizers)."""
+    out = out or _LIB
+    if force or not os.path.exists(out):
         cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fopenmp", "-shared",
-               "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-fPIC", *extra, "-o", out + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd, cwd=_HERE)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class Robot(C.Structure):

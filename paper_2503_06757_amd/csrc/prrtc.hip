@@ -9,6 +9,9 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -291,8 +294,8 @@ struct Server {
     std::unordered_map<uint64_t, ServeDone> done;
     long long launches = 0;
     size_t in_flight() const { return queue.size() + running.size() + done.size(); }
-    // persistent mode (uniform sampling): one long launch takes queries as
-    // they are published into a ring (see k_serve)
+    // persistent mode: one long launch takes queries as they are published
+    // into a ring (see k_serve)
     bool persistent = false;
     int ring = 0, path_stride = 0, groups = 0, W = 0;
     size_t lds = 0;
@@ -332,6 +335,8 @@ struct prrtc_ctx {
     EdgeCounter* counters = nullptr;  // kCounterSlots self-resetting work counters
     unsigned counter_next = 0;
     std::unordered_map<uint64_t, int> plan_per_cu;   // resident planner workgroups per CU by (tile, LDS bytes)
+    std::string arch;                  // device architecture name (gcnArchName), part of the tuning keys
+    std::map<std::string, std::string> tuning;   // tuning records: key -> value (see prrtc_tuning_save)
     int edge_grid[4] = {0, 0, 0, 0};   // resident workgroups of each k_check_edges kernel (cached)
     size_t edge_grid_lds[4] = {0, 0, 0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -343,6 +348,12 @@ struct prrtc_ctx {
 };
 
 constexpr int kPinnedFloats = 1024;
+
+namespace {
+inline hipStream_t stream_of(const prrtc_ctx* ctx, void* stream) {
+    return stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+}
+}  // namespace
 
 constexpr int kCounterSlots = 256;
 
@@ -403,6 +414,9 @@ size_t align_up(size_t x) {
 }  // namespace
 
 namespace {
+// The stream an asynchronous call enqueues on: the caller's, or for NULL the
+// context's own stream.
+inline hipStream_t stream_of(const prrtc_ctx* ctx, void* stream);
 void serve_shutdown(prrtc_ctx* ctx);   // stops and joins a context's serving thread
 hipError_t scratch_address(int device, float** out);   // the static scratch array on a device
 }  // namespace
@@ -420,6 +434,8 @@ prrtc_status prrtc_create(prrtc_ctx** out, int device) {
     hipDeviceProp_t prop;
     PRRTC_HIP(ctx.get(), hipGetDeviceProperties(&prop, device));
     ctx->n_cu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    ctx->arch = ctx->arch.substr(0, ctx->arch.find(':'));   // "gfx950", without the target features
     int wall_khz = 0;
     if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && wall_khz > 0)
         ctx->wall_khz = (double)wall_khz;
@@ -776,12 +792,24 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     const size_t o_sph = 0;
     const size_t o_box = align_up<int>(sizeof(float4) * sph.size());
     const size_t o_cyl = align_up<int>(o_box + sizeof(float) * box.size());
-    const size_t o_sb = align_up<int>(o_cyl + sizeof(float) * cyl.size());
-    const size_t o_bb = align_up<int>(o_sb + sizeof(float4) * sph_b.size());
-    const size_t o_cb = align_up<int>(o_bb + sizeof(float4) * box_b.size());
-    const size_t o_be = align_up<int>(o_cb + sizeof(float4) * cyl_b.size());
-    const size_t o_ce = align_up<int>(o_be + sizeof(float4) * box_e.size());
-    const size_t bytes = std::max<size_t>(256, align_up<int>(o_ce + sizeof(float4) * cyl_e.size()));
+    // one bounds table and one world-box table over all types, spheres,
+    // cuboids, cylinders (a type's boxes are used when a quarter of it is
+    // thin; 3e38 half-sizes keep everything else)
+    const bool use_box_e = PRRTC_EXT_CULL && box_thin > 0 && 4 * box_thin >= (int)box_e.size();
+    const bool use_cyl_e = PRRTC_EXT_CULL && cyl_thin > 0 && 4 * cyl_thin >= (int)cyl_e.size();
+    const float4 wide = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
+    std::vector<float4> bnd(sph_b), ext(sph_b.size(), wide);
+    bnd.insert(bnd.end(), box_b.begin(), box_b.end());
+    bnd.insert(bnd.end(), cyl_b.begin(), cyl_b.end());
+    for (const float4& e : box_e) ext.push_back(use_box_e ? e : wide);
+    for (const float4& e : cyl_e) ext.push_back(use_cyl_e ? e : wide);
+    if (bnd.empty()) {   // an empty scene keeps one zero entry of each
+        bnd.push_back(make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+        ext.push_back(make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+    }
+    const size_t o_bnd = align_up<int>(o_cyl + sizeof(float) * cyl.size());
+    const size_t o_ext = align_up<int>(o_bnd + sizeof(float4) * bnd.size());
+    const size_t bytes = std::max<size_t>(256, align_up<int>(o_ext + sizeof(float4) * ext.size()));
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     SceneRec rec;
     PRRTC_HIP(ctx, hipMalloc(&rec.mem, bytes));
@@ -789,11 +817,8 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     if (!sph.empty()) memcpy(host.data() + o_sph, sph.data(), sizeof(float4) * sph.size());
     if (!box.empty()) memcpy(host.data() + o_box, box.data(), sizeof(float) * box.size());
     if (!cyl.empty()) memcpy(host.data() + o_cyl, cyl.data(), sizeof(float) * cyl.size());
-    if (!sph_b.empty()) memcpy(host.data() + o_sb, sph_b.data(), sizeof(float4) * sph_b.size());
-    if (!box_b.empty()) memcpy(host.data() + o_bb, box_b.data(), sizeof(float4) * box_b.size());
-    if (!cyl_b.empty()) memcpy(host.data() + o_cb, cyl_b.data(), sizeof(float4) * cyl_b.size());
-    if (!box_e.empty()) memcpy(host.data() + o_be, box_e.data(), sizeof(float4) * box_e.size());
-    if (!cyl_e.empty()) memcpy(host.data() + o_ce, cyl_e.data(), sizeof(float4) * cyl_e.size());
+    if (!bnd.empty()) memcpy(host.data() + o_bnd, bnd.data(), sizeof(float4) * bnd.size());
+    if (!ext.empty()) memcpy(host.data() + o_ext, ext.data(), sizeof(float4) * ext.size());
     hipError_t e = hipMemcpy(rec.mem, host.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(rec.mem);
@@ -806,13 +831,9 @@ prrtc_status prrtc_load_scene(prrtc_ctx* ctx, const prrtc_prim* p, int32_t n, in
     rec.args.sph = reinterpret_cast<const float4*>(base + o_sph);
     rec.args.box = reinterpret_cast<const float*>(base + o_box);
     rec.args.cyl = reinterpret_cast<const float*>(base + o_cyl);
-    rec.args.sph_bnd = reinterpret_cast<const float4*>(base + o_sb);
-    rec.args.box_bnd = reinterpret_cast<const float4*>(base + o_bb);
-    rec.args.cyl_bnd = reinterpret_cast<const float4*>(base + o_cb);
-    rec.args.box_ext = 4 * box_thin >= (int)box_e.size() && box_thin > 0 ? reinterpret_cast<const float4*>(base + o_be)
-                                                                         : nullptr;
-    rec.args.cyl_ext = 4 * cyl_thin >= (int)cyl_e.size() && cyl_thin > 0 ? reinterpret_cast<const float4*>(base + o_ce)
-                                                                         : nullptr;
+    rec.args.bnd = reinterpret_cast<const float4*>(base + o_bnd);
+    rec.args.ext = reinterpret_cast<const float4*>(base + o_ext);
+    rec.args.ext_cull = use_box_e || use_cyl_e;
     rec.n = n;
     e = hipMalloc(&rec.dev_args, sizeof(SceneArgs));
     if (e == hipSuccess) e = hipMemcpy(rec.dev_args, &rec.args, sizeof(SceneArgs), hipMemcpyHostToDevice);
@@ -941,7 +962,7 @@ prrtc_status prrtc_esdf_from_scene(prrtc_ctx* ctx, int32_t scene_id, const float
     if (!esdf_geometry_ok(ctx, origin, voxel, dims)) return PRRTC_E_ARG;
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     const long long n = (long long)dims[0] * dims[1] * dims[2];
-    hipLaunchKernelGGL(k_esdf_build, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+    hipLaunchKernelGGL(k_esdf_build, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream_of(ctx, stream),
                        ctx->scenes[scene_id].args, origin[0], origin[1], origin[2], voxel, dims[0], dims[1], dims[2],
                        values);
     PRRTC_HIP(ctx, hipGetLastError());
@@ -988,6 +1009,55 @@ size_t check_lds_bytes(const RobotArgs& R, int tp) {
            sizeof(int) * (tp + 4) + two_stage_lds_bytes(R, tp);
 }
 
+// Tuning records are keyed by what decides the timing: the device, and the
+// robot's and scene's shape with counts in power-of-two buckets.
+int bucket(int n) {
+    int b = 0;
+    while (n > 0) {
+        ++b;
+        n >>= 1;
+    }
+    return b;
+}
+
+std::string edge_tuning_key(const prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id) {
+    const RobotArgs& R = ctx->robots[robot_id].args;
+    const SceneArgs& S = ctx->scenes[scene_id].args;
+    std::ostringstream k;
+    k << "edge " << ctx->arch << " dof=" << R.dof << " moving=" << bucket(R.n_move) << " coarse=" << (R.n_cmove > 0)
+      << " pairs=" << bucket(R.n_pairs + R.n_bip_a * R.n_bip_b) << " spheres=" << bucket(S.n_sph)
+      << " cuboids=" << bucket(S.n_box) << " cylinders=" << bucket(S.n_cyl) << " esdf=" << (S.esdf != nullptr);
+    return k.str();
+}
+
+// A (robot, scene) pair without a schedule takes a stored record's.
+void adopt_tuned_schedule(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id) {
+    auto& m = ctx->scenes[scene_id].edge_schedule;
+    if (m.count(robot_id) || ctx->tuning.empty()) return;
+    auto t = ctx->tuning.find(edge_tuning_key(ctx, robot_id, scene_id));
+    if (t != ctx->tuning.end() && (t->second == "0" || t->second == "1")) m[robot_id] = t->second == "1";
+}
+
+std::string launch_tuning_key(const prrtc_ctx* ctx, const prrtc_query* q, int n, const int32_t* workers,
+                              int n_workers, const int32_t* tiles, int n_tiles) {
+    std::map<int, int> dofs;
+    int obstacles = 0;
+    for (int i = 0; i < n; ++i) {
+        if (q[i].robot_id < 0 || q[i].robot_id >= (int)ctx->robots.size()) continue;
+        dofs[ctx->robots[q[i].robot_id].dof] = 1;
+        if (q[i].scene_id >= 0 && q[i].scene_id < (int)ctx->scenes.size())
+            obstacles = std::max(obstacles, ctx->scenes[q[i].scene_id].n);
+    }
+    std::ostringstream k;
+    k << "launch " << ctx->arch << " dofs=";
+    for (const auto& d : dofs) k << d.first << ",";
+    k << " obstacles=" << bucket(obstacles) << " workers=";
+    for (int i = 0; i < n_workers; ++i) k << workers[i] << ",";
+    k << " tiles=";
+    for (int i = 0; i < n_tiles; ++i) k << tiles[i] << ",";
+    return k.str();
+}
+
 prrtc_status lookup(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id, const RobotRec** r,
                     const SceneRec** s) {
     if (robot_id < 0 || robot_id >= (int32_t)ctx->robots.size())
@@ -1019,7 +1089,7 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
     if (!(res > 0.0f) || !std::isfinite(res)) return fail(ctx, PRRTC_E_ARG, "res must be finite and > 0");
     if (n_edges == 0) return PRRTC_OK;
     if (!a || !b || !valid) return fail(ctx, PRRTC_E_ARG, "null buffer");
-    hipStream_t sm = static_cast<hipStream_t>(stream);
+    hipStream_t sm = stream_of(ctx, stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     const size_t lds = check_lds_bytes(r->args, kEdgeTile);
     const bool two = r->args.n_cmove > 0;
@@ -1045,6 +1115,7 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
         return PRRTC_OK;
     };
     SceneRec& sr = ctx->scenes[scene_id];
+    adopt_tuned_schedule(ctx, robot_id, scene_id);
     auto it = sr.edge_schedule.find(robot_id);
     int schedule = it == sr.edge_schedule.end() ? 0 : it->second;
     if (it == sr.edge_schedule.end() && n_edges >= kEdgeTuneMin) {
@@ -1068,6 +1139,7 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
             }
         }
         sr.edge_schedule[robot_id] = schedule;
+        ctx->tuning[edge_tuning_key(ctx, robot_id, scene_id)] = std::to_string(schedule);
     }
     return launch(schedule, n_edges);
 }
@@ -1082,9 +1154,13 @@ prrtc_status prrtc_edge_schedule(prrtc_ctx* ctx, int32_t robot_id, int32_t scene
     prrtc_status st = lookup(ctx, robot_id, scene_id, &r, &s);
     if (st != PRRTC_OK) return st;
     if (set < -2 || set > 1) return fail(ctx, PRRTC_E_ARG, "schedule must be -2, -1, 0 or 1");
+    if (set == -2) adopt_tuned_schedule(ctx, robot_id, scene_id);
     auto& m = ctx->scenes[scene_id].edge_schedule;
     if (set >= 0) m[robot_id] = set;
-    if (set == -1) m.erase(robot_id);
+    if (set == -1) {   // timed again by the next large batch
+        m.erase(robot_id);
+        ctx->tuning.erase(edge_tuning_key(ctx, robot_id, scene_id));
+    }
     if (schedule) {
         auto it = m.find(robot_id);
         *schedule = it == m.end() ? -1 : it->second;
@@ -1103,7 +1179,7 @@ prrtc_status prrtc_fk_spheres(prrtc_ctx* ctx, int32_t robot_id, const float* q, 
     if (n < 0) return fail(ctx, PRRTC_E_ARG, "n < 0");
     if (n == 0) return PRRTC_OK;
     if (!q || !xyz) return fail(ctx, PRRTC_E_ARG, "null buffer");
-    hipStream_t sm = static_cast<hipStream_t>(stream);
+    hipStream_t sm = stream_of(ctx, stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     const long long blocks = (n + kFkPerBlock - 1) / kFkPerBlock;
     if (blocks > 0x7fffffffLL) return fail(ctx, PRRTC_E_ARG, "n too large for one launch");
@@ -1690,7 +1766,54 @@ prrtc_status prrtc_tune_launch(prrtc_ctx* ctx, const prrtc_query* queries, int32
             }
         }
     ctx->err.clear();
-    return best_rate > 0.0f ? PRRTC_OK : fail(ctx, PRRTC_E_CAPACITY, "no candidate could launch");
+    if (best_rate <= 0.0f) return fail(ctx, PRRTC_E_CAPACITY, "no candidate could launch");
+    ctx->tuning[launch_tuning_key(ctx, queries, n, workers, n_workers, tiles, n_tiles)] =
+        std::to_string(*best_workers) + " " + std::to_string(*best_tile);
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_tuned_launch(prrtc_ctx* ctx, const prrtc_query* queries, int32_t n, const int32_t* workers,
+                                int32_t n_workers, const int32_t* tiles, int32_t n_tiles, int32_t* best_workers,
+                                int32_t* best_tile) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (n < 1 || !queries || !workers || n_workers < 1 || !tiles || n_tiles < 1 || !best_workers || !best_tile)
+        return fail(ctx, PRRTC_E_ARG, "bad tuning arguments");
+    auto t = ctx->tuning.find(launch_tuning_key(ctx, queries, n, workers, n_workers, tiles, n_tiles));
+    if (t == ctx->tuning.end()) return fail(ctx, PRRTC_E_STATE, "no tuning record for these queries and candidates");
+    std::istringstream v(t->second);
+    if (!(v >> *best_workers >> *best_tile)) return fail(ctx, PRRTC_E_STATE, "malformed tuning record");
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_tuning_save(prrtc_ctx* ctx, const char* path) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (!path) return fail(ctx, PRRTC_E_ARG, "null path");
+    std::ofstream f(path);
+    if (!f) return fail(ctx, PRRTC_E_ARG, "cannot write %s", path);
+    f << "# prrtc tuning records v1: key | value\n";
+    for (const auto& kv : ctx->tuning) f << kv.first << " | " << kv.second << "\n";
+    if (!f) return fail(ctx, PRRTC_E_ARG, "cannot write %s", path);
+    return PRRTC_OK;
+}
+
+prrtc_status prrtc_tuning_load(prrtc_ctx* ctx, const char* path) {
+    if (!ctx) return PRRTC_E_ARG;
+    ctx->err.clear();
+    if (!path) return fail(ctx, PRRTC_E_ARG, "null path");
+    std::ifstream f(path);
+    if (!f) return fail(ctx, PRRTC_E_ARG, "cannot read %s", path);
+    std::string line;
+    std::map<std::string, std::string> add;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        const size_t bar = line.find(" | ");
+        if (bar == std::string::npos) return fail(ctx, PRRTC_E_ARG, "malformed tuning line: %s", line.c_str());
+        add[line.substr(0, bar)] = line.substr(bar + 3);
+    }
+    for (const auto& kv : add) ctx->tuning[kv.first] = kv.second;
+    return PRRTC_OK;
 }
 
 }  // extern "C"
@@ -1947,7 +2070,7 @@ void serve_loop_persistent(prrtc_ctx* ctx) {
 }
 
 #ifndef PRRTC_SERVE_PERSISTENT
-#define PRRTC_SERVE_PERSISTENT 1   // uniform-sampling servers run one persistent launch
+#define PRRTC_SERVE_PERSISTENT 1   // servers run one persistent launch (0: launch-granular batches)
 #endif
 constexpr int kServeRingMax = 16384;  // queries per persistent launch before it drains (64 x slots, at most)
 
@@ -2501,7 +2624,7 @@ prrtc_status prrtc_voxelize(prrtc_ctx* ctx, int32_t scene_id, uint8_t* vox, void
         return fail(ctx, PRRTC_E_STATE, "unknown or unloaded scene id %d", scene_id);
     if (!vox) return fail(ctx, PRRTC_E_ARG, "null buffer");
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+    hipLaunchKernelGGL(k_voxelize, dim3(blocks(kVoxCells, 256)), dim3(256), 0, stream_of(ctx, stream),
                        ctx->scenes[scene_id].args, vox);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
@@ -2533,7 +2656,7 @@ prrtc_status prrtc_proposal_forward(prrtc_ctx* ctx, int32_t model_id, int32_t ro
     if (n == 0) return PRRTC_OK;
     if (!vox || !scene_of || !start || !goal || !gmm) return fail(ctx, PRRTC_E_ARG, "null buffer");
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    hipStream_t sm = static_cast<hipStream_t>(stream);
+    hipStream_t sm = stream_of(ctx, stream);
     PropWs W;
     st = prop_workspace(ctx, *M, n, n_scenes, W);
     if (st != PRRTC_OK) return st;
@@ -2560,7 +2683,7 @@ prrtc_status prrtc_proposal_forward_noalloc(prrtc_ctx* ctx, int32_t model_id, in
     if (!vox || !scene_of || !start || !goal || !gmm) return fail(ctx, PRRTC_E_ARG, "null buffer");
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
     const PropWs W = noalloc_workspace(ctx->scratch, n, n_scenes, M->L.dof);
-    prop_forward(static_cast<hipStream_t>(stream), *M, W, ctx->robots[robot_id].dev_args, vox, n_scenes, scene_of,
+    prop_forward(stream_of(ctx, stream), *M, W, ctx->robots[robot_id].dev_args, vox, n_scenes, scene_of,
                  start, goal, nullptr, n, gmm);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
@@ -2579,7 +2702,7 @@ prrtc_status prrtc_proposal_sample(prrtc_ctx* ctx, int32_t robot_id, const float
     if (!gmm || !q || !inside) return fail(ctx, PRRTC_E_ARG, "null buffer");
     const RobotRec& r = ctx->robots[robot_id];
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    hipLaunchKernelGGL(k_gmm_sample, dim3((unsigned)n), dim3(kWave), 0, static_cast<hipStream_t>(stream), gmm,
+    hipLaunchKernelGGL(k_gmm_sample, dim3((unsigned)n), dim3(kWave), 0, stream_of(ctx, stream), gmm,
                        r.dev_args, seed, query, round, attempt, n, q, inside);
     PRRTC_HIP(ctx, hipGetLastError());
     return PRRTC_OK;
@@ -2599,7 +2722,7 @@ prrtc_status prrtc_train_proposal(prrtc_ctx* ctx, int32_t model_id, int32_t robo
         return fail(ctx, PRRTC_E_ARG, "bad training batch");
     if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(ctx, PRRTC_E_ARG, "lr must be > 0");
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    hipStream_t sm = static_cast<hipStream_t>(stream);
+    hipStream_t sm = stream_of(ctx, stream);
     PropWs W;
     st = prop_workspace(ctx, *M, b->n, b->n_scenes, W);
     if (st != PRRTC_OK) return st;

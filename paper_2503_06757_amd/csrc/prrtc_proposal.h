@@ -55,10 +55,16 @@ __global__ void k_voxelize(SceneArgs S, uint8_t* __restrict__ vox) {
 // C[M][N] = op(A)[M][K] op(B)[K][N] (+ bias[N]); optional GELU epilogue that
 // keeps the pre-activation in Z and writes GELU(Z) to C.  op(A) = A
 // ([M][lda]) or A^T ([K][lda]); op(B) = B ([K][ldb]) or B^T ([N][ldb]).
-// Block tile 64 x 64, K step 16, 256 threads; each wave owns a 32 x 32
-// quarter as 2 x 2 v_mfma_f32_16x16x16_bf16 tiles.
+// Block tile 64 x 64, K step 32, 256 threads; each wave owns a 32 x 32
+// quarter as 2 x 2 tiles of gfx950's v_mfma_f32_16x16x32_bf16 (lane l holds
+// row / column l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7 of its operands).
+// Operands are rounded to bfloat16 while staged into LDS; the next K step's
+// global values are loaded into registers while the current one multiplies.
 // ---------------------------------------------------------------------------
-constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
+constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 32;
+constexpr int kGemmLd = kGemmBK + 8;   // LDS row: 80 bytes, 16-byte aligned fragments
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 template <typename TA, bool TRANS_A, bool TRANS_B, bool GELU>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int lda,
@@ -66,8 +72,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
                                                    const float* __restrict__ bias,
                                                    float* __restrict__ C, float* __restrict__ Z, int ldc,
                                                    int M, int N, int K) {
-    __shared__ unsigned short As[kGemmBM][kGemmBK + 4];   // [row][k]
-    __shared__ unsigned short Bt[kGemmBN][kGemmBK + 4];   // [col][k]
+    __shared__ __attribute__((aligned(16))) unsigned short As[kGemmBM][kGemmLd];   // [row][k]
+    __shared__ __attribute__((aligned(16))) unsigned short Bt[kGemmBN][kGemmLd];   // [col][k]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int row0 = blockIdx.y * kGemmBM, col0 = blockIdx.x * kGemmBN;
@@ -77,33 +83,57 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4f_acc{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += kGemmBK) {
-        // stage 64 x 16 of A and 16 x 64 of B (4 elements per thread each)
+    // staging: 64 x 32 of A and 32 x 64 of B, 8 elements per thread each.
+    // Element e of thread t, idx = t + 256 e, is (row or column, k) =
+    // (idx / 32, idx % 32) when the operand is contiguous along k, else
+    // (idx % 64, idx / 64): consecutive threads read consecutive addresses.
+    auto rk = [](int idx, bool along_k, int& r, int& k) {
+        if (along_k) {
+            r = idx / kGemmBK;
+            k = idx % kGemmBK;
+        } else {
+            r = idx % kGemmBM;
+            k = idx / kGemmBM;
+        }
+    };
+    float ra[8], rb[8];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e;           // 0..1023
-            const int r = idx / kGemmBK, k = idx % kGemmBK;
-            const int gr = row0 + r, gk = k0 + k;
-            float va = 0.0f;
-            if (gr < M && gk < K) va = (float)(TRANS_A ? A[(size_t)gk * lda + gr] : A[(size_t)gr * lda + gk]);
-            As[r][k] = bf16_bits(va);
-            const int c = idx / kGemmBK;
-            const int gc = col0 + c;
-            float vb = 0.0f;
-            if (gc < N && gk < K) vb = TRANS_B ? Bm[(size_t)gc * ldb + gk] : Bm[(size_t)gk * ldb + gc];
-            Bt[c][k] = bf16_bits(vb);
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + 256 * e;
+            int r, k;
+            rk(idx, !TRANS_A, r, k);
+            const int gr = row0 + r, gka = k0 + k;
+            ra[e] = (gr < M && gka < K) ? (float)(TRANS_A ? A[(size_t)gka * lda + gr] : A[(size_t)gr * lda + gka])
+                                        : 0.0f;
+            rk(idx, TRANS_B, r, k);
+            const int gc = col0 + r, gkb = k0 + k;
+            rb[e] = (gc < N && gkb < K) ? (TRANS_B ? Bm[(size_t)gc * ldb + gkb] : Bm[(size_t)gkb * ldb + gc]) : 0.0f;
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += kGemmBK) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + 256 * e;
+            int r, k;
+            rk(idx, !TRANS_A, r, k);
+            As[r][k] = bf16_bits(ra[e]);
+            rk(idx, TRANS_B, r, k);
+            Bt[r][k] = bf16_bits(rb[e]);
         }
         __syncthreads();
-        const int kk = 4 * (lane >> 4);
+        if (k0 + kGemmBK < K) fetch(k0 + kGemmBK);   // in flight during the products
+        const int kk = 8 * (lane >> 4);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
             const int ar = 32 * wr + 16 * mi + (lane & 15);
-            const v4s av = v4s{(short)As[ar][kk], (short)As[ar][kk + 1], (short)As[ar][kk + 2], (short)As[ar][kk + 3]};
+            const v8bf av = *reinterpret_cast<const v8bf*>(&As[ar][kk]);
 #pragma unroll
             for (int ni = 0; ni < 2; ++ni) {
                 const int bc = 32 * wc + 16 * ni + (lane & 15);
-                const v4s bv = v4s{(short)Bt[bc][kk], (short)Bt[bc][kk + 1], (short)Bt[bc][kk + 2], (short)Bt[bc][kk + 3]};
-                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[mi][ni], 0, 0, 0);
+                const v8bf bv = *reinterpret_cast<const v8bf*>(&Bt[bc][kk]);
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mi][ni], 0, 0, 0);
             }
         }
         __syncthreads();

@@ -28,6 +28,19 @@ PRRTC_E_HIP = -7
 
 MAX_DOF = 16
 
+# hipStreamLegacy: the null stream named explicitly (a NULL stream argument
+# means the context's own stream)
+HIP_STREAM_LEGACY = 1
+
+
+def _stream(stream: int | None):
+    """A stream argument: None -> NULL (the context's stream); 0, the handle
+    torch reports for its default (null) stream -> hipStreamLegacy, so the
+    call is ordered with torch's work on that stream; other handles as given."""
+    if stream is None:
+        return None
+    return HIP_STREAM_LEGACY if int(stream) == 0 else int(stream)
+
 
 class prrtc_robot_desc(C.Structure):
     _fields_ = [
@@ -175,6 +188,13 @@ def _load():
     L.prrtc_proposal_sample.argtypes = [P, I32, VP, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, I32, VP, VP,
                                         VP]
     L.prrtc_proposal_sample.restype = I32
+    L.prrtc_tuned_launch.argtypes = [P, C.POINTER(prrtc_query), I32, VP, I32, VP, I32, C.POINTER(I32),
+                                     C.POINTER(I32)]
+    L.prrtc_tuned_launch.restype = I32
+    L.prrtc_tuning_save.argtypes = [P, C.c_char_p]
+    L.prrtc_tuning_save.restype = I32
+    L.prrtc_tuning_load.argtypes = [P, C.c_char_p]
+    L.prrtc_tuning_load.restype = I32
     if hasattr(L, "prrtc_plan"):
         L.prrtc_plan_params_default.argtypes = [C.POINTER(prrtc_plan_params)]
         L.prrtc_plan_params_default.restype = None
@@ -205,6 +225,7 @@ EXPORTED = ("prrtc_create", "prrtc_destroy", "prrtc_last_error", "prrtc_load_rob
             "prrtc_load_scene", "prrtc_unload_scene", "prrtc_scene_set_esdf", "prrtc_esdf_from_scene",
             "prrtc_check_edges", "prrtc_edge_schedule", "prrtc_fk_spheres",
             "prrtc_plan_params_default", "prrtc_plan", "prrtc_plan_batch", "prrtc_tune_launch",
+            "prrtc_tuned_launch", "prrtc_tuning_save", "prrtc_tuning_load",
             "prrtc_serve_start", "prrtc_submit", "prrtc_poll", "prrtc_serve_stop", "prrtc_load_proposal", "prrtc_save_proposal",
             "prrtc_voxelize", "prrtc_proposal_forward", "prrtc_proposal_forward_noalloc", "prrtc_proposal_sample",
             "prrtc_train_proposal")
@@ -309,13 +330,13 @@ def prrtc_esdf_from_scene(ctx: int, scene_id: int, origin, voxel: float, dims, v
     o = np.ascontiguousarray(origin, np.float32)
     d = np.ascontiguousarray(dims, np.int32)
     _check(ctx, lib.prrtc_esdf_from_scene(ctx, int(scene_id), o.ctypes.data, float(voxel), d.ctypes.data,
-                                          values_dev, stream))
+                                          values_dev, _stream(stream)))
 
 
 def prrtc_check_edges(ctx: int, robot_id: int, scene_id: int, a_dev: int, b_dev: int, n_edges: int,
                       res: float, valid_dev: int, stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_check_edges(ctx, robot_id, scene_id, a_dev, b_dev, int(n_edges),
-                                             float(res), valid_dev, stream))
+                                             float(res), valid_dev, _stream(stream)))
 
 
 def prrtc_edge_schedule(ctx: int, robot_id: int, scene_id: int, set: int = -2) -> int:
@@ -328,7 +349,7 @@ def prrtc_edge_schedule(ctx: int, robot_id: int, scene_id: int, set: int = -2) -
 
 def prrtc_fk_spheres(ctx: int, robot_id: int, q_dev: int, n: int, xyz_dev: int,
                      stream: int | None = None) -> int:
-    return _check(ctx, lib.prrtc_fk_spheres(ctx, robot_id, q_dev, int(n), xyz_dev, stream))
+    return _check(ctx, lib.prrtc_fk_spheres(ctx, robot_id, q_dev, int(n), xyz_dev, _stream(stream)))
 
 
 def prrtc_plan_params_default() -> prrtc_plan_params:
@@ -416,6 +437,29 @@ def prrtc_tune_launch(ctx: int, queries, params, workers=(16, 32, 64, 128, 256),
                                   for j, t in enumerate(tl)}
 
 
+def prrtc_tuned_launch(ctx: int, queries, workers=(16, 32, 64, 128, 256), tiles=(16, 64)):
+    """(workers, tile) stored by prrtc_tune_launch for these queries and
+    candidates, or None without a record."""
+    arr = _query_array(queries)
+    wk = np.asarray(workers, np.int32)
+    tl = np.asarray(tiles, np.int32)
+    bw, bt = C.c_int32(0), C.c_int32(0)
+    st = lib.prrtc_tuned_launch(ctx, arr.ctypes.data_as(C.POINTER(prrtc_query)), len(queries), wk.ctypes.data,
+                                len(wk), tl.ctypes.data, len(tl), C.byref(bw), C.byref(bt))
+    if st == PRRTC_E_STATE:
+        return None
+    _check(ctx, st)
+    return bw.value, bt.value
+
+
+def prrtc_tuning_save(ctx: int, path: str) -> None:
+    _check(ctx, lib.prrtc_tuning_save(ctx, os.fsencode(path)))
+
+
+def prrtc_tuning_load(ctx: int, path: str) -> None:
+    _check(ctx, lib.prrtc_tuning_load(ctx, os.fsencode(path)))
+
+
 def prrtc_serve_start(ctx: int, params, slots: int = 256, max_pending: int = 1024, memory_budget: int = 0,
                       path_cap: int = 256) -> None:
     _check(ctx, lib.prrtc_serve_start(ctx, C.byref(params), int(slots), int(max_pending), int(memory_budget),
@@ -480,30 +524,30 @@ def prrtc_save_proposal(ctx: int, model_id: int) -> bytes:
 
 
 def prrtc_voxelize(ctx: int, scene_id: int, vox_dev: int, stream: int | None = None) -> int:
-    return _check(ctx, lib.prrtc_voxelize(ctx, scene_id, vox_dev, stream))
+    return _check(ctx, lib.prrtc_voxelize(ctx, scene_id, vox_dev, _stream(stream)))
 
 
 def prrtc_proposal_forward(ctx: int, model_id: int, robot_id: int, vox_dev: int, n_scenes: int,
                            scene_of_dev: int, start_dev: int, goal_dev: int, n: int, gmm_dev: int,
                            stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_proposal_forward(ctx, model_id, robot_id, vox_dev, n_scenes, scene_of_dev,
-                                                  start_dev, goal_dev, n, gmm_dev, stream))
+                                                  start_dev, goal_dev, n, gmm_dev, _stream(stream)))
 
 
 def prrtc_proposal_forward_noalloc(ctx: int, model_id: int, robot_id: int, vox_dev: int, n_scenes: int,
                                    scene_of_dev: int, start_dev: int, goal_dev: int, n: int, gmm_dev: int,
                                    stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_proposal_forward_noalloc(ctx, model_id, robot_id, vox_dev, n_scenes, scene_of_dev,
-                                                          start_dev, goal_dev, n, gmm_dev, stream))
+                                                          start_dev, goal_dev, n, gmm_dev, _stream(stream)))
 
 
 def prrtc_train_proposal(ctx: int, model_id: int, robot_id: int, batch: prrtc_train_batch, lr: float,
                          loss_dev: int, stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_train_proposal(ctx, model_id, robot_id, C.byref(batch), float(lr), loss_dev,
-                                                stream))
+                                                _stream(stream)))
 
 
 def prrtc_proposal_sample(ctx: int, robot_id: int, gmm_dev: int, seed: int, query: int, rnd: int, attempt: int,
                           n: int, q_dev: int, inside_dev: int, stream: int | None = None) -> int:
     return _check(ctx, lib.prrtc_proposal_sample(ctx, robot_id, gmm_dev, int(seed), int(query), int(rnd),
-                                                 int(attempt), int(n), q_dev, inside_dev, stream))
+                                                 int(attempt), int(n), q_dev, inside_dev, _stream(stream)))

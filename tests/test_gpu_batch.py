@@ -362,3 +362,42 @@ def test_tune_launch_and_tiles(gpu, mixed):
             assert np.array_equal(outs[0][1], outs[1][1])
     with pytest.raises(P.PrrtcError):
         _single(P, ctx, mixed[0], params(P, tile=32))
+
+
+def test_tuning_records_persist(gpu, mixed, r7, tmp_path):
+    """What a context timed (the check_edges schedule of a robot and scene
+    shape, the best launch shape for a query mix) is saved to a file and
+    taken up by a new context without timing again."""
+    P, ctx, torch = gpu
+    say("tuning records")
+    prims = W.scene_s64(r7)
+    rid, sid = P.prrtc_load_robot(ctx, r7), P.prrtc_load_scene(ctx, prims)
+    P.prrtc_edge_schedule(ctx, rid, sid, -1)
+    a, b = W.random_edges(r7, 16384, seed=31)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    tv = torch.zeros(16384, dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), 16384, 32.0, tv.data_ptr(), None)
+    torch.cuda.synchronize()
+    chosen = P.prrtc_edge_schedule(ctx, rid, sid)
+    assert chosen in (0, 1)
+    best, _ = P.prrtc_tune_launch(ctx, mixed[:4], params(P, max_rounds=100), workers=(16, 32), tiles=(16,))
+    assert P.prrtc_tuned_launch(ctx, mixed[:4], workers=(16, 32), tiles=(16,)) == best
+    assert P.prrtc_tuned_launch(ctx, mixed[:4], workers=(16, 64), tiles=(16,)) is None   # other candidates
+    path = str(tmp_path / "tuning.txt")
+    P.prrtc_tuning_save(ctx, path)
+    ctx2 = P.prrtc_create(0)
+    try:
+        rid2 = P.prrtc_load_robot(ctx2, r7)
+        sid2 = P.prrtc_load_scene(ctx2, W.scene_s64(r7, seed=W.SEED_S64 + 5))   # same shape, other scene
+        assert P.prrtc_edge_schedule(ctx2, rid2, sid2) == -1
+        P.prrtc_tuning_load(ctx2, path)
+        assert P.prrtc_edge_schedule(ctx2, rid2, sid2) == chosen
+        q2 = [(rid2, sid2) + q[2:] for q in mixed[:4] if len(q[2]) == 7]
+        assert P.prrtc_tuned_launch(ctx2, q2, workers=(16, 32), tiles=(16,)) is None   # another query mix
+        bad = tmp_path / "bad.txt"
+        bad.write_text("no separator here\n")
+        with pytest.raises(P.PrrtcError) as e:
+            P.prrtc_tuning_load(ctx2, str(bad))
+        assert e.value.status == P.PRRTC_E_ARG
+    finally:
+        P.prrtc_destroy(ctx2)

@@ -86,6 +86,9 @@ def test_check_edges_schedules_agree(gpu, orc, r7, r14):
         rid, sid = P.prrtc_load_robot(ctx, robot), P.prrtc_load_scene(ctx, prims)
         a, b = W.random_edges(robot, 12011, seed=4321)
         say("check_edges schedules", name, a.shape)
+        # a pair of the same shape timed by an earlier test left a record
+        # that a new pair adopts; forget it so this pair is timed afresh
+        P.prrtc_edge_schedule(ctx, rid, sid, -1)
         assert P.prrtc_edge_schedule(ctx, rid, sid) == -1          # nothing chosen yet
         outs = []
         for k in (0, 1):
@@ -295,3 +298,112 @@ def test_esdf_argument_errors(gpu, r7):
     with pytest.raises(P.PrrtcError) as e:
         P.prrtc_scene_set_esdf(ctx, 10_000, (0, 0, 0), 0.1, np.zeros((2, 2, 2)))
     assert e.value.status == P.PRRTC_E_STATE
+
+
+@pytest.mark.parametrize("case", ["r7-s64", "r7-s12", "r14-shelf", "r14-esdf"])
+def test_check_edges_two_stage(gpu, orc, r7, r14, case):
+    """A robot with coarse spheres (two-stage checks) gives the one-stage
+    robot's verdicts on every edge, flagged ones included (the coarse gate
+    only skips fine tests that cannot hit), and so the oracle's."""
+    P, ctx, _ = gpu
+    name, scene = case.split("-")
+    robot = r7 if name == "r7" else r14
+    two = W.with_coarse_spheres(robot)
+    prims = {"s64": lambda: W.scene_s64(robot), "s12": lambda: W.scene_s12(robot, 3),
+             "shelf": lambda: W.scene_shelf(robot), "esdf": lambda: np.zeros(0, W.PRIM_DTYPE)}[scene]()
+    rid1, rid2 = P.prrtc_load_robot(ctx, robot), P.prrtc_load_robot(ctx, two)
+    sid = P.prrtc_load_scene(ctx, prims)
+    grid = None
+    if scene == "esdf":
+        grid = orc.EsdfGrid(ESDF_O, ESDF_H, orc.esdf_of_scene(W.scene_shelf(robot), ESDF_O, ESDF_H, ESDF_N))
+        P.prrtc_scene_set_esdf(ctx, sid, ESDF_O, ESDF_H, grid.values)
+    a, b = W.random_edges(robot, 1 << 16 if scene == "s64" else 12011, seed=2024)
+    for sched in (0, 1):
+        P.prrtc_edge_schedule(ctx, rid1, sid, sched)
+        P.prrtc_edge_schedule(ctx, rid2, sid, sched)
+        one = gpu_check(gpu, rid1, sid, a, b)
+        got = gpu_check(gpu, rid2, sid, a, b)
+        assert np.array_equal(got, one), (sched, np.nonzero(got != one)[0][:10])
+    if grid is not None:
+        with grid:
+            v, f = assert_parity(orc, robot, prims, a, b, got, threads=16)
+    else:
+        v, f = assert_parity(orc, robot, prims, a, b, got, threads=16)
+    say("two-stage %s: %d edges, valid frac %.4f, flagged %d" % (case, len(a), v.mean(), f.sum()))
+
+
+def test_two_stage_descriptor_checked(gpu, r7):
+    """Coarse spheres that do not enclose their fine spheres are refused."""
+    P, ctx, _ = gpu
+    bad = W.with_coarse_spheres(r7)
+    bad["coarse_xyzr"] = bad["coarse_xyzr"].copy()
+    bad["coarse_xyzr"][2, 3] *= 0.5
+    with pytest.raises(P.PrrtcError) as e:
+        P.prrtc_load_robot(ctx, bad)
+    assert e.value.status == P.PRRTC_E_ARG
+
+
+def test_check_edges_in_hip_graph(gpu, orc, r7):
+    """check_edges launches captured in a HIP graph (after the schedule is
+    chosen, so the call does not synchronise): every replay gives the eager
+    verdicts, with eager work and synchronisation between the replays."""
+    P, ctx, torch = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    prims = W.scene_s64(r7)
+    sid = P.prrtc_load_scene(ctx, prims)
+    P.prrtc_edge_schedule(ctx, rid, sid, 1)
+    batches = [W.random_edges(r7, n, seed=600 + k) for k, n in enumerate((4096, 777, 20011))]
+    dev = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), torch.zeros(a.shape[0], dtype=torch.uint8,
+                                                                             device="cuda")) for a, b in batches]
+    eager = [gpu_check(gpu, rid, sid, a, b) for a, b in batches]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for ta, tb, tv in dev:
+            tv.zero_()
+            P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), ta.shape[0], 32.0, tv.data_ptr(),
+                                s.cuda_stream)
+    for rep in range(4):
+        for _, _, tv in dev:
+            tv.fill_(7)                                   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, tv), want in zip(dev, eager):
+            assert np.array_equal(tv.cpu().numpy(), want), rep
+    say("graph replays equal the eager verdicts")
+
+
+def test_check_edges_stream_order(gpu, r7):
+    """Stream arguments: torch's default stream (handle 0, passed on as
+    hipStreamLegacy) orders the call with torch's own work on that stream, so
+    a copy issued after it sees the verdicts and events recorded around it
+    bracket the kernel; NULL (None) runs on the context's stream, which a
+    device synchronisation waits for.  Both give the same verdicts."""
+    P, ctx, torch = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    sid = P.prrtc_load_scene(ctx, W.scene_s64(r7))
+    P.prrtc_edge_schedule(ctx, rid, sid, 1)
+    n = 1 << 18
+    a, b = W.random_edges(r7, n, seed=611)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    want = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), n, 32.0, want.data_ptr(), None)
+    torch.cuda.synchronize()
+    want = want.cpu().numpy()
+    assert set(np.unique(want)) <= {0, 1}
+    cur = torch.cuda.current_stream()
+    assert cur.cuda_stream == 0
+    for rep in range(3):
+        tv = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), n, 32.0, tv.data_ptr(), cur.cuda_stream)
+        e1.record(cur)
+        got = tv.cpu().numpy()                 # a copy on the same stream, no synchronisation first
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        say("  default-stream launch %d: %.3f ms" % (rep, ms))
+        assert np.array_equal(got, want), rep
+        assert ms > 0.02                       # the kernel ran between the events

@@ -279,3 +279,27 @@ def test_plan_esdf_replay(gpu, orc, r7, instance):
         assert st == 0, (st, stats)
         path_ok(orc, r7, empty, path, s, g)
         assert replay_equal(orc, r7, empty, s, g, st, path, stats, **kw)
+
+
+@pytest.mark.parametrize("case", ["r7-0", "r7-3", "r14-1"])
+def test_plan_two_stage_replay(gpu, orc, r7, r14, case):
+    """Plans of a robot with coarse spheres (two-stage checks in the planner's
+    edge and connect checks) equal the oracle's replay of the fine robot."""
+    P, ctx, _ = gpu
+    name, k = case.split("-")
+    robot = r7 if name == "r7" else r14
+    if name == "r7":
+        prims = W.scene_s12(robot, int(k))
+        s, g = free_query(orc, orc.OracleRobot(robot), prims, robot, W.SEED_QUERY + int(k))
+    else:
+        prims = W.scene_mixed(0x53140000 + int(k), robot, 12)
+        s, g = free_query(orc, orc.OracleRobot(robot), prims, robot, W.SEED_QUERY + 100 + int(k), n=3000)
+    say("two-stage plan", case)
+    for tile in (64, 16):
+        rid = P.prrtc_load_robot(ctx, W.with_coarse_spheres(robot))
+        sid = P.prrtc_load_scene(ctx, prims)
+        kw = dict(seed=77 + int(k), max_rounds=300)
+        st, path, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, tile=tile, **kw))
+        assert st == 0, (st, stats)
+        path_ok(orc, robot, prims, path, s, g)
+        assert replay_equal(orc, robot, prims, s, g, st, path, stats, **kw)
