@@ -77,8 +77,9 @@ def point_flops(robot, prims):
 
 def kernel_source_hash():
     """Hash of the source text that decides what k_check_edges executes: the
-    shared device header, the device part of prrtc.hip and its launch
-    configuration (planner, proposal and other host code are excluded)."""
+    shared device header, the device part of prrtc.hip, the robot and scene
+    table layouts and the launch configuration (planner, proposal and other
+    host code are excluded)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_06757_amd", "csrc")
     with open(os.path.join(csrc, "prrtc_device.h"), "rb") as fh:
@@ -86,7 +87,7 @@ def kernel_source_hash():
     with open(os.path.join(csrc, "prrtc.hip")) as fh:
         text = fh.read()
     h.update(text[:text.index("// Host side")].encode())
-    a = text.index("#ifndef PRRTC_EDGE_TILE")
+    a = text.index("prrtc_status prrtc_load_robot(")
     h.update(text[a:text.index("prrtc_status prrtc_fk_spheres(", a)].encode())
     return h.hexdigest()[:16]
 
@@ -104,8 +105,8 @@ def load_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
-EDGE_SCHEDULES = {0: "k_check_edges<16, 3, false>: 3 items per lane, spheres swept first",
-                  1: "k_check_edges<16, 2, true>: 2 items per lane, cuboids swept first"}
+EDGE_SCHEDULES = {0: "k_check_edges<16, 3, false, false>: 3 items per lane, spheres swept first",
+                  1: "k_check_edges<16, 2, true, false>: 2 items per lane, cuboids swept first"}
 
 
 def edge_counts(a, b, res):
@@ -273,8 +274,28 @@ def bench_graph_launches(P, ctx, torch, n_edges=4096, launches=200):
     g.replay()
     torch.cuda.synchronize()
     graph = time.perf_counter() - t0
+    # what one planner launch costs beyond its work: a query whose start and
+    # goal connect in the first round of an empty scene, as a single plan and
+    # as a one-query batch (host calls, argument upload, the launch, result
+    # copy); a batch of a thousand queries pays this once
+    sid0 = P.prrtc_load_scene(ctx, np.zeros(0, W.PRIM_DTYPE))
+    q0 = np.zeros(7, np.float32)
+    q1 = np.full(7, 0.05, np.float32)
+    prm = P.prrtc_plan_params_default()
+    prm.workers = 64
+    ts, tb_, ok = [], [], 0
+    for rep in range(60):
+        t0 = time.perf_counter()
+        st, _, _ = P.prrtc_plan(ctx, rid, sid0, q0, q1, prm)
+        ts.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        P.prrtc_plan_batch(ctx, [(rid, sid0, q0, q1, 1, 0)], prm)
+        tb_.append(time.perf_counter() - t0)
+        ok += st == P.PRRTC_OK
     return {"edges_per_launch": n_edges, "launches": launches, "eager_us_per_launch": eager / launches * 1e6,
-            "graph_us_per_launch": graph / launches * 1e6}
+            "graph_us_per_launch": graph / launches * 1e6,
+            "trivial_plan_ms": float(np.median(ts[10:]) * 1e3), "trivial_plan_batch_ms": float(np.median(tb_[10:]) * 1e3),
+            "trivial_plans_solved": int(ok)}
 
 
 def bench_plan(P, ctx, n_instances=100, n_seeds=50):

@@ -475,6 +475,45 @@ __device__ inline float wave_reduce_f(float v) {
 __device__ inline float wave_min_f(float v) { return wave_reduce_f<false>(v); }
 __device__ inline float wave_max_f(float v) { return wave_reduce_f<true>(v); }
 
+// Wave-wide minima of (lx, ly, lz) and maxima of (hx, hy, hz), returned in
+// every lane: the same six DPP steps as wave_reduce_f, each a single
+// v_min/v_max with the DPP operand (the compiler's form copies the value,
+// moves it with DPP, quiets NaNs and then takes the min: four instructions a
+// step).  The six reductions are interleaved, so each DPP read comes six
+// instructions after the write it depends on (two wait states are needed);
+// the leading and trailing s_nop cover the writes before and the reads after
+// the block.  Needs every lane of the wave active and no NaN inputs.
+#ifndef PRRTC_DPP_ASM
+#define PRRTC_DPP_ASM 1
+#endif
+__device__ inline void wave_box(float& lx, float& ly, float& lz, float& hx, float& hy, float& hz) {
+#if PRRTC_DPP_ASM
+#define PRRTC_BOX_STEP(ctrl)                                  \
+    "v_min_f32_dpp %0, %0, %0 " ctrl "\n"                     \
+    "v_min_f32_dpp %1, %1, %1 " ctrl "\n"                     \
+    "v_min_f32_dpp %2, %2, %2 " ctrl "\n"                     \
+    "v_max_f32_dpp %3, %3, %3 " ctrl "\n"                     \
+    "v_max_f32_dpp %4, %4, %4 " ctrl "\n"                     \
+    "v_max_f32_dpp %5, %5, %5 " ctrl "\n"
+    asm volatile("s_nop 1\n"
+                 PRRTC_BOX_STEP("quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf")
+                 PRRTC_BOX_STEP("quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf")
+                 PRRTC_BOX_STEP("row_half_mirror row_mask:0xf bank_mask:0xf")
+                 PRRTC_BOX_STEP("row_mirror row_mask:0xf bank_mask:0xf")
+                 PRRTC_BOX_STEP("row_bcast:15 row_mask:0xa bank_mask:0xf")
+                 PRRTC_BOX_STEP("row_bcast:31 row_mask:0xc bank_mask:0xf")
+                 "s_nop 1"
+                 : "+v"(lx), "+v"(ly), "+v"(lz), "+v"(hx), "+v"(hy), "+v"(hz));
+#undef PRRTC_BOX_STEP
+    auto last = [](float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1)); };
+    lx = last(lx); ly = last(ly); lz = last(lz);
+    hx = last(hx); hy = last(hy); hz = last(hz);
+#else
+    lx = wave_min_f(lx); ly = wave_min_f(ly); lz = wave_min_f(lz);
+    hx = wave_max_f(hx); hy = wave_max_f(hy); hz = wave_max_f(hz);
+#endif
+}
+
 // Does an obstacle's bounding sphere b reach the box [lo, hi]?
 __device__ inline bool sphere_meets_box(float4 b, float lx, float ly, float lz, float hx, float hy,
                                         float hz) {
@@ -759,8 +798,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     ly = fminf(ly, w.y - loc.w); hy = fmaxf(hy, w.y + loc.w);
                     lz = fminf(lz, w.z - loc.w); hz = fmaxf(hz, w.z + loc.w);
                 }
-                lx = wave_min_f(lx); ly = wave_min_f(ly); lz = wave_min_f(lz);
-                hx = wave_max_f(hx); hy = wave_max_f(hy); hz = wave_max_f(hz);
+                wave_box(lx, ly, lz, hx, hy, hz);
                 auto gate = [&](auto&& exact) {
 #pragma unroll
                     for (int b = 0; b < B; ++b) hit[b] |= exact(cx[b], cy[b], cz[b], cr[b]);
@@ -828,11 +866,16 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 const int it = min(base + lane + kWave * b, nitems - 1);
 #if PRRTC_ITEM_ORDER == 1
 #if PRRTC_FASTDIV
-                int s = (int)(((unsigned)it * div_m) >> 20);   // sphere-major
+                // sphere-major; the low 20 bits of it m are (it mod np) / np
+                // in 2^-20 units plus less than it / 2^20 < 1 / np, so
+                // scaling them by np and dropping 20 bits gives it mod np
+                const unsigned itm = (unsigned)it * div_m;
+                int s = (int)(itm >> 20);
+                int p = (int)(__umul24(itm & 0xFFFFFu, (unsigned)np) >> 20);
 #else
                 int s = it / np;
-#endif
                 int p = it - s * np;
+#endif
 #else
                 int p = it / S_move;      // point-major
                 int s = it - p * S_move;
@@ -843,7 +886,8 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     p = e & 255;
                 }
                 const float4 loc = ws.sph[s];
-                const float3 c = frame_apply(ws.frames + p * fstride + ws.slot3[s], loc.x, loc.y, loc.z);
+                const float3 c = frame_apply(ws.frames + __umul24((unsigned)p, (unsigned)fstride) + ws.slot3[s], loc.x,
+                                             loc.y, loc.z);
                 cx[b] = c.x; cy[b] = c.y; cz[b] = c.z; cr[b] = loc.w;
                 ck[b] = MULTI ? ws.pk[p] : 0;
             }
@@ -891,8 +935,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                     lz = fminf(lz, cz[b] - cr[b]); hz = fmaxf(hz, cz[b] + cr[b]);
                 }
             }
-            lx = wave_min_f(lx); ly = wave_min_f(ly); lz = wave_min_f(lz);
-            hx = wave_max_f(hx); hy = wave_max_f(hy); hz = wave_max_f(hz);
+            wave_box(lx, ly, lz, hx, hy, hz);
             // Cuboids and cylinders must also reach the block's box with
             // their own world-axis box where the scene keeps them (far
             // tighter than the bounding sphere for flat or long ones, such as
@@ -969,12 +1012,10 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
                 for (int a0 = 0; a0 < R.n_bip_a && !hit; a0 += kWave) {
                     const bool va = a0 + lane < R.n_bip_a;
                     const float4 ca = va ? centre(R.bip_a[a0 + lane]) : make_float4(0.f, 0.f, 0.f, 0.f);
-                    const float lx = wave_min_f(va ? ca.x - ca.w : 3.0e38f);
-                    const float ly = wave_min_f(va ? ca.y - ca.w : 3.0e38f);
-                    const float lz = wave_min_f(va ? ca.z - ca.w : 3.0e38f);
-                    const float hx = wave_max_f(va ? ca.x + ca.w : -3.0e38f);
-                    const float hy = wave_max_f(va ? ca.y + ca.w : -3.0e38f);
-                    const float hz = wave_max_f(va ? ca.z + ca.w : -3.0e38f);
+                    float lx = va ? ca.x - ca.w : 3.0e38f, ly = va ? ca.y - ca.w : 3.0e38f;
+                    float lz = va ? ca.z - ca.w : 3.0e38f, hx = va ? ca.x + ca.w : -3.0e38f;
+                    float hy = va ? ca.y + ca.w : -3.0e38f, hz = va ? ca.z + ca.w : -3.0e38f;
+                    wave_box(lx, ly, lz, hx, hy, hz);
                     for (int b0 = 0; b0 < R.n_bip_b && !hit; b0 += kWave) {
                         const bool vb = b0 + lane < R.n_bip_b;
                         const float4 cb = vb ? centre(R.bip_b[b0 + lane]) : make_float4(0.f, 0.f, 0.f, 0.f);

@@ -258,23 +258,46 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
 
 // Wave argmin of the FP32 squared distance (in joint order, no FMA) over
 // the non-blocked nodes 0..size-1 of a [dof][cap] tree; ties -> lowest index.
-__device__ inline int wave_nearest(const float* tq, const unsigned char* blocked, int cap, int size,
-                                   const float* x, int dof) {
+// Each lane takes U nodes per step and issues all their loads (D >= dof
+// joints; the joints past dof load joint dof-1 and add an exact zero) before
+// using any, so a step waits for one memory latency instead of one per joint
+// and node.  Nodes are visited in increasing index order per lane and the
+// strict compare keeps the first of equal distances.
+template <int D, int U>
+__device__ inline int wave_nearest_t(const float* tq, const unsigned char* blocked, int cap, int size,
+                                     const float* x, int dof) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & (kWave - 1);
+    float xr[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xr[j] = j < dof ? x[j] : 0.0f;
     float bd = __builtin_inff();
     int bi = 0x7fffffff;
-    for (int i = lane; i < size; i += kWave) {
-        if (blocked[i]) continue;
-        float s = 0.0f;
-        for (int j = 0; j < dof; ++j) {
-            const float d = x[j] - tq[(size_t)j * cap + i];
-            const float sq = d * d;
-            s = s + sq;
+    for (int i0 = lane; i0 < size; i0 += kWave * U) {
+        float v[U][D];
+        int idx[U];
+        bool skip[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            idx[u] = i0 + u * kWave;
+            const int ic = min(idx[u], size - 1);
+            skip[u] = blocked[ic] != 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[u][j] = tq[(size_t)min(j, dof - 1) * cap + ic];
         }
-        if (s < bd) {
-            bd = s;
-            bi = i;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float s = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float d = xr[j] - (j < dof ? v[u][j] : 0.0f);
+                const float sq = d * d;
+                s = s + sq;
+            }
+            if (idx[u] < size && !skip[u] && s < bd) {
+                bd = s;
+                bi = idx[u];
+            }
         }
     }
 #pragma unroll
@@ -287,6 +310,12 @@ __device__ inline int wave_nearest(const float* tq, const unsigned char* blocked
         }
     }
     return bi == 0x7fffffff ? -1 : bi;
+}
+
+__device__ inline int wave_nearest(const float* tq, const unsigned char* blocked, int cap, int size,
+                                   const float* x, int dof) {
+    return dof <= 8 ? wave_nearest_t<8, 4>(tq, blocked, cap, size, x, dof)
+                    : wave_nearest_t<kMaxDof, 2>(tq, blocked, cap, size, x, dof);
 }
 
 // One query on the W workers of a group (worker w); false if the group
