@@ -37,8 +37,11 @@ using namespace prrtc;
 // check_edges: one wavefront per workgroup.  Collision-free edges cost far
 // more than colliding ones, so edges are handed out dynamically: the batch is
 // split into one contiguous range per XCD (workgroup ids are dealt to the 8
-// XCDs round-robin) and each wave takes chunks of kEdgeChunk edges from its
-// XCD's counter, keeping the atomics off a single shared address.  The next
+// XCDs round-robin) and each wave takes chunks of `chunk` edges from its
+// XCD's counter, keeping the atomics off a single shared address (kEdgeChunk
+// for large batches; fewer for batches that do not fill every resident wave
+// with several chunks, down to one edge, so a small batch is spread over as
+// many waves as it has edges).  The next
 // chunk's first endpoints are fetched while the current edge is checked.  The
 // last wave to finish resets the counters for the next launch.
 #ifndef PRRTC_EDGE_CHUNK
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
                                                        const float* __restrict__ Bv,
                                                        long long n_edges, float res,
                                                        uint8_t* __restrict__ valid,
-                                                       EdgeCounter* ctr) {
+                                                       EdgeCounter* ctr, int chunk) {
     extern __shared__ float4 lds4[];
     const int lane = threadIdx.x;
     const int dof = R.dof;
@@ -88,22 +91,22 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
     unsigned long long* my_ctr = &ctr->next[xcd * 8];
     auto grab = [&]() {
         unsigned long long v = 0;
-        if (lane == 0) v = atomicAdd(my_ctr, (unsigned long long)kEdgeChunk);
+        if (lane == 0) v = atomicAdd(my_ctr, (unsigned long long)chunk);
         return lo + (long long)__shfl(v, 0, kWave);
     };
     const long long stride = 1, end = hi;
 #elif PRRTC_EDGE_SCHED == 1
     auto grab = [&]() {
         unsigned long long v = 0;
-        if (lane == 0) v = atomicAdd(&ctr->next[0], (unsigned long long)kEdgeChunk);
+        if (lane == 0) v = atomicAdd(&ctr->next[0], (unsigned long long)chunk);
         return (long long)__shfl(v, 0, kWave);
     };
     const long long stride = 1, end = n_edges;
 #else
-    long long cursor = (long long)blockIdx.x * kEdgeChunk;
+    long long cursor = (long long)blockIdx.x * chunk;
     auto grab = [&]() {
         const long long v = cursor;
-        cursor += (long long)gridDim.x * kEdgeChunk;
+        cursor += (long long)gridDim.x * chunk;
         return v;
     };
     const long long stride = 1, end = n_edges;
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kWave) void k_check_edges(RobotArgs R, SceneArgs S,
     }
     while (c0 < end) {
         const long long c1 = grab();
-        const long long cend = min(c0 + (long long)kEdgeChunk, end);
+        const long long cend = min(c0 + (long long)chunk, end);
         for (long long e = c0; e < cend; e += stride) {
             if (lane < dof) {
                 wp[lane] = ra;
@@ -1101,8 +1104,10 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
             ctx->edge_grid[kk] = std::max(1, per_cu) * ctx->n_cu;
             ctx->edge_grid_lds[kk] = lds;
         }
-        // at least one workgroup per XCD range (empty ranges exit at once)
+        // at least one workgroup per XCD range (empty ranges exit at once);
+        // chunks of up to kEdgeChunk edges, at least four per resident wave
         const long long grid = std::max<long long>(std::min<long long>(n, ctx->edge_grid[kk]), kXcds);
+        int chunk = (int)std::min<long long>(kEdgeChunk, std::max<long long>(1, n / (4LL * ctx->edge_grid[kk])));
         EdgeCounter* ctr = ctx->counters + (ctx->counter_next++ % kCounterSlots);
         RobotArgs ra = r->args;
         SceneArgs sa = s->args;
@@ -1110,7 +1115,7 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
         const float* pb = b;
         float fres = res;
         uint8_t* pv = valid;
-        void* kargs[] = {&ra, &sa, &pa, &pb, &n, &fres, &pv, &ctr};
+        void* kargs[] = {&ra, &sa, &pa, &pb, &n, &fres, &pv, &ctr, &chunk};
         PRRTC_HIP(ctx, hipLaunchKernel(edge_kernel(schedule, two), dim3((unsigned)grid), dim3(kWave), kargs, lds, sm));
         return PRRTC_OK;
     };
@@ -2401,12 +2406,29 @@ prrtc_status prop_workspace(prrtc_ctx* ctx, ModelRec& M, int n, int S, PropWs& W
 
 inline unsigned blocks(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// With a partials buffer (part_floats floats), a product of fewer than 64
+// output tiles and K >= 1024 is split along K (deterministic: the partials
+// are added in order by k_split_sum).
 template <typename TA, bool TA_, bool TB_, bool GELU>
 void gemm(hipStream_t sm, const TA* A, int lda, const float* B, int ldb, const float* bias, float* C, float* Z,
-          int ldc, int M, int N, int K) {
+          int ldc, int M, int N, int K, float* part = nullptr, size_t part_floats = 0) {
     dim3 grid(blocks(N, kGemmBN), blocks(M, kGemmBM));
+    const int tiles = (int)(grid.x * grid.y);
+    if (!GELU && part && tiles < 64 && K >= 1024 && ldc == N) {
+        int ks = std::min<int>((128 + tiles - 1) / tiles, K / 256);
+        ks = std::min<int>(ks, (int)(part_floats / ((size_t)M * N)));
+        if (ks >= 2) {
+            const int chunk = (int)((((K + ks - 1) / ks) + kGemmBK - 1) / kGemmBK * kGemmBK);
+            ks = (K + chunk - 1) / chunk;
+            hipLaunchKernelGGL((k_gemm_bf16<TA, TA_, TB_, false>), dim3(grid.x, grid.y, ks), dim3(256), 0, sm, A, lda,
+                               B, ldb, nullptr, part, nullptr, ldc, M, N, K, chunk);
+            hipLaunchKernelGGL(k_split_sum, dim3(blocks((size_t)M * N, 256)), dim3(256), 0, sm, part, ks, M, N, ldc,
+                               bias, C);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_gemm_bf16<TA, TA_, TB_, GELU>), grid, dim3(256), 0, sm, A, lda, B, ldb, bias, C, Z, ldc, M,
-                       N, K);
+                       N, K, 0);
 }
 
 // Forward pass for n samples over S scenes; with q (training) also the NLL
@@ -2426,8 +2448,9 @@ void prop_forward(hipStream_t sm, ModelRec& M, const PropWs& W, const RobotArgs*
                            M.p(pb1), M.p(pW2), M.p(pb2), M.p(pW3), M.p(pb3), M.p(pW4), M.p(pb4), gmm_out);
         return;
     }
+    // few scenes and K = 4096: split K, the partials in W.part
     gemm<uint8_t, false, false, false>(sm, vox, kVoxCells, M.p(pWv), kHidden, M.p(pbv), W.E, nullptr, kHidden, S,
-                                       kHidden, kVoxCells);
+                                       kHidden, kVoxCells, W.part, (size_t)kEmbedSlices * kSmallRows * kHidden);
     hipLaunchKernelGGL(k_build_x0, dim3(blocks((size_t)n * L.D0, 256)), dim3(256), 0, sm, s, g, q, scene_of, W.E,
                        lo, hi, n, L.dof, W.X0, W.qh);
     gemm<float, false, false, true>(sm, W.X0, L.D0, M.p(pW1), kHidden, M.p(pb1), W.H1, W.Z1, kHidden, n, kHidden, L.D0);
@@ -2446,7 +2469,8 @@ void prop_backward(hipStream_t sm, ModelRec& M, const PropWs& W, const uint8_t* 
     const PropLayout& L = M.L;
     // head
     gemm<float, true, false, false>(sm, W.H3, kHidden, W.dO, L.Cw, nullptr, M.g(pW4), nullptr, L.Cw, kHidden, L.Cw, n);
-    hipLaunchKernelGGL(k_col_sum, dim3(blocks(L.Cw, 128)), dim3(128), 0, sm, W.dO, n, L.Cw, L.Cw, 0, M.g(pb4));
+    hipLaunchKernelGGL(k_col_sum, dim3(blocks(L.Cw, 64)), dim3(kColGroups * 64), 0, sm, W.dO, n, L.Cw, L.Cw, 0,
+                       M.g(pb4));
     gemm<float, false, true, false>(sm, W.dO, L.Cw, M.p(pW4), L.Cw, nullptr, W.dH, nullptr, kHidden, n, kHidden, L.Cw);
     // hidden layers 3, 2
     const float* Zs[3] = {W.Z1, W.Z2, W.Z3};
@@ -2458,7 +2482,7 @@ void prop_backward(hipStream_t sm, ModelRec& M, const PropWs& W, const uint8_t* 
         const int din = l == 0 ? L.D0 : kHidden;
         gemm<float, true, false, false>(sm, Hin[l], din, W.dZ, kHidden, nullptr, M.g(pw[l]), nullptr, kHidden, din,
                                         kHidden, n);
-        hipLaunchKernelGGL(k_col_sum, dim3(blocks(kHidden, 128)), dim3(128), 0, sm, W.dZ, n, kHidden, kHidden, 0,
+        hipLaunchKernelGGL(k_col_sum, dim3(blocks(kHidden, 64)), dim3(kColGroups * 64), 0, sm, W.dZ, n, kHidden, kHidden, 0,
                            M.g(pb[l]));
         float* dIn = l == 0 ? W.dX0 : W.dH;
         gemm<float, false, true, false>(sm, W.dZ, kHidden, M.p(pw[l]), kHidden, nullptr, dIn, nullptr, din, n, din,
@@ -2469,7 +2493,7 @@ void prop_backward(hipStream_t sm, ModelRec& M, const PropWs& W, const uint8_t* 
                        scene_start, S, W.dE);
     gemm<uint8_t, true, false, false>(sm, vox, kVoxCells, W.dE, kHidden, nullptr, M.g(pWv), nullptr, kHidden,
                                       kVoxCells, kHidden, S);
-    hipLaunchKernelGGL(k_col_sum, dim3(blocks(kHidden, 128)), dim3(128), 0, sm, W.dE, S, kHidden, kHidden, 0,
+    hipLaunchKernelGGL(k_col_sum, dim3(blocks(kHidden, 64)), dim3(kColGroups * 64), 0, sm, W.dE, S, kHidden, kHidden, 0,
                        M.g(pbv));
 }
 

@@ -135,7 +135,7 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
             __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
                 if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
@@ -148,6 +148,7 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // pairs with the release that ended the wait
         __threadfence();
         if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
         ok_s = ok;
@@ -164,6 +165,9 @@ __device__ inline bool grid_barrier(int* bar, int nblocks) {
 // acquire loads at agent scope carry each workgroup's earlier writes through
 // workgroup 0 to everyone.  Flags and generation only grow, so nothing is
 // reset between barriers, queries or rounds.  Waits are bounded as above.
+// Waiting loops read with relaxed loads and take one acquire fence after the
+// value they wait for appears: an acquire load in the loop would invalidate
+// the caches on every poll, slowing the waiter and every wave sharing them.
 #ifndef PRRTC_FLAG_BARRIER
 #define PRRTC_FLAG_BARRIER 1
 #endif
@@ -210,7 +214,7 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
                 break;
             }
         }
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);   // the flags' release stores happen before what follows
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the flags' release stores happen before what follows
         if (ok) {
             act();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -226,7 +230,7 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(flags + w, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
             __builtin_amdgcn_s_sleep(1);
             if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ok = 0;
@@ -238,6 +242,7 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // pairs with workgroup 0's release of gen
     }
     if (threadIdx.x == 0) {
         if (__hip_atomic_load(bar + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
@@ -855,13 +860,15 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(WPE)
                 const unsigned long long t0 = wall_clock64();
                 for (;;) {
                     if (__hip_atomic_load(closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                    const int pub = __hip_atomic_load(SA.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    const int pub = __hip_atomic_load(SA.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     const int n = __hip_atomic_load(SA.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (n < pub && n < SA.cap) {
                         int want = n;
                         if (__hip_atomic_compare_exchange_strong(SA.next, &want, n + 1, __ATOMIC_RELAXED,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                             __hip_atomic_store(last, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            // the host wrote the query's arguments before it raised `published`
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
                             k = n;
                             break;
                         }

@@ -60,6 +60,10 @@ __global__ void k_voxelize(SceneArgs S, uint8_t* __restrict__ vox) {
 // row / column l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7 of its operands).
 // Operands are rounded to bfloat16 while staged into LDS; the next K step's
 // global values are loaded into registers while the current one multiplies.
+// With k_chunk > 0 (split K, for shapes with few output tiles and a long K)
+// blockIdx.z takes k = z k_chunk .. (z + 1) k_chunk - 1 and writes its plain
+// partial product to C + z M ldc (no bias or GELU); k_split_sum adds the
+// partials in order.
 // ---------------------------------------------------------------------------
 constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 32;
 constexpr int kGemmLd = kGemmBK + 8;   // LDS row: 80 bytes, 16-byte aligned fragments
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
                                                    const float* __restrict__ Bm, int ldb,
                                                    const float* __restrict__ bias,
                                                    float* __restrict__ C, float* __restrict__ Z, int ldc,
-                                                   int M, int N, int K) {
+                                                   int M, int N, int K, int k_chunk) {
     __shared__ __attribute__((aligned(16))) unsigned short As[kGemmBM][kGemmLd];   // [row][k]
     __shared__ __attribute__((aligned(16))) unsigned short Bt[kGemmBN][kGemmLd];   // [col][k]
     const int tid = threadIdx.x;
@@ -96,6 +100,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
             k = idx / kGemmBM;
         }
     };
+    const int kb = k_chunk > 0 ? (int)blockIdx.z * k_chunk : 0;
+    const int ke = k_chunk > 0 ? min(K, kb + k_chunk) : K;
     float ra[8], rb[8];
     auto fetch = [&](int k0) {
 #pragma unroll
@@ -104,15 +110,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
             int r, k;
             rk(idx, !TRANS_A, r, k);
             const int gr = row0 + r, gka = k0 + k;
-            ra[e] = (gr < M && gka < K) ? (float)(TRANS_A ? A[(size_t)gka * lda + gr] : A[(size_t)gr * lda + gka])
+            ra[e] = (gr < M && gka < ke) ? (float)(TRANS_A ? A[(size_t)gka * lda + gr] : A[(size_t)gr * lda + gka])
                                         : 0.0f;
             rk(idx, TRANS_B, r, k);
             const int gc = col0 + r, gkb = k0 + k;
-            rb[e] = (gc < N && gkb < K) ? (TRANS_B ? Bm[(size_t)gc * ldb + gkb] : Bm[(size_t)gkb * ldb + gc]) : 0.0f;
+            rb[e] = (gc < N && gkb < ke) ? (TRANS_B ? Bm[(size_t)gc * ldb + gkb] : Bm[(size_t)gkb * ldb + gc]) : 0.0f;
         }
     };
-    fetch(0);
-    for (int k0 = 0; k0 < K; k0 += kGemmBK) {
+    fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += kGemmBK) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int idx = tid + 256 * e;
@@ -123,7 +129,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
             Bt[r][k] = bf16_bits(rb[e]);
         }
         __syncthreads();
-        if (k0 + kGemmBK < K) fetch(k0 + kGemmBK);   // in flight during the products
+        if (k0 + kGemmBK < ke) fetch(k0 + kGemmBK);   // in flight during the products
         const int kk = 8 * (lane >> 4);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
@@ -147,7 +153,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
             for (int i = 0; i < 4; ++i) {
                 const int r = row0 + 32 * wr + 16 * mi + 4 * (lane >> 4) + i;
                 const int c = col0 + 32 * wc + 16 * ni + (lane & 15);
-                if (r < M && c < N) {
+                if (r < M && c < N && k_chunk > 0) {
+                    C[(size_t)blockIdx.z * M * ldc + (size_t)r * ldc + c] = acc[mi][ni][i];
+                } else if (r < M && c < N) {
                     float v = acc[mi][ni][i] + (bias ? bias[c] : 0.0f);
                     if (GELU) {
                         Z[(size_t)r * ldc + c] = v;
@@ -156,6 +164,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const TA* __restrict__ A, int
                     C[(size_t)r * ldc + c] = v;
                 }
             }
+}
+
+// C[r][c] = bias[c] + the ks split-K partials P[z][r][c] (ld = ldc), added in
+// z order.
+__global__ void k_split_sum(const float* __restrict__ P, int ks, int M, int N, int ldc, const float* __restrict__ bias,
+                            float* __restrict__ C) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * N) return;
+    const int r = i / N, c = i - r * N;
+    float v = 0.0f;
+    for (int z = 0; z < ks; ++z) v += P[(size_t)z * M * ldc + (size_t)r * ldc + c];
+    C[(size_t)r * ldc + c] = v + (bias ? bias[c] : 0.0f);
 }
 
 // x0[b] = [s_hat, g_hat, E[scene_of[b]]]; q_hat likewise when q is given.
@@ -461,13 +481,25 @@ __global__ void k_gelu_bwd(const float* __restrict__ dH, const float* __restrict
     dZ[i] = dH[i] * (cdf + x * pdf);
 }
 
-// db[c] = sum over rows of D[r][c] (ld = N), fixed order.
-__global__ void k_col_sum(const float* __restrict__ D, int rows, int N, int ld, int col_off, float* __restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
+// db[c] = sum over rows of D[r][c] (ld), fixed order: a workgroup of
+// kColGroups x 64 threads takes 64 columns; thread (g, c) adds rows g,
+// g + kColGroups, ... in order, and the group sums are added in g order.
+constexpr int kColGroups = 16;
+__global__ __launch_bounds__(kColGroups * 64) void k_col_sum(const float* __restrict__ D, int rows, int N, int ld,
+                                                              int col_off, float* __restrict__ out) {
+    __shared__ float part[kColGroups][64];
+    const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += D[(size_t)r * ld + col_off + c];
-    out[c] = s;
+    if (c < N)
+        for (int r = g; r < rows; r += kColGroups) s += D[(size_t)r * ld + col_off + c];
+    part[g][cl] = s;
+    __syncthreads();
+    if (g == 0 && c < N) {
+        float t = part[0][cl];
+        for (int k = 1; k < kColGroups; ++k) t += part[k][cl];
+        out[c] = t;
+    }
 }
 
 // dE[s][c] = sum of dX0[b][2 dof + c] over the samples b of scene s
