@@ -1250,8 +1250,8 @@ GroupLayout group_layout(int dof, int cap, int W, int stage_cap) {
     L.bb = take((size_t)cap);
     L.rb = take(sizeof(float) * (size_t)cap);
     L.bar = take(sizeof(int) * ((size_t)kBarWords + W));
-    L.stage = take(sizeof(float) * (size_t)W * stage_cap * dof);
-    L.st = take(sizeof(int) * 5 * (size_t)W);
+    L.stage = take(sizeof(float) * 2 * (size_t)W * stage_cap * dof);   // two round parities
+    L.st = take(sizeof(int) * 2 * 5 * (size_t)W);
     L.path = take(sizeof(float) * (size_t)path_cap * dof);
     L.path_idx = take(sizeof(int) * (size_t)path_cap);
     L.bytes = o;

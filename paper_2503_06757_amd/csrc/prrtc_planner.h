@@ -261,23 +261,30 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
 #endif
 }
 
-// Wave argmin of the FP32 squared distance (in joint order, no FMA) over
-// the non-blocked nodes 0..size-1 of a [dof][cap] tree; ties -> lowest index.
-// Each lane takes U nodes per step and issues all their loads (D >= dof
-// joints; the joints past dof load joint dof-1 and add an exact zero) before
-// using any, so a step waits for one memory latency instead of one per joint
-// and node.  Nodes are visited in increasing index order per lane and the
-// strict compare keeps the first of equal distances.
+// Nearest neighbour: the FP32 squared distance (in joint order, no FMA) to
+// x, argmin over the non-blocked nodes of a tree, ties -> lowest index.  The
+// scan keeps a per-lane best (distance, index, source); nearest_reduce makes
+// it wave-wide.  source < 0: a node of the tree's [dof][cap] arrays; else the
+// offset of a staged node's row in the staging buffers.
+struct NearBest {
+    float d;
+    int i, src;
+};
+
+// Nodes 0..size-1 of the tree arrays.  Each lane takes U nodes per step and
+// issues all their loads (D >= dof joints; the joints past dof load joint
+// dof-1 and add an exact zero) before using any, so a step waits for one
+// memory latency instead of one per joint and node.  Nodes are visited in
+// increasing index order per lane and the strict compare keeps the first of
+// equal distances.
 template <int D, int U>
-__device__ inline int wave_nearest_t(const float* tq, const unsigned char* blocked, int cap, int size,
-                                     const float* x, int dof) {
+__device__ inline void near_scan_t(const float* tq, const unsigned char* blocked, int cap, int size, const float* x,
+                                   int dof, NearBest& b) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & (kWave - 1);
     float xr[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) xr[j] = j < dof ? x[j] : 0.0f;
-    float bd = __builtin_inff();
-    int bi = 0x7fffffff;
     for (int i0 = lane; i0 < size; i0 += kWave * U) {
         float v[U][D];
         int idx[U];
@@ -299,28 +306,84 @@ __device__ inline int wave_nearest_t(const float* tq, const unsigned char* block
                 const float sq = d * d;
                 s = s + sq;
             }
-            if (idx[u] < size && !skip[u] && s < bd) {
-                bd = s;
-                bi = idx[u];
+            if (idx[u] < size && !skip[u] && s < b.d) {
+                b.d = s;
+                b.i = idx[u];
+                b.src = -1;
             }
         }
     }
+}
+
+__device__ inline void near_scan(const float* tq, const unsigned char* blocked, int cap, int size, const float* x,
+                                 int dof, NearBest& b) {
+    if (dof <= 8)
+        near_scan_t<8, 4>(tq, blocked, cap, size, x, dof, b);
+    else
+        near_scan_t<kMaxDof, 2>(tq, blocked, cap, size, x, dof, b);
+}
+
+// The previous round's staged nodes of a tree that are not yet guaranteed to
+// be in its arrays: worker v's nodes k < cnt[v] are rows v stage_cap + k of
+// `stage` ([.][dof]) with tree index first + (counts of workers < v) + k,
+// kept below cap.  Lane l takes workers l, l + 64, ...; indices grow with
+// the worker and k, and every one exceeds the tree-array indices, so the
+// strict compare again keeps the lowest index of equal distances.
+__device__ inline void near_scan_staged(const float* stage, int stage_cap, const int* cnt, int W, int first, int cap,
+                                        const float* x, int dof, NearBest& b) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & (kWave - 1);
+    int running = first;
+    for (int c0 = 0; c0 < W; c0 += kWave) {
+        const int v = c0 + lane;
+        const int c = v < W ? cnt[v] : 0;
+        int incl = c;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int t = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += t;
+        }
+        const int base = running + incl - c;
+        const int kept = max(0, min(c, cap - base));
+        for (int k = 0; k < kept; ++k) {
+            const float* row = stage + ((size_t)v * stage_cap + k) * dof;
+            float s = 0.0f;
+            for (int j = 0; j < dof; ++j) {
+                const float d = x[j] - row[j];
+                const float sq = d * d;
+                s = s + sq;
+            }
+            if (s < b.d) {
+                b.d = s;
+                b.i = base + k;
+                b.src = (int)(((size_t)v * stage_cap + k) * dof);
+            }
+        }
+        running += __shfl(incl, kWave - 1, kWave);
+    }
+}
+
+__device__ inline NearBest nearest_reduce(NearBest b) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-        const float ob = __shfl_xor(bd, off, kWave);
-        const int oi = __shfl_xor(bi, off, kWave);
-        if (ob < bd || (ob == bd && oi < bi)) {
-            bd = ob;
-            bi = oi;
+        const float od = __shfl_xor(b.d, off, kWave);
+        const int oi = __shfl_xor(b.i, off, kWave);
+        const int os = __shfl_xor(b.src, off, kWave);
+        if (od < b.d || (od == b.d && oi < b.i)) {
+            b.d = od;
+            b.i = oi;
+            b.src = os;
         }
     }
-    return bi == 0x7fffffff ? -1 : bi;
+    return b;
 }
 
 __device__ inline int wave_nearest(const float* tq, const unsigned char* blocked, int cap, int size,
                                    const float* x, int dof) {
-    return dof <= 8 ? wave_nearest_t<8, 4>(tq, blocked, cap, size, x, dof)
-                    : wave_nearest_t<kMaxDof, 2>(tq, blocked, cap, size, x, dof);
+    NearBest b{__builtin_inff(), 0x7fffffff, -1};
+    near_scan(tq, blocked, cap, size, x, dof, b);
+    b = nearest_reduce(b);
+    return b.i == 0x7fffffff ? -1 : b.i;
 }
 
 // One query on the W workers of a group (worker w); false if the group
@@ -362,12 +425,17 @@ struct GroupView {
     __device__ unsigned char* bb() const { return moved(P.bb, off()); }
     __device__ float* rb() const { return moved(P.rb, off()); }
     __device__ int* bar() const { return moved(P.bar, off()); }
-    __device__ float* stage() const { return moved(P.stage, off()); }
-    __device__ int* st_count() const { return moved(P.st_count, off()); }
-    __device__ int* st_nn() const { return moved(P.st_nn, off()); }
-    __device__ int* st_other() const { return moved(P.st_other, off()); }
-    __device__ int* st_conn() const { return moved(P.st_conn, off()); }
-    __device__ int* st_fail() const { return moved(P.st_fail, off()); }
+    __device__ float* stage(int par, int dof) const {
+        return moved(P.stage, off()) + (size_t)par * P.W * P.stage_cap * dof;
+    }
+    // per-round worker results and staged nodes, double-buffered by round
+    // parity: [parity][count | nn | other | conn | fail][W] and
+    // [parity][W][stage_cap][dof]
+    __device__ int* st_count(int par) const { return moved(P.st_count, off()) + (size_t)par * 5 * P.W; }
+    __device__ int* st_nn(int par) const { return moved(P.st_nn, off()) + (size_t)par * 5 * P.W; }
+    __device__ int* st_other(int par) const { return moved(P.st_other, off()) + (size_t)par * 5 * P.W; }
+    __device__ int* st_conn(int par) const { return moved(P.st_conn, off()) + (size_t)par * 5 * P.W; }
+    __device__ int* st_fail(int par) const { return moved(P.st_fail, off()) + (size_t)par * 5 * P.W; }
     __device__ float* path() const { return moved(P.path, off()); }
     __device__ int* path_idx() const { return moved(P.path_idx, off()); }
 };
@@ -467,17 +535,35 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     const unsigned long long t_start = wall_clock64();
     int status = kStNoSolution;
     int round = 0;
+    // One group barrier per round.  A round's nodes are copied into the tree
+    // arrays after its barrier, by their own workers, while faster workers may
+    // already run the next round; that copy is only guaranteed visible after
+    // the next round's barrier.  So every worker tracks the sizes itself, and
+    // the next round reads the previous round's nodes (indices lr_first..) of
+    // the tree that grew (lr_tree: 0 = A, 1 = B, -1 = none pending) from the
+    // staging buffers, which are double-buffered by round parity.  Domain
+    // shrinks of the previous round (its workers' failed extension starts,
+    // lr_fail_tree) are taken from its fail words for the same reason.
+    int na = 1, nb = 1;
+    int lr_tree = -1, lr_first = 0, lr_fail_tree = -1;
+    int par = 0;
     for (; round < P.max_rounds; ++round) {
-        const int na = __hip_atomic_load(ctl + kSizeA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int nb = __hip_atomic_load(ctl + kSizeB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const bool s_is_a = na <= nb;
+        const int ts = s_is_a ? 0 : 1;
+        // arrays part (visible) and staged part of each tree
+        const int vis_a = lr_tree == 0 ? lr_first : na, vis_b = lr_tree == 1 ? lr_first : nb;
+        const int vis_s = s_is_a ? vis_a : vis_b, vis_o = s_is_a ? vis_b : vis_a;
+        const bool staged_s = lr_tree == ts, staged_o = lr_tree == 1 - ts;
+        const float* stage_prev = G.stage(par ^ 1, dof);
+        const int* cnt_prev = G.st_count(par ^ 1);
+        const int* fail_prev = G.st_fail(par ^ 1);
         float* qs = s_is_a ? G.qa() : G.qb();
         int* ps = s_is_a ? G.pa() : G.pb();
         unsigned char* bs = s_is_a ? G.ba() : G.bb();
         float* rs = s_is_a ? G.ra() : G.rb();
         const float* qo = s_is_a ? G.qb() : G.qa();
         const unsigned char* bo = s_is_a ? G.bb() : G.ba();
-        const int ns = s_is_a ? na : nb, no = s_is_a ? nb : na;
+        const int ns = s_is_a ? na : nb;
         // ===== phase A: sample, nearest, extend, connect
         int count = 0, nn = -1, other = -1, conn = 0, fail = -1;
         // RANDOM_CONFIG + NEAREST_NEIGHBOR; with dynamic-domain sampling a sample
@@ -504,11 +590,30 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                                         : sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof,
                                                        lane, pick(R.lo, lane), pick(R.hi, lane));
             __syncthreads();
-            const int cand = wave_nearest(qs, bs, cap, ns, c_rand, dof);
+            NearBest nb_s{__builtin_inff(), 0x7fffffff, -1};
+            near_scan(qs, bs, cap, vis_s, c_rand, dof, nb_s);
+            if (staged_s) near_scan_staged(stage_prev, P.stage_cap, cnt_prev, P.W, lr_first, cap, c_rand, dof, nb_s);
+            nb_s = nearest_reduce(nb_s);
+            const int cand = nb_s.i == 0x7fffffff ? -1 : nb_s.i;
             if (cand < 0) break;
-            if (lead && lane < dof) c_nn[lane] = qs[(size_t)lane * cap + cand];
+            if (lead && lane < dof)
+                c_nn[lane] = nb_s.src < 0 ? qs[(size_t)lane * cap + cand] : stage_prev[nb_s.src + lane];
             __syncthreads();
-            if (P.dds_radius > 0.0f && !(norm_diff_f32(c_nn, c_rand, dof) <= rs[cand])) continue;
+            if (P.dds_radius > 0.0f) {
+                // the node's domain: unbounded for the previous round's new
+                // nodes, dds_radius if it failed an extension in the previous
+                // round (its own write may not be visible yet), else its word
+                float radius = __builtin_inff();
+                if (nb_s.src < 0) {
+                    radius = rs[cand];
+                    if (lr_fail_tree == ts) {
+                        bool hit = false;
+                        for (int v = lane; v < P.W; v += kWave) hit |= fail_prev[v] == cand;
+                        if (__any(hit)) radius = P.dds_radius;
+                    }
+                }
+                if (!(norm_diff_f32(c_nn, c_rand, dof) <= radius)) continue;
+            }
             nn = cand;
             break;
         }
@@ -533,9 +638,15 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             if (!ext_ok) fail = nn;
             if (ext_ok) {
                 count = 1;
-                other = wave_nearest(qo, bo, cap, no, c_new, dof);
+                NearBest nb_o{__builtin_inff(), 0x7fffffff, -1};
+                near_scan(qo, bo, cap, vis_o, c_new, dof, nb_o);
+                if (staged_o)
+                    near_scan_staged(stage_prev, P.stage_cap, cnt_prev, P.W, lr_first, cap, c_new, dof, nb_o);
+                nb_o = nearest_reduce(nb_o);
+                other = nb_o.i == 0x7fffffff ? -1 : nb_o.i;
                 if (other >= 0) {
-                    if (lead && lane < dof) c_nno[lane] = qo[(size_t)lane * cap + other];
+                    if (lead && lane < dof)
+                        c_nno[lane] = nb_o.src < 0 ? qo[(size_t)lane * cap + other] : stage_prev[nb_o.src + lane];
                     __syncthreads();
                     int n_ext;
                     {
@@ -570,24 +681,31 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     conn = K == n_ext;
                 }
                 // stage c_new and the valid intermediate targets
-                float* st = G.stage() + (size_t)w * P.stage_cap * dof;
+                float* st = G.stage(par, dof) + (size_t)w * P.stage_cap * dof;
                 for (int e = tid; e < count * dof; e += nth) st[e] = (e < dof) ? c_new[e] : wp[e];
             }
         }
         if (tid == 0) {
-            G.st_count()[w] = count;
-            G.st_nn()[w] = nn;
-            G.st_other()[w] = other;
-            G.st_conn()[w] = conn;
-            G.st_fail()[w] = fail;
+            G.st_count(par)[w] = count;
+            G.st_nn(par)[w] = nn;
+            G.st_other(par)[w] = other;
+            G.st_conn(par)[w] = conn;
+            G.st_fail(par)[w] = fail;
         }
-        if (!group_barrier(G.bar(), w, P.W)) break;
+        // the time budget is checked once every worker has arrived, so all of
+        // them read the same stop word after the barrier
+        auto budget = [&]() {
+            if (lane == 0 && P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks)
+                ctl[kStop] = 1;
+        };
+        if (!group_barrier(G.bar(), w, P.W, nullptr, budget)) break;
+        const bool stop = __hip_atomic_load(ctl + kStop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         // ===== phase B: ordered commit
         int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1;
         for (int c0 = 0; c0 < P.W; c0 += kWave) {
             const int wi = c0 + lane;
-            const int cnt = wi < P.W ? G.st_count()[wi] : 0;
-            const int cn = wi < P.W ? G.st_conn()[wi] : 0;
+            const int cnt = wi < P.W ? G.st_count(par)[wi] : 0;
+            const int cn = wi < P.W ? G.st_conn(par)[wi] : 0;
             int incl = cnt;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
@@ -604,7 +722,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 const int fb = __shfl(base_i, src, kWave);
                 const int fc = __shfl(cnt, src, kWave);
                 first_last = fb + fc - 1;
-                first_other = G.st_other()[cand];
+                first_other = G.st_other(par)[cand];
             }
             running += __shfl(incl, kWave - 1, kWave);
         }
@@ -612,7 +730,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         my_base = sh_i[0];
         {
             const int c = max(0, min(count, cap - my_base));
-            const float* st = G.stage() + (size_t)w * P.stage_cap * dof;
+            const float* st = G.stage(par, dof) + (size_t)w * P.stage_cap * dof;
             for (int e = tid; e < c * dof; e += nth) {
                 const int k = e / dof, j = e - k * dof;
                 qs[(size_t)j * cap + my_base + k] = st[e];
@@ -626,14 +744,18 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             // from every worker, so the order of these writes does not matter)
             if (tid == 0 && fail >= 0 && P.dds_radius > 0.0f) rs[fail] = P.dds_radius;
         }
-        if (w == 0 && tid == 0) {
-            const int new_size = min(cap, ns + running);
-            ctl[s_is_a ? kSizeA : kSizeB] = new_size;
-            if (P.budget_ticks > 0 && (long long)(wall_clock64() - t_start) > P.budget_ticks) ctl[kStop] = 1;
-        }
-        if (!group_barrier(G.bar(), w, P.W)) break;
+        const int new_size = min(cap, ns + running);
+        if (w == 0 && tid == 0) ctl[s_is_a ? kSizeA : kSizeB] = new_size;   // for the statistics
+        lr_tree = new_size > ns ? ts : -1;
+        lr_first = ns;
+        lr_fail_tree = ts;
+        if (s_is_a) na = new_size; else nb = new_size;
         // ===== phase C: path and re-check
         if (first != 0x7fffffff) {
+            // the walk needs every node of this round in the arrays
+            if (!group_barrier(G.bar(), w, P.W)) break;
+            lr_tree = -1;        // after this phase's barriers everything is visible,
+            lr_fail_tree = -1;   // the domain shrinks included
             const int xa = s_is_a ? first_last : first_other;
             const int xb = s_is_a ? first_other : first_last;
             if (w == 0) {
@@ -715,10 +837,11 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             }
             if (w == 0 && tid == 0) ctl[kValFails] += 1;
         }
-        if (ctl[kStop]) {
+        if (stop) {
             ++round;
             break;
         }
+        par ^= 1;
     }
     if (tid == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
     if (tid == 0 && my_learned)
