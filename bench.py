@@ -376,7 +376,8 @@ def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, budget_
 
 
 def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None, slots=256, max_pending=1024,
-                budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None, models=None, tile=16):
+                budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None, models=None, tile=16,
+                arrivals=None):
     """The served workload through the library's serving thread: queries
     arrive as a Poisson stream (exponential gaps) and are submitted at their
     arrival time (refused submissions are retried: admission); the thread
@@ -387,7 +388,10 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
     on the host clock."""
     pool, tried = pool
     rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_queries))
+    gaps = rng.exponential(1.0 / rate, n_queries)
+    if arrivals is None:
+        arrivals = np.cumsum(gaps)
+    n_queries = len(arrivals)
     picks = rng.integers(0, len(pool), n_queries)
     prm = P.prrtc_plan_params_default()
     prm.max_rounds, prm.time_budget_ms = max_rounds, budget_ms
@@ -443,7 +447,33 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
             "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
             "queries_per_s": n_queries / span, "launches": launches, "mean_batch": n_queries / max(launches, 1),
             "refused_submissions": refused, "pool": len(pool), "pool_tried": tried, "tuning": tune,
-            "time_budget_ms": budget_ms}
+            "time_budget_ms": budget_ms, "_latency_ms": lat, "_ok": ok}
+
+
+def bench_serve_burst(P, ctx, torch, pool, log=None):
+    """A quiet stream then a burst through one server: 200 queries at 100/s
+    (about 2 s; the mean gap of 10 ms is below the launch's 50 ms idle
+    limit), a 0.2 s pause (the launch closes: no group has claimed a query
+    for 50 ms), then 2000 queries submitted at once, which start a new launch
+    with every group.  Reports each phase's latency, the burst's throughput
+    and the number of launches."""
+    rng = np.random.default_rng(0x56100000)
+    quiet = np.cumsum(rng.exponential(1.0 / 100.0, 200))
+    t_burst = float(quiet[-1]) + 0.2
+    arrivals = np.concatenate([quiet, np.full(2000, t_burst)])
+    r = bench_serve(P, ctx, torch, pool, workers=16, tile=16, arrivals=arrivals, log=log)
+    lat, ok = r.pop("_latency_ms"), r.pop("_ok")
+    q, b = slice(0, 200), slice(200, None)
+    out = {"workload": "serve_mixed_r7_r14 quiet 100/s then a burst of 2000", "workers": 16, "tile": 16,
+           "launches": r["launches"],
+           "quiet": {"queries": 200, "success": float(ok[q].mean()), "p50_latency_ms": float(np.percentile(lat[q], 50)),
+                     "p99_latency_ms": float(np.percentile(lat[q], 99))},
+           "burst": {"queries": 2000, "success": float(ok[b].mean()), "p50_latency_ms": float(np.percentile(lat[b], 50)),
+                     "p99_latency_ms": float(np.percentile(lat[b], 99)),
+                     "queries_per_s": 2000.0 / (float(np.max(lat[b])) / 1e3)}}
+    if log:
+        log("  %s" % json.dumps(out))
+    return out
 
 
 def bench_throughput(P, ctx, torch, pool, n_queries=1024, workers=(16, 64, 256), max_rounds=4000,
@@ -764,7 +794,7 @@ def main():
         log("sampling variants")
         sampling = bench_sampling(P, ctx)
         log("  " + json.dumps(finite_or_null(sampling)))
-    serve = batch = pool = None
+    serve = batch = pool = burst = None
     if not args.skip_serve:
         log("batched planner: launch shapes")
         pool = query_pool(P, ctx, torch)
@@ -772,7 +802,10 @@ def main():
         batch = bench_throughput(P, ctx, torch, pool, log=log)
         log("served planner: Poisson arrivals")
         serve = bench_serve(P, ctx, torch, pool, n_queries=args.serve_queries, log=log)
+        serve.pop("_latency_ms"), serve.pop("_ok")
         log("  " + json.dumps(finite_or_null(serve)))
+        log("served planner: quiet stream, then a burst")
+        burst = bench_serve_burst(P, ctx, torch, pool, log=log)
     learned = None
     if not args.skip_learned:
         log("learned proposal")
@@ -792,6 +825,7 @@ def main():
         served_learned = bench_serve(P, ctx, torch, pool, n_queries=args.serve_queries, log=log,
                                      models=(learned["_model"], learned_shelf["_model"]),
                                      workers=serve["workers"], tile=serve["tile"])
+        served_learned.pop("_latency_ms"), served_learned.pop("_ok")
         log("  " + json.dumps(finite_or_null(served_learned)))
     for leg in (learned, learned_shelf):
         if leg is not None:
@@ -838,6 +872,7 @@ def main():
         "sampling_variants": sampling,
         "batched": batch,
         "served": serve,
+        "served_burst": burst,
         "served_learned": served_learned,
         "learned": learned,
         "learned_r14_shelf": learned_shelf,
