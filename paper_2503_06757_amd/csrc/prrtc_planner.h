@@ -476,18 +476,22 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     long long my_learned = 0;
     __shared__ float gmm_s[kComp * (1 + 2 * kMaxDof)];
 
-    // ---- prologue: roots, endpoint checks
-    if (w == 0 && lead && lane < dof) {
+    // ---- prologue: roots, endpoint checks.  Every worker writes the roots
+    // (the same values), so its own first round can read them without a
+    // barrier; nothing else writes them before the first round's barrier.
+    if (lead && lane < dof) {
         G.qa()[(size_t)lane * cap] = P.start[lane];
         G.qb()[(size_t)lane * cap] = P.goal[lane];
     }
-    if (w == 0 && tid == 0) {
+    if (tid == 0) {
         G.pa()[0] = -1;
         G.pb()[0] = -1;
         G.ba()[0] = 0;
         G.bb()[0] = 0;
         G.ra()[0] = __builtin_inff();
         G.rb()[0] = __builtin_inff();
+    }
+    if (w == 0 && tid == 0) {
         ctl[kSizeA] = 1;
         ctl[kSizeB] = 1;
     }
@@ -517,10 +521,19 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         mixture_in_block(*P.model, P.emb, ends, R.lo, R.hi, reinterpret_cast<float*>(ws.frames), gmm_s,
                          const_cast<float*>(P.gmm));
     }
-    if (!group_barrier(G.bar(), w, P.W)) return false;
-    if (ctl[kEndpointBad]) {
+    // The endpoint verdict is read after the first barrier: the first round
+    // runs meanwhile and is discarded if an endpoint collides.  Only a
+    // mixture computed in this launch needs a barrier before the rounds.
+    bool ends_checked = false;
+    auto ends_bad = [&]() {
+        ends_checked = true;
+        if (__hip_atomic_load(ctl + kEndpointBad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return false;
         if (w == 0 && tid == 0) ctl[kStatus] = kStInvalidEndpoint;
         return true;
+    };
+    if (P.model) {
+        if (!group_barrier(G.bar(), w, P.W)) return false;
+        if (ends_bad()) return true;
     }
     bool use_gmm = false;
     if (P.gmm) {
@@ -699,9 +712,10 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 ctl[kStop] = 1;
         };
         if (!group_barrier(G.bar(), w, P.W, nullptr, budget)) break;
+        if (!ends_checked && ends_bad()) return true;
         const bool stop = __hip_atomic_load(ctl + kStop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         // ===== phase B: ordered commit
-        int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1;
+        int running = 0, my_base = 0, first = 0x7fffffff, first_last = -1, first_other = -1, first_base = -1;
         for (int c0 = 0; c0 < P.W; c0 += kWave) {
             const int wi = c0 + lane;
             const int cnt = wi < P.W ? G.st_count(par)[wi] : 0;
@@ -722,6 +736,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                 const int fb = __shfl(base_i, src, kWave);
                 const int fc = __shfl(cnt, src, kWave);
                 first_last = fb + fc - 1;
+                first_base = fb;
                 first_other = G.st_other(par)[cand];
             }
             running += __shfl(incl, kWave - 1, kWave);
@@ -752,25 +767,33 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         if (s_is_a) na = new_size; else nb = new_size;
         // ===== phase C: path and re-check
         if (first != 0x7fffffff) {
-            // the walk needs every node of this round in the arrays
-            if (!group_barrier(G.bar(), w, P.W)) break;
             lr_tree = -1;        // after this phase's barriers everything is visible,
             lr_fail_tree = -1;   // the domain shrinks included
             const int xa = s_is_a ? first_last : first_other;
             const int xb = s_is_a ? first_other : first_last;
+            // The connecting worker's nodes of this round (first_base ..
+            // first_last of tree s) may not be in the arrays yet: the walk
+            // follows their chain itself (each node's parent is the one before,
+            // the first one's is that worker's nn) and reads their coordinates
+            // from its staging rows.  Everything older is in the arrays.
+            const int first_nn = G.st_nn(par)[first];
+            const float* first_rows = G.stage(par, dof) + (size_t)first * P.stage_cap * dof;
+            auto fresh = [&](bool tree_a, int x) { return tree_a == s_is_a && x >= first_base; };
             if (w == 0) {
                 if (tid == 0) {
                     // one walk per tree: A from the connection node up to its root
                     // (stored reversed, flipped below), B from its node up to its root
                     int bad = 0, la = 0, lb = 0, x = xa;
-                    for (; x >= 0 && la < cap; x = G.pa()[x]) {
+                    for (; x >= 0 && la < cap;
+                         x = fresh(true, x) ? (x > first_base ? x - 1 : first_nn) : G.pa()[x]) {
                         G.path_idx()[la++] = x;
-                        bad |= G.ba()[x];
+                        if (!fresh(true, x)) bad |= G.ba()[x];
                     }
                     int y = xb;
-                    for (; y >= 0 && lb < cap; y = G.pb()[y]) {
+                    for (; y >= 0 && lb < cap;
+                         y = fresh(false, y) ? (y > first_base ? y - 1 : first_nn) : G.pb()[y]) {
                         G.path_idx()[la + lb++] = y;
-                        bad |= G.bb()[y];
+                        if (!fresh(false, y)) bad |= G.bb()[y];
                     }
                     int len = la + lb;
                     if (x >= 0 || y >= 0) {           // a parent chain longer than the tree
@@ -782,13 +805,10 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     ctl[kNa] = la;
                     ctl[kPathLen] = len;
                     ctl[kValBad] = bad;
-                    if (bad && len <= P.path_cap) {
-                        if (xa != 0) G.ba()[xa] = 1;
-                        if (xb != 0) G.bb()[xb] = 1;
-                    }
                     __threadfence_block();
                     sh_i[1] = la;
                     sh_i[2] = len;
+                    sh_i[3] = bad && len <= P.path_cap;   // block the ends after the barrier
                 }
                 __syncthreads();
                 __threadfence_block();
@@ -804,12 +824,19 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                     for (int e = tid; e < len * dof; e += nth) {
                         const int m = e / dof, j = e - m * dof;
                         const bool in_a = m < la;
+                        const int x = G.path_idx()[m];
                         const float* q = in_a ? G.qa() : G.qb();
-                        G.path()[e] = q[(size_t)j * cap + G.path_idx()[m]];
+                        G.path()[e] = fresh(in_a, x) ? first_rows[(size_t)(x - first_base) * dof + j]
+                                                     : q[(size_t)j * cap + x];
                     }
                 }
             }
             if (!group_barrier(G.bar(), w, P.W)) break;
+            // every worker's nodes of this round are in the arrays now
+            if (w == 0 && tid == 0 && sh_i[3]) {
+                if (xa != 0) G.ba()[xa] = 1;
+                if (xb != 0) G.bb()[xb] = 1;
+            }
             const int la = ctl[kNa], len = ctl[kPathLen];
             if (P.validate > 0) {
                 // each segment's points in kValChunks chunks, one per worker
