@@ -85,7 +85,9 @@ typedef struct {
      * flags the links that may collide; only their fine spheres are checked).
      * n_coarse = 0 (all three NULL): one stage.  Else sphere k lies inside
      * coarse sphere sphere_coarse[k], on the same frame (|p_k - c| + r_k <=
-     * R, checked: E_ARG).  Verdicts do not change, only the work. */
+     * R, checked: E_ARG).  Verdicts do not change, only the work: the
+     * planner always runs the two-stage pass for such a robot; check_edges
+     * times it against one stage per (robot, scene) pair (schedules). */
     int32_t n_coarse;                          /* 0..256 */
     const int32_t *coarse_frame;               /* host [n_coarse] global frame id */
     const float *coarse_xyzr;                  /* host [n_coarse][4] centre in frame, radius */
@@ -170,21 +172,25 @@ prrtc_status prrtc_esdf_from_scene(prrtc_ctx *ctx, int32_t scene_id, const float
  *         draw from a ring of 256 work counters, so at most 256 launches of
  *         one context may be in flight at once.
  *
- * Two kernel schedules give the same verdicts at different speeds (items
- * per lane, order of the obstacle types).  The first batch of at least 8192
- * edges on a (robot, scene) pair times both on its first 2^20 edges (all of
- * a smaller batch) and keeps the faster for that pair; that one call waits
- * for the stream.
+ * Kernel schedules give the same verdicts at different speeds: 0 and 1
+ * differ in items per lane and the order of the obstacle types; for a robot
+ * with coarse spheres, 2 and 3 are the same with the two-stage pass (coarse
+ * spheres gating the fine ones), 0 and 1 then ignoring the coarse spheres.
+ * The first batch of at least 8192 edges on a (robot, scene) pair times every
+ * schedule the robot has on its first 2^20 edges (all of a smaller batch) and
+ * keeps the fastest for that pair; that one call waits for the stream.  Until
+ * then a pair runs schedule 0 (2 with coarse spheres).
  */
 prrtc_status prrtc_check_edges(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id,
                                const float *a, const float *b, int64_t n_edges, float res,
                                uint8_t *valid, void *stream);
 
-/* The check_edges schedule of a (robot, scene) pair: set = 0 or 1 pins that
- * schedule, -1 forgets the choice and its tuning record (the next large
- * batch times both again), -2 changes nothing (a stored tuning record for the
- * pair's key is taken up).  *schedule (may be NULL) = the schedule in force
- * after the call, -1 while none is chosen.  E_ARG for another set value. */
+/* The check_edges schedule of a (robot, scene) pair: set = 0 or 1 (2 or 3
+ * for a robot with coarse spheres) pins that schedule, -1 forgets the choice
+ * and its tuning record (the next large batch times every schedule again),
+ * -2 changes nothing (a stored tuning record for the pair's key is taken
+ * up).  *schedule (may be NULL) = the schedule in force after the call, -1
+ * while none is chosen.  E_ARG for another set value. */
 prrtc_status prrtc_edge_schedule(prrtc_ctx *ctx, int32_t robot_id, int32_t scene_id, int32_t set,
                                  int32_t *schedule);
 

@@ -985,20 +985,23 @@ namespace {
 constexpr int kEdgeTile = PRRTC_EDGE_TILE;
 constexpr int kEdgeItems = PRRTC_EDGE_ITEMS;
 
-// The two check_edges schedules: (items per lane, cuboids swept first).  They
-// return the same verdicts; which is faster depends on the robot and scene
-// (measured: 2 items with cuboids first is 10% faster on the 7-DoF arm among
-// 64 mixed obstacles, 3 items with spheres first 8% faster on the dual arm
-// in the shelf), so the first large batch on a (robot, scene) pair times both.
-// two: the robot has coarse spheres (the two-stage instantiations).
-const void* edge_kernel(int schedule, bool two) {
-    static const void* k[2][2] = {
-        {reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false, false>),
-         reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true, false>)},
-        {reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false, true>),
-         reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true, true>)}};
-    return k[two ? 1 : 0][schedule];
+// The check_edges schedules: bit 0 picks (items per lane, cuboids swept
+// first) = (3, no) or (2, yes); bit 1, for robots with coarse spheres, adds
+// the two-stage pass (schedules 2 and 3).  They return the same verdicts;
+// which is faster depends on the robot and scene (measured: 2 items with
+// cuboids first is 9% faster on the 7-DoF arm among 64 mixed obstacles, 3
+// items with spheres first 3% faster on the dual arm in the shelf; the
+// two-stage pass is 15% faster on the 7-DoF arm among 12 obstacles and 2x
+// slower among 64), so the first large batch on a (robot, scene) pair times
+// every schedule the robot has.
+const void* edge_kernel(int schedule) {
+    static const void* k[4] = {reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false, false>),
+                               reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true, false>),
+                               reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, kEdgeItems, false, true>),
+                               reinterpret_cast<const void*>(&k_check_edges<kEdgeTile, 2, true, true>)};
+    return k[schedule];
 }
+int edge_schedules(const RobotArgs& R) { return R.n_cmove > 0 ? 4 : 2; }
 constexpr long long kEdgeTuneMin = 8192;      // batches at least this large pick the schedule
 constexpr long long kEdgeTuneEdges = 1 << 20;  // edges timed per schedule (at most): small prefixes
                                                // mostly time the launch's tail, not the schedule
@@ -1007,9 +1010,10 @@ size_t sphere_lds_bytes(const RobotArgs& R) {
     return sizeof(float4) * R.n_move + sizeof(int) * ((R.n_move + 3) & ~3);
 }
 
-size_t check_lds_bytes(const RobotArgs& R, int tp) {
+// two: a two-stage schedule (its flag and item tables are only needed then)
+size_t check_lds_bytes(const RobotArgs& R, int tp, bool two) {
     return sphere_lds_bytes(R) + sizeof(float4) * tp * 3 * R.n_slots + sizeof(float) * 2 * kMaxDof +
-           sizeof(int) * (tp + 4) + two_stage_lds_bytes(R, tp);
+           sizeof(int) * (tp + 4) + (two ? two_stage_lds_bytes(R, tp) : 0);
 }
 
 // Tuning records are keyed by what decides the timing: the device, and the
@@ -1038,7 +1042,9 @@ void adopt_tuned_schedule(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_id) {
     auto& m = ctx->scenes[scene_id].edge_schedule;
     if (m.count(robot_id) || ctx->tuning.empty()) return;
     auto t = ctx->tuning.find(edge_tuning_key(ctx, robot_id, scene_id));
-    if (t != ctx->tuning.end() && (t->second == "0" || t->second == "1")) m[robot_id] = t->second == "1";
+    if (t == ctx->tuning.end() || t->second.size() != 1) return;
+    const int v = t->second[0] - '0';
+    if (v >= 0 && v < edge_schedules(ctx->robots[robot_id].args)) m[robot_id] = v;
 }
 
 std::string launch_tuning_key(const prrtc_ctx* ctx, const prrtc_query* q, int n, const int32_t* workers,
@@ -1094,13 +1100,12 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
     if (!a || !b || !valid) return fail(ctx, PRRTC_E_ARG, "null buffer");
     hipStream_t sm = stream_of(ctx, stream);
     PRRTC_HIP(ctx, hipSetDevice(ctx->device));
-    const size_t lds = check_lds_bytes(r->args, kEdgeTile);
-    const bool two = r->args.n_cmove > 0;
     auto launch = [&](int schedule, long long n) -> prrtc_status {
-        const int kk = schedule + (two ? 2 : 0);
+        const int kk = schedule;
+        const size_t lds = check_lds_bytes(r->args, kEdgeTile, schedule >= 2);
         if (ctx->edge_grid[kk] == 0 || ctx->edge_grid_lds[kk] != lds) {
             int per_cu = 0;
-            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_kernel(schedule, two), kWave, lds));
+            PRRTC_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_kernel(schedule), kWave, lds));
             ctx->edge_grid[kk] = std::max(1, per_cu) * ctx->n_cu;
             ctx->edge_grid_lds[kk] = lds;
         }
@@ -1116,19 +1121,20 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
         float fres = res;
         uint8_t* pv = valid;
         void* kargs[] = {&ra, &sa, &pa, &pb, &n, &fres, &pv, &ctr, &chunk};
-        PRRTC_HIP(ctx, hipLaunchKernel(edge_kernel(schedule, two), dim3((unsigned)grid), dim3(kWave), kargs, lds, sm));
+        PRRTC_HIP(ctx, hipLaunchKernel(edge_kernel(schedule), dim3((unsigned)grid), dim3(kWave), kargs, lds, sm));
         return PRRTC_OK;
     };
     SceneRec& sr = ctx->scenes[scene_id];
     adopt_tuned_schedule(ctx, robot_id, scene_id);
     auto it = sr.edge_schedule.find(robot_id);
-    int schedule = it == sr.edge_schedule.end() ? 0 : it->second;
+    const int n_sched = edge_schedules(r->args);
+    int schedule = it == sr.edge_schedule.end() ? n_sched - 2 : it->second;   // untimed: two-stage if it has it
     if (it == sr.edge_schedule.end() && n_edges >= kEdgeTuneMin) {
-        // time both schedules on (a prefix of) this batch; its verdicts are
+        // time every schedule on (a prefix of) this batch; its verdicts are
         // written again by the launch below.  Synchronises this once.
         const long long m = std::min<long long>(n_edges, kEdgeTuneEdges);
         float best = 0.0f;
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < n_sched; ++k) {
             st = launch(k, kEdgeTuneMin);   // warm-up
             if (st != PRRTC_OK) return st;
             PRRTC_HIP(ctx, hipEventRecord(ctx->ev0, sm));
@@ -1158,7 +1164,8 @@ prrtc_status prrtc_edge_schedule(prrtc_ctx* ctx, int32_t robot_id, int32_t scene
     const SceneRec* s = nullptr;
     prrtc_status st = lookup(ctx, robot_id, scene_id, &r, &s);
     if (st != PRRTC_OK) return st;
-    if (set < -2 || set > 1) return fail(ctx, PRRTC_E_ARG, "schedule must be -2, -1, 0 or 1");
+    if (set < -2 || set >= edge_schedules(r->args))
+        return fail(ctx, PRRTC_E_ARG, "schedule must be -2, -1, 0 or 1 (2 or 3 with coarse spheres)");
     if (set == -2) adopt_tuned_schedule(ctx, robot_id, scene_id);
     auto& m = ctx->scenes[scene_id].edge_schedule;
     if (set >= 0) m[robot_id] = set;

@@ -320,10 +320,20 @@ def test_check_edges_two_stage(gpu, orc, r7, r14, case):
     a, b = W.random_edges(robot, 1 << 16 if scene == "s64" else 12011, seed=2024)
     for sched in (0, 1):
         P.prrtc_edge_schedule(ctx, rid1, sid, sched)
-        P.prrtc_edge_schedule(ctx, rid2, sid, sched)
+        P.prrtc_edge_schedule(ctx, rid2, sid, sched + 2)   # the same layout with the two-stage pass
         one = gpu_check(gpu, rid1, sid, a, b)
         got = gpu_check(gpu, rid2, sid, a, b)
         assert np.array_equal(got, one), (sched, np.nonzero(got != one)[0][:10])
+    # the coarse robot's one-stage schedules ignore its coarse spheres
+    P.prrtc_edge_schedule(ctx, rid2, sid, 1)
+    assert np.array_equal(gpu_check(gpu, rid2, sid, a, b), one)
+    # timing on a large batch picks among all four schedules
+    if len(a) >= 8192:
+        P.prrtc_edge_schedule(ctx, rid2, sid, -1)
+        assert np.array_equal(gpu_check(gpu, rid2, sid, a, b), one)
+        assert P.prrtc_edge_schedule(ctx, rid2, sid) in (0, 1, 2, 3)
+    with pytest.raises(P.PrrtcError):
+        P.prrtc_edge_schedule(ctx, rid2, sid, 4)
     if grid is not None:
         with grid:
             v, f = assert_parity(orc, robot, prims, a, b, got, threads=16)
