@@ -196,7 +196,9 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
         // only wave 0 of workgroup 0 polls and releases: a second wave that
         // read the generation after the release would wait for the next one
         const int lane = threadIdx.x & (kWave - 1);
-        const unsigned g = __shfl(lane == 0 ? __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0u,
+        // the group's current generation (workgroup 0 wrote it last; a
+        // relaxed load of the same word returns it)
+        const unsigned g = __shfl(lane == 0 ? __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u,
                                   0, kWave);
         const unsigned target = g + 1u;
         const unsigned long long t0 = wall_clock64();
@@ -227,7 +229,11 @@ __device__ inline bool group_barrier(int* bar, int w, int nblocks, int* next = n
             __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (threadIdx.x == 0) {
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        // the current generation: this workgroup saw the word reach it at the
+        // end of the last barrier (or it is the launch's initial 0), and it
+        // cannot advance before this workgroup arrives, so a relaxed load of
+        // the same word returns it
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(flags + w, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long t0 = wall_clock64();
         while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
