@@ -276,7 +276,8 @@ __device__ inline void fk_frames(const RobotArgs& R, QF qf, float4* out) {
 // j4..j4+3 of the chain, lane r takes sincos of joint j4 + r and each joint's
 // pair is broadcast from the lane that made it (DPP within the quad).  ALL =
 // true stores every frame at 3 * f; otherwise only slotted frames, at
-// 3 * slot.  The whole quad must be active.
+// 3 * slot.  The whole quad must be active.  Chains c_lo..c_hi-1 only
+// (each chain's frames depend on that chain alone).
 #ifndef PRRTC_FK_QUAD
 #define PRRTC_FK_QUAD 1
 #endif
@@ -287,9 +288,9 @@ __device__ inline float quad_bcast(float v) {
 }
 
 template <bool ALL, class QF>
-__device__ inline void fk_rows(const RobotArgs& R, QF qf, float4* out, int r) {
+__device__ inline void fk_rows(const RobotArgs& R, QF qf, float4* out, int r, int c_lo = 0, int c_hi = kMaxChains) {
     const int rr = r < 3 ? r : 2;   // lane 3 shadows row 2 and stores nothing
-    for (int c = 0; c < R.n_chains; ++c) {
+    for (int c = c_lo; c < min(c_hi, R.n_chains); ++c) {
         const float* B = R.base[c] + 4 * rr;
         float x = B[0], y = B[1], z = B[2], t = B[3];
         int f = R.chain_f0[c];
@@ -757,8 +758,12 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
         // the tile leaves room for it)
         constexpr int CPW = TP / NW;
         constexpr int LPC = (PRRTC_FK_QUAD && 4 * CPW <= kWave) ? 4 : 1;
-        const int slot = wave * CPW + lane / LPC;
-        if (lane < CPW * LPC && slot < np) {
+        // a tile that fits one wave's share, of a two-chain robot: waves 0 and
+        // 1 take one chain each of the same configurations (the FK's latency
+        // halves; the other waves would idle anyway)
+        const bool by_chain = NW >= 2 && LPC == 4 && R.n_chains == 2 && np <= CPW;
+        const int slot = (by_chain ? 0 : wave * CPW) + lane / LPC;
+        if ((!by_chain || wave < 2) && lane < CPW * LPC && slot < np) {
             const int g = g0 + slot;
             int k = 0;
             if (MULTI)
@@ -770,7 +775,8 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             if (lane % LPC == 0) ws.pk[slot] = k;
             auto qf = [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); };
             if (LPC == 4)
-                fk_rows<false>(R, qf, ws.frames + slot * fstride, lane & 3);
+                fk_rows<false>(R, qf, ws.frames + slot * fstride, lane & 3, by_chain ? wave : 0,
+                               by_chain ? wave + 1 : kMaxChains);
             else
                 fk_frames<false>(R, qf, ws.frames + slot * fstride);
         }
