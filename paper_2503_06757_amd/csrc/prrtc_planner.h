@@ -876,6 +876,12 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         }
         par ^= 1;
     }
+    // no round ran (max_rounds 0): the endpoint verdict still decides the
+    // status, after a barrier of its own
+    if (!ends_checked && P.max_rounds <= 0) {
+        if (!group_barrier(G.bar(), w, P.W)) return false;
+        if (ends_bad()) return true;
+    }
     if (tid == 0 && my_edges) atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kEdgesLo), (unsigned long long)my_edges);
     if (tid == 0 && my_learned)
         atomicAdd(reinterpret_cast<unsigned long long*>(ctl + kLearnedLo), (unsigned long long)my_learned);

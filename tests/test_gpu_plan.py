@@ -145,6 +145,8 @@ def test_plan_status_codes(gpu, orc, r7):
     big = W.make_prims([(W.PRIM_SPHERE, (0, 0, 0.5), np.eye(3), (5.0, 0, 0))])
     sid_big = P.prrtc_load_scene(ctx, big)
     assert P.prrtc_plan(ctx, rid, sid_big, s, g, params(P))[0] == P.PRRTC_E_INVALID_ENDPOINT
+    # the endpoints are checked even when no round may run (as the oracle does)
+    assert P.prrtc_plan(ctx, rid, sid_big, s, g, params(P, max_rounds=0))[0] == P.PRRTC_E_INVALID_ENDPOINT
     # two-call pattern: too small a buffer reports the size needed
     st, _, stats = P.prrtc_plan(ctx, rid, sid, s, g, params(P, seed=1), path_cap=1)
     assert st == P.PRRTC_E_CAPACITY and stats["path_len"] > 1

@@ -86,6 +86,7 @@ def test_failure_codes(orc, r7):
     assert orc.plan(rob, prims, bad, g)[0] == E_INVALID_ENDPOINT
     big = W.make_prims([(W.PRIM_SPHERE, (0, 0, 0.5), np.eye(3), (5.0, 0, 0))])
     assert orc.plan(rob, big, s, g)[0] == E_INVALID_ENDPOINT
+    assert orc.plan(rob, big, s, g, max_rounds=0)[0] == E_INVALID_ENDPOINT   # checked before any round
     assert orc.plan(rob, prims, s, g, workers=0)[0] == E_ARG
     # a tree of capacity 2 fills after one node; the planner must stop cleanly
     st, _, stats = orc.plan(rob, prims, s, g, tree_capacity=2, workers=8, max_rounds=20)
