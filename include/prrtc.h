@@ -246,7 +246,9 @@ typedef struct {
     int32_t tile;            /* configurations per FK tile of the collision checks:
                                 64 (0 = default; lowest latency per query) or 16
                                 (a quarter of the LDS: more groups per batched
-                                launch); results do not depend on it */
+                                launch); a single plan of tile 64 runs workers
+                                of eight waves when all of them can be resident,
+                                else of four; results do not depend on it */
 } prrtc_plan_params;
 
 typedef struct {

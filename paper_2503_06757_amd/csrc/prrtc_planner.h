@@ -282,16 +282,17 @@ struct NearBest {
 // dof-1 and add an exact zero) before using any, so a step waits for one
 // memory latency instead of one per joint and node.  Nodes are visited in
 // increasing index order per lane and the strict compare keeps the first of
-// equal distances.
+// equal distances.  With parts > 1 the caller's waves split the steps: wave
+// `part` takes every parts-th one.
 template <int D, int U>
 __device__ inline void near_scan_t(const float* tq, const unsigned char* blocked, int cap, int size, const float* x,
-                                   int dof, NearBest& b) {
+                                   int dof, NearBest& b, int part, int parts) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & (kWave - 1);
     float xr[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) xr[j] = j < dof ? x[j] : 0.0f;
-    for (int i0 = lane; i0 < size; i0 += kWave * U) {
+    for (int i0 = lane + part * kWave * U; i0 < size; i0 += kWave * U * parts) {
         float v[U][D];
         int idx[U];
         bool skip[U];
@@ -322,11 +323,11 @@ __device__ inline void near_scan_t(const float* tq, const unsigned char* blocked
 }
 
 __device__ inline void near_scan(const float* tq, const unsigned char* blocked, int cap, int size, const float* x,
-                                 int dof, NearBest& b) {
+                                 int dof, NearBest& b, int part = 0, int parts = 1) {
     if (dof <= 8)
-        near_scan_t<8, 4>(tq, blocked, cap, size, x, dof, b);
+        near_scan_t<8, 4>(tq, blocked, cap, size, x, dof, b, part, parts);
     else
-        near_scan_t<kMaxDof, 2>(tq, blocked, cap, size, x, dof, b);
+        near_scan_t<kMaxDof, 2>(tq, blocked, cap, size, x, dof, b, part, parts);
 }
 
 // The previous round's staged nodes of a tree that are not yet guaranteed to
@@ -334,9 +335,10 @@ __device__ inline void near_scan(const float* tq, const unsigned char* blocked, 
 // `stage` ([.][dof]) with tree index first + (counts of workers < v) + k,
 // kept below cap.  Lane l takes workers l, l + 64, ...; indices grow with
 // the worker and k, and every one exceeds the tree-array indices, so the
-// strict compare again keeps the lowest index of equal distances.
+// strict compare again keeps the lowest index of equal distances.  With
+// parts > 1, wave `part` takes the nodes k = part, part + parts, ...
 __device__ inline void near_scan_staged(const float* stage, int stage_cap, const int* cnt, int W, int first, int cap,
-                                        const float* x, int dof, NearBest& b) {
+                                        const float* x, int dof, NearBest& b, int part = 0, int parts = 1) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & (kWave - 1);
     int running = first;
@@ -351,7 +353,7 @@ __device__ inline void near_scan_staged(const float* stage, int stage_cap, const
         }
         const int base = running + incl - c;
         const int kept = max(0, min(c, cap - base));
-        for (int k = 0; k < kept; ++k) {
+        for (int k = part; k < kept; k += parts) {
             const float* row = stage + ((size_t)v * stage_cap + k) * dof;
             float s = 0.0f;
             for (int j = 0; j < dof; ++j) {
@@ -401,7 +403,8 @@ typedef __attribute__((address_space(4))) const PlanArgs CPlanArgs;
 
 // A worker is a workgroup of NW waves: wave 0 ("lead") does the worker's
 // scalar bookkeeping and writes its small LDS vectors; every wave computes the
-// same samples and nearest neighbours and shares the collision checks.
+// same samples, the waves split the nearest-neighbour scans and share the
+// collision checks.
 // The group's own memory: the query's group-0 pointers moved by goff bytes.
 // Each pointer is formed where it is used (a scalar load and add), so the
 // seventeen of them do not all stay live in registers.
@@ -476,6 +479,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
     two_stage_ws(R, TP, ws.sub_off + P.stage_cap + 2, ws);
     __shared__ int sh_i[8];
     __shared__ int sh_check[2];
+    __shared__ NearBest sh_nb[NW];
     ws.shared = sh_check;
     int* ctl = P.ctl;
     long long my_edges = 0;
@@ -576,6 +580,29 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
         const float* stage_prev = G.stage(par ^ 1, dof);
         const int* cnt_prev = G.st_count(par ^ 1);
         const int* fail_prev = G.st_fail(par ^ 1);
+        // Nearest neighbour of x among a tree's visible nodes (and the previous
+        // round's staged ones when that tree grew), the scan split over the
+        // worker's waves and their results combined through LDS by the same
+        // (distance, index) order as within a wave: the same node as one
+        // wave scanning everything.
+        auto nearest = [&](const float* tq, const unsigned char* bl, int vis, bool staged, const float* x) {
+            const int part = NW > 1 ? tid / kWave : 0;
+            NearBest b{__builtin_inff(), 0x7fffffff, -1};
+            near_scan(tq, bl, cap, vis, x, dof, b, part, NW);
+            if (staged) near_scan_staged(stage_prev, P.stage_cap, cnt_prev, P.W, lr_first, cap, x, dof, b, part, NW);
+            b = nearest_reduce(b);
+            if (NW > 1) {
+                // the last reads of sh_nb were followed by a workgroup barrier
+                if (lane == 0) sh_nb[part] = b;
+                __syncthreads();
+                b = sh_nb[0];
+                for (int k = 1; k < NW; ++k) {
+                    const NearBest o = sh_nb[k];
+                    if (o.d < b.d || (o.d == b.d && o.i < b.i)) b = o;
+                }
+            }
+            return b;
+        };
         float* qs = s_is_a ? G.qa() : G.qb();
         int* ps = s_is_a ? G.pa() : G.pb();
         unsigned char* bs = s_is_a ? G.ba() : G.bb();
@@ -609,10 +636,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
                                         : sample_joint(P.seed, P.query, (unsigned)round, (unsigned)w, (unsigned)t, dof,
                                                        lane, pick(R.lo, lane), pick(R.hi, lane));
             __syncthreads();
-            NearBest nb_s{__builtin_inff(), 0x7fffffff, -1};
-            near_scan(qs, bs, cap, vis_s, c_rand, dof, nb_s);
-            if (staged_s) near_scan_staged(stage_prev, P.stage_cap, cnt_prev, P.W, lr_first, cap, c_rand, dof, nb_s);
-            nb_s = nearest_reduce(nb_s);
+            const NearBest nb_s = nearest(qs, bs, vis_s, staged_s, c_rand);
             const int cand = nb_s.i == 0x7fffffff ? -1 : nb_s.i;
             if (cand < 0) break;
             if (lead && lane < dof)
@@ -657,11 +681,7 @@ __device__ __attribute__((always_inline)) bool plan_query(CPlanArgs& P, int w, f
             if (!ext_ok) fail = nn;
             if (ext_ok) {
                 count = 1;
-                NearBest nb_o{__builtin_inff(), 0x7fffffff, -1};
-                near_scan(qo, bo, cap, vis_o, c_new, dof, nb_o);
-                if (staged_o)
-                    near_scan_staged(stage_prev, P.stage_cap, cnt_prev, P.W, lr_first, cap, c_new, dof, nb_o);
-                nb_o = nearest_reduce(nb_o);
+                const NearBest nb_o = nearest(qo, bo, vis_o, staged_o, c_new);
                 other = nb_o.i == 0x7fffffff ? -1 : nb_o.i;
                 if (other >= 0) {
                     if (lead && lane < dof)
