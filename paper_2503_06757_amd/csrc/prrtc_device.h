@@ -758,12 +758,15 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
         // the tile leaves room for it)
         constexpr int CPW = TP / NW;
         constexpr int LPC = (PRRTC_FK_QUAD && 4 * CPW <= kWave) ? 4 : 1;
-        // a tile that fits one wave's share, of a two-chain robot: waves 0 and
-        // 1 take one chain each of the same configurations (the FK's latency
-        // halves; the other waves would idle anyway)
-        const bool by_chain = NW >= 2 && LPC == 4 && R.n_chains == 2 && np <= CPW;
-        const int slot = (by_chain ? 0 : wave * CPW) + lane / LPC;
-        if ((!by_chain || wave < 2) && lane < CPW * LPC && slot < np) {
+        // a tile that fits half the waves' shares, of a two-chain robot: the
+        // first half of the waves takes chain 0 of the configurations, the
+        // second half chain 1 (the FK's latency halves; the waves past the
+        // configurations would idle anyway)
+        constexpr int HALF = NW >= 2 ? NW / 2 : 1;
+        const bool by_chain = NW >= 2 && LPC == 4 && R.n_chains == 2 && np <= CPW * HALF;
+        const int chain = wave / HALF;
+        const int slot = (by_chain ? (wave % HALF) : wave) * CPW + lane / LPC;
+        if (lane < CPW * LPC && slot < np) {
             const int g = g0 + slot;
             int k = 0;
             if (MULTI)
@@ -775,8 +778,8 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
             if (lane % LPC == 0) ws.pk[slot] = k;
             auto qf = [&](int j) { return fmaf(t, w1[j] - w0[j], w0[j]); };
             if (LPC == 4)
-                fk_rows<false>(R, qf, ws.frames + slot * fstride, lane & 3, by_chain ? wave : 0,
-                               by_chain ? wave + 1 : kMaxChains);
+                fk_rows<false>(R, qf, ws.frames + slot * fstride, lane & 3, by_chain ? chain : 0,
+                               by_chain ? chain + 1 : kMaxChains);
             else
                 fk_frames<false>(R, qf, ws.frames + slot * fstride);
         }
