@@ -35,25 +35,27 @@ using namespace prrtc;
 // ----------------------------------------------------------------------------
 
 // check_edges: one wavefront per workgroup.  Collision-free edges cost far
-// more than colliding ones, so edges are handed out dynamically: the batch is
-// split into one contiguous range per XCD (workgroup ids are dealt to the 8
-// XCDs round-robin) and each wave takes chunks of `chunk` edges from its
-// XCD's counter, keeping the atomics off a single shared address (kEdgeChunk
-// for large batches; fewer for batches that do not fill every resident wave
-// with several chunks, down to one edge, so a small batch is spread over as
-// many waves as it has edges).  The next
-// chunk's first endpoints are fetched while the current edge is checked.  The
-// last wave to finish resets the counters for the next launch.
+// more than colliding ones, so large batches are handed out dynamically: the
+// batch is split into one contiguous range per XCD (workgroup ids are dealt
+// to the 8 XCDs round-robin) and each wave takes chunks of `chunk` edges from
+// its XCD's counter, keeping the atomics off a single shared address; the
+// last wave to finish resets the counters for the next launch.  Batches of
+// at most kEdgeStatic edges per resident wave take chunk = 0: wave b checks
+// edges b, b + grid, b + 2 grid, ... with no atomics at all (there, the
+// counters' serialised atomics, thousands per address, cost more than the
+// imbalance: 4096 edges 122 -> 36 us, 131072 edges 305 -> 249 us).  The next
+// edge's endpoints are fetched while the current edge is checked.
 #ifndef PRRTC_EDGE_CHUNK
 #define PRRTC_EDGE_CHUNK 8
 #endif
 #ifndef PRRTC_EDGE_WAVES
 #define PRRTC_EDGE_WAVES 6
 #endif
-#ifndef PRRTC_EDGE_SCHED
-#define PRRTC_EDGE_SCHED 2  // 0: static stride, 1: one counter, 2: per-XCD chunked counters
+#ifndef PRRTC_EDGE_STATIC
+#define PRRTC_EDGE_STATIC 48
 #endif
 constexpr int kEdgeChunk = PRRTC_EDGE_CHUNK;
+constexpr long long kEdgeStatic = PRRTC_EDGE_STATIC;
 constexpr int kXcds = 8;
 
 struct EdgeCounter {
@@ -93,32 +95,23 @@ void k_check_edges(RobotArgs R, SceneArgs S,
     load_bounds(S, ws);
     const bool fixed_hit = static_collision(R, S);
     __syncthreads();
-#if PRRTC_EDGE_SCHED == 2
+    const bool dyn = chunk > 0;
     const int xcd = blockIdx.x % kXcds;
-    const long long lo = n_edges * xcd / kXcds, hi = n_edges * (xcd + 1) / kXcds;
+    const long long lo = dyn ? n_edges * xcd / kXcds : 0;
+    const long long end = dyn ? n_edges * (xcd + 1) / kXcds : n_edges;
+    const long long step = dyn ? chunk : 1;
     unsigned long long* my_ctr = &ctr->next[xcd * 8];
-    auto grab = [&]() {
-        unsigned long long v = 0;
-        if (lane == 0) v = atomicAdd(my_ctr, (unsigned long long)chunk);
-        return lo + (long long)__shfl(v, 0, kWave);
-    };
-    const long long stride = 1, end = hi;
-#elif PRRTC_EDGE_SCHED == 1
-    auto grab = [&]() {
-        unsigned long long v = 0;
-        if (lane == 0) v = atomicAdd(&ctr->next[0], (unsigned long long)chunk);
-        return (long long)__shfl(v, 0, kWave);
-    };
-    const long long stride = 1, end = n_edges;
-#else
-    long long cursor = (long long)blockIdx.x * chunk;
-    auto grab = [&]() {
+    long long cursor = blockIdx.x;
+    auto grab = [&]() -> long long {
+        if (dyn) {
+            unsigned long long v = 0;
+            if (lane == 0) v = atomicAdd(my_ctr, (unsigned long long)chunk);
+            return lo + (long long)__shfl(v, 0, kWave);
+        }
         const long long v = cursor;
-        cursor += (long long)gridDim.x * chunk;
+        cursor += gridDim.x;
         return v;
     };
-    const long long stride = 1, end = n_edges;
-#endif
     long long c0 = grab();
     float ra = 0.0f, rb = 0.0f;
     if (c0 < end && lane < dof) {
@@ -127,8 +120,8 @@ void k_check_edges(RobotArgs R, SceneArgs S,
     }
     while (c0 < end) {
         const long long c1 = grab();
-        const long long cend = min(c0 + (long long)chunk, end);
-        for (long long e = c0; e < cend; e += stride) {
+        const long long cend = min(c0 + step, end);
+        for (long long e = c0; e < cend; ++e) {
             if (lane < dof) {
                 wp[lane] = ra;
                 wp[dof + lane] = rb;
@@ -146,7 +139,7 @@ void k_check_edges(RobotArgs R, SceneArgs S,
         }
         c0 = c1;
     }
-    if (PRRTC_EDGE_SCHED != 0 && lane == 0) {
+    if (dyn && lane == 0) {
         __threadfence();
         if (atomicAdd(&ctr->done, 1u) == gridDim.x - 1) {
             for (int x = 0; x < kXcds; ++x) atomicExch(&ctr->next[x * 8], 0ull);
@@ -1118,9 +1111,12 @@ prrtc_status prrtc_check_edges(prrtc_ctx* ctx, int32_t robot_id, int32_t scene_i
             ctx->edge_grid_lds[kk] = lds;
         }
         // at least one workgroup per XCD range (empty ranges exit at once);
-        // chunks of up to kEdgeChunk edges, at least four per resident wave
+        // chunks of up to kEdgeChunk edges, at least four per resident wave;
+        // small batches: the static interleave (chunk 0)
         const long long grid = std::max<long long>(std::min<long long>(n, ctx->edge_grid[kk]), kXcds);
-        int chunk = (int)std::min<long long>(kEdgeChunk, std::max<long long>(1, n / (4LL * ctx->edge_grid[kk])));
+        int chunk = n <= kEdgeStatic * ctx->edge_grid[kk]
+                        ? 0
+                        : (int)std::min<long long>(kEdgeChunk, std::max<long long>(1, n / (4LL * ctx->edge_grid[kk])));
         EdgeCounter* ctr = ctx->counters + (ctx->counter_next++ % kCounterSlots);
         RobotArgs ra = r->args;
         SceneArgs sa = s->args;
