@@ -360,17 +360,19 @@ def bench_plan(P, ctx, n_instances=100, n_seeds=50):
             "time_budget_ms": prm.time_budget_ms}
 
 
-def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, budget_ms=100.0):
+def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, max_rounds=3000):
     """Served workload pool: scenes with U{8..128} obstacles (6:4:2 mix) for
     the 7-DoF arm and the dual arm alternately, up to `per_scene` free
     queries each (endpoints checked by prrtc_check_edges), kept when the
-    uniform planner solves them within budget_ms (many generated queries in
-    dense scenes have no solution; serving them measures only the budget)."""
+    uniform planner (256 workers, its seed) solves them within max_rounds
+    rounds (many generated queries in dense scenes have no solution; serving
+    them measures only the budget).  A round budget, not a time budget,
+    keeps the pool the same for every build of the planner."""
     from paper_2503_06757_amd import proposal as PR
     robots = [W.robot_r7(), W.robot_r14()]
     rids = [P.prrtc_load_robot(ctx, r) for r in robots]
     prm = P.prrtc_plan_params_default()
-    prm.max_rounds, prm.time_budget_ms = 4000, budget_ms
+    prm.max_rounds, prm.time_budget_ms = max_rounds, 0.0
     pool, tried = [], 0
     for i in range(n_scenes):
         kind = i % 2
