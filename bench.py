@@ -119,11 +119,13 @@ def edge_counts(a, b, res):
     return np.maximum(n, 1)
 
 
-def bench_check_edges(P, ctx, torch, steps, warmup):
+def bench_check_edges(P, ctx, torch, steps, warmup, schedule_pin=-1):
     robot = W.robot_r7()
     prims = W.scene_s64(robot)
     rid = P.prrtc_load_robot(ctx, robot)
     sid = P.prrtc_load_scene(ctx, prims)
+    if schedule_pin >= 0:
+        P.prrtc_edge_schedule(ctx, rid, sid, schedule_pin)   # a profiler run times every launch the same way
     a, b = W.random_edges(robot, N_EDGES)
     ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
     tv = torch.empty(N_EDGES, dtype=torch.uint8, device="cuda")
@@ -776,6 +778,8 @@ def main():
     ap.add_argument("--skip-sampling", action="store_true",
                     help="omit the sampling variants (uniform, dynamic domain, Halton)")
     ap.add_argument("--serve-queries", type=int, default=10000)
+    ap.add_argument("--edge-schedule", type=int, default=-1,
+                    help="pin the check_edges schedule of the headline leg (default: the timed choice)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -786,7 +790,7 @@ def main():
     import torch
     from paper_2503_06757_amd import prrtc as P
     ctx = P.prrtc_create(0)
-    ce = bench_check_edges(P, ctx, torch, args.steps, args.warmup)
+    ce = bench_check_edges(P, ctx, torch, args.steps, args.warmup, args.edge_schedule)
     if args.calibrate_copy:
         n = args.calibrate_copy << 20
         src = torch.empty(n, dtype=torch.uint8, device="cuda")
