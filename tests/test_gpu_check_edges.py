@@ -417,3 +417,35 @@ def test_check_edges_stream_order(gpu, r7):
         say("  default-stream launch %d: %.3f ms" % (rep, ms))
         assert np.array_equal(got, want), rep
         assert ms > 0.02                       # the kernel ran between the events
+
+
+@pytest.mark.gpu
+def test_check_edges_static_and_dynamic_handout_agree(gpu, orc, r7):
+    """A batch of up to 48 edges per resident wave is interleaved statically
+    over the waves, a larger one handed out in chunks from per-XCD counters.
+    The same 2^19 edges as one batch (dynamic on a 256-CU device) and as
+    eight batches of 2^16 (static) give the same verdicts, and a sample of
+    them equals the oracle's."""
+    P, ctx, torch = gpu
+    rid = P.prrtc_load_robot(ctx, r7)
+    prims = W.scene_s64(r7)
+    sid = P.prrtc_load_scene(ctx, prims)
+    P.prrtc_edge_schedule(ctx, rid, sid, 1)
+    n, part = 1 << 19, 1 << 16
+    a, b = W.random_edges(r7, n, seed=733)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    whole = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    P.prrtc_check_edges(ctx, rid, sid, ta.data_ptr(), tb.data_ptr(), n, 32.0, whole.data_ptr(), None)
+    parts = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    for k in range(0, n, part):
+        P.prrtc_check_edges(ctx, rid, sid, ta[k:].data_ptr(), tb[k:].data_ptr(), part, 32.0,
+                            parts[k:].data_ptr(), None)
+    torch.cuda.synchronize()
+    whole, parts = whole.cpu().numpy(), parts.cpu().numpy()
+    say("  static vs dynamic hand-out: %d valid of %d" % (int(whole.sum()), n))
+    assert set(np.unique(whole)) <= {0, 1}
+    assert np.array_equal(whole, parts)
+    idx = np.random.default_rng(9).choice(n, 3000, replace=False)
+    want, flag, _ = orc.check_edges(orc.OracleRobot(r7), prims, a[idx], b[idx], 32.0, early_exit=True)
+    ok = flag == 0
+    assert np.array_equal(whole[idx][ok], want[ok].astype(np.uint8))
