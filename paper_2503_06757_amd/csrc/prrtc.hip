@@ -89,7 +89,8 @@ void k_check_edges(RobotArgs R, SceneArgs S,
     ws.pk = reinterpret_cast<int*>(wp + 2 * kMaxDof);
     ws.sub_n = ws.pk + TP;
     ws.sub_off = ws.sub_n + 2;
-    two_stage_ws(R, TP, ws.sub_off + 2, ws);
+    int* chunk_n = ws.sub_off + 2;   // point counts of the current chunk's edges
+    two_stage_ws(R, TP, chunk_n + kEdgeChunk, ws);
     ws.shared = nullptr;   // single-wave checks share nothing
     stage_spheres(R, sph, slot3);
     load_bounds(S, ws);
@@ -121,6 +122,9 @@ void k_check_edges(RobotArgs R, SceneArgs S,
     while (c0 < end) {
         const long long c1 = grab();
         const long long cend = min(c0 + step, end);
+        // the chunk's point counts, one edge per lane (lane l: edge c0 + l),
+        // instead of the whole wave computing each edge's count in turn
+        if (lane < cend - c0) chunk_n[lane] = edge_count_f32(A + (c0 + lane) * dof, Bv + (c0 + lane) * dof, dof, res);
         for (long long e = c0; e < cend; ++e) {
             if (lane < dof) {
                 wp[lane] = ra;
@@ -133,7 +137,9 @@ void k_check_edges(RobotArgs R, SceneArgs S,
                 rb = Bv[nx * dof + lane];
             }
             __syncthreads();
-            const int ok = fixed_hit ? 0 : (wave_check<TP, B, false, 1, BOX_FIRST, TWO>(R, S, wp, 1, 0, res, ws) == 1);
+            const int n_e = chunk_n[e - c0];
+            const int ok =
+                fixed_hit ? 0 : (wave_check<TP, B, false, 1, BOX_FIRST, TWO>(R, S, wp, 1, 0, res, ws, 0, 1, n_e) == 1);
             if (lane == 0) valid[e] = (uint8_t)ok;
             __syncthreads();
         }
@@ -1014,7 +1020,7 @@ size_t sphere_lds_bytes(const RobotArgs& R) {
 // two: a two-stage schedule (its flag and item tables are only needed then)
 size_t check_lds_bytes(const RobotArgs& R, int tp, bool two) {
     return sphere_lds_bytes(R) + sizeof(float4) * tp * 3 * R.n_slots + sizeof(float) * 2 * kMaxDof +
-           sizeof(int) * (tp + 4) + (two ? two_stage_lds_bytes(R, tp) : 0);
+           sizeof(int) * (tp + 4 + kEdgeChunk) + (two ? two_stage_lds_bytes(R, tp) : 0);
 }
 
 // Tuning records are keyed by what decides the timing: the device, and the

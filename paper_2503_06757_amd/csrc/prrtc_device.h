@@ -684,7 +684,9 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
 }
 
 // With n_chunks > 1 (one sub-edge only) the points i_first..n are split into
-// n_chunks equal runs and only run `chunk` is checked.
+// n_chunks equal runs and only run `chunk` is checked.  n_known >= 0 (one
+// sub-edge): the edge's point count, already computed by the caller from the
+// same endpoints (edge_count_f32).
 //
 // BOX_FIRST: cuboids are swept before spheres (the first hit ends the
 // check, so the order only changes the time; check_edges picks it by timing).
@@ -699,7 +701,8 @@ __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3
 // sub-edge; ws.shared[1]: a wave found a hit, single sub-edge).
 template <int TP, int B, bool MULTI, int NW = 1, bool BOX_FIRST = false, bool TWO = false>
 __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, const SceneArgs& S, const float* wp, int n_sub,
-                          int i_first, float res, const WaveWs& ws, int chunk = 0, int n_chunks = 1) {
+                          int i_first, float res, const WaveWs& ws, int chunk = 0, int n_chunks = 1,
+                          int n_known = -1) {
     static_assert(TP >= 1 && TP <= kWave, "one configuration per lane in the FK tile");
     static_assert(NW >= 1 && TP % NW == 0, "the FK tile splits evenly over the waves");
     const int lane = threadIdx.x & (kWave - 1);
@@ -711,7 +714,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
     // sub-edge: every lane computes the same count from the same LDS words)
     int total = 0;
     if (!MULTI) {
-        const int n = edge_count_f32(wp, wp + dof, dof, res);
+        const int n = n_known >= 0 ? n_known : edge_count_f32(wp, wp + dof, dof, res);
         int cnt = n - i_first + 1, lo = 0;
         if (n_chunks > 1) {
             lo = cnt * chunk / n_chunks;
