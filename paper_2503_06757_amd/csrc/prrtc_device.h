@@ -675,6 +675,17 @@ __device__ __attribute__((always_inline)) bool cull_sweep(const SceneArgs& S, fl
     return false;
 }
 
+// ceil(2^20 / n) for the item decode's multiply-and-shift division by the
+// tile's configuration count n = 1..64: a table lookup instead of an integer
+// division per tile.
+struct FastDivTable {
+    unsigned m[kWave + 1];
+    constexpr FastDivTable() : m{} {
+        for (int n = 1; n <= kWave; ++n) m[n] = ((1u << 20) + (unsigned)n - 1u) / (unsigned)n;
+    }
+};
+__device__ constexpr FastDivTable kFastDiv{};
+
 // Stage the moving spheres' records in LDS (once per workgroup).
 __device__ inline void stage_spheres(const RobotArgs& R, float4* sph, int* slot3) {
     for (int s = threadIdx.x; s < R.n_move; s += blockDim.x) {
@@ -867,7 +878,7 @@ __device__ __attribute__((always_inline)) int wave_check(const RobotArgs& R, con
         // equals floor(it / np) for it < np * 256 and np <= 64 (the rounding
         // excess it (m - 2^20 / np) / 2^20 stays below 1/64 <= 1/np), and
         // it m < 2^32
-        const unsigned div_m = ((1u << 20) + (unsigned)np - 1u) / (unsigned)np;
+        const unsigned div_m = kFastDiv.m[np];
         bool stop = false;
         for (int base = wave * kWave * B; base < nitems && !stop; base += NW * kWave * B) {
             if (NW > 1 && !MULTI && shared[1]) break;   // another wave found a hit
