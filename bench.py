@@ -396,6 +396,19 @@ def query_pool(P, ctx, torch, n_scenes=64, per_scene=4, seed=0x56000000, max_rou
 SERVE_HEADROOM = 1.05  # tuned batch rate over the arrival rate a served launch shape must keep
 
 
+def served_shape(rates, rate, fastest):
+    """Launch shape for serving at `rate` queries/s from the tuner's
+    {(workers, tile): queries/s}: a query's latency falls with its worker
+    count as long as the launch keeps up with the arrivals, so the most
+    workers per query whose rate has SERVE_HEADROOM over the arrival rate
+    (the faster tile among those), else the fastest shape."""
+    fits = [(w, v, t) for (w, t), v in rates.items() if v >= SERVE_HEADROOM * rate]
+    if not fits:
+        return fastest
+    w, _, t = max(fits)
+    return w, t
+
+
 def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None, slots=256, max_pending=1024,
                 budget=2 << 30, max_rounds=4000, budget_ms=100.0, seed=0x56000000, log=None, models=None, tile=16,
                 arrivals=None):
@@ -426,12 +439,7 @@ def bench_serve(P, ctx, torch, pool, n_queries=10000, rate=2000.0, workers=None,
         sample = [(pool[k % len(pool)][0], pool[k % len(pool)][1], pool[k % len(pool)][2], pool[k % len(pool)][3],
                    seed + 777 + k, 0) for k in range(slots)]
         (best_w, best_t), rates = P.prrtc_tune_launch(ctx, sample, prm, memory_budget=budget)
-        # A query's latency falls with its worker count as long as the launch
-        # keeps up with the arrivals, so serve with the most workers per query
-        # whose tuned rate has 5% headroom over the arrival rate (else the
-        # fastest shape).
-        fits = [(w, v, t) for (w, t), v in rates.items() if v >= SERVE_HEADROOM * rate]
-        workers, tile = (max(fits)[0], max(fits)[2]) if fits else (best_w, best_t)
+        workers, tile = served_shape(rates, rate, (best_w, best_t))
         tune = {"workers": workers, "tile": tile, "fastest": {"workers": best_w, "tile": best_t},
                 "headroom": SERVE_HEADROOM, "queries_per_s": {"%d/%d" % k: v for k, v in rates.items()}}
         if log:

@@ -56,3 +56,16 @@ def test_bench_percentiles_report_failures_as_null():
     p = bench.pcts(t)
     assert p["p50_ms"] == 2.5 and p["p90_ms"] is None and p["p99_ms"] is None
     assert bench.pcts(np.array([]))["p50_ms"] is None
+
+
+def test_served_shape_most_workers_with_headroom():
+    """Serving takes the most workers per query whose tuned rate keeps the
+    headroom over the arrival rate; with none, the tuner's fastest shape."""
+    import bench
+    rates = {(16, 16): 2484.0, (16, 64): 2116.0, (32, 16): 2422.0, (32, 64): 1721.0, (64, 16): 2219.0,
+             (64, 64): 1196.0, (128, 16): 2043.0, (128, 64): 1255.0, (256, 16): 1508.0, (256, 64): 655.0}
+    assert bench.served_shape(rates, 2000.0, (16, 16)) == (64, 16)
+    assert bench.served_shape(rates, 1000.0, (16, 16)) == (256, 16)
+    assert bench.served_shape(rates, 1450.0, (16, 16)) == (128, 16)   # 1508 < 1.05 x 1450
+    assert bench.served_shape(rates, 600.0, (16, 16)) == (256, 16)    # both tiles keep up: the faster one
+    assert bench.served_shape(rates, 5000.0, (16, 16)) == (16, 16)    # nothing keeps up: the fastest
